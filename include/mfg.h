@@ -1,0 +1,192 @@
+/*
+ * mfg.h -- C ABI of the MI355X (gfx950) solver for time-dependent variational
+ * mean field games, after Ljosheim, Kalise, Pearson and Silva,
+ * "Parallel-in-Time Preconditioning for Time-Dependent Variational Mean Field
+ * Games" (arXiv 2507.01958).
+ *
+ * The library runs the paper's Chambolle-Pock iteration (Section 3,
+ * eq. pasosChamPock) on the finite-difference discretisation (Section 2,
+ * problem VMFG_h): a per-cell proximal step on the cost b-hat + F, then the
+ * projection onto the discrete Fokker-Planck constraint (eq. CC*), which is a
+ * conjugate-gradient solve with the reduced matrix of eq. largeA,
+ * preconditioned by the parallel-in-time operator of eq. pstrec
+ * (Algorithms 1 and 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All vector arguments are DEVICE pointers to contiguous float64 arrays on
+ *   the GPU that was current when the plan was made, unless stated otherwise.
+ *   The caller owns them; the library never frees or keeps them.
+ * - Sizes: M = N_x * N_y (N_y = 1 when d = 1), n = N_t * M, and a primal
+ *   vector holds (1 + 2d) n values.
+ * - Layout: an n-vector is [t][i][j] with j fastest (time slice t, node (i, j)).
+ *   A primal vector is the block m (n values) followed by the 2d flux blocks
+ *   w^(c) (n values each, c = 0..2d-1; even c is the non-negative and odd c the
+ *   non-positive half-line of the cone K of Section 2; c = 0, 1 act along x,
+ *   c = 2, 3 along y). Slice t of m holds m^{t+1}; slice t of w holds w^t; the
+ *   initial density m^0 = m0 is eliminated (Section 2.1: 5 N_t N_x N_y
+ *   unknowns when d = 2).
+ * - Every call is asynchronous on the plan's stream, except outputs written to
+ *   host pointers (iteration counts, residuals, statistics), which synchronise
+ *   the stream before returning.
+ * - Return value: MFG_OK or an mfg_status_t error code; nothing is thrown
+ *   across the ABI. On error the contents of output buffers are unspecified
+ *   and mfg_last_error() describes the failure (thread-local string).
+ * - A plan is not thread-safe; different plans are independent.
+ */
+#ifndef MFG_H
+#define MFG_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MFG_OK = 0,
+  MFG_ERR_INVALID_ARG = 1,   /* bad shape, parameter or pointer */
+  MFG_ERR_UNSUPPORTED = 2,   /* valid but not implemented (q' != 2, FFT size) */
+  MFG_ERR_NOT_CONVERGED = 3, /* PCG hit maxit; iters/relres are still filled */
+  MFG_ERR_BREAKDOWN = 4,     /* non-positive curvature or r.z in PCG */
+  MFG_ERR_NONFINITE = 5,     /* NaN or Inf met in an input or a residual */
+  MFG_ERR_HIP = 6,           /* a HIP runtime call failed */
+  MFG_ERR_OOM = 7            /* device allocation failed */
+} mfg_status_t;
+
+typedef enum { MFG_BC_PERIODIC = 0, MFG_BC_NEUMANN = 1 } mfg_bc_t;
+
+/* Arithmetic of the preconditioner inside PCG. The outer PCG recurrences,
+ * the reduced-matrix products, the right-hand side and the prox are float64
+ * in every mode. MIXED modes run the spatial solves (Algorithm 2) in float32,
+ * the time transform (Algorithm 1) on the matrix cores with float16/bfloat16
+ * (or float32) inputs and float32 accumulation, and switch PCG to its
+ * flexible form. */
+typedef enum {
+  MFG_FP64 = 0,
+  MFG_MIXED_FP32 = 1,  /* time transform fp32 inputs, spatial solves fp32 */
+  MFG_MIXED_FP16 = 2,  /* time transform fp16 inputs / fp32 accumulate */
+  MFG_MIXED_BF16 = 3   /* time transform bf16 inputs / fp32 accumulate */
+} mfg_precision_t;
+
+/* Problem statement (Sections 1-2, Section 5 setup). */
+typedef struct {
+  int d;             /* space dimension, 1 or 2 */
+  int n[2];          /* N_x, N_y: nodes per axis (interior nodes if Neumann);
+                        n[1] is ignored when d = 1. Each must be >= 4 and of
+                        the form 2^a 3^b (spatial transform sizes). */
+  int nt;            /* N_t >= 2 time steps; any value */
+  double T;          /* horizon T > 0; dt = T / N_t */
+  double lo[2], hi[2]; /* domain [a,b] x [c,d]: periodic dx = (b-a)/N_x,
+                          Neumann dx = (b-a)/(N_x+1) (Section 2) */
+  int bc;            /* mfg_bc_t, applied on every axis */
+  double nu;         /* viscosity nu >= 0 */
+  double qprime;     /* Hamiltonian |p|^q'/q' (eq. power_hamiltonian); only 2 */
+  double gamma;      /* strong-convexity constant of the accelerated CP
+                        step sizes (Section 5); > 0 */
+  int l;             /* time preconditioner of eq. prec: 1 = DCT-VIII (exact
+                        at nu = 0), 2 = DST-I */
+  int precision;     /* mfg_precision_t */
+} mfg_problem_t;
+
+typedef struct mfg_plan_s* mfg_plan_t;
+
+/* Build a plan: validate the problem, compute the grid constants and the
+ * eigenvalue / transform tables (eqs. eigs, lambda1, lambda2) and allocate the
+ * plan's workspace (about 7 n-vectors). V (the potential of the coupling
+ * f(x, m) = m + V(x), M values) and m0 (initial density, M values, >= 0 and
+ * finite) are device pointers; the plan copies them. stream may be 0 (the
+ * null stream). The coupling is f = m + V and the terminal cost g = 0. */
+int mfg_plan(const mfg_problem_t* pb, const double* V, const double* m0,
+             hipStream_t stream, mfg_plan_t* out);
+
+/* Release a plan and its workspace (synchronises its stream). */
+int mfg_destroy(mfg_plan_t plan);
+
+/* Replace the stream that later calls run on. */
+int mfg_set_stream(mfg_plan_t plan, hipStream_t stream);
+
+/* Replace the potential V and/or the initial density m0 (device pointers, M
+ * values; NULL keeps the current one). */
+int mfg_set_data(mfg_plan_t plan, const double* V, const double* m0);
+
+/* Proximal step of Section 3: y = prox_{tau phi}(v) for phi = B-hat + F, cell by
+ * cell, with F(m) = m^2/2 + V m (primitive of f = m + V) and b-hat(m, w) =
+ * |w|^2/(2m) on the cone. v, y: primal vectors; y may alias v. tau > 0. */
+int mfg_prox(mfg_plan_t plan, const double* v, double tau, double* y);
+
+/* q = A u with A = Cr Cr^T the reduced matrix of eq. largeA (u, q: n-vectors;
+ * must not alias). */
+int mfg_apply_AAt(mfg_plan_t plan, const double* u, double* q);
+
+/* b = Cr y: the reduced constraint matrix of eq. ABC (first block row
+ * eliminated) applied to a primal vector y; b is an n-vector. The constant
+ * part m0/dt of the constraint is not included. */
+int mfg_apply_C(mfg_plan_t plan, const double* y, double* b);
+
+/* y = Cr^T u (u: n-vector, y: primal vector). */
+int mfg_apply_CT(mfg_plan_t plan, const double* u, double* y);
+
+/* z = P^{-1} r with P the preconditioner of eq. prec applied through
+ * eq. pstrec (Algorithm 1 along time, Algorithm 2 per time step). Exact (to
+ * rounding) in MFG_FP64, approximate in the MIXED modes. r, z: n-vectors, must
+ * not alias. */
+int mfg_precond(mfg_plan_t plan, const double* r, double* z);
+
+/* Preconditioned CG on A u = b from u = 0 (Sections 3-4): stops when the
+ * recursively updated residual satisfies ||r||_2 <= rtol ||b||_2 or after
+ * maxit iterations. MIXED modes use the flexible (Polak-Ribiere) update.
+ * b, u: n-vectors (must not alias). iters (host, may be NULL): iterations
+ * done. relres (host, may be NULL): if non-NULL, the TRUE float64 relative
+ * residual ||b - A u|| / ||b|| is computed (one extra product) and stored.
+ * Returns MFG_ERR_NOT_CONVERGED if maxit was reached. */
+int mfg_pcg(mfg_plan_t plan, const double* b, double* u, double rtol, int maxit,
+            int* iters, double* relres);
+
+/* Chambolle-Pock state (Section 3, Section 5 schedule). The three vectors are
+ * caller-owned device primal vectors ((1+2d) n values each): the dual variable
+ * xi, the primal y = (m, w) and its extrapolation ybar. sigma, tau, theta are
+ * the current step sizes; iter counts completed iterations. Copying the
+ * vectors and the scalars is a complete checkpoint. */
+typedef struct {
+  double* xi;
+  double* y;
+  double* ybar;
+  double sigma, tau, theta;
+  long iter;
+} mfg_state_t;
+
+/* Per-iteration statistics of mfg_cp_solve; every pointer is a HOST array of
+ * at least n_iter entries, or NULL to skip it. */
+typedef struct {
+  int* pcg_iters;     /* PCG iterations of each projection */
+  double* pcg_relres; /* final recursive relative residual of each PCG */
+  double* dm;         /* ||m_{l+1} - m_l||_2 */
+} mfg_stats_t;
+
+/* Initial point: xi = 0, y = ybar = (m0 at every time slice, w = 0),
+ * sigma = tau = theta = 1, iter = 0. */
+int mfg_cp_init(mfg_plan_t plan, mfg_state_t* st);
+
+/* Run n_iter accelerated Chambolle-Pock iterations (eq. pasosChamPock):
+ *   xi <- Cr^T A^{-1} (Cr (xi + sigma ybar) - sigma dr)        (eq. CC*)
+ *   y' <- prox_{tau phi}(y - tau xi);  theta = (1 + 2 gamma tau)^{-1/2}
+ *   ybar <- y' + theta (y' - y);  tau <- theta tau;  sigma <- sigma / theta
+ * with each A-solve done by PCG to pcg_rtol (at most pcg_maxit iterations,
+ * zero initial guess). The state is updated in place. stats may be NULL.
+ * Returns MFG_ERR_NOT_CONVERGED (after finishing all iterations) if some PCG
+ * solve hit pcg_maxit. */
+int mfg_cp_solve(mfg_plan_t plan, mfg_state_t* st, int n_iter, double pcg_rtol,
+                 int pcg_maxit, mfg_stats_t* stats);
+
+/* Human-readable description of the last error on this thread. */
+const char* mfg_last_error(void);
+
+/* Library version string. */
+const char* mfg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFG_H */

@@ -1,0 +1,482 @@
+// C ABI entry points (include/mfg.h): plan construction, operators, PCG and
+// the Chambolle-Pock driver.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "plan.h"
+
+namespace mfg {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return fail(MFG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e));     \
+  } while (0)
+
+static bool size_ok(int N) {
+  if (N < 4 || N > kMaxAxisN) return false;
+  int n = N;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+static void radices(int N, int* r, int* np) {
+  int n = N, k = 0;
+  while (n % 4 == 0) { r[k++] = 4; n /= 4; }
+  while (n % 2 == 0) { r[k++] = 2; n /= 2; }
+  while (n % 3 == 0) { r[k++] = 3; n /= 3; }
+  *np = k;
+}
+
+template <typename T>
+static int dalloc(Plan& P, T** ptr, size_t count) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, count * sizeof(T) + 256);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MFG_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  }
+  P.dev_allocs.push_back(p);
+  *ptr = static_cast<T*>(p);
+  return MFG_OK;
+}
+
+template <typename T>
+static int upload(Plan& P, T** dst, const std::vector<T>& h) {
+  int rc = dalloc(P, dst, h.size());
+  if (rc) return rc;
+  HIP_TRY(hipMemcpy(*dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return MFG_OK;
+}
+
+static unsigned short to_bf16(float f) {
+  unsigned int u;
+  std::memcpy(&u, &f, 4);
+  const unsigned int lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;  // round to nearest even
+  return (unsigned short)(u >> 16);
+}
+
+// One spatial axis: FFT plan, twiddles, DCT post-twiddles and the eigenvalues
+// of the one-axis negative Laplacian divided by h^2 (Algorithm 2).
+static int build_axis(Plan& P, Axis& ax, int N, bool neumann, double h) {
+  ax.N = N;
+  radices(N, ax.radix, &ax.npass);
+  ax.kind = neumann ? 1 : 0;
+  std::vector<double> tw(2 * N), ct(2 * N), lam(N);
+  std::vector<float> twf(2 * N), ctf(2 * N);
+  const double pi = 3.14159265358979323846264338327950288;
+  for (int m = 0; m < N; ++m) {
+    tw[2 * m] = std::cos(2.0 * pi * m / N);
+    tw[2 * m + 1] = std::sin(2.0 * pi * m / N);
+    ct[2 * m] = std::cos(pi * m / (2.0 * N));
+    ct[2 * m + 1] = std::sin(pi * m / (2.0 * N));
+    const double ev = neumann ? 2.0 - 2.0 * std::cos(pi * m / N) : 2.0 - 2.0 * std::cos(2.0 * pi * m / N);
+    lam[m] = ev / (h * h);
+  }
+  for (int i = 0; i < 2 * N; ++i) {
+    twf[i] = (float)tw[i];
+    ctf[i] = (float)ct[i];
+  }
+  double *dtw, *dct, *dlam;
+  float *dtwf, *dctf;
+  int rc;
+  if ((rc = upload(P, &dtw, tw)) || (rc = upload(P, &dct, ct)) || (rc = upload(P, &dlam, lam)) ||
+      (rc = upload(P, &dtwf, twf)) || (rc = upload(P, &dctf, ctf)))
+    return rc;
+  ax.tw = dtw;
+  ax.ct = dct;
+  ax.lam = dlam;
+  ax.twf = dtwf;
+  ax.ctf = dctf;
+  return MFG_OK;
+}
+
+static int check_fields(const Plan& P, const double* V, const double* m0, bool need_both) {
+  const int M = P.g.M;
+  std::vector<double> h(M);
+  if (V) {
+    HIP_TRY(hipMemcpy(h.data(), V, M * sizeof(double), hipMemcpyDeviceToHost));
+    for (int i = 0; i < M; ++i)
+      if (!std::isfinite(h[i])) return fail(MFG_ERR_NONFINITE, "V has a non-finite entry");
+  } else if (need_both) {
+    return fail(MFG_ERR_INVALID_ARG, "V is NULL");
+  }
+  if (m0) {
+    HIP_TRY(hipMemcpy(h.data(), m0, M * sizeof(double), hipMemcpyDeviceToHost));
+    for (int i = 0; i < M; ++i) {
+      if (!std::isfinite(h[i])) return fail(MFG_ERR_NONFINITE, "m0 has a non-finite entry");
+      if (h[i] < 0.0) return fail(MFG_ERR_INVALID_ARG, "m0 has a negative entry");
+    }
+  } else if (need_both) {
+    return fail(MFG_ERR_INVALID_ARG, "m0 is NULL");
+  }
+  return MFG_OK;
+}
+
+static void release(Plan& P) {
+  if (P.stream) (void)hipStreamSynchronize(P.stream);
+  else (void)hipDeviceSynchronize();
+  for (void* p : P.dev_allocs) (void)hipFree(p);
+  for (void* p : P.host_allocs) (void)hipHostFree(p);
+  P.dev_allocs.clear();
+  P.host_allocs.clear();
+}
+
+static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const double* m0,
+                      hipStream_t stream) {
+  if (!pb) return fail(MFG_ERR_INVALID_ARG, "problem is NULL");
+  if (pb->d != 1 && pb->d != 2) return fail(MFG_ERR_INVALID_ARG, "d must be 1 or 2");
+  for (int a = 0; a < pb->d; ++a) {
+    if (pb->n[a] < 4) return fail(MFG_ERR_INVALID_ARG, "each axis needs at least 4 nodes");
+    if (!size_ok(pb->n[a]))
+      return fail(MFG_ERR_UNSUPPORTED, "axis sizes must be 2^a 3^b and at most 1024");
+    if (!(pb->hi[a] > pb->lo[a]) || !std::isfinite(pb->hi[a] - pb->lo[a]))
+      return fail(MFG_ERR_INVALID_ARG, "domain needs hi > lo");
+  }
+  if (pb->nt < 2 || pb->nt > kMaxNt) return fail(MFG_ERR_INVALID_ARG, "nt must be in [2, 4096]");
+  if (!(pb->T > 0.0) || !std::isfinite(pb->T)) return fail(MFG_ERR_INVALID_ARG, "T must be > 0");
+  if (pb->bc != MFG_BC_PERIODIC && pb->bc != MFG_BC_NEUMANN)
+    return fail(MFG_ERR_INVALID_ARG, "bc must be periodic or neumann");
+  if (!(pb->nu >= 0.0) || !std::isfinite(pb->nu)) return fail(MFG_ERR_INVALID_ARG, "nu must be >= 0");
+  if (pb->qprime != 2.0) return fail(MFG_ERR_UNSUPPORTED, "only q' = 2 is implemented");
+  if (!(pb->gamma > 0.0) || !std::isfinite(pb->gamma))
+    return fail(MFG_ERR_INVALID_ARG, "gamma must be > 0");
+  if (pb->l != 1 && pb->l != 2) return fail(MFG_ERR_INVALID_ARG, "l must be 1 or 2");
+  if (pb->precision < MFG_FP64 || pb->precision > MFG_MIXED_BF16)
+    return fail(MFG_ERR_INVALID_ARG, "unknown precision");
+
+  P.pb = *pb;
+  P.stream = stream;
+  HIP_TRY(hipGetDevice(&P.device));
+  P.precision = pb->precision;
+  P.l = pb->l;
+  P.gamma = pb->gamma;
+  Geom& g = P.g;
+  const bool neu = pb->bc == MFG_BC_NEUMANN;
+  auto spacing = [&](int a) {
+    const double L = pb->hi[a] - pb->lo[a];
+    return neu ? L / (pb->n[a] + 1) : L / pb->n[a];
+  };
+  g.neumann = neu ? 1 : 0;
+  g.nt = pb->nt;
+  g.nu = pb->nu;
+  g.dt = pb->T / pb->nt;
+  g.idt = 1.0 / g.dt;
+  g.idt2 = g.idt * g.idt;
+  if (pb->d == 2) {
+    g.n0 = pb->n[0];
+    g.n1 = pb->n[1];
+    g.has0 = 1;
+    const double h0 = spacing(0), h1 = spacing(1);
+    g.ih0 = 1.0 / h0;
+    g.ih1 = 1.0 / h1;
+    g.ih0sq = g.ih0 * g.ih0;
+    g.ih1sq = g.ih1 * g.ih1;
+    g.ncomp = 4;
+    g.cb1 = 2;
+  } else {
+    g.n0 = 1;
+    g.n1 = pb->n[0];
+    g.has0 = 0;
+    const double h1 = spacing(0);
+    g.ih0 = 0.0;
+    g.ih0sq = 0.0;
+    g.ih1 = 1.0 / h1;
+    g.ih1sq = g.ih1 * g.ih1;
+    g.ncomp = 2;
+    g.cb1 = 0;
+  }
+  g.M = g.n0 * g.n1;
+  g.n = (long long)g.nt * g.M;
+
+  int rc = check_fields(P, V, m0, true);
+  if (rc) return rc;
+
+  // problem data
+  if ((rc = dalloc(P, &P.V, g.M)) || (rc = dalloc(P, &P.m0, g.M))) return rc;
+  HIP_TRY(hipMemcpy(P.V, V, g.M * sizeof(double), hipMemcpyDeviceToDevice));
+  HIP_TRY(hipMemcpy(P.m0, m0, g.M * sizeof(double), hipMemcpyDeviceToDevice));
+
+  // time transform (eq. eigs and the DCT-VIII / DST-I of Section 4.1)
+  const int nt = g.nt;
+  const double pi = 3.14159265358979323846264338327950288;
+  std::vector<double> Vm((size_t)nt * nt), Vt((size_t)nt * nt), lt(nt);
+  for (int k = 1; k <= nt; ++k) {
+    lt[k - 1] = 2.0 - 2.0 * std::cos(pi * (k - 1 + 0.5 * P.l) / (nt + 0.5 * P.l));
+    for (int j = 1; j <= nt; ++j) {
+      double v;
+      if (P.l == 1)
+        v = std::sqrt(4.0 / (2 * nt + 1)) *
+            std::cos(pi * (double)((2 * k - 1) * (2 * j - 1)) / (2.0 * (2 * nt + 1)));
+      else
+        v = std::sqrt(2.0 / (nt + 1)) * std::sin(pi * (double)(k * j) / (nt + 1.0));
+      Vm[(size_t)(k - 1) * nt + (j - 1)] = v;
+    }
+  }
+  for (int t = 0; t < nt; ++t)
+    for (int k = 0; k < nt; ++k) Vt[(size_t)t * nt + k] = Vm[(size_t)k * nt + t];
+  std::vector<float> Vt32(Vt.size());
+  std::vector<_Float16> Vt16(Vt.size());
+  std::vector<unsigned short> Vtbf(Vt.size());
+  for (size_t i = 0; i < Vt.size(); ++i) {
+    Vt32[i] = (float)Vt[i];
+    Vt16[i] = (_Float16)Vt[i];
+    Vtbf[i] = to_bf16((float)Vt[i]);
+  }
+  if ((rc = upload(P, &P.Vt64, Vt)) || (rc = upload(P, &P.Vt32, Vt32)) ||
+      (rc = upload(P, &P.Vt16, Vt16)) || (rc = upload(P, &P.Vtbf, Vtbf)) ||
+      (rc = upload(P, &P.lam_t, lt)))
+    return rc;
+
+  // spatial axes
+  if (g.has0) {
+    if ((rc = build_axis(P, P.ax0, g.n0, neu, spacing(0)))) return rc;
+    if ((rc = build_axis(P, P.ax1, g.n1, neu, spacing(1)))) return rc;
+  } else {
+    if ((rc = build_axis(P, P.ax1, g.n1, neu, spacing(0)))) return rc;
+  }
+
+  // workspace
+  const size_t n = (size_t)g.n;
+  if ((rc = dalloc(P, &P.r, n)) || (rc = dalloc(P, &P.z, n)) || (rc = dalloc(P, &P.p, n)) ||
+      (rc = dalloc(P, &P.q, n)) || (rc = dalloc(P, &P.tmp, n)) || (rc = dalloc(P, &P.b, n)) ||
+      (rc = dalloc(P, &P.u, n)))
+    return rc;
+  P.red.max_blocks = 32768;
+  {
+    // the time-transform GEMM reduces one partial per block
+    const long long colblk = (g.M + 63) / 64;
+    const long long kchunks = (((g.nt + 15) / 16) + 7) / 8;
+    if (colblk * kchunks > P.red.max_blocks)
+      return fail(MFG_ERR_UNSUPPORTED, "grid too large for the time-transform reduction");
+  }
+  if ((rc = dalloc(P, &P.red.partials, (size_t)T_COUNT * kSlotsPerSite * P.red.max_blocks)) ||
+      (rc = dalloc(P, &P.red.tickets, T_COUNT)) || (rc = dalloc(P, &P.red.scal, S_COUNT)))
+    return rc;
+  HIP_TRY(hipMemset(P.red.tickets, 0, T_COUNT * sizeof(unsigned)));
+  HIP_TRY(hipMemset(P.red.scal, 0, S_COUNT * sizeof(double)));
+  void* hs = nullptr;
+  HIP_TRY(hipHostMalloc(&hs, S_COUNT * sizeof(double), hipHostMallocDefault));
+  P.host_allocs.push_back(hs);
+  P.host_scal = static_cast<double*>(hs);
+  HIP_TRY(hipDeviceSynchronize());
+  return MFG_OK;
+}
+
+static int read_scalars(Plan& P) {
+  HIP_TRY(hipMemcpyAsync(P.host_scal, P.red.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                         P.stream));
+  HIP_TRY(hipStreamSynchronize(P.stream));
+  return MFG_OK;
+}
+
+// Preconditioned CG (flexible in the mixed modes) from x = 0.
+static int run_pcg(Plan& P, const double* b, double* x, double rtol, int maxit, int* iters_out,
+                   double* relres_rec, double* relres_true) {
+  hipStream_t s = P.stream;
+  const bool flex = P.precision != MFG_FP64;
+  launch_pcg_init(P, b, x, P.r, rtol, s);
+  HIP_TRY(hipGetLastError());
+  int rc = read_scalars(P);
+  if (rc) return rc;
+  if (P.host_scal[S_BAD] != 0.0) return fail(MFG_ERR_NONFINITE, "right-hand side is not finite");
+  const double bb = P.host_scal[S_BB];
+  int k = 0;
+  bool conv = (bb == 0.0);
+  if (!conv) {
+    launch_precond(P, P.r, P.z, true, nullptr, s);
+    for (k = 1; k <= maxit; ++k) {
+      launch_pdir_AAt(P, P.z, P.p, P.q, k == 1, s);
+      launch_update(P, x, P.r, P.p, P.q, s);
+      HIP_TRY(hipGetLastError());
+      if ((rc = read_scalars(P))) return rc;
+      const double bad = P.host_scal[S_BAD];
+      if (bad == 2.0) return fail(MFG_ERR_NONFINITE, "non-finite value in PCG");
+      if (bad == 1.0) return fail(MFG_ERR_BREAKDOWN, "PCG breakdown (p.Ap or r.z not positive)");
+      if (P.host_scal[S_DONE] != 0.0) {
+        conv = true;
+        break;
+      }
+      if (k == maxit) break;
+      launch_precond(P, P.r, P.z, true, P.q, s);
+    }
+    (void)flex;
+  }
+  if (k > maxit) k = maxit;
+  if (iters_out) *iters_out = k;
+  if (relres_rec) *relres_rec = (bb > 0.0) ? std::sqrt(P.host_scal[S_RR] / bb) : 0.0;
+  if (relres_true) {
+    launch_AAt(P, x, P.p, false, s);
+    launch_residual(P, b, P.p, s);
+    if ((rc = read_scalars(P))) return rc;
+    const double b2 = P.host_scal[S_AUX1];
+    *relres_true = (b2 > 0.0) ? std::sqrt(P.host_scal[S_AUX0] / b2) : 0.0;
+  }
+  if (!conv) return fail(MFG_ERR_NOT_CONVERGED, "PCG reached maxit without converging");
+  return MFG_OK;
+}
+
+}  // namespace mfg
+
+using mfg::fail;
+
+extern "C" {
+
+int mfg_plan(const mfg_problem_t* pb, const double* V, const double* m0, hipStream_t stream,
+             mfg_plan_t* out) {
+  if (!out) return fail(MFG_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  mfg_plan_s* h = new (std::nothrow) mfg_plan_s();
+  if (!h) return fail(MFG_ERR_OOM, "host allocation failed");
+  int rc = mfg::build_plan(h->P, pb, V, m0, stream);
+  if (rc) {
+    std::string msg = mfg::g_last_error;
+    mfg::release(h->P);
+    delete h;
+    mfg::g_last_error = msg;
+    return rc;
+  }
+  *out = h;
+  return MFG_OK;
+}
+
+int mfg_destroy(mfg_plan_t plan) {
+  if (!plan) return MFG_OK;
+  mfg::release(plan->P);
+  delete plan;
+  return MFG_OK;
+}
+
+int mfg_set_stream(mfg_plan_t plan, hipStream_t stream) {
+  if (!plan) return fail(MFG_ERR_INVALID_ARG, "plan is NULL");
+  plan->P.stream = stream;
+  return MFG_OK;
+}
+
+int mfg_set_data(mfg_plan_t plan, const double* V, const double* m0) {
+  if (!plan) return fail(MFG_ERR_INVALID_ARG, "plan is NULL");
+  mfg::Plan& P = plan->P;
+  HIP_TRY(hipStreamSynchronize(P.stream));
+  int rc = mfg::check_fields(P, V, m0, false);
+  if (rc) return rc;
+  if (V) HIP_TRY(hipMemcpyAsync(P.V, V, P.g.M * sizeof(double), hipMemcpyDeviceToDevice, P.stream));
+  if (m0)
+    HIP_TRY(hipMemcpyAsync(P.m0, m0, P.g.M * sizeof(double), hipMemcpyDeviceToDevice, P.stream));
+  return MFG_OK;
+}
+
+int mfg_prox(mfg_plan_t plan, const double* v, double tau, double* y) {
+  if (!plan || !v || !y) return fail(MFG_ERR_INVALID_ARG, "NULL argument");
+  if (!(tau > 0.0) || !std::isfinite(tau)) return fail(MFG_ERR_INVALID_ARG, "tau must be > 0");
+  mfg::launch_prox(plan->P, v, tau, y, plan->P.stream);
+  HIP_TRY(hipGetLastError());
+  return MFG_OK;
+}
+
+int mfg_apply_AAt(mfg_plan_t plan, const double* u, double* q) {
+  if (!plan || !u || !q) return fail(MFG_ERR_INVALID_ARG, "NULL argument");
+  if (u == q) return fail(MFG_ERR_INVALID_ARG, "u and q must not alias");
+  mfg::launch_AAt(plan->P, u, q, false, plan->P.stream);
+  HIP_TRY(hipGetLastError());
+  return MFG_OK;
+}
+
+int mfg_apply_C(mfg_plan_t plan, const double* y, double* b) {
+  if (!plan || !y || !b) return fail(MFG_ERR_INVALID_ARG, "NULL argument");
+  mfg::launch_apply_C(plan->P, y, b, plan->P.stream);
+  HIP_TRY(hipGetLastError());
+  return MFG_OK;
+}
+
+int mfg_apply_CT(mfg_plan_t plan, const double* u, double* y) {
+  if (!plan || !u || !y) return fail(MFG_ERR_INVALID_ARG, "NULL argument");
+  mfg::launch_apply_CT(plan->P, u, y, plan->P.stream);
+  HIP_TRY(hipGetLastError());
+  return MFG_OK;
+}
+
+int mfg_precond(mfg_plan_t plan, const double* r, double* z) {
+  if (!plan || !r || !z) return fail(MFG_ERR_INVALID_ARG, "NULL argument");
+  if (r == z) return fail(MFG_ERR_INVALID_ARG, "r and z must not alias");
+  mfg::launch_precond(plan->P, r, z, false, nullptr, plan->P.stream);
+  HIP_TRY(hipGetLastError());
+  return MFG_OK;
+}
+
+int mfg_pcg(mfg_plan_t plan, const double* b, double* u, double rtol, int maxit, int* iters,
+            double* relres) {
+  if (!plan || !b || !u) return fail(MFG_ERR_INVALID_ARG, "NULL argument");
+  if (b == u) return fail(MFG_ERR_INVALID_ARG, "b and u must not alias");
+  if (!(rtol >= 0.0) || maxit < 1) return fail(MFG_ERR_INVALID_ARG, "need rtol >= 0, maxit >= 1");
+  return mfg::run_pcg(plan->P, b, u, rtol, maxit, iters, nullptr, relres);
+}
+
+int mfg_cp_init(mfg_plan_t plan, mfg_state_t* st) {
+  if (!plan || !st || !st->xi || !st->y || !st->ybar)
+    return fail(MFG_ERR_INVALID_ARG, "NULL argument");
+  mfg::launch_cp_init(plan->P, st->xi, st->y, st->ybar, plan->P.stream);
+  HIP_TRY(hipGetLastError());
+  st->sigma = 1.0;
+  st->tau = 1.0;
+  st->theta = 1.0;
+  st->iter = 0;
+  return MFG_OK;
+}
+
+int mfg_cp_solve(mfg_plan_t plan, mfg_state_t* st, int n_iter, double pcg_rtol, int pcg_maxit,
+                 mfg_stats_t* stats) {
+  if (!plan || !st || !st->xi || !st->y || !st->ybar)
+    return fail(MFG_ERR_INVALID_ARG, "NULL argument");
+  if (n_iter < 0 || pcg_maxit < 1 || !(pcg_rtol >= 0.0))
+    return fail(MFG_ERR_INVALID_ARG, "bad iteration arguments");
+  if (!(st->sigma > 0.0) || !(st->tau > 0.0)) return fail(MFG_ERR_INVALID_ARG, "bad step sizes");
+  mfg::Plan& P = plan->P;
+  hipStream_t s = P.stream;
+  int final_rc = MFG_OK;
+  for (int it = 0; it < n_iter; ++it) {
+    mfg::launch_rhs(P, st->xi, st->ybar, st->sigma, P.m0, P.b, s);
+    int its = 0;
+    double rel = 0.0;
+    int rc = mfg::run_pcg(P, P.b, P.u, pcg_rtol, pcg_maxit, &its, &rel, nullptr);
+    if (rc == MFG_ERR_NOT_CONVERGED) final_rc = rc;
+    else if (rc) return rc;
+    const double theta = 1.0 / std::sqrt(1.0 + 2.0 * P.gamma * st->tau);
+    mfg::launch_backproj_prox(P, P.u, st->xi, st->y, st->ybar, st->tau, theta, s);
+    HIP_TRY(hipGetLastError());
+    if (stats) {
+      if (stats->pcg_iters) stats->pcg_iters[it] = its;
+      if (stats->pcg_relres) stats->pcg_relres[it] = rel;
+      if (stats->dm) {
+        int r2 = mfg::read_scalars(P);
+        if (r2) return r2;
+        stats->dm[it] = std::sqrt(P.host_scal[mfg::S_DM]);
+      }
+    }
+    st->tau *= theta;
+    st->sigma /= theta;
+    st->theta = theta;
+    st->iter += 1;
+  }
+  if (final_rc) return fail(final_rc, "some PCG solve reached maxit");
+  return MFG_OK;
+}
+
+const char* mfg_last_error(void) { return mfg::g_last_error.c_str(); }
+
+const char* mfg_version(void) { return "mfg 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Device helpers: neighbour index maps, wave64 / block reductions and the
+// deterministic last-block reduction.
+#pragma once
+
+#include "mfg_internal.h"
+
+namespace mfg {
+
+
+
+// Neighbour index along an axis of n nodes. Periodic: indices mod n (Section 2).
+// Neumann: half-sample reflection (-1 -> 0, n -> n-1), which reproduces the
+// Section 4.3 Laplacian whose corner entries are 1, and makes the transposed
+// one-sided differences vanish at the boundary.
+__device__ __forceinline__ int nbr(int p, int n, int neumann) {
+  if (neumann) {
+    if (p < 0) p = -1 - p;
+    else if (p >= n) p = 2 * n - 1 - p;
+    p = p < 0 ? 0 : (p >= n ? n - 1 : p);
+    return p;
+  }
+  p %= n;
+  return p < 0 ? p + n : p;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum NV values over the block; the result is valid in thread 0 only.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[k * 16 + wid] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += sh[k * 16 + w];
+      v[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// Publish this block's partial sums; the last block to arrive sums all partials
+// in block order and returns true (totals valid in thread 0). The ticket is
+// reset by the last block so the site is reusable by the next launch.
+template <int NV>
+__device__ bool reduce_commit(double (&v)[NV], const RedBuf& rb, int site, int nblocks,
+                              double (&tot)[NV]) {
+  static_assert(NV <= kSlotsPerSite, "too many reduction slots");
+  __shared__ double sh[NV * 16];
+  __shared__ int last;
+  block_sum<NV>(v, sh);
+  double* part = rb.partials + (size_t)site * kSlotsPerSite * rb.max_blocks;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) part[(size_t)k * rb.max_blocks + blockIdx.x] = v[k];
+    __threadfence();
+    unsigned t = atomicAdd(&rb.tickets[site], 1u);
+    last = (t == (unsigned)(nblocks - 1));
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+      s += __builtin_nontemporal_load(&part[(size_t)k * rb.max_blocks + b]);
+    v[k] = s;
+  }
+  block_sum<NV>(v, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) tot[k] = v[k];
+    atomicExch(&rb.tickets[site], 0u);
+  }
+  return true;
+}
+
+__device__ __forceinline__ bool finite_d(double x) { return __builtin_isfinite(x); }
+
+// XCD-aware block order: blocks b and b+8 run on the same XCD, so map them to
+// neighbouring logical tiles (shared cache lines and halos stay in one L2).
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int full = nb & ~7;
+  if (b >= full) return b;
+  const int per = full >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+}  // namespace mfg

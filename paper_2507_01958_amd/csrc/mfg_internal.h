@@ -1,0 +1,105 @@
+// Internal declarations shared by the HIP translation units of libmfg.
+//
+// Internal axes: a space-time n-vector is [t][i0][i1] with i1 contiguous.
+// For d = 2, axis 0 is x (N_x nodes, stride N_y) and axis 1 is y (N_y nodes,
+// stride 1); flux components 0,1 act along x and 2,3 along y. For d = 1 the
+// single axis x is stored as axis 1 (n0 = 1) and its components are 0,1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/mfg.h"
+
+namespace mfg {
+
+constexpr int kMaxPass = 16;
+constexpr int kMaxAxisN = 1024;
+constexpr int kMaxNt = 4096;
+constexpr int kSlotsPerSite = 4;  // reduction values per site
+
+// Geometry and constants of one problem, passed by value to kernels.
+struct Geom {
+  int n0, n1;      // internal axis sizes (n0 = 1 when d = 1)
+  int nt, M;       // time steps, nodes per slice
+  long long n;     // nt * M
+  int has0;        // axis 0 present (d = 2)
+  int neumann;     // 1: Neumann, 0: periodic (all axes)
+  int ncomp;       // 2d flux components
+  int cb1;         // first flux component acting along axis 1 (2 if d=2, 0 if d=1)
+  double ih0, ih1;     // 1/h per axis (0 when absent)
+  double ih0sq, ih1sq; // 1/h^2 per axis (0 when absent)
+  double nu, dt, idt, idt2;
+};
+
+// Deterministic two-level reduction: per-block partials, then the last block
+// to finish (device-scope ticket) sums them in a fixed order.
+struct RedBuf {
+  double* partials;   // [slot][block]
+  unsigned* tickets;  // one counter per reduction site, left at zero
+  double* scal;       // device scalar block
+  int max_blocks;
+};
+
+// Device scalar slots.
+enum ScalarSlot {
+  S_RHO = 0,    // r.z of the current iterate
+  S_PQ = 1,     // p.q
+  S_ALPHA = 2,
+  S_BETA = 3,
+  S_RR = 4,     // r.r
+  S_BB = 5,     // b.b
+  S_ZQ = 6,     // z.q (flexible beta)
+  S_DONE = 7,   // 1 when converged
+  S_TOL2 = 8,   // (rtol ||b||)^2 threshold factor rtol^2 (set by host)
+  S_BAD = 9,    // 1: breakdown, 2: non-finite
+  S_DM = 10,    // ||m' - m||^2 of the last CP step
+  S_AUX0 = 11,
+  S_AUX1 = 12,
+  S_COUNT = 16
+};
+
+enum TicketSite { T_BB = 0, T_PQ = 1, T_RR = 2, T_RZ = 3, T_DM = 4, T_AUX = 5, T_COUNT = 8 };
+
+// One spatial transform axis (Algorithm 2): real-to-real transform built on a
+// complex Stockham FFT of length N with two real lines packed per complex one.
+struct Axis {
+  int N;
+  int npass;
+  int radix[kMaxPass];
+  int kind;            // 0: discrete Hartley (periodic), 1: DCT-II (Neumann)
+  const double* tw;    // cos/sin(2 pi m / N), interleaved, m < N
+  const float* twf;
+  const double* ct;    // cos/sin(pi k / (2N)), interleaved, k < N
+  const float* ctf;
+  const double* lam;   // eigenvalue of the negative Laplacian / h^2 at frequency k
+};
+
+struct Plan;
+
+// ---- launchers (each defined in its .hip file) ----
+// stencil.hip
+void launch_rhs(const Plan& P, const double* xi, const double* ybar, double sigma,
+                const double* m0, double* b, hipStream_t s);
+void launch_apply_C(const Plan& P, const double* y, double* b, hipStream_t s);
+void launch_apply_CT(const Plan& P, const double* u, double* y, hipStream_t s);
+void launch_AAt(const Plan& P, const double* u, double* q, bool reduce_pq, hipStream_t s);
+void launch_pdir_AAt(const Plan& P, const double* z, double* p, double* q, bool first,
+                     hipStream_t s);
+void launch_prox(const Plan& P, const double* v, double tau, double* y, hipStream_t s);
+void launch_backproj_prox(const Plan& P, const double* u, double* xi, double* y, double* ybar,
+                          double tau, double theta, hipStream_t s);
+// vec.hip
+void launch_pcg_init(const Plan& P, const double* b, double* x, double* r, double rtol,
+                     hipStream_t s);
+void launch_update(const Plan& P, double* x, double* r, const double* p, const double* q,
+                   hipStream_t s);
+void launch_residual(const Plan& P, const double* b, const double* Ax, hipStream_t s);
+void launch_fill(double* x, long long n, double v, hipStream_t s);
+void launch_cp_init(const Plan& P, double* xi, double* y, double* ybar, hipStream_t s);
+// precond.hip
+void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
+                    const double* q, hipStream_t s);
+
+}  // namespace mfg

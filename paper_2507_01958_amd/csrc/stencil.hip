@@ -1,0 +1,333 @@
+// Space-time stencils of the discrete constraint (Section 2, Section 3):
+//   Cr y     (eq. ABC, first block row eliminated),
+//   Cr^T u,
+//   A u = Cr Cr^T u (eq. largeA),
+// plus the per-cell proximal step (Section 3) and the fused
+// back-projection + prox + extrapolation of one Chambolle-Pock iteration.
+//
+// One-axis operators, with h the spacing of the axis:
+//   K:   (2u_i - u_{i+1} - u_{i-1}) / h^2     (periodic mod N; Neumann by the
+//        half-sample reflection, i.e. the Section 4.3 matrix with corners 1)
+//   D^1 w (even flux component):  w_i - w_{i-1}     (Neumann: w_{N-1} and w_{-1}
+//        do not enter, the printed D^1 has a zero last column)
+//   D^2 w (odd flux component):   w_{i+1} - w_i     (Neumann: w_0 and w_N do not
+//        enter, zero first column)
+//   (D^1)^T u = u_i - u_{i+1},  (D^2)^T u = u_{i-1} - u_i (both vanish across a
+//        Neumann boundary under the reflection).
+// B = [D^1_x, D^2_x, D^1_y, D^2_y] / h and L = nu K + I/dt (Section 3).
+#include "device_util.h"
+#include "plan.h"
+
+namespace mfg {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ size_t at(const Geom& g, int t, int i0, int i1) {
+  return (size_t)t * g.M + (size_t)i0 * g.n1 + i1;
+}
+
+// (K v)(i0, i1) in slice t of v.
+__device__ __forceinline__ double Kop(const double* __restrict__ v, const Geom& g, int t, int i0,
+                                      int i1) {
+  const double c = v[at(g, t, i0, i1)];
+  double r = (2.0 * c - v[at(g, t, i0, nbr(i1 + 1, g.n1, g.neumann))] -
+              v[at(g, t, i0, nbr(i1 - 1, g.n1, g.neumann))]) * g.ih1sq;
+  if (g.has0)
+    r += (2.0 * c - v[at(g, t, nbr(i0 + 1, g.n0, g.neumann), i1)] -
+          v[at(g, t, nbr(i0 - 1, g.n0, g.neumann), i1)]) * g.ih0sq;
+  return r;
+}
+
+// (D^1 w)_i and (D^2 w)_i along one axis for the value accessor f(index).
+template <class F>
+__device__ __forceinline__ double D1w(F f, int i, int n, int neumann) {
+  if (!neumann) return f(i) - f(nbr(i - 1, n, 0));
+  return (i <= n - 2 ? f(i) : 0.0) - (i >= 1 ? f(i - 1) : 0.0);
+}
+template <class F>
+__device__ __forceinline__ double D2w(F f, int i, int n, int neumann) {
+  if (!neumann) return f(nbr(i + 1, n, 0)) - f(i);
+  return (i <= n - 2 ? f(i + 1) : 0.0) - (i >= 1 ? f(i) : 0.0);
+}
+
+// b = Cr (xi + sigma ybar) - sigma [t==0] m0/dt. With ybar == nullptr this is
+// b = Cr xi (apply_C).
+template <bool HASBAR>
+__global__ __launch_bounds__(kThreads) void k_rhs(Geom g, const double* __restrict__ xi,
+                                                  const double* __restrict__ ybar, double sigma,
+                                                  const double* __restrict__ m0,
+                                                  double* __restrict__ b) {
+  const long long n = g.n;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int t = (int)(p / g.M);
+    const int rem = (int)(p - (long long)t * g.M);
+    const int i0 = rem / g.n1, i1 = rem - i0 * g.n1;
+    auto z = [&](int c, size_t idx) -> double {
+      const size_t k = (size_t)c * n + idx;
+      return HASBAR ? xi[k] + sigma * ybar[k] : xi[k];
+    };
+    // m-part: L z_t - [t>=1] z_{t-1}/dt
+    const double zc = z(0, at(g, t, i0, i1));
+    double Kz = (2.0 * zc - z(0, at(g, t, i0, nbr(i1 + 1, g.n1, g.neumann))) -
+                 z(0, at(g, t, i0, nbr(i1 - 1, g.n1, g.neumann)))) * g.ih1sq;
+    if (g.has0)
+      Kz += (2.0 * zc - z(0, at(g, t, nbr(i0 + 1, g.n0, g.neumann), i1)) -
+             z(0, at(g, t, nbr(i0 - 1, g.n0, g.neumann), i1))) * g.ih0sq;
+    double r = g.nu * Kz + zc * g.idt;
+    if (t >= 1) r -= z(0, at(g, t - 1, i0, i1)) * g.idt;
+    // flux part: sum_c B_c w^(c)_t
+    {
+      const int ce = 1 + g.cb1, co = 2 + g.cb1;
+      auto fe = [&](int j) { return z(ce, at(g, t, i0, j)); };
+      auto fo = [&](int j) { return z(co, at(g, t, i0, j)); };
+      r += (D1w(fe, i1, g.n1, g.neumann) + D2w(fo, i1, g.n1, g.neumann)) * g.ih1;
+    }
+    if (g.has0) {
+      auto fe = [&](int i) { return z(1, at(g, t, i, i1)); };
+      auto fo = [&](int i) { return z(2, at(g, t, i, i1)); };
+      r += (D1w(fe, i0, g.n0, g.neumann) + D2w(fo, i0, g.n0, g.neumann)) * g.ih0;
+    }
+    if (HASBAR && t == 0) r -= sigma * m0[rem] * g.idt;
+    b[p] = r;
+  }
+}
+
+// Components of Cr^T u at one cell: out[0] = m-part, out[1+c] = B_c^T u_t.
+__device__ __forceinline__ void CT_cell(const Geom& g, const double* __restrict__ u, int t, int i0,
+                                        int i1, double* out) {
+  const double uc = u[at(g, t, i0, i1)];
+  double m = g.nu * Kop(u, g, t, i0, i1) + uc * g.idt;
+  if (t <= g.nt - 2) m -= u[at(g, t + 1, i0, i1)] * g.idt;
+  out[0] = m;
+  {
+    const double up = u[at(g, t, i0, nbr(i1 + 1, g.n1, g.neumann))];
+    const double um = u[at(g, t, i0, nbr(i1 - 1, g.n1, g.neumann))];
+    out[1 + g.cb1] = (uc - up) * g.ih1;
+    out[2 + g.cb1] = (um - uc) * g.ih1;
+  }
+  if (g.has0) {
+    const double up = u[at(g, t, nbr(i0 + 1, g.n0, g.neumann), i1)];
+    const double um = u[at(g, t, nbr(i0 - 1, g.n0, g.neumann), i1)];
+    out[1] = (uc - up) * g.ih0;
+    out[2] = (um - uc) * g.ih0;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_apply_CT(Geom g, const double* __restrict__ u,
+                                                       double* __restrict__ y) {
+  const long long n = g.n;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int t = (int)(p / g.M);
+    const int rem = (int)(p - (long long)t * g.M);
+    const int i0 = rem / g.n1, i1 = rem - i0 * g.n1;
+    double out[5];
+    CT_cell(g, u, t, i0, i1, out);
+    for (int c = 0; c <= g.ncomp; ++c) y[(size_t)c * n + p] = out[c];
+  }
+}
+
+// g-field of the factorised reduced matrix at one node of slice t:
+//   g = nu^2 K u_t + (2 nu/dt + 2) u_t - (nu/dt) s,  s = u_{t-1} + u_{t+1}
+// so that (A u)_t = K g + ((1 + [t>=1]) u_t - s)/dt^2, which is eq. largeA with
+// C = L^2 + B B^T = nu^2 K^2 + (2nu/dt) K + I/dt^2 + 2K (B B^T = 2K, eq. precstead).
+__device__ __forceinline__ double gfield(const double* __restrict__ u, const Geom& g, int t,
+                                         int i0, int i1, double& uc_out, double& s_out) {
+  const double uc = u[at(g, t, i0, i1)];
+  double s = 0.0;
+  if (t >= 1) s += u[at(g, t - 1, i0, i1)];
+  if (t <= g.nt - 2) s += u[at(g, t + 1, i0, i1)];
+  uc_out = uc;
+  s_out = s;
+  const double c1 = 2.0 * g.nu * g.idt + 2.0;
+  const double c2 = g.nu * g.idt;
+  return g.nu * g.nu * Kop(u, g, t, i0, i1) + c1 * uc - c2 * s;
+}
+
+template <bool REDUCE>
+__global__ __launch_bounds__(kThreads) void k_AAt(Geom g, const double* __restrict__ u,
+                                                  double* __restrict__ q, RedBuf rb) {
+  const long long n = g.n;
+  double acc[1] = {0.0};
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int t = (int)(p / g.M);
+    const int rem = (int)(p - (long long)t * g.M);
+    const int i0 = rem / g.n1, i1 = rem - i0 * g.n1;
+    double uc, s, d0, d1;
+    const double gc = gfield(u, g, t, i0, i1, uc, s);
+    double Kg = (2.0 * gc - gfield(u, g, t, i0, nbr(i1 + 1, g.n1, g.neumann), d0, d1) -
+                 gfield(u, g, t, i0, nbr(i1 - 1, g.n1, g.neumann), d0, d1)) * g.ih1sq;
+    if (g.has0)
+      Kg += (2.0 * gc - gfield(u, g, t, nbr(i0 + 1, g.n0, g.neumann), i1, d0, d1) -
+             gfield(u, g, t, nbr(i0 - 1, g.n0, g.neumann), i1, d0, d1)) * g.ih0sq;
+    const double diag = (t >= 1) ? 2.0 : 1.0;
+    const double val = Kg + (diag * uc - s) * g.idt2;
+    q[p] = val;
+    if (REDUCE) acc[0] += uc * val;
+  }
+  if (REDUCE) {
+    double tot[1];
+    if (reduce_commit<1>(acc, rb, T_PQ, gridDim.x, tot) && threadIdx.x == 0) {
+      const double pq = tot[0];
+      const double rho = rb.scal[S_RHO];
+      rb.scal[S_PQ] = pq;
+      if (!(pq > 0.0) || !finite_d(pq)) {
+        rb.scal[S_BAD] = finite_d(pq) ? 1.0 : 2.0;
+        rb.scal[S_ALPHA] = 0.0;
+      } else {
+        rb.scal[S_ALPHA] = rho / pq;
+      }
+    }
+  }
+}
+
+// p = z + beta p (first: p = z), beta from the device scalars.
+__global__ __launch_bounds__(kThreads) void k_pdir(long long n, const double* __restrict__ z,
+                                                   double* __restrict__ p, const double* scal,
+                                                   int first) {
+  const double beta = first ? 0.0 : scal[S_BETA];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = first ? z[i] : z[i] + beta * p[i];
+}
+
+// Per-cell prox of Section 3 (derivation in the oracle's prox module):
+// w~ = P_K(wbar), a = |w~|^2; m = 0 if 2 tau^2 V - 2 tau mbar - a >= 0, else the
+// root of h'(m) = -a/(2(m+tau)^2) + (1 + 1/tau) m + V - mbar/tau by Newton from
+// max(0, (mbar - tau V)/(1 + tau)) while the iterate still increases (<= 64);
+// w = m/(m + tau) w~.
+__device__ __forceinline__ double prox_cell(double mbar, double* w, int ncomp, double V,
+                                            double tau) {
+  double a = 0.0;
+  for (int c = 0; c < ncomp; ++c) {
+    double v = w[c];
+    v = (c & 1) ? fmin(v, 0.0) : fmax(v, 0.0);
+    w[c] = v;
+    a += v * v;
+  }
+  if (2.0 * tau * tau * V - 2.0 * tau * mbar - a >= 0.0) {
+    for (int c = 0; c < ncomp; ++c) w[c] = 0.0;
+    return 0.0;
+  }
+  double m = fmax(0.0, (mbar - tau * V) / (1.0 + tau));
+  const double k1 = 1.0 + 1.0 / tau;
+  for (int it = 0; it < 64; ++it) {
+    const double s = m + tau;
+    const double hp = -a / (2.0 * s * s) + k1 * m + V - mbar / tau;
+    const double hpp = a / (s * s * s) + k1;
+    const double mn = m - hp / hpp;
+    if (!(mn > m)) break;
+    m = mn;
+  }
+  const double f = m / (m + tau);
+  for (int c = 0; c < ncomp; ++c) w[c] *= f;
+  return m;
+}
+
+__global__ __launch_bounds__(kThreads) void k_prox(Geom g, const double* __restrict__ v,
+                                                   const double* __restrict__ Vpot, double tau,
+                                                   double* __restrict__ y) {
+  const long long n = g.n;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int rem = (int)(p % g.M);
+    double w[4];
+    for (int c = 0; c < g.ncomp; ++c) w[c] = v[(size_t)(c + 1) * n + p];
+    const double m = prox_cell(v[p], w, g.ncomp, Vpot[rem], tau);
+    y[p] = m;
+    for (int c = 0; c < g.ncomp; ++c) y[(size_t)(c + 1) * n + p] = w[c];
+  }
+}
+
+// One CP iteration after the projection solve:
+//   xi' = Cr^T u;  y' = prox_{tau phi}(y - tau xi');  ybar = y' + theta (y' - y);
+// partial ||m' - m||^2 reduced into the device scalar S_DM.
+__global__ __launch_bounds__(kThreads) void k_backproj_prox(Geom g, const double* __restrict__ u,
+                                                            double* __restrict__ xi,
+                                                            double* __restrict__ y,
+                                                            double* __restrict__ ybar,
+                                                            const double* __restrict__ Vpot,
+                                                            double tau, double theta,
+                                                            RedBuf rb) {
+  const long long n = g.n;
+  double acc[1] = {0.0};
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int t = (int)(p / g.M);
+    const int rem = (int)(p - (long long)t * g.M);
+    const int i0 = rem / g.n1, i1 = rem - i0 * g.n1;
+    double x[5], yo[5], w[4];
+    CT_cell(g, u, t, i0, i1, x);
+    for (int c = 0; c <= g.ncomp; ++c) yo[c] = y[(size_t)c * n + p];
+    for (int c = 0; c < g.ncomp; ++c) w[c] = yo[1 + c] - tau * x[1 + c];
+    const double m = prox_cell(yo[0] - tau * x[0], w, g.ncomp, Vpot[rem], tau);
+    for (int c = 0; c <= g.ncomp; ++c) xi[(size_t)c * n + p] = x[c];
+    y[p] = m;
+    ybar[p] = m + theta * (m - yo[0]);
+    for (int c = 0; c < g.ncomp; ++c) {
+      y[(size_t)(c + 1) * n + p] = w[c];
+      ybar[(size_t)(c + 1) * n + p] = w[c] + theta * (w[c] - yo[1 + c]);
+    }
+    const double dm = m - yo[0];
+    acc[0] += dm * dm;
+  }
+  double tot[1];
+  if (reduce_commit<1>(acc, rb, T_DM, gridDim.x, tot) && threadIdx.x == 0) rb.scal[S_DM] = tot[0];
+}
+
+int grid_for(long long n, int max_blocks) {
+  long long b = (n + kThreads - 1) / kThreads;
+  if (b < 1) b = 1;
+  if (b > max_blocks) b = max_blocks;
+  return (int)b;
+}
+
+}  // namespace
+
+void launch_rhs(const Plan& P, const double* xi, const double* ybar, double sigma,
+                const double* m0, double* b, hipStream_t s) {
+  hipLaunchKernelGGL(k_rhs<true>, dim3(grid_for(P.g.n, P.red.max_blocks)), dim3(kThreads), 0, s,
+                     P.g, xi, ybar, sigma, m0, b);
+}
+
+void launch_apply_C(const Plan& P, const double* y, double* b, hipStream_t s) {
+  hipLaunchKernelGGL(k_rhs<false>, dim3(grid_for(P.g.n, P.red.max_blocks)), dim3(kThreads), 0, s,
+                     P.g, y, (const double*)nullptr, 0.0, (const double*)nullptr, b);
+}
+
+void launch_apply_CT(const Plan& P, const double* u, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_apply_CT, dim3(grid_for(P.g.n, P.red.max_blocks)), dim3(kThreads), 0, s,
+                     P.g, u, y);
+}
+
+void launch_AAt(const Plan& P, const double* u, double* q, bool reduce_pq, hipStream_t s) {
+  const int grid = grid_for(P.g.n, P.red.max_blocks);
+  if (reduce_pq)
+    hipLaunchKernelGGL(k_AAt<true>, dim3(grid), dim3(kThreads), 0, s, P.g, u, q, P.red);
+  else
+    hipLaunchKernelGGL(k_AAt<false>, dim3(grid), dim3(kThreads), 0, s, P.g, u, q, P.red);
+}
+
+void launch_pdir_AAt(const Plan& P, const double* z, double* p, double* q, bool first,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_pdir, dim3(grid_for(P.g.n, P.red.max_blocks)), dim3(kThreads), 0, s,
+                     P.g.n, z, p, (const double*)P.red.scal, first ? 1 : 0);
+  launch_AAt(P, p, q, true, s);
+}
+
+void launch_prox(const Plan& P, const double* v, double tau, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_prox, dim3(grid_for(P.g.n, P.red.max_blocks)), dim3(kThreads), 0, s, P.g,
+                     v, (const double*)P.V, tau, y);
+}
+
+void launch_backproj_prox(const Plan& P, const double* u, double* xi, double* y, double* ybar,
+                          double tau, double theta, hipStream_t s) {
+  hipLaunchKernelGGL(k_backproj_prox, dim3(grid_for(P.g.n, P.red.max_blocks)), dim3(kThreads), 0,
+                     s, P.g, u, xi, y, ybar, (const double*)P.V, tau, theta, P.red);
+}
+
+}  // namespace mfg

@@ -1,0 +1,43 @@
+"""Helpers shared by the GPU tests: build a GPU plan and the matching oracle
+grid from one workload instance, and move arrays between NumPy and torch."""
+import numpy as np
+
+from oracle.grid import Grid
+
+
+def grid_of(inst, l=None):
+    d = inst.d
+    return Grid(d=d, nx=inst.nx, ny=inst.ny, nt=inst.nt, bc=inst.bc, nu=inst.nu, T=inst.T,
+                lo=tuple(inst.lo) + (0.0,) * (2 - d), hi=tuple(inst.hi) + (1.0,) * (2 - d),
+                l=inst.l if l is None else l, gamma=inst.gamma)
+
+
+def plan_of(inst, precision="fp64", l=None):
+    import torch
+    from paper_2507_01958_amd import mfg
+    pb = mfg.make_problem(inst.d, inst.nx, inst.ny, inst.nt, inst.bc, inst.nu, inst.gamma,
+                          l=inst.l if l is None else l, precision=precision, T=inst.T,
+                          lo=inst.lo, hi=inst.hi)
+    V = torch.from_numpy(inst.V).cuda()
+    m0 = torch.from_numpy(inst.m0).cuda()
+    return mfg.mfg_plan(pb, V, m0)
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def empty(n):
+    import torch
+    return torch.empty(n, dtype=torch.float64, device="cuda")
+
+
+def say(msg):
+    print(msg, flush=True)
