@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--variants", default="fp64")
+    ap.add_argument("--variants", default="fp64,mixed_fp32,mixed_fp16,mixed_bf16")
     ap.add_argument("--pcg-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--size", type=int, default=256)

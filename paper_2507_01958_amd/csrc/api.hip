@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -253,6 +254,7 @@ static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const d
   // workspace
   const size_t n = (size_t)g.n;
   if ((rc = dalloc(P, &P.r, n)) || (rc = dalloc(P, &P.z, n)) || (rc = dalloc(P, &P.p, n)) ||
+      (rc = dalloc(P, &P.p2, n)) ||
       (rc = dalloc(P, &P.q, n)) || (rc = dalloc(P, &P.tmp, n)) || (rc = dalloc(P, &P.b, n)) ||
       (rc = dalloc(P, &P.u, n)))
     return rc;
@@ -265,9 +267,8 @@ static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const d
       return fail(MFG_ERR_UNSUPPORTED, "grid too large for the time-transform reduction");
   }
   if ((rc = dalloc(P, &P.red.partials, (size_t)T_COUNT * kSlotsPerSite * P.red.max_blocks)) ||
-      (rc = dalloc(P, &P.red.tickets, T_COUNT)) || (rc = dalloc(P, &P.red.scal, S_COUNT)))
+      (rc = dalloc(P, &P.red.scal, S_COUNT)))
     return rc;
-  HIP_TRY(hipMemset(P.red.tickets, 0, T_COUNT * sizeof(unsigned)));
   HIP_TRY(hipMemset(P.red.scal, 0, S_COUNT * sizeof(double)));
   void* hs = nullptr;
   HIP_TRY(hipHostMalloc(&hs, S_COUNT * sizeof(double), hipHostMallocDefault));
@@ -299,9 +300,12 @@ static int run_pcg(Plan& P, const double* b, double* x, double rtol, int maxit, 
   bool conv = (bb == 0.0);
   if (!conv) {
     launch_precond(P, P.r, P.z, true, nullptr, s);
+    double* pold = P.p2;
+    double* pnew = P.p;
     for (k = 1; k <= maxit; ++k) {
-      launch_pdir_AAt(P, P.z, P.p, P.q, k == 1, s);
-      launch_update(P, x, P.r, P.p, P.q, s);
+      launch_pdir_AAt(P, P.z, pold, pnew, P.q, k == 1, s);
+      launch_update(P, x, P.r, pnew, P.q, s);
+      std::swap(pold, pnew);
       HIP_TRY(hipGetLastError());
       if ((rc = read_scalars(P))) return rc;
       const double bad = P.host_scal[S_BAD];

@@ -51,41 +51,20 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
   __syncthreads();
 }
 
-// Publish this block's partial sums; the last block to arrive sums all partials
-// in block order and returns true (totals valid in thread 0). The ticket is
-// reset by the last block so the site is reusable by the next launch.
+// Store this block's partial sums (slot k of `site` at index blockIdx.x).
+// A separate single-block finisher kernel sums them in block order after the
+// producing kernel has completed, so no device-scope fence is needed here (on
+// a multi-XCD part such a fence writes back the whole L2 of the XCD).
 template <int NV>
-__device__ bool reduce_commit(double (&v)[NV], const RedBuf& rb, int site, int nblocks,
-                              double (&tot)[NV]) {
+__device__ __forceinline__ void reduce_store(double (&v)[NV], const RedBuf& rb, int site) {
   static_assert(NV <= kSlotsPerSite, "too many reduction slots");
   __shared__ double sh[NV * 16];
-  __shared__ int last;
   block_sum<NV>(v, sh);
-  double* part = rb.partials + (size_t)site * kSlotsPerSite * rb.max_blocks;
   if (threadIdx.x == 0) {
+    double* part = rb.partials + (size_t)site * kSlotsPerSite * rb.max_blocks;
 #pragma unroll
     for (int k = 0; k < NV; ++k) part[(size_t)k * rb.max_blocks + blockIdx.x] = v[k];
-    __threadfence();
-    unsigned t = atomicAdd(&rb.tickets[site], 1u);
-    last = (t == (unsigned)(nblocks - 1));
   }
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
-      s += __builtin_nontemporal_load(&part[(size_t)k * rb.max_blocks + b]);
-    v[k] = s;
-  }
-  block_sum<NV>(v, sh);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) tot[k] = v[k];
-    atomicExch(&rb.tickets[site], 0u);
-  }
-  return true;
 }
 
 __device__ __forceinline__ bool finite_d(double x) { return __builtin_isfinite(x); }

@@ -33,11 +33,10 @@ struct Geom {
   double nu, dt, idt, idt2;
 };
 
-// Deterministic two-level reduction: per-block partials, then the last block
-// to finish (device-scope ticket) sums them in a fixed order.
+// Deterministic two-level reduction: per-block partials, then one finisher
+// block sums them in block order.
 struct RedBuf {
   double* partials;   // [slot][block]
-  unsigned* tickets;  // one counter per reduction site, left at zero
   double* scal;       // device scalar block
   int max_blocks;
 };
@@ -60,7 +59,21 @@ enum ScalarSlot {
   S_COUNT = 16
 };
 
-enum TicketSite { T_BB = 0, T_PQ = 1, T_RR = 2, T_RZ = 3, T_DM = 4, T_AUX = 5, T_COUNT = 8 };
+enum ReduceSite { T_BB = 0, T_PQ = 1, T_RR = 2, T_RZ = 3, T_DM = 4, T_AUX = 5, T_COUNT = 8 };
+
+// What the finisher does with the summed partials of a site.
+enum FinishOp {
+  OP_BB = 0,        // b.b -> S_BB, S_RR; S_DONE if zero; S_BAD if non-finite
+  OP_PQ = 1,        // p.q -> S_PQ, S_ALPHA = S_RHO / p.q
+  OP_RR = 2,        // r.r -> S_RR; S_DONE if r.r <= S_TOL2 * S_BB
+  OP_RZ_INIT = 3,   // r.z -> S_RHO, S_BETA = 0
+  OP_RZ_STD = 4,    // beta = r'.z' / r.z
+  OP_RZ_FLEX = 5,   // beta = -alpha z'.q / r.z (flexible)
+  OP_DM = 6,        // -> S_DM
+  OP_AUX = 7        // -> S_AUX0, S_AUX1
+};
+
+constexpr int kStreamGrid = 2048;  // blocks of the streaming kernels
 
 // One spatial transform axis (Algorithm 2): real-to-real transform built on a
 // complex Stockham FFT of length N with two real lines packed per complex one.
@@ -85,8 +98,8 @@ void launch_rhs(const Plan& P, const double* xi, const double* ybar, double sigm
 void launch_apply_C(const Plan& P, const double* y, double* b, hipStream_t s);
 void launch_apply_CT(const Plan& P, const double* u, double* y, hipStream_t s);
 void launch_AAt(const Plan& P, const double* u, double* q, bool reduce_pq, hipStream_t s);
-void launch_pdir_AAt(const Plan& P, const double* z, double* p, double* q, bool first,
-                     hipStream_t s);
+void launch_pdir_AAt(const Plan& P, const double* z, const double* pold, double* pnew, double* q,
+                     bool first, hipStream_t s);
 void launch_prox(const Plan& P, const double* v, double tau, double* y, hipStream_t s);
 void launch_backproj_prox(const Plan& P, const double* u, double* xi, double* y, double* ybar,
                           double tau, double theta, hipStream_t s);
@@ -96,6 +109,7 @@ void launch_pcg_init(const Plan& P, const double* b, double* x, double* r, doubl
 void launch_update(const Plan& P, double* x, double* r, const double* p, const double* q,
                    hipStream_t s);
 void launch_residual(const Plan& P, const double* b, const double* Ax, hipStream_t s);
+void launch_finish(const Plan& P, int site, int nblocks, int op, hipStream_t s);
 void launch_fill(double* x, long long n, double v, hipStream_t s);
 void launch_cp_init(const Plan& P, double* xi, double* y, double* ybar, hipStream_t s);
 // precond.hip

@@ -34,7 +34,7 @@ struct Plan {
   Axis ax0{}, ax1{};
 
   // workspace (n-vectors)
-  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double *r = nullptr, *z = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr;
   double *tmp = nullptr;  // preconditioner intermediate (float64 or float32 view)
   double *b = nullptr, *u = nullptr;
   double *xi_tmp = nullptr;

@@ -15,6 +15,7 @@
 // Stockham FFT staged in LDS.
 #include "device_util.h"
 #include "plan.h"
+#include "tgemm.h"
 
 namespace mfg {
 
@@ -315,108 +316,6 @@ __global__ __launch_bounds__(256) void k_cols_solve(T* __restrict__ data, Geom g
   }
 }
 
-// ---------------------------------------------------------------------------
-// Time transform (Algorithm 1): Y[k][s] = sum_t V[k][t] X[t][s] on the float64
-// matrix cores (v_mfma_f64_16x16x4f64). Each wave computes all k of one block
-// of 16 nodes s; blockIdx also selects a chunk of KB*16 output rows k.
-// Optional fused epilogue: r.z and z.q partials (z = Y) for PCG.
-// ---------------------------------------------------------------------------
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-enum DotMode { DOT_NONE = 0, DOT_INIT = 1, DOT_STD = 2, DOT_FLEX = 3 };
-
-__device__ void beta_finish(RedBuf rb, double rz, double zq, int mode) {
-  if (!finite_d(rz) || !finite_d(zq)) {
-    rb.scal[S_BAD] = 2.0;
-    return;
-  }
-  if (!(rz > 0.0)) {
-    rb.scal[S_BAD] = 1.0;
-    return;
-  }
-  if (mode == DOT_INIT) {
-    rb.scal[S_RHO] = rz;
-    rb.scal[S_BETA] = 0.0;
-    return;
-  }
-  const double rho = rb.scal[S_RHO];
-  const double beta = (mode == DOT_FLEX) ? -rb.scal[S_ALPHA] * zq / rho : rz / rho;
-  rb.scal[S_BETA] = beta;
-  rb.scal[S_RHO] = rz;
-}
-
-template <int KB, typename TX, typename TY>
-__global__ __launch_bounds__(256) void k_tgemm_f64(const double* __restrict__ Vt,
-                                                   const TX* __restrict__ X, TY* __restrict__ Y,
-                                                   int nt, int M, int ncolblk, int dotmode,
-                                                   const double* __restrict__ rvec,
-                                                   const double* __restrict__ qvec, RedBuf rb) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int cb = blockIdx.x % ncolblk;
-  const int kc = blockIdx.x / ncolblk;
-  const int col = (cb * 4 + wave) * 16 + (lane & 15);
-  const int kq = lane >> 4;
-  const int kbase = kc * KB * 16;
-  v4d acc[KB];
-#pragma unroll
-  for (int kb = 0; kb < KB; ++kb) acc[kb] = (v4d){0.0, 0.0, 0.0, 0.0};
-  const bool cv = col < M;
-  for (int t0 = 0; t0 < nt; t0 += 4) {
-    const int t = t0 + kq;
-    const bool tv = t < nt;
-    const double bv = (cv && tv) ? (double)X[(size_t)t * M + col] : 0.0;
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-      const int k = kbase + kb * 16 + (lane & 15);
-      const double av = (tv && k < nt) ? Vt[(size_t)t * nt + k] : 0.0;
-      acc[kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[kb], 0, 0, 0);
-    }
-  }
-  double dots[2] = {0.0, 0.0};
-#pragma unroll
-  for (int kb = 0; kb < KB; ++kb) {
-#pragma unroll
-    for (int jr = 0; jr < 4; ++jr) {
-      // v_mfma_f64_16x16x4f64 result layout: register jr of lane l holds
-      // row (l / 16) + 4 jr, column l % 16
-      const int k = kbase + kb * 16 + kq + 4 * jr;
-      if (cv && k < nt) {
-        const size_t o = (size_t)k * M + col;
-        const double v = acc[kb][jr];
-        Y[o] = (TY)v;
-        if (dotmode != DOT_NONE) {
-          dots[0] += rvec[o] * v;
-          if (dotmode == DOT_FLEX) dots[1] += qvec[o] * v;
-        }
-      }
-    }
-  }
-  if (dotmode != DOT_NONE) {
-    double tot[2];
-    if (reduce_commit<2>(dots, rb, T_RZ, gridDim.x, tot) && threadIdx.x == 0)
-      beta_finish(rb, tot[0], tot[1], dotmode);
-  }
-}
-
-template <typename TX, typename TY>
-void tgemm_f64(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r, const double* q,
-               hipStream_t s) {
-  const int nt = P.g.nt, M = P.g.M;
-  const int ncolblk = (M + 63) / 64;
-  const int kb_needed = (nt + 15) / 16;
-  if (kb_needed <= 2) {
-    hipLaunchKernelGGL((k_tgemm_f64<2, TX, TY>), dim3(ncolblk), dim3(256), 0, s, P.Vt64, X, Y,
-                       nt, M, ncolblk, dotmode, r, q, P.red);
-  } else if (kb_needed <= 4) {
-    hipLaunchKernelGGL((k_tgemm_f64<4, TX, TY>), dim3(ncolblk), dim3(256), 0, s, P.Vt64, X, Y,
-                       nt, M, ncolblk, dotmode, r, q, P.red);
-  } else {
-    const int nkc = (kb_needed + 7) / 8;
-    hipLaunchKernelGGL((k_tgemm_f64<8, TX, TY>), dim3(ncolblk * nkc), dim3(256), 0, s, P.Vt64,
-                       X, Y, nt, M, ncolblk, dotmode, r, q, P.red);
-  }
-}
-
 SolveCtx solve_ctx(const Plan& P) {
   SolveCtx sc;
   sc.lam_t = P.lam_t;
@@ -467,14 +366,24 @@ void spatial_solves(const Plan& P, T* data, hipStream_t s) {
 
 void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
                     const double* q, hipStream_t s) {
-  (void)fused_dots;
-  // dot mode is carried in q's role: see mfg_api (DOT_* passed via S_AUX slot)
   int dotmode = DOT_NONE;
-  if (fused_dots) dotmode = (q == nullptr) ? DOT_INIT : (P.precision == MFG_FP64 ? DOT_STD : DOT_FLEX);
-  double* tmp = P.tmp;
-  tgemm_f64<double, double>(P, r, tmp, DOT_NONE, nullptr, nullptr, s);
-  spatial_solves<double>(P, tmp, s);
-  tgemm_f64<double, double>(P, tmp, z, dotmode, r, q, s);
+  if (fused_dots)
+    dotmode = (q == nullptr) ? DOT_INIT : (P.precision == MFG_FP64 ? DOT_STD : DOT_FLEX);
+  if (P.precision == MFG_FP64) {
+    double* tmp = P.tmp;
+    tgemm<double, double>(P, GM_F64, r, tmp, DOT_NONE, nullptr, nullptr, s);
+    spatial_solves<double>(P, tmp, s);
+    tgemm<double, double>(P, GM_F64, tmp, z, dotmode, r, q, s);
+    return;
+  }
+  // mixed: float32 intermediate and spatial solves; time transform in the
+  // plan's matrix-core precision
+  const int mode = P.precision == MFG_MIXED_FP32 ? GM_F32
+                   : (P.precision == MFG_MIXED_FP16 ? GM_F16 : GM_BF16);
+  float* tmp = reinterpret_cast<float*>(P.tmp);
+  tgemm<double, float>(P, mode, r, tmp, DOT_NONE, nullptr, nullptr, s);
+  spatial_solves<float>(P, tmp, s);
+  tgemm<float, double>(P, mode, tmp, z, dotmode, r, q, s);
 }
 
 }  // namespace mfg

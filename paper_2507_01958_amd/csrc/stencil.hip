@@ -130,69 +130,116 @@ __global__ __launch_bounds__(kThreads) void k_apply_CT(Geom g, const double* __r
   }
 }
 
-// g-field of the factorised reduced matrix at one node of slice t:
-//   g = nu^2 K u_t + (2 nu/dt + 2) u_t - (nu/dt) s,  s = u_{t-1} + u_{t+1}
-// so that (A u)_t = K g + ((1 + [t>=1]) u_t - s)/dt^2, which is eq. largeA with
-// C = L^2 + B B^T = nu^2 K^2 + (2nu/dt) K + I/dt^2 + 2K (B B^T = 2K, eq. precstead).
-__device__ __forceinline__ double gfield(const double* __restrict__ u, const Geom& g, int t,
-                                         int i0, int i1, double& uc_out, double& s_out) {
-  const double uc = u[at(g, t, i0, i1)];
-  double s = 0.0;
-  if (t >= 1) s += u[at(g, t - 1, i0, i1)];
-  if (t <= g.nt - 2) s += u[at(g, t + 1, i0, i1)];
-  uc_out = uc;
-  s_out = s;
-  const double c1 = 2.0 * g.nu * g.idt + 2.0;
-  const double c2 = g.nu * g.idt;
-  return g.nu * g.nu * Kop(u, g, t, i0, i1) + c1 * uc - c2 * s;
-}
+// (A u)_t = K g_t + ((1 + [t>=1]) u_t - s_t)/dt^2 with
+//   g_t = nu^2 K u_t + (2 nu/dt + 2) u_t - (nu/dt) s_t,   s_t = u_{t-1} + u_{t+1},
+// which is eq. largeA with C = L^2 + B B^T = nu^2 K^2 + (2nu/dt) K + I/dt^2 + 2K
+// (B B^T = 2K, eq. precstead) and the off-diagonal blocks -L/dt.
+//
+// Each block owns a TI x TJ spatial tile and a chunk of time slices and walks
+// the chunk in time, keeping slices t-1, t, t+1 (tile plus a 2-node halo) in an
+// LDS ring, so every slice is read once per block; g is staged in LDS on the
+// tile plus a 1-node halo. In FUSE mode the input is the PCG direction formed on
+// the fly, p = z + beta p_old (p = z on the first iteration), written to p_new
+// by the block that owns the node; p_old and p_new are different buffers, so
+// halo reads never see a value updated by a neighbouring block.
+constexpr int kTJ = 64;
+template <bool HAS0>
+struct Tile {
+  static constexpr int TI = HAS0 ? 16 : 1;   // tile rows (axis 0)
+  static constexpr int HI = HAS0 ? 2 : 0;    // halo rows of the u slots
+  static constexpr int GH = HAS0 ? 1 : 0;    // halo rows of g
+  static constexpr int SI = TI + 2 * HI;
+  static constexpr int SJ = kTJ + 4;
+  static constexpr int GI = TI + 2 * GH;
+  static constexpr int GJ = kTJ + 2;
+};
 
-template <bool REDUCE>
-__global__ __launch_bounds__(kThreads) void k_AAt(Geom g, const double* __restrict__ u,
-                                                  double* __restrict__ q, RedBuf rb) {
-  const long long n = g.n;
-  double acc[1] = {0.0};
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-       p += (long long)gridDim.x * blockDim.x) {
-    const int t = (int)(p / g.M);
-    const int rem = (int)(p - (long long)t * g.M);
-    const int i0 = rem / g.n1, i1 = rem - i0 * g.n1;
-    double uc, s, d0, d1;
-    const double gc = gfield(u, g, t, i0, i1, uc, s);
-    double Kg = (2.0 * gc - gfield(u, g, t, i0, nbr(i1 + 1, g.n1, g.neumann), d0, d1) -
-                 gfield(u, g, t, i0, nbr(i1 - 1, g.n1, g.neumann), d0, d1)) * g.ih1sq;
-    if (g.has0)
-      Kg += (2.0 * gc - gfield(u, g, t, nbr(i0 + 1, g.n0, g.neumann), i1, d0, d1) -
-             gfield(u, g, t, nbr(i0 - 1, g.n0, g.neumann), i1, d0, d1)) * g.ih0sq;
+template <bool HAS0, bool FUSE>
+__global__ __launch_bounds__(kThreads) void k_AAt_tile(Geom g, const double* __restrict__ src,
+                                                       const double* __restrict__ pold,
+                                                       double* __restrict__ pnew,
+                                                       double* __restrict__ q, RedBuf rb, int tc,
+                                                       int first, int reduce) {
+  using C = Tile<HAS0>;
+  __shared__ double U[3][C::SI * C::SJ];
+  __shared__ double G[C::GI * C::GJ];
+  const int tiles1 = (g.n1 + kTJ - 1) / kTJ;
+  const int tiles0 = HAS0 ? (g.n0 + C::TI - 1) / C::TI : 1;
+  const int nchunk = (g.nt + tc - 1) / tc;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = blk / nchunk, chunk = blk - tile * nchunk;
+  const int i0 = (tile / tiles1) * C::TI, j0 = (tile % tiles1) * kTJ;
+  (void)tiles0;
+  const int t_lo = chunk * tc;
+  const int t_hi = (t_lo + tc < g.nt) ? t_lo + tc : g.nt;
+  const double beta = (FUSE && !first) ? rb.scal[S_BETA] : 0.0;
+  const double c1 = 2.0 * g.nu * g.idt + 2.0, c2 = g.nu * g.idt, nu2 = g.nu * g.nu;
+
+  auto load_slot = [&](int t, double* dst) {
+    for (int idx = threadIdx.x; idx < C::SI * C::SJ; idx += blockDim.x) {
+      const int ii = idx / C::SJ - C::HI, jj = idx % C::SJ - 2;
+      double v = 0.0;
+      if (t >= 0 && t < g.nt) {
+        const int gi = HAS0 ? nbr(i0 + ii, g.n0, g.neumann) : 0;
+        const int gj = nbr(j0 + jj, g.n1, g.neumann);
+        const size_t o = (size_t)t * g.M + (size_t)gi * g.n1 + gj;
+        if (FUSE) {
+          v = first ? src[o] : src[o] + beta * pold[o];
+          if (t >= t_lo && t < t_hi && ii >= 0 && ii < C::TI && jj >= 0 && jj < kTJ &&
+              i0 + ii < g.n0 && j0 + jj < g.n1)
+            pnew[o] = v;
+        } else {
+          v = src[o];
+        }
+      }
+      dst[idx] = v;
+    }
+  };
+
+  double acc = 0.0;
+  int sp = 0, sc = 1, sn = 2;
+  load_slot(t_lo - 1, U[sp]);
+  load_slot(t_lo, U[sc]);
+  for (int t = t_lo; t < t_hi; ++t) {
+    load_slot(t + 1, U[sn]);
+    __syncthreads();
+    const double* Up = U[sp];
+    const double* Uc = U[sc];
+    const double* Un = U[sn];
+    for (int idx = threadIdx.x; idx < C::GI * C::GJ; idx += blockDim.x) {
+      const int gi = idx / C::GJ, gj = idx - gi * C::GJ;
+      const int c = (gi - C::GH + C::HI) * C::SJ + gj + 1;
+      const double u = Uc[c];
+      double Ku = (2.0 * u - Uc[c + 1] - Uc[c - 1]) * g.ih1sq;
+      if (HAS0) Ku += (2.0 * u - Uc[c + C::SJ] - Uc[c - C::SJ]) * g.ih0sq;
+      G[idx] = nu2 * Ku + c1 * u - c2 * (Up[c] + Un[c]);
+    }
+    __syncthreads();
     const double diag = (t >= 1) ? 2.0 : 1.0;
-    const double val = Kg + (diag * uc - s) * g.idt2;
-    q[p] = val;
-    if (REDUCE) acc[0] += uc * val;
-  }
-  if (REDUCE) {
-    double tot[1];
-    if (reduce_commit<1>(acc, rb, T_PQ, gridDim.x, tot) && threadIdx.x == 0) {
-      const double pq = tot[0];
-      const double rho = rb.scal[S_RHO];
-      rb.scal[S_PQ] = pq;
-      if (!(pq > 0.0) || !finite_d(pq)) {
-        rb.scal[S_BAD] = finite_d(pq) ? 1.0 : 2.0;
-        rb.scal[S_ALPHA] = 0.0;
-      } else {
-        rb.scal[S_ALPHA] = rho / pq;
+    for (int idx = threadIdx.x; idx < C::TI * kTJ; idx += blockDim.x) {
+      const int ii = idx / kTJ, jj = idx - ii * kTJ;
+      if (i0 + ii < g.n0 && j0 + jj < g.n1) {
+        const int gc = (ii + C::GH) * C::GJ + jj + 1;
+        const double gv = G[gc];
+        double Kg = (2.0 * gv - G[gc + 1] - G[gc - 1]) * g.ih1sq;
+        if (HAS0) Kg += (2.0 * gv - G[gc + C::GJ] - G[gc - C::GJ]) * g.ih0sq;
+        const int c = (ii + C::HI) * C::SJ + jj + 2;
+        const double u = Uc[c];
+        const double val = Kg + (diag * u - (Up[c] + Un[c])) * g.idt2;
+        q[(size_t)t * g.M + (size_t)(i0 + ii) * g.n1 + j0 + jj] = val;
+        acc += u * val;
       }
     }
+    __syncthreads();
+    const int tmp = sp;
+    sp = sc;
+    sc = sn;
+    sn = tmp;
   }
-}
-
-// p = z + beta p (first: p = z), beta from the device scalars.
-__global__ __launch_bounds__(kThreads) void k_pdir(long long n, const double* __restrict__ z,
-                                                   double* __restrict__ p, const double* scal,
-                                                   int first) {
-  const double beta = first ? 0.0 : scal[S_BETA];
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x)
-    p[i] = first ? z[i] : z[i] + beta * p[i];
+  if (reduce) {
+    double a[1] = {acc};
+    reduce_store<1>(a, rb, T_PQ);
+  }
 }
 
 // Per-cell prox of Section 3 (derivation in the oracle's prox module):
@@ -275,15 +322,38 @@ __global__ __launch_bounds__(kThreads) void k_backproj_prox(Geom g, const double
     const double dm = m - yo[0];
     acc[0] += dm * dm;
   }
-  double tot[1];
-  if (reduce_commit<1>(acc, rb, T_DM, gridDim.x, tot) && threadIdx.x == 0) rb.scal[S_DM] = tot[0];
+  reduce_store<1>(acc, rb, T_DM);
 }
 
-int grid_for(long long n, int max_blocks) {
+int grid_for(long long n, int = 0) {
   long long b = (n + kThreads - 1) / kThreads;
   if (b < 1) b = 1;
-  if (b > max_blocks) b = max_blocks;
+  if (b > kStreamGrid) b = kStreamGrid;
   return (int)b;
+}
+
+// Time-chunk length of the tiled A kernel: enough blocks to fill the chip.
+// The grid also stays within the reduction's partial-sum capacity.
+int aat_chunk(const Geom& g, int ntile, int max_blocks) {
+  long long tc = ((long long)g.nt * ntile) / 1024;
+  if (tc < 1) tc = 1;
+  if (tc > 16) tc = 16;
+  const long long need = ((long long)g.nt * ntile + max_blocks - 1) / max_blocks;
+  if (tc < need) tc = need;
+  return (int)tc;
+}
+
+template <bool HAS0, bool FUSE>
+void aat_launch(const Plan& P, const double* src, const double* pold, double* pnew, double* q,
+                bool first, bool reduce, hipStream_t s) {
+  const Geom& g = P.g;
+  const int ntile = ((g.n0 + Tile<HAS0>::TI - 1) / Tile<HAS0>::TI) * ((g.n1 + kTJ - 1) / kTJ);
+  const int tc = aat_chunk(g, ntile, P.red.max_blocks);
+  const int nchunk = (g.nt + tc - 1) / tc;
+  const int grid = ntile * nchunk;
+  hipLaunchKernelGGL((k_AAt_tile<HAS0, FUSE>), dim3(grid), dim3(kThreads), 0, s, g, src, pold,
+                     pnew, q, P.red, tc, first ? 1 : 0, reduce ? 1 : 0);
+  if (reduce) launch_finish(P, T_PQ, grid, OP_PQ, s);
 }
 
 }  // namespace
@@ -305,18 +375,14 @@ void launch_apply_CT(const Plan& P, const double* u, double* y, hipStream_t s) {
 }
 
 void launch_AAt(const Plan& P, const double* u, double* q, bool reduce_pq, hipStream_t s) {
-  const int grid = grid_for(P.g.n, P.red.max_blocks);
-  if (reduce_pq)
-    hipLaunchKernelGGL(k_AAt<true>, dim3(grid), dim3(kThreads), 0, s, P.g, u, q, P.red);
-  else
-    hipLaunchKernelGGL(k_AAt<false>, dim3(grid), dim3(kThreads), 0, s, P.g, u, q, P.red);
+  if (P.g.has0) aat_launch<true, false>(P, u, nullptr, nullptr, q, false, reduce_pq, s);
+  else aat_launch<false, false>(P, u, nullptr, nullptr, q, false, reduce_pq, s);
 }
 
-void launch_pdir_AAt(const Plan& P, const double* z, double* p, double* q, bool first,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(k_pdir, dim3(grid_for(P.g.n, P.red.max_blocks)), dim3(kThreads), 0, s,
-                     P.g.n, z, p, (const double*)P.red.scal, first ? 1 : 0);
-  launch_AAt(P, p, q, true, s);
+void launch_pdir_AAt(const Plan& P, const double* z, const double* pold, double* pnew, double* q,
+                     bool first, hipStream_t s) {
+  if (P.g.has0) aat_launch<true, true>(P, z, pold, pnew, q, first, true, s);
+  else aat_launch<false, true>(P, z, pold, pnew, q, first, true, s);
 }
 
 void launch_prox(const Plan& P, const double* v, double tau, double* y, hipStream_t s) {
@@ -326,8 +392,10 @@ void launch_prox(const Plan& P, const double* v, double tau, double* y, hipStrea
 
 void launch_backproj_prox(const Plan& P, const double* u, double* xi, double* y, double* ybar,
                           double tau, double theta, hipStream_t s) {
-  hipLaunchKernelGGL(k_backproj_prox, dim3(grid_for(P.g.n, P.red.max_blocks)), dim3(kThreads), 0,
-                     s, P.g, u, xi, y, ybar, (const double*)P.V, tau, theta, P.red);
+  const int grid = grid_for(P.g.n);
+  hipLaunchKernelGGL(k_backproj_prox, dim3(grid), dim3(kThreads), 0, s, P.g, u, xi, y, ybar,
+                     (const double*)P.V, tau, theta, P.red);
+  launch_finish(P, T_DM, grid, OP_DM, s);
 }
 
 }  // namespace mfg

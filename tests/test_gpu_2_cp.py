@@ -43,7 +43,10 @@ def test_torus1d_200_iterations():
     assert abs(st.tau - ref.tau) <= 1e-15 * ref.tau and abs(st.sigma - ref.sigma) <= 1e-15 * ref.sigma
     _compare(st, ref, g, 1e-10)
     dm_ref = np.array([info["dm"] for info in log])
-    np.testing.assert_allclose(np.array(stats["dm"]), dm_ref, rtol=1e-8, atol=1e-12)
+    # ||m_{l+1} - m_l|| differences nearly equal iterates: its error is bounded by
+    # twice the state error, 1e-10 ||m|| (not relative to the tiny late values)
+    mnorm = np.linalg.norm(ref.y[: g.n])
+    np.testing.assert_allclose(np.array(stats["dm"]), dm_ref, rtol=1e-8, atol=2e-10 * mnorm)
     P.close()
 
 
