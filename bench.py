@@ -25,6 +25,114 @@ sys.path.insert(0, ROOT)
 RTOL = 1e-8
 PCG_MAXIT = 200
 
+# Published MI355X peaks used for the roofline fraction.
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_neumann256x256x128.json")
+
+
+def kernel_sources_hash():
+    """Hash of the HIP sources; stored HBM-counter readings are only reported
+    while it matches (a changed kernel invalidates them)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2507_01958_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic(kernel, inst, variant):
+    """Algorithmic work of ONE launch of `kernel` on this workload: the minimal
+    HBM bytes of a fused implementation, or the flops of the float64 time GEMM
+    (matrix-core bound: 2 N_t flops per element against 16 bytes)."""
+    n = inst.n
+    nb = 1 + 2 * inst.d  # primal blocks
+    fsz = 8 if variant == "fp64" else 4  # preconditioner intermediate
+    flex = variant != "fp64"
+    if kernel.startswith("tgemm_f64"):
+        return "mfma", 2.0 * inst.nt * inst.nt * inst.M, "fp64"
+    table = {
+        "aat_fused": 4 * 8 * n,      # read z, p_old; write p_new, q
+        "aat": 2 * 8 * n,
+        "update": 6 * 8 * n,         # read x, r, p, q; write x, r
+        "pcg_init": 3 * 8 * n,
+        "residual": 2 * 8 * n,
+        "rows_fwd": 2 * fsz * n, "rows_inv": 2 * fsz * n, "rows_solve": 2 * fsz * n,
+        "cols_solve": 2 * fsz * n,
+        "rhs": (2 * nb + 1) * 8 * n,             # read xi, ybar; write b
+        "backproj_prox": (1 + 4 * nb) * 8 * n,   # read u, y; write xi, y, ybar
+        "cp_init": 3 * nb * 8 * n,
+    }
+    if kernel.startswith("tgemm_") and kernel.endswith("_fwd"):
+        return "hbm", (8 + 4) * n, None          # read r (f64), write f32
+    if kernel.startswith("tgemm_") and kernel.endswith("_inv"):
+        return "hbm", (4 + 8 + 8 + (8 if flex else 0)) * n, None  # + r (and q) for the dots
+    if kernel in table:
+        return "hbm", table[kernel], None
+    return None, None, None
+
+
+def roofline(report, inst, variant):
+    """Roofline object of the dominant kernel (largest total time)."""
+    cands = {k: v for k, v in report.items() if k != "finish"}
+    dom = max(cands, key=lambda k: cands[k]["total_ms"])
+    calls = cands[dom]["calls"]
+    avg_s = cands[dom]["total_ms"] / 1e3 / calls
+    bound, work, dtype = algorithmic(dom, inst, variant)
+    out = {"kernel": dom, "bound": bound, "calls": calls, "avg_us": avg_s * 1e6}
+    if bound == "mfma":
+        out.update(achieved=work / avg_s / 1e12, peak=PEAK_TFLOPS[dtype], unit="TFLOP/s",
+                   algorithmic_per_launch=work)
+    elif bound == "hbm":
+        out.update(achieved=work / avg_s / 1e9, peak=PEAK_HBM_GBS, unit="GB/s",
+                   algorithmic_per_launch=work)
+    if bound:
+        out["frac"] = out["achieved"] / out["peak"]
+    out["traffic"] = None
+    try:
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        kern = tr.get("variants", {}).get(variant, {})
+        if tr.get("sources_hash") == kernel_sources_hash() and dom in kern:
+            out["traffic"] = kern[dom]["bytes_per_launch"]
+    except (OSError, ValueError):
+        pass
+    return out
+
+
+def cpu_baseline(inst, seconds_hint=20.0):
+    """The oracle as it stands (fast mode: PCG with Algorithms 1+2 through a
+    dense V and scipy.fft) timed on the host: CP iterations from the initial
+    point at the same PCG tolerance, on a bounded sample."""
+    import threadpoolctl
+    from oracle import cp as ocp
+    from oracle import operators as ops
+    from oracle.grid import Grid
+    g = Grid(d=inst.d, nx=inst.nx, ny=inst.ny, nt=inst.nt, bc=inst.bc, nu=inst.nu, T=inst.T,
+             l=1, gamma=inst.gamma)
+    t0 = time.perf_counter()
+    S = ops.Spatial(g)
+    setup = time.perf_counter() - t0
+    st = ocp.cp_init(g, inst.m0)
+    proj = ocp.Projector(g, S, "pcg", RTOL, PCG_MAXIT)
+    iters, t_iter = 0, 0.0
+    while iters < 3 and t_iter < seconds_hint:
+        t1 = time.perf_counter()
+        ocp.cp_step(g, S, st, inst.V, inst.m0, proj)
+        t_iter += time.perf_counter() - t1
+        iters += 1
+    threads = 1
+    for info in threadpoolctl.threadpool_info():
+        threads = max(threads, int(info.get("num_threads", 1)))
+    return {"value": iters / t_iter, "unit": "CP iters/s", "cores": threads, "kind": "oracle",
+            "sample": f"{iters} CP iterations of the float64 oracle (PCG with Algorithms 1+2 via "
+                      f"dense V and scipy.fft, rtol {RTOL:g}) on the same 256x256x128 workload; "
+                      f"setup {setup:.1f} s excluded; {os.cpu_count()} host CPUs visible"}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -36,11 +144,30 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--nt", type=int, default=128)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 512 MiB device copy (HBM counter calibration)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain device-to-device copy of known size (512 MiB read + 512 MiB
+    written), repeated 4 times; used to scale the HBM byte counters."""
+    import torch
+    n = (512 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(4):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read": 8 * n, "bytes_written": 8 * n,
+                      "repeats": 4}))
 
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(use --gpus 1)", file=sys.stderr)
@@ -94,13 +221,23 @@ def main():
             torch.cuda.synchronize()
             pt = (time.perf_counter() - t0) / args.pcg_reps
             pcg[name] = dict(solves_per_s=1.0 / pt, iters=its, true_relres=rel)
+        # second pass with per-kernel HIP events on the plan's stream
+        mfg.mfg_profile(P, True)
+        mfg.mfg_cp_solve(P, st, args.steps, RTOL, PCG_MAXIT, stats=False)
+        report = mfg.mfg_profile_report(P)
+        mfg.mfg_profile(P, False)
         results[variant] = dict(cp_iters_per_s=cp_rate, ms_per_cp_iter=1e3 * dt / args.steps,
                                 mean_pcg_iters=float(np.mean(stats["pcg_iters"])),
                                 max_pcg_iters=int(np.max(stats["pcg_iters"])),
-                                pcg=pcg)
+                                pcg=pcg, roofline=roofline(report, inst, variant),
+                                kernels_us={k: round(1e3 * v["total_ms"] / v["calls"], 2)
+                                            for k, v in report.items()})
         P.close()
 
     best = max(results, key=lambda k: results[k]["cp_iters_per_s"])
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(inst)
     out = {
         "metric": "CP iters/s & PCG solves/s (1e-8 rel) at 2D 256^2x128; mixed vs FP64 GPU",
         "value": results[best]["cp_iters_per_s"],
@@ -116,6 +253,9 @@ def main():
         "data": "synthetic (seeded)",
         "config": {"workload": f"neumann2d_{inst.nx}x{inst.ny}x{inst.nt}_nu{inst.nu:g}",
                    "pcg_rtol": RTOL, "variant": best, "l": 1},
+        "pcg_solves_per_s": results[best]["pcg"]["cp_iter1"]["solves_per_s"],
+        "roofline": results[best]["roofline"],
+        "cpu_baseline": cpu,
         "variants": results,
     }
     print(json.dumps(out))

@@ -179,6 +179,18 @@ int mfg_cp_init(mfg_plan_t plan, mfg_state_t* st);
 int mfg_cp_solve(mfg_plan_t plan, mfg_state_t* st, int n_iter, double pcg_rtol,
                  int pcg_maxit, mfg_stats_t* stats);
 
+/* Per-kernel timing: enable != 0 starts recording a HIP event pair on the
+ * plan's stream around every kernel launch of the plan (totals reset); 0
+ * stops. Recording adds host work per launch but does not change what the
+ * kernels do. */
+int mfg_profile(mfg_plan_t plan, int enable);
+
+/* Write the recorded per-kernel totals as a JSON object
+ * {"kernel": {"calls": n, "total_ms": t}, ...} into buf (len bytes, host
+ * memory); synchronises the plan's stream. MFG_ERR_INVALID_ARG if buf is too
+ * small. */
+int mfg_profile_report(mfg_plan_t plan, char* buf, int len);
+
 /* Human-readable description of the last error on this thread. */
 const char* mfg_last_error(void);
 

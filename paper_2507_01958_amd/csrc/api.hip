@@ -2,6 +2,7 @@
 // the Chambolle-Pock driver.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <utility>
@@ -131,10 +132,41 @@ static int check_fields(const Plan& P, const double* V, const double* m0, bool n
 static void release(Plan& P) {
   if (P.stream) (void)hipStreamSynchronize(P.stream);
   else (void)hipDeviceSynchronize();
+  for (auto& r : P.prof.pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : P.prof.pool) (void)hipEventDestroy(e);
+  P.prof.pending.clear();
+  P.prof.pool.clear();
   for (void* p : P.dev_allocs) (void)hipFree(p);
   for (void* p : P.host_allocs) (void)hipHostFree(p);
   P.dev_allocs.clear();
   P.host_allocs.clear();
+}
+
+// MFG_TUNE="key=value,..." overrides launch-shape choices (see Tune).
+static void read_tune_env(Tune& t) {
+  const char* env = std::getenv("MFG_TUNE");
+  if (!env) return;
+  std::string str(env);
+  size_t pos = 0;
+  while (pos < str.size()) {
+    size_t end = str.find(',', pos);
+    if (end == std::string::npos) end = str.size();
+    const std::string kv = str.substr(pos, end - pos);
+    const size_t eq = kv.find('=');
+    if (eq != std::string::npos) {
+      const std::string k = kv.substr(0, eq);
+      const int v = std::atoi(kv.c_str() + eq + 1);
+      if (k == "f64_cb" && (v == 1 || v == 2)) t.f64_cb = v;
+      else if (k == "lp_cb" && (v == 1 || v == 2)) t.lp_cb = v;
+      else if (k == "rows_elems" && v >= 64 && v <= 8192) t.rows_elems = v;
+      else if (k == "cols_lines" && v >= 1 && v <= 16) t.cols_lines = v;
+      else if (k == "tgemm_pers" && (v == 0 || v == 1)) t.tgemm_pers = v;
+    }
+    pos = end + 1;
+  }
 }
 
 static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const double* m0,
@@ -162,7 +194,13 @@ static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const d
 
   P.pb = *pb;
   P.stream = stream;
+  read_tune_env(P.tune);
   HIP_TRY(hipGetDevice(&P.device));
+  {
+    int ncu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P.device));
+    P.num_cus = ncu > 0 ? ncu : 256;
+  }
   P.precision = pb->precision;
   P.l = pb->l;
   P.gamma = pb->gamma;
@@ -238,6 +276,26 @@ static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const d
     Vt16[i] = (_Float16)Vt[i];
     Vtbf[i] = to_bf16((float)Vt[i]);
   }
+  if (nt <= 128) {
+    const int ntp = (nt + 15) / 16 * 16;
+    P.ntp = ntp;
+    std::vector<float> p32((size_t)ntp * ntp, 0.0f);
+    std::vector<_Float16> p16((size_t)ntp * ntp, (_Float16)0.0f);
+    std::vector<unsigned short> pbf((size_t)ntp * ntp, 0);
+    std::vector<double> p64((size_t)ntp * ntp, 0.0);
+    for (int k = 0; k < nt; ++k)
+      for (int t = 0; t < nt; ++t) {
+        const double v = Vm[(size_t)k * nt + t];
+        p64[(size_t)t * ntp + k] = v;
+        p32[(size_t)k * ntp + t] = (float)v;
+        p16[(size_t)k * ntp + t] = (_Float16)v;
+        pbf[(size_t)k * ntp + t] = to_bf16((float)v);
+      }
+    if ((rc = upload(P, &P.Vp64, p64)) || (rc = upload(P, &P.Vp32, p32)) ||
+        (rc = upload(P, &P.Vp16, p16)) ||
+        (rc = upload(P, &P.Vpbf, pbf)))
+      return rc;
+  }
   if ((rc = upload(P, &P.Vt64, Vt)) || (rc = upload(P, &P.Vt32, Vt32)) ||
       (rc = upload(P, &P.Vt16, Vt16)) || (rc = upload(P, &P.Vtbf, Vtbf)) ||
       (rc = upload(P, &P.lam_t, lt)))
@@ -276,6 +334,52 @@ static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const d
   P.host_scal = static_cast<double*>(hs);
   HIP_TRY(hipDeviceSynchronize());
   return MFG_OK;
+}
+
+static hipEvent_t pool_event(Plan& P) {
+  if (!P.prof.pool.empty()) {
+    hipEvent_t e = P.prof.pool.back();
+    P.prof.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Resolve pending event pairs into the per-kernel totals (synchronises).
+static void prof_flush(const Plan& Pc) {
+  Plan& P = const_cast<Plan&>(Pc);
+  if (P.prof.pending.empty()) return;
+  (void)hipStreamSynchronize(P.stream);
+  for (auto& r : P.prof.pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      auto& a = P.prof.acc[r.name];
+      a.first += 1;
+      a.second += ms;
+    }
+    P.prof.pool.push_back(r.a);
+    P.prof.pool.push_back(r.b);
+  }
+  P.prof.pending.clear();
+}
+
+int prof_begin(const Plan& Pc, const char* name, hipStream_t s) {
+  Plan& P = const_cast<Plan&>(Pc);
+  if (!P.prof.on) return -1;
+  if (P.prof.pending.size() >= 4096) prof_flush(P);
+  Profiler::Rec r{name, pool_event(P), pool_event(P)};
+  if (!r.a || !r.b) return -1;
+  (void)hipEventRecord(r.a, s);
+  P.prof.pending.push_back(r);
+  return (int)P.prof.pending.size() - 1;
+}
+
+void prof_end(const Plan& Pc, int id, hipStream_t s) {
+  Plan& P = const_cast<Plan&>(Pc);
+  if (id < 0 || id >= (int)P.prof.pending.size()) return;
+  (void)hipEventRecord(P.prof.pending[id].b, s);
 }
 
 static int read_scalars(Plan& P) {
@@ -476,6 +580,34 @@ int mfg_cp_solve(mfg_plan_t plan, mfg_state_t* st, int n_iter, double pcg_rtol, 
     st->iter += 1;
   }
   if (final_rc) return fail(final_rc, "some PCG solve reached maxit");
+  return MFG_OK;
+}
+
+int mfg_profile(mfg_plan_t plan, int enable) {
+  if (!plan) return fail(MFG_ERR_INVALID_ARG, "plan is NULL");
+  mfg::Plan& P = plan->P;
+  mfg::prof_flush(P);
+  if (enable) P.prof.acc.clear();
+  P.prof.on = enable != 0;
+  return MFG_OK;
+}
+
+int mfg_profile_report(mfg_plan_t plan, char* buf, int len) {
+  if (!plan || !buf || len < 3) return fail(MFG_ERR_INVALID_ARG, "bad arguments");
+  mfg::Plan& P = plan->P;
+  mfg::prof_flush(P);
+  std::string out = "{";
+  bool first = true;
+  char tmp[256];
+  for (auto& kv : P.prof.acc) {
+    std::snprintf(tmp, sizeof(tmp), "%s\"%s\": {\"calls\": %ld, \"total_ms\": %.6f}",
+                  first ? "" : ", ", kv.first.c_str(), kv.second.first, kv.second.second);
+    out += tmp;
+    first = false;
+  }
+  out += "}";
+  if ((int)out.size() + 1 > len) return fail(MFG_ERR_INVALID_ARG, "buffer too small");
+  std::memcpy(buf, out.c_str(), out.size() + 1);
   return MFG_OK;
 }
 

@@ -1,6 +1,7 @@
 // Host-side plan object behind mfg_plan_t.
 #pragma once
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -10,14 +11,42 @@ struct mfg_plan_s;
 
 namespace mfg {
 
+// Launch-shape choices of the kernels that have more than one (set by the
+// autotuner or the MFG_TUNE environment variable, "key=value,...").
+struct Tune {
+  int f64_cb = 1;    // time GEMM (float64): 16-node column blocks per wave
+  int lp_cb = 2;     // time GEMM (low precision): column blocks per wave
+  int rows_elems = 1024;  // row transforms: complex elements per block
+  int cols_lines = 4;     // column solves: complex lines (column pairs) per block
+  int aat_ti = 16;        // A kernel tile rows (d = 2)
+  int tgemm_pers = 0;     // persistent time GEMM (whole V in LDS) when N_t <= 128
+};
+
+// Optional per-kernel timing with HIP events recorded on the plan's stream
+// around each launch (enabled by mfg_profile). Event pairs are resolved when a
+// report is requested or when many are pending.
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::string, std::pair<long, double>> acc;  // name -> (calls, total ms)
+};
+
 struct Plan {
   mfg_problem_t pb{};
+  Tune tune{};
+  mutable Profiler prof;
   Geom g{};
   int precision = MFG_FP64;
   int l = 1;
   double gamma = 0.0;
   hipStream_t stream = nullptr;
   int device = 0;
+  int num_cus = 256;
 
   // problem data (plan-owned copies)
   double* V = nullptr;   // M
@@ -29,6 +58,13 @@ struct Plan {
   _Float16* Vt16 = nullptr;
   unsigned short* Vtbf = nullptr;
   double* lam_t = nullptr;  // N_t eigenvalues (eq. eigs)
+  // V zero-padded to ntp x ntp (ntp = N_t rounded up to 16, when N_t <= 128)
+  // for the low-precision kernels, which copy it to LDS with 16-byte loads
+  int ntp = 0;
+  double* Vp64 = nullptr;  // float64 copy: Vp64[t * ntp + k] = V[k][t]
+  float* Vp32 = nullptr;
+  _Float16* Vp16 = nullptr;
+  unsigned short* Vpbf = nullptr;
 
   // spatial transforms (Algorithm 2)
   Axis ax0{}, ax1{};
@@ -43,6 +79,18 @@ struct Plan {
 
   std::vector<void*> dev_allocs;
   std::vector<void*> host_allocs;
+};
+
+// Record the start / end of a launch for the profiler (no-op when disabled).
+int prof_begin(const Plan& P, const char* name, hipStream_t s);
+void prof_end(const Plan& P, int id, hipStream_t s);
+
+struct ProfScope {
+  const Plan& P;
+  hipStream_t s;
+  int id;
+  ProfScope(const Plan& p, const char* name, hipStream_t st) : P(p), s(st), id(prof_begin(p, name, st)) {}
+  ~ProfScope() { prof_end(P, id, s); }
 };
 
 }  // namespace mfg

@@ -26,6 +26,8 @@ struct C2 {
   T x, y;
 };
 
+constexpr int kLoadBatch = 8;  // global loads per thread issued before their LDS stores
+
 template <typename T>
 __device__ __forceinline__ const T* tw_table(const Axis& ax);
 template <>
@@ -48,9 +50,8 @@ __device__ __forceinline__ C2<T> cmul(C2<T> a, T c, T s) {
 // ping-pong partner). sign = -1 forward, +1 inverse (unnormalised). Returns the
 // buffer that holds the result. Must be called by the whole block.
 template <typename T>
-__device__ C2<T>* fft_lds(C2<T>* a, C2<T>* b, int nlines, const Axis& ax, int sign) {
+__device__ C2<T>* fft_lds(C2<T>* a, C2<T>* b, int nlines, const Axis& ax, const T* tw, int sign) {
   const int N = ax.N;
-  const T* tw = tw_table<T>(ax);
   const T sg = (T)sign;
   int Ns = 1;
   for (int ps = 0; ps < ax.npass; ++ps) {
@@ -125,9 +126,8 @@ __device__ __forceinline__ int dct_perm(int n, int N) {
 // DHT: H_a = (p + r - q + s)/2, H_b = (q + s + p - r)/2 with Z[k] = p + iq,
 // Z[N-k] = r + is.  DCT-II: C = Re(e^{-i pi k/(2N)} V[k]) of each line.
 template <typename T>
-__device__ void post_forward(const C2<T>* Z, C2<T>* out, int nlines, const Axis& ax) {
+__device__ void post_forward(const C2<T>* Z, C2<T>* out, int nlines, const Axis& ax, const T* ct) {
   const int N = ax.N;
-  const T* ct = ct_table<T>(ax);
   for (int idx = threadIdx.x; idx < nlines * N; idx += blockDim.x) {
     const int line = idx / N, k = idx - line * N;
     const int kr = (k == 0) ? 0 : N - k;
@@ -150,9 +150,9 @@ __device__ void post_forward(const C2<T>* Z, C2<T>* out, int nlines, const Axis&
 // Complex spectrum for the inverse DCT-II of two packed real spectra:
 // V[k] = e^{i pi k/(2N)} (C[k] - i C[N-k]) per line, Z = V_a + i V_b.
 template <typename T>
-__device__ void pre_inverse_dct(const C2<T>* Cin, C2<T>* Z, int nlines, const Axis& ax) {
+__device__ void pre_inverse_dct(const C2<T>* Cin, C2<T>* Z, int nlines, const Axis& ax,
+                                const T* ct) {
   const int N = ax.N;
-  const T* ct = ct_table<T>(ax);
   for (int idx = threadIdx.x; idx < nlines * N; idx += blockDim.x) {
     const int line = idx / N, k = idx - line * N;
     const C2<T> cur = Cin[line * N + k];
@@ -170,15 +170,31 @@ __device__ void pre_inverse_dct(const C2<T>* Cin, C2<T>* Z, int nlines, const Ax
 // returns the buffer with the (unnormalised, times N) spatial lines in natural
 // order for the DHT, or in Makhoul order for the DCT (caller applies dct_perm).
 template <typename T>
-__device__ C2<T>* inverse_real(C2<T>* buf, C2<T>* other, int nlines, const Axis& ax) {
+__device__ C2<T>* inverse_real(C2<T>* buf, C2<T>* other, int nlines, const Axis& ax,
+                               const T* tw, const T* ct) {
   if (ax.kind == 0) {
-    C2<T>* z = fft_lds<T>(buf, other, nlines, ax, -1);
+    C2<T>* z = fft_lds<T>(buf, other, nlines, ax, tw, -1);
     C2<T>* o = (z == buf) ? other : buf;
-    post_forward<T>(z, o, nlines, ax);
+    post_forward<T>(z, o, nlines, ax, ct);
     return o;
   }
-  pre_inverse_dct<T>(buf, other, nlines, ax);
-  return fft_lds<T>(other, buf, nlines, ax, +1);
+  pre_inverse_dct<T>(buf, other, nlines, ax, ct);
+  return fft_lds<T>(other, buf, nlines, ax, tw, +1);
+}
+
+// Copy the axis' twiddle (cos/sin 2 pi m/N) and DCT (cos/sin pi k/2N) tables
+// into LDS; returns pointers through tw and ct.
+template <typename T>
+__device__ void stage_tables(const Axis& ax, T* lds, const T*& tw, const T*& ct) {
+  const int N = ax.N;
+  const T* gtw = tw_table<T>(ax);
+  const T* gct = ct_table<T>(ax);
+  for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) {
+    lds[i] = gtw[i];
+    lds[2 * N + i] = gct[i];
+  }
+  tw = lds;
+  ct = lds + 2 * N;
 }
 
 struct SolveCtx {
@@ -202,28 +218,46 @@ __global__ __launch_bounds__(256) void k_rows(T* __restrict__ data, int nrows, A
   const int N = ax.N;
   C2<T>* A = reinterpret_cast<C2<T>*>(smem);
   C2<T>* B = A + lpb * N;
+  const T *tw, *ct;
+  stage_tables<T>(ax, reinterpret_cast<T*>(B + lpb * N), tw, ct);
   const int line0 = blockIdx.x * lpb;
   int nl = (nrows + 1) / 2 - line0;
   if (nl > lpb) nl = lpb;
   const bool dct = (ax.kind == 1);
-  // load
-  for (int idx = threadIdx.x; idx < nl * N; idx += blockDim.x) {
-    const int l = idx / N, n = idx - l * N;
-    const int ra = 2 * (line0 + l), rb = ra + 1;
-    const int src = (mode != 1 && dct) ? dct_perm(n, N) : n;
-    C2<T> v;
-    v.x = data[(size_t)ra * N + src];
-    v.y = (rb < nrows) ? data[(size_t)rb * N + src] : (T)0;
-    A[l * N + n] = v;
+  // load: batches of kLoadBatch elements per thread in flight before the LDS
+  // stores (blockDim.x == 256)
+  {
+    const int total = nl * N;
+    for (int base = 0; base < total; base += 256 * kLoadBatch) {
+      T va[kLoadBatch], vb[kLoadBatch];
+#pragma unroll
+      for (int e = 0; e < kLoadBatch; ++e) {
+        const int idx = base + threadIdx.x + 256 * e;
+        va[e] = (T)0;
+        vb[e] = (T)0;
+        if (idx < total) {
+          const int l = idx / N, n = idx - l * N;
+          const int ra = 2 * (line0 + l), rb = ra + 1;
+          const int src = (mode != 1 && dct) ? dct_perm(n, N) : n;
+          va[e] = data[(size_t)ra * N + src];
+          if (rb < nrows) vb[e] = data[(size_t)rb * N + src];
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < kLoadBatch; ++e) {
+        const int idx = base + threadIdx.x + 256 * e;
+        if (idx < total) A[idx] = C2<T>{va[e], vb[e]};
+      }
+    }
   }
   __syncthreads();
   C2<T>* res;
   if (mode == 1) {
-    res = inverse_real<T>(A, B, nl, ax);
+    res = inverse_real<T>(A, B, nl, ax, tw, ct);
   } else {
-    C2<T>* z = fft_lds<T>(A, B, nl, ax, -1);
+    C2<T>* z = fft_lds<T>(A, B, nl, ax, tw, -1);
     C2<T>* o = (z == A) ? B : A;
-    post_forward<T>(z, o, nl, ax);
+    post_forward<T>(z, o, nl, ax, ct);
     if (mode == 0) {
       res = o;
     } else {
@@ -240,7 +274,7 @@ __global__ __launch_bounds__(256) void k_rows(T* __restrict__ data, int nrows, A
         o[idx] = v;
       }
       __syncthreads();
-      res = inverse_real<T>(o, (o == A) ? B : A, nl, ax);
+      res = inverse_real<T>(o, (o == A) ? B : A, nl, ax, tw, ct);
     }
   }
   // store
@@ -265,31 +299,46 @@ __global__ __launch_bounds__(256) void k_cols_solve(T* __restrict__ data, Geom g
   const int nlines = cw / 2;
   C2<T>* A = reinterpret_cast<C2<T>*>(smem);
   C2<T>* B = A + nlines * N;
+  const T *tw, *ct;
+  stage_tables<T>(ax, reinterpret_cast<T*>(B + nlines * N), tw, ct);
   const int ncb = (g.n1 + cw - 1) / cw;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int t = blk / ncb;
   const int j0 = (blk - t * ncb) * cw;
   const bool dct = (ax.kind == 1);
   T* slice = data + (size_t)t * g.M;
-  for (int idx = threadIdx.x; idx < N * cw; idx += blockDim.x) {
-    const int i = idx / cw, jj = idx - i * cw;
-    const int j = j0 + jj;
-    const T v = (j < g.n1) ? slice[(size_t)i * g.n1 + j] : (T)0;
-    // position along the line: Makhoul order for the DCT
-    int n;
-    if (dct) {
-      // inverse of dct_perm: element i goes to position n with perm(n) = i
-      n = (i & 1) ? (N - 1 - (i >> 1)) : (i >> 1);
-    } else {
-      n = i;
+  {
+    const int total = N * cw;
+    for (int base = 0; base < total; base += 256 * kLoadBatch) {
+      T v[kLoadBatch];
+#pragma unroll
+      for (int e = 0; e < kLoadBatch; ++e) {
+        const int idx = base + threadIdx.x + 256 * e;
+        v[e] = (T)0;
+        if (idx < total) {
+          const int i = idx / cw, jj = idx - i * cw;
+          const int j = j0 + jj;
+          if (j < g.n1) v[e] = slice[(size_t)i * g.n1 + j];
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < kLoadBatch; ++e) {
+        const int idx = base + threadIdx.x + 256 * e;
+        if (idx < total) {
+          const int i = idx / cw, jj = idx - i * cw;
+          // position along the line: Makhoul order for the DCT (inverse of
+          // dct_perm: element i goes to position n with perm(n) = i)
+          const int n = dct ? ((i & 1) ? (N - 1 - (i >> 1)) : (i >> 1)) : i;
+          T* dst = reinterpret_cast<T*>(&A[(jj >> 1) * N + n]);
+          dst[jj & 1] = v[e];
+        }
+      }
     }
-    C2<T>& dst = A[(jj >> 1) * N + n];
-    if (jj & 1) dst.y = v; else dst.x = v;
   }
   __syncthreads();
-  C2<T>* z = fft_lds<T>(A, B, nlines, ax, -1);
+  C2<T>* z = fft_lds<T>(A, B, nlines, ax, tw, -1);
   C2<T>* o = (z == A) ? B : A;
-  post_forward<T>(z, o, nlines, ax);
+  post_forward<T>(z, o, nlines, ax, ct);
   const double lt = sc.lam_t[t];
   for (int idx = threadIdx.x; idx < nlines * N; idx += blockDim.x) {
     const int l = idx / N, k = idx - l * N;
@@ -303,7 +352,7 @@ __global__ __launch_bounds__(256) void k_cols_solve(T* __restrict__ data, Geom g
     o[idx] = v;
   }
   __syncthreads();
-  C2<T>* res = inverse_real<T>(o, (o == A) ? B : A, nlines, ax);
+  C2<T>* res = inverse_real<T>(o, (o == A) ? B : A, nlines, ax, tw, ct);
   for (int idx = threadIdx.x; idx < N * cw; idx += blockDim.x) {
     const int i = idx / cw, jj = idx - i * cw;
     const int j = j0 + jj;
@@ -333,31 +382,46 @@ void spatial_solves(const Plan& P, T* data, hipStream_t s) {
   const Geom& g = P.g;
   const SolveCtx sc = solve_ctx(P);
   const int N1 = g.n1;
-  int lpb = 1024 / N1;
+  int lpb = P.tune.rows_elems / N1;
   if (lpb < 1) lpb = 1;
-  if (lpb > 16) lpb = 16;
+  if (lpb > 32) lpb = 32;
   const int nrows = g.nt * g.n0;
   const int nlines = (nrows + 1) / 2;
+  if (lpb > nlines) lpb = nlines;
+  // keep dynamic LDS (two buffers + tables) within 64 KB
+  const int lpb_max = (int)((65536 - 4 * (size_t)N1 * sizeof(T)) / (2 * (size_t)N1 * sizeof(C2<T>)));
+  if (lpb > lpb_max) lpb = lpb_max;
+  if (lpb < 1) lpb = 1;
   const int rblocks = (nlines + lpb - 1) / lpb;
-  const size_t rshm = 2 * (size_t)lpb * N1 * sizeof(C2<T>);
+  // two complex buffers plus the twiddle and DCT tables
+  const size_t rshm = 2 * (size_t)lpb * N1 * sizeof(C2<T>) + 4 * (size_t)N1 * sizeof(T);
   if (!g.has0) {
+    ProfScope ps(P, "rows_solve", s);
     hipLaunchKernelGGL(k_rows<T>, dim3(rblocks), dim3(256), rshm, s, data, nrows, P.ax1, 2, lpb,
                        sc, 1);
     return;
   }
-  hipLaunchKernelGGL(k_rows<T>, dim3(rblocks), dim3(256), rshm, s, data, nrows, P.ax1, 0, lpb, sc,
-                     g.n0);
-  // columns per block: two real columns per complex line, LDS (two buffers)
-  // kept at or below 32 KB
-  int lines = (int)(32768 / (2 * (size_t)g.n0 * sizeof(C2<T>)));
-  const int maxl = (sizeof(T) == 8) ? 4 : 8;
-  if (lines > maxl) lines = maxl;
+  {
+    ProfScope ps(P, "rows_fwd", s);
+    hipLaunchKernelGGL(k_rows<T>, dim3(rblocks), dim3(256), rshm, s, data, nrows, P.ax1, 0, lpb,
+                       sc, g.n0);
+  }
+  // columns per block: two real columns per complex line; LDS (two buffers)
+  // kept at or below 64 KB
+  int lines = P.tune.cols_lines;
+  const int lmax =
+      (int)((65536 - 4 * (size_t)g.n0 * sizeof(T)) / (2 * (size_t)g.n0 * sizeof(C2<T>)));
+  if (lines > lmax) lines = lmax;
   if (lines < 1) lines = 1;
   const int cw = 2 * lines;
   const int ncb = (g.n1 + cw - 1) / cw;
-  const size_t cshm = 2 * (size_t)(cw / 2) * g.n0 * sizeof(C2<T>);
-  hipLaunchKernelGGL(k_cols_solve<T>, dim3(g.nt * ncb), dim3(256), cshm, s, data, g, P.ax0, cw,
-                     sc);
+  const size_t cshm = 2 * (size_t)lines * g.n0 * sizeof(C2<T>) + 4 * (size_t)g.n0 * sizeof(T);
+  {
+    ProfScope ps(P, "cols_solve", s);
+    hipLaunchKernelGGL(k_cols_solve<T>, dim3(g.nt * ncb), dim3(256), cshm, s, data, g, P.ax0, cw,
+                       sc);
+  }
+  ProfScope ps(P, "rows_inv", s);
   hipLaunchKernelGGL(k_rows<T>, dim3(rblocks), dim3(256), rshm, s, data, nrows, P.ax1, 1, lpb, sc,
                      g.n0);
 }
@@ -371,9 +435,9 @@ void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
     dotmode = (q == nullptr) ? DOT_INIT : (P.precision == MFG_FP64 ? DOT_STD : DOT_FLEX);
   if (P.precision == MFG_FP64) {
     double* tmp = P.tmp;
-    tgemm<double, double>(P, GM_F64, r, tmp, DOT_NONE, nullptr, nullptr, s);
+    tgemm<double, double>(P, GM_F64, r, tmp, DOT_NONE, nullptr, nullptr, s, "tgemm_f64_fwd");
     spatial_solves<double>(P, tmp, s);
-    tgemm<double, double>(P, GM_F64, tmp, z, dotmode, r, q, s);
+    tgemm<double, double>(P, GM_F64, tmp, z, dotmode, r, q, s, "tgemm_f64_inv");
     return;
   }
   // mixed: float32 intermediate and spatial solves; time transform in the
@@ -381,9 +445,13 @@ void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
   const int mode = P.precision == MFG_MIXED_FP32 ? GM_F32
                    : (P.precision == MFG_MIXED_FP16 ? GM_F16 : GM_BF16);
   float* tmp = reinterpret_cast<float*>(P.tmp);
-  tgemm<double, float>(P, mode, r, tmp, DOT_NONE, nullptr, nullptr, s);
+  static const char* fwd_names[4] = {"tgemm_f64_fwd", "tgemm_f32_fwd", "tgemm_f16_fwd",
+                                     "tgemm_bf16_fwd"};
+  static const char* inv_names[4] = {"tgemm_f64_inv", "tgemm_f32_inv", "tgemm_f16_inv",
+                                     "tgemm_bf16_inv"};
+  tgemm<double, float>(P, mode, r, tmp, DOT_NONE, nullptr, nullptr, s, fwd_names[mode]);
   spatial_solves<float>(P, tmp, s);
-  tgemm<float, double>(P, mode, tmp, z, dotmode, r, q, s);
+  tgemm<float, double>(P, mode, tmp, z, dotmode, r, q, s, inv_names[mode]);
 }
 
 }  // namespace mfg

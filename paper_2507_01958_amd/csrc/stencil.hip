@@ -175,34 +175,55 @@ __global__ __launch_bounds__(kThreads) void k_AAt_tile(Geom g, const double* __r
   const double beta = (FUSE && !first) ? rb.scal[S_BETA] : 0.0;
   const double c1 = 2.0 * g.nu * g.idt + 2.0, c2 = g.nu * g.idt, nu2 = g.nu * g.nu;
 
-  auto load_slot = [&](int t, double* dst) {
-    for (int idx = threadIdx.x; idx < C::SI * C::SJ; idx += blockDim.x) {
-      const int ii = idx / C::SJ - C::HI, jj = idx % C::SJ - 2;
-      double v = 0.0;
-      if (t >= 0 && t < g.nt) {
+  // Slot loads are split into issue (global loads into registers) and commit
+  // (combine, publish p_new, store to LDS), so the loads of slice t+2 are in
+  // flight while slice t is being computed.
+  constexpr int NS = C::SI * C::SJ;
+  constexpr int NPER = (NS + kThreads - 1) / kThreads;
+  double rz[NPER], rp[NPER];
+  auto issue = [&](int t) {
+#pragma unroll
+    for (int e = 0; e < NPER; ++e) {
+      const int idx = threadIdx.x + kThreads * e;
+      rz[e] = 0.0;
+      rp[e] = 0.0;
+      if (idx < NS && t >= 0 && t < g.nt) {
+        const int ii = idx / C::SJ - C::HI, jj = idx % C::SJ - 2;
         const int gi = HAS0 ? nbr(i0 + ii, g.n0, g.neumann) : 0;
         const int gj = nbr(j0 + jj, g.n1, g.neumann);
         const size_t o = (size_t)t * g.M + (size_t)gi * g.n1 + gj;
-        if (FUSE) {
-          v = first ? src[o] : src[o] + beta * pold[o];
-          if (t >= t_lo && t < t_hi && ii >= 0 && ii < C::TI && jj >= 0 && jj < kTJ &&
-              i0 + ii < g.n0 && j0 + jj < g.n1)
-            pnew[o] = v;
-        } else {
-          v = src[o];
-        }
+        rz[e] = src[o];
+        if (FUSE && !first) rp[e] = pold[o];
       }
-      dst[idx] = v;
+    }
+  };
+  auto commit = [&](int t, double* dst) {
+#pragma unroll
+    for (int e = 0; e < NPER; ++e) {
+      const int idx = threadIdx.x + kThreads * e;
+      if (idx < NS) {
+        const double v = FUSE ? rz[e] + beta * rp[e] : rz[e];
+        if (FUSE && t >= t_lo && t < t_hi) {
+          const int ii = idx / C::SJ - C::HI, jj = idx % C::SJ - 2;
+          if (ii >= 0 && ii < C::TI && jj >= 0 && jj < kTJ && i0 + ii < g.n0 && j0 + jj < g.n1)
+            pnew[(size_t)t * g.M + (size_t)(i0 + ii) * g.n1 + j0 + jj] = v;
+        }
+        dst[idx] = v;
+      }
     }
   };
 
   double acc = 0.0;
   int sp = 0, sc = 1, sn = 2;
-  load_slot(t_lo - 1, U[sp]);
-  load_slot(t_lo, U[sc]);
+  issue(t_lo - 1);
+  commit(t_lo - 1, U[sp]);
+  issue(t_lo);
+  commit(t_lo, U[sc]);
+  issue(t_lo + 1);
   for (int t = t_lo; t < t_hi; ++t) {
-    load_slot(t + 1, U[sn]);
+    commit(t + 1, U[sn]);
     __syncthreads();
+    if (t + 1 < t_hi) issue(t + 2);
     const double* Up = U[sp];
     const double* Uc = U[sc];
     const double* Un = U[sn];
@@ -325,10 +346,11 @@ __global__ __launch_bounds__(kThreads) void k_backproj_prox(Geom g, const double
   reduce_store<1>(acc, rb, T_DM);
 }
 
-int grid_for(long long n, int = 0) {
+// One thread per node up to `cap` blocks (grid-stride beyond that).
+int grid_for(long long n, int cap = kStreamGrid) {
   long long b = (n + kThreads - 1) / kThreads;
   if (b < 1) b = 1;
-  if (b > kStreamGrid) b = kStreamGrid;
+  if (b > cap) b = cap;
   return (int)b;
 }
 
@@ -351,8 +373,11 @@ void aat_launch(const Plan& P, const double* src, const double* pold, double* pn
   const int tc = aat_chunk(g, ntile, P.red.max_blocks);
   const int nchunk = (g.nt + tc - 1) / tc;
   const int grid = ntile * nchunk;
-  hipLaunchKernelGGL((k_AAt_tile<HAS0, FUSE>), dim3(grid), dim3(kThreads), 0, s, g, src, pold,
-                     pnew, q, P.red, tc, first ? 1 : 0, reduce ? 1 : 0);
+  {
+    ProfScope ps(P, FUSE ? "aat_fused" : "aat", s);
+    hipLaunchKernelGGL((k_AAt_tile<HAS0, FUSE>), dim3(grid), dim3(kThreads), 0, s, g, src, pold,
+                       pnew, q, P.red, tc, first ? 1 : 0, reduce ? 1 : 0);
+  }
   if (reduce) launch_finish(P, T_PQ, grid, OP_PQ, s);
 }
 
@@ -360,17 +385,20 @@ void aat_launch(const Plan& P, const double* src, const double* pold, double* pn
 
 void launch_rhs(const Plan& P, const double* xi, const double* ybar, double sigma,
                 const double* m0, double* b, hipStream_t s) {
-  hipLaunchKernelGGL(k_rhs<true>, dim3(grid_for(P.g.n, P.red.max_blocks)), dim3(kThreads), 0, s,
+  ProfScope ps(P, "rhs", s);
+  hipLaunchKernelGGL(k_rhs<true>, dim3(grid_for(P.g.n, 1 << 20)), dim3(kThreads), 0, s,
                      P.g, xi, ybar, sigma, m0, b);
 }
 
 void launch_apply_C(const Plan& P, const double* y, double* b, hipStream_t s) {
-  hipLaunchKernelGGL(k_rhs<false>, dim3(grid_for(P.g.n, P.red.max_blocks)), dim3(kThreads), 0, s,
+  ProfScope ps(P, "apply_C", s);
+  hipLaunchKernelGGL(k_rhs<false>, dim3(grid_for(P.g.n, 1 << 20)), dim3(kThreads), 0, s,
                      P.g, y, (const double*)nullptr, 0.0, (const double*)nullptr, b);
 }
 
 void launch_apply_CT(const Plan& P, const double* u, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_apply_CT, dim3(grid_for(P.g.n, P.red.max_blocks)), dim3(kThreads), 0, s,
+  ProfScope ps(P, "apply_CT", s);
+  hipLaunchKernelGGL(k_apply_CT, dim3(grid_for(P.g.n, 1 << 20)), dim3(kThreads), 0, s,
                      P.g, u, y);
 }
 
@@ -386,15 +414,19 @@ void launch_pdir_AAt(const Plan& P, const double* z, const double* pold, double*
 }
 
 void launch_prox(const Plan& P, const double* v, double tau, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_prox, dim3(grid_for(P.g.n, P.red.max_blocks)), dim3(kThreads), 0, s, P.g,
+  ProfScope ps(P, "prox", s);
+  hipLaunchKernelGGL(k_prox, dim3(grid_for(P.g.n, 1 << 20)), dim3(kThreads), 0, s, P.g,
                      v, (const double*)P.V, tau, y);
 }
 
 void launch_backproj_prox(const Plan& P, const double* u, double* xi, double* y, double* ybar,
                           double tau, double theta, hipStream_t s) {
-  const int grid = grid_for(P.g.n);
-  hipLaunchKernelGGL(k_backproj_prox, dim3(grid), dim3(kThreads), 0, s, P.g, u, xi, y, ybar,
-                     (const double*)P.V, tau, theta, P.red);
+  const int grid = grid_for(P.g.n, P.red.max_blocks);
+  {
+    ProfScope ps(P, "backproj_prox", s);
+    hipLaunchKernelGGL(k_backproj_prox, dim3(grid), dim3(kThreads), 0, s, P.g, u, xi, y, ybar,
+                       (const double*)P.V, tau, theta, P.red);
+  }
   launch_finish(P, T_DM, grid, OP_DM, s);
 }
 

@@ -20,8 +20,9 @@ inline int finish_op(int dotmode) {
 enum GemmMode { GM_F64 = 0, GM_F32 = 1, GM_F16 = 2, GM_BF16 = 3 };
 
 // X (float64 or float32) -> Y (float64 or float32).
+// `name` labels the launch for the profiler (a string literal).
 template <typename TX, typename TY>
 void tgemm(const Plan& P, int mode, const TX* X, TY* Y, int dotmode, const double* r,
-           const double* q, hipStream_t s);
+           const double* q, hipStream_t s, const char* name);
 
 }  // namespace mfg

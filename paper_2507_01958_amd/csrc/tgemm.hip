@@ -154,14 +154,6 @@ __global__ __launch_bounds__(256) void k_tgemm_lp(const typename LpTraits<MODE>:
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int kq = lane >> 4;
   const int col0 = (blockIdx.x * 4 + wave) * CB * 16 + (lane & 15);
-  // stage V (symmetric: row k read with unit stride in t)
-  for (int idx = threadIdx.x; idx < NTP * NTP; idx += 256) {
-    const int k = idx / NTP, t = idx - k * NTP;
-    VT v;
-    if (k < nt && t < nt) v = Vg[(size_t)k * nt + t];
-    else v = (VT)0;
-    Vs[idx] = v;
-  }
   // operands: t = KSTEP*ks + PER*kq + j
   float xs[CB][NKS][PER];
   float amax = 0.0f;
@@ -177,6 +169,25 @@ __global__ __launch_bounds__(256) void k_tgemm_lp(const typename LpTraits<MODE>:
         xs[cb][ks][j] = v;
         amax = fmaxf(amax, fabsf(v));
       }
+  }
+  // stage V (zero-padded NTP x NTP copy, row k = V[k][.]) after the operand
+  // loads are in flight: an unrolled 16-byte copy
+  {
+    constexpr int NV16 = NTP * NTP * (int)sizeof(VT) / 16;
+    constexpr int PERT = (NV16 + 255) / 256;
+    const uint4* src = reinterpret_cast<const uint4*>(Vg);
+    uint4* dst = reinterpret_cast<uint4*>(Vs);
+    uint4 tmp[PERT];
+#pragma unroll
+    for (int e = 0; e < PERT; ++e) {
+      const int i = threadIdx.x + 256 * e;
+      if (i < NV16) tmp[e] = src[i];
+    }
+#pragma unroll
+    for (int e = 0; e < PERT; ++e) {
+      const int i = threadIdx.x + 256 * e;
+      if (i < NV16) dst[i] = tmp[e];
+    }
   }
   float scale = 1.0f, unscale = 1.0f;
   if (MODE == GM_F16) {
@@ -266,28 +277,266 @@ __global__ __launch_bounds__(256) void k_tgemm_lp(const typename LpTraits<MODE>:
   if (dotmode != DOT_NONE) reduce_store<2>(dots, rb, T_RZ);
 }
 
+// Persistent form for N_t <= 128 (NTP = N_t rounded up to 16): each block
+// stages all of V in LDS once, then every wave independently streams 16-node
+// column tiles (tile c, c + #waves, ...), fetching the next tile's operands into
+// registers while it multiplies the current one. float16 operands are scaled
+// per wave tile (16 columns) by a power of two; the scaling is exact per column.
+// LDS layout: float64 Vs[t][k] (the f64 A operand is one k per lane); low
+// precision Vs[k][t] (four consecutive t per lane).
+template <int MODE>
+struct PersTraits;
+template <>
+struct PersTraits<GM_F64> {
+  using VT = double;
+  using XT = double;  // register type of a fetched operand
+  static constexpr int KSTEP = 4;
+};
+template <>
+struct PersTraits<GM_F32> {
+  using VT = float;
+  using XT = float;
+  static constexpr int KSTEP = 4;
+};
+template <>
+struct PersTraits<GM_F16> {
+  using VT = _Float16;
+  using XT = float;
+  static constexpr int KSTEP = 16;
+};
+template <>
+struct PersTraits<GM_BF16> {
+  using VT = unsigned short;
+  using XT = float;
+  static constexpr int KSTEP = 16;
+};
+
+template <int MODE, int NTP, int WAVES, typename TX, typename TY>
+__global__ __launch_bounds__(WAVES * 64) void k_tgemm_pers(const typename PersTraits<MODE>::VT* __restrict__ Vg,
+                                                    const TX* __restrict__ X, TY* __restrict__ Y,
+                                                    int nt, int M, int dotmode,
+                                                    const double* __restrict__ rvec,
+                                                    const double* __restrict__ qvec, RedBuf rb) {
+  using VT = typename PersTraits<MODE>::VT;
+  using XT = typename PersTraits<MODE>::XT;
+  constexpr int KSTEP = PersTraits<MODE>::KSTEP;
+  constexpr int PER = KSTEP / 4;
+  constexpr int NKS = NTP / KSTEP;
+  constexpr int NKB = NTP / 16;
+  constexpr int NX = NKS * PER;  // operand values per lane per tile
+  __shared__ __align__(16) VT Vs[NTP * NTP];
+  {
+    constexpr int NT = WAVES * 64;
+    constexpr int NV16 = NTP * NTP * (int)sizeof(VT) / 16;
+    const uint4* src = reinterpret_cast<const uint4*>(Vg);
+    uint4* dst = reinterpret_cast<uint4*>(Vs);
+    for (int base = 0; base < NV16; base += 8 * NT) {
+      uint4 tmp[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int i = base + threadIdx.x + NT * e;
+        if (i < NV16) tmp[e] = src[i];
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int i = base + threadIdx.x + NT * e;
+        if (i < NV16) dst[i] = tmp[e];
+      }
+    }
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int kq = lane >> 4, cl = lane & 15;
+  const int nw = gridDim.x * WAVES;
+  const int ncb = (M + 15) / 16;
+  XT xn[NX];
+  auto fetch = [&](int cb) {
+    const int col = cb * 16 + cl;
+    const bool cv = col < M;
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int t = KSTEP * ks + PER * kq + j;
+        xn[ks * PER + j] = (cv && t < nt) ? (XT)X[(size_t)t * M + col] : (XT)0;
+      }
+  };
+  double dots[2] = {0.0, 0.0};
+  int cb = blockIdx.x * WAVES + wave;
+  if (cb < ncb) fetch(cb);
+  for (; cb < ncb; cb += nw) {
+    XT xc[NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) xc[i] = xn[i];
+    if (cb + nw < ncb) fetch(cb + nw);
+    const int col = cb * 16 + cl;
+    if constexpr (MODE == GM_F64) {
+      v4d acc[NKB];
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) acc[kb] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+      for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb)
+          acc[kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[(4 * ks + kq) * NTP + kb * 16 + cl],
+                                                         xc[ks], acc[kb], 0, 0, 0);
+      if (col < M) {
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+          for (int jr = 0; jr < 4; ++jr) {
+            // f64 result layout: row (l / 16) + 4 jr
+            const int k = kb * 16 + kq + 4 * jr;
+            if (k < nt) {
+              const size_t o = (size_t)k * M + col;
+              const double v = acc[kb][jr];
+              Y[o] = (TY)v;
+              if (dotmode != DOT_NONE) {
+                dots[0] += rvec[o] * v;
+                if (dotmode == DOT_FLEX) dots[1] += qvec[o] * v;
+              }
+            }
+          }
+      }
+    } else {
+      float scale = 1.0f, unscale = 1.0f;
+      if constexpr (MODE == GM_F16) {
+        float amax = 0.0f;
+#pragma unroll
+        for (int i = 0; i < NX; ++i) amax = fmaxf(amax, fabsf(xc[i]));
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
+        if (amax > 0.0f && __builtin_isfinite(amax)) {
+          int e;
+          frexpf(amax, &e);
+          e = e < -100 ? -100 : e;
+          scale = ldexpf(1.0f, 14 - e);
+          unscale = ldexpf(1.0f, e - 14);
+        }
+      }
+      v4f acc[NKB];
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) acc[kb] = (v4f){0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+      for (int ks = 0; ks < NKS; ++ks) {
+        if constexpr (MODE == GM_F32) {
+#pragma unroll
+          for (int kb = 0; kb < NKB; ++kb)
+            acc[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                Vs[(kb * 16 + cl) * NTP + 4 * ks + kq], xc[ks], acc[kb], 0, 0, 0);
+        } else if constexpr (MODE == GM_F16) {
+          v4h b;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) b[j] = (_Float16)(xc[ks * 4 + j] * scale);
+#pragma unroll
+          for (int kb = 0; kb < NKB; ++kb) {
+            const v4h a = *reinterpret_cast<const v4h*>(&Vs[(kb * 16 + cl) * NTP + 16 * ks + 4 * kq]);
+            acc[kb] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc[kb], 0, 0, 0);
+          }
+        } else {
+          v4s b;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) b[j] = f2bf(xc[ks * 4 + j]);
+#pragma unroll
+          for (int kb = 0; kb < NKB; ++kb) {
+            const v4s a = *reinterpret_cast<const v4s*>(&Vs[(kb * 16 + cl) * NTP + 16 * ks + 4 * kq]);
+            acc[kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[kb], 0, 0, 0);
+          }
+        }
+      }
+      if (col < M) {
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+          for (int jr = 0; jr < 4; ++jr) {
+            // f32-accumulating result layout: row 4 (l / 16) + jr
+            const int k = kb * 16 + 4 * kq + jr;
+            if (k < nt) {
+              const size_t o = (size_t)k * M + col;
+              const double v = (double)(acc[kb][jr] * unscale);
+              Y[o] = (TY)v;
+              if (dotmode != DOT_NONE) {
+                dots[0] += rvec[o] * v;
+                if (dotmode == DOT_FLEX) dots[1] += qvec[o] * v;
+              }
+            }
+          }
+      }
+    }
+  }
+  if (dotmode != DOT_NONE) reduce_store<2>(dots, rb, T_RZ);
+}
+
 template <int MODE, int NTP, typename TX, typename TY>
-int lp_launch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r, const double* q,
-              hipStream_t s) {
-  constexpr int CB = 2;
+int pers_launch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r, const double* q,
+                hipStream_t s) {
+  using VT = typename PersTraits<MODE>::VT;
+  const int M = P.g.M;
+  const int ncb = (M + 15) / 16;
+  // float64: 4 waves (one per SIMD, the full register file each) and one
+  // block per CU (up to 128 KB of V in LDS); low precision: 8 waves, two
+  // blocks per CU
+  constexpr int WAVES = (MODE == GM_F64) ? 4 : 8;
+  const int per_cu = (MODE == GM_F64) ? 1 : 2;
+  int grid = P.num_cus * per_cu;
+  const int need = (ncb + WAVES - 1) / WAVES;
+  if (grid > need) grid = need;
+  if (grid < 1) grid = 1;
+  const void* V = (MODE == GM_F64) ? (const void*)P.Vp64
+                  : (MODE == GM_F32) ? (const void*)P.Vp32
+                  : (MODE == GM_F16) ? (const void*)P.Vp16 : (const void*)P.Vpbf;
+  hipLaunchKernelGGL((k_tgemm_pers<MODE, NTP, WAVES, TX, TY>), dim3(grid), dim3(WAVES * 64), 0, s,
+                     (const VT*)V, X, Y, P.g.nt, M, dotmode, r, q, P.red);
+  return grid;
+}
+
+template <int MODE, typename TX, typename TY>
+int pers_dispatch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r,
+                  const double* q, hipStream_t s) {
+  switch (P.ntp) {
+    case 16: return pers_launch<MODE, 16>(P, X, Y, dotmode, r, q, s);
+    case 32: return pers_launch<MODE, 32>(P, X, Y, dotmode, r, q, s);
+    case 48: return pers_launch<MODE, 48>(P, X, Y, dotmode, r, q, s);
+    case 64: return pers_launch<MODE, 64>(P, X, Y, dotmode, r, q, s);
+    case 80: return pers_launch<MODE, 80>(P, X, Y, dotmode, r, q, s);
+    case 96: return pers_launch<MODE, 96>(P, X, Y, dotmode, r, q, s);
+    case 112: return pers_launch<MODE, 112>(P, X, Y, dotmode, r, q, s);
+    default: return pers_launch<MODE, 128>(P, X, Y, dotmode, r, q, s);
+  }
+}
+
+template <int MODE, int NTP, int CB, typename TX, typename TY>
+int lp_launch_cb(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r, const double* q,
+                 hipStream_t s) {
   const int M = P.g.M;
   const int grid = (M + 64 * CB - 1) / (64 * CB);
-  const void* V = (MODE == GM_F32) ? (const void*)P.Vt32
-                  : (MODE == GM_F16) ? (const void*)P.Vt16 : (const void*)P.Vtbf;
+  const void* V = (MODE == GM_F32) ? (const void*)P.Vp32
+                  : (MODE == GM_F16) ? (const void*)P.Vp16 : (const void*)P.Vpbf;
   hipLaunchKernelGGL((k_tgemm_lp<MODE, NTP, CB, TX, TY>), dim3(grid), dim3(256), 0, s,
                      (const typename LpTraits<MODE>::VT*)V, X, Y, P.g.nt, M, dotmode, r, q, P.red);
   return grid;
 }
 
+template <int MODE, int NTP, typename TX, typename TY>
+int lp_launch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r, const double* q,
+              hipStream_t s) {
+  if (P.tune.lp_cb == 1) return lp_launch_cb<MODE, NTP, 1>(P, X, Y, dotmode, r, q, s);
+  return lp_launch_cb<MODE, NTP, 2>(P, X, Y, dotmode, r, q, s);
+}
+
 template <int MODE, typename TX, typename TY>
 int lp_dispatch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r, const double* q,
                 hipStream_t s) {
-  const int nt = P.g.nt;
-  if (nt <= 16) return lp_launch<MODE, 16>(P, X, Y, dotmode, r, q, s);
-  if (nt <= 32) return lp_launch<MODE, 32>(P, X, Y, dotmode, r, q, s);
-  if (nt <= 64) return lp_launch<MODE, 64>(P, X, Y, dotmode, r, q, s);
-  if (nt <= 96) return lp_launch<MODE, 96>(P, X, Y, dotmode, r, q, s);
-  return lp_launch<MODE, 128>(P, X, Y, dotmode, r, q, s);
+  switch (P.ntp) {
+    case 16: return lp_launch<MODE, 16>(P, X, Y, dotmode, r, q, s);
+    case 32: return lp_launch<MODE, 32>(P, X, Y, dotmode, r, q, s);
+    case 48: return lp_launch<MODE, 48>(P, X, Y, dotmode, r, q, s);
+    case 64: return lp_launch<MODE, 64>(P, X, Y, dotmode, r, q, s);
+    case 80: return lp_launch<MODE, 80>(P, X, Y, dotmode, r, q, s);
+    case 96: return lp_launch<MODE, 96>(P, X, Y, dotmode, r, q, s);
+    case 112: return lp_launch<MODE, 112>(P, X, Y, dotmode, r, q, s);
+    default: return lp_launch<MODE, 128>(P, X, Y, dotmode, r, q, s);
+  }
 }
 
 template <int KB, int CB, typename TX, typename TY>
@@ -302,32 +551,50 @@ int f64_launch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r, 
   return grid;
 }
 
+
+template <typename TX, typename TY>
+int tgemm_launch(const Plan& P, int mode, const TX* X, TY* Y, int dotmode, const double* r,
+                 const double* q, hipStream_t s) {
+  const int nt = P.g.nt;
+  if (P.ntp > 0 && P.tune.tgemm_pers) {
+    if (mode == GM_F64) return pers_dispatch<GM_F64>(P, X, Y, dotmode, r, q, s);
+    if (mode == GM_F32) return pers_dispatch<GM_F32>(P, X, Y, dotmode, r, q, s);
+    if (mode == GM_F16) return pers_dispatch<GM_F16>(P, X, Y, dotmode, r, q, s);
+    return pers_dispatch<GM_BF16>(P, X, Y, dotmode, r, q, s);
+  }
+  if (mode != GM_F64 && P.ntp > 0) {
+    if (mode == GM_F32) return lp_dispatch<GM_F32>(P, X, Y, dotmode, r, q, s);
+    if (mode == GM_F16) return lp_dispatch<GM_F16>(P, X, Y, dotmode, r, q, s);
+    return lp_dispatch<GM_BF16>(P, X, Y, dotmode, r, q, s);
+  }
+  if (P.tune.f64_cb == 1) {
+    if (nt <= 32) return f64_launch<2, 1>(P, X, Y, dotmode, r, q, s);
+    if (nt <= 64) return f64_launch<4, 1>(P, X, Y, dotmode, r, q, s);
+    return f64_launch<8, 1>(P, X, Y, dotmode, r, q, s);
+  }
+  if (nt <= 32) return f64_launch<2, 2>(P, X, Y, dotmode, r, q, s);
+  if (nt <= 64) return f64_launch<4, 2>(P, X, Y, dotmode, r, q, s);
+  return f64_launch<8, 2>(P, X, Y, dotmode, r, q, s);
+}
+
 }  // namespace
 
 template <typename TX, typename TY>
 void tgemm(const Plan& P, int mode, const TX* X, TY* Y, int dotmode, const double* r,
-           const double* q, hipStream_t s) {
-  const int nt = P.g.nt;
+           const double* q, hipStream_t s, const char* name) {
   int grid;
-  if (mode != GM_F64 && nt <= 128) {
-    if (mode == GM_F32) grid = lp_dispatch<GM_F32>(P, X, Y, dotmode, r, q, s);
-    else if (mode == GM_F16) grid = lp_dispatch<GM_F16>(P, X, Y, dotmode, r, q, s);
-    else grid = lp_dispatch<GM_BF16>(P, X, Y, dotmode, r, q, s);
-  } else if (nt <= 32) {
-    grid = f64_launch<2, 2>(P, X, Y, dotmode, r, q, s);
-  } else if (nt <= 64) {
-    grid = f64_launch<4, 2>(P, X, Y, dotmode, r, q, s);
-  } else {
-    grid = f64_launch<8, 2>(P, X, Y, dotmode, r, q, s);
+  {
+    ProfScope ps(P, name, s);
+    grid = tgemm_launch(P, mode, X, Y, dotmode, r, q, s);
   }
   if (dotmode != DOT_NONE) launch_finish(P, T_RZ, grid, finish_op(dotmode), s);
 }
 
-template void tgemm<double, double>(const Plan&, int, const double*, double*, int, const double*,
-                                    const double*, hipStream_t);
-template void tgemm<double, float>(const Plan&, int, const double*, float*, int, const double*,
-                                   const double*, hipStream_t);
-template void tgemm<float, double>(const Plan&, int, const float*, double*, int, const double*,
-                                   const double*, hipStream_t);
+template void tgemm<double, double>(const Plan&, int, const double*, double*, int,
+                                    const double*, const double*, hipStream_t, const char*);
+template void tgemm<double, float>(const Plan&, int, const double*, float*, int,
+                                    const double*, const double*, hipStream_t, const char*);
+template void tgemm<float, double>(const Plan&, int, const float*, double*, int,
+                                    const double*, const double*, hipStream_t, const char*);
 
 }  // namespace mfg

@@ -160,6 +160,7 @@ __global__ __launch_bounds__(kThreads) void k_cp_init(Geom g, const double* __re
 }  // namespace
 
 void launch_finish(const Plan& P, int site, int nblocks, int op, hipStream_t s) {
+  ProfScope ps(P, "finish", s);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, P.red, site, nblocks, op);
 }
 
@@ -167,20 +168,29 @@ void launch_pcg_init(const Plan& P, const double* b, double* x, double* r, doubl
                      hipStream_t s) {
   hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, P.red.scal, rtol * rtol);
   const int grid = grid_for(P.g.n);
-  hipLaunchKernelGGL(k_pcg_init, dim3(grid), dim3(kThreads), 0, s, P.g.n, b, x, r, P.red);
+  {
+    ProfScope ps(P, "pcg_init", s);
+    hipLaunchKernelGGL(k_pcg_init, dim3(grid), dim3(kThreads), 0, s, P.g.n, b, x, r, P.red);
+  }
   launch_finish(P, T_BB, grid, OP_BB, s);
 }
 
 void launch_update(const Plan& P, double* x, double* r, const double* p, const double* q,
                    hipStream_t s) {
   const int grid = grid_for(P.g.n);
-  hipLaunchKernelGGL(k_update, dim3(grid), dim3(kThreads), 0, s, P.g.n, x, r, p, q, P.red);
+  {
+    ProfScope ps(P, "update", s);
+    hipLaunchKernelGGL(k_update, dim3(grid), dim3(kThreads), 0, s, P.g.n, x, r, p, q, P.red);
+  }
   launch_finish(P, T_RR, grid, OP_RR, s);
 }
 
 void launch_residual(const Plan& P, const double* b, const double* Ax, hipStream_t s) {
   const int grid = grid_for(P.g.n);
-  hipLaunchKernelGGL(k_residual, dim3(grid), dim3(kThreads), 0, s, P.g.n, b, Ax, P.red);
+  {
+    ProfScope ps(P, "residual", s);
+    hipLaunchKernelGGL(k_residual, dim3(grid), dim3(kThreads), 0, s, P.g.n, b, Ax, P.red);
+  }
   launch_finish(P, T_AUX, grid, OP_AUX, s);
 }
 
@@ -189,6 +199,7 @@ void launch_fill(double* x, long long n, double v, hipStream_t s) {
 }
 
 void launch_cp_init(const Plan& P, double* xi, double* y, double* ybar, hipStream_t s) {
+  ProfScope ps(P, "cp_init", s);
   hipLaunchKernelGGL(k_cp_init, dim3(grid_for(P.g.n * (1 + P.g.ncomp))), dim3(kThreads), 0, s,
                      P.g, (const double*)P.m0, xi, y, ybar);
 }

@@ -59,6 +59,8 @@ SIGNATURES = {
                         POINTER(c_double)]),
     "mfg_cp_init": (c_int, [c_void_p, POINTER(State)]),
     "mfg_cp_solve": (c_int, [c_void_p, POINTER(State), c_int, c_double, c_int, POINTER(Stats)]),
+    "mfg_profile": (c_int, [c_void_p, c_int]),
+    "mfg_profile_report": (c_int, [c_void_p, ctypes.c_char_p, c_int]),
     "mfg_last_error": (c_char_p, []),
     "mfg_version": (c_char_p, []),
 }
@@ -274,6 +276,17 @@ def mfg_cp_solve(plan: Plan, st: CPState, n_iter: int, pcg_rtol: float, pcg_maxi
         out = dict(pcg_iters=list(its), pcg_relres=list(rel), dm=list(dm))
     out["status"] = rc
     return out
+
+
+def mfg_profile(plan: Plan, enable: bool):
+    _check(load().mfg_profile(plan.handle, 1 if enable else 0))
+
+
+def mfg_profile_report(plan: Plan) -> dict:
+    import json
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(load().mfg_profile_report(plan.handle, buf, len(buf)))
+    return json.loads(buf.value.decode())
 
 
 def mfg_last_error() -> str:

@@ -1,0 +1,176 @@
+"""Summaries of rocprofv3 databases for the library's kernels.
+
+  python -m paper_2507_01958_amd.profiling stats DB --cmd "..." --out FILE.md
+      per-kernel calls / average / total time from a --kernel-trace --stats run
+  python -m paper_2507_01958_amd.profiling traffic --variant V --fetch DB --write DB \
+         --cal-fetch DB --cal-write DB --out FILE.json [--merge]
+      HBM bytes per launch from FETCH_SIZE / WRITE_SIZE passes, each scaled by
+      what the same counter reads for a plain device copy of known size
+
+Kernels are reported under the names the library's own profiler uses
+(tgemm_f64_fwd, aat_fused, cols_solve, ...): a dispatch of a template kernel
+is classified by its template arguments and, where one kernel serves two
+roles (the float64 time GEMM, the row transforms), by its neighbours in the
+dispatch order.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import json
+import os
+import re
+import sqlite3
+import sys
+
+MODES = {"0": "f64", "1": "f32", "2": "f16", "3": "bf16"}
+
+
+def _short(name: str) -> str:
+    m = re.match(r"(?:void )?mfg::\(anonymous namespace\)::([^(]+)", name)
+    return m.group(1).strip() if m else name
+
+
+def classify(seq):
+    """Map an ordered list of raw kernel names to logical names."""
+    shorts = [_short(n) for n in seq]
+    out = []
+    for i, s in enumerate(shorts):
+        prev = shorts[i - 1] if i else ""
+        nxt = shorts[i + 1] if i + 1 < len(shorts) else ""
+        if s.startswith("k_AAt_tile"):
+            out.append("aat_fused" if s.endswith("true>") else "aat")
+        elif s.startswith("k_rhs"):
+            out.append("rhs" if "<true>" in s else "apply_C")
+        elif s.startswith(("k_tgemm64", "k_tgemm_lp", "k_tgemm_pers")):
+            args = s[s.index("<") + 1:-1].split(",")
+            args = [a.strip() for a in args]
+            mode = "f64" if s.startswith("k_tgemm64") else MODES.get(args[0], "f64")
+            tx, ty = args[-2], args[-1]
+            if tx == "double" and ty == "float":
+                d = "fwd"
+            elif tx == "float" and ty == "double":
+                d = "inv"
+            else:
+                d = "inv" if prev.startswith(("k_rows", "k_cols_solve")) else "fwd"
+            out.append(f"tgemm_{mode}_{d}")
+        elif s.startswith("k_rows"):
+            if nxt.startswith("k_cols_solve"):
+                out.append("rows_fwd")
+            elif prev.startswith("k_cols_solve"):
+                out.append("rows_inv")
+            else:
+                out.append("rows_solve")
+        elif s.startswith("k_"):
+            out.append(s[2:].split("<")[0])
+        else:
+            out.append(s[:60])
+    return out
+
+
+def _dispatches(db, counter=None):
+    con = sqlite3.connect(db)
+    if counter is None:
+        rows = con.execute("select name, start, end from kernels order by start").fetchall()
+        return [(n, (e - s) / 1e3) for n, s, e in rows]
+    rows = con.execute("select name, counter_value, start from pmc_events where counter_name=? "
+                       "order by start", (counter,)).fetchall()
+    return [(n, v) for n, v, _ in rows]
+
+
+def kernel_stats(db):
+    d = _dispatches(db)
+    names = classify([n for n, _ in d])
+    acc = collections.OrderedDict()
+    for name, (_, us) in zip(names, d):
+        a = acc.setdefault(name, [0, 0.0])
+        a[0] += 1
+        a[1] += us
+    return {k: {"calls": c, "avg_us": t / c, "total_ms": t / 1e3} for k, (c, t) in acc.items()}
+
+
+def counter_per_launch(db, counter):
+    d = _dispatches(db, counter)
+    names = classify([n for n, _ in d])
+    acc = collections.defaultdict(list)
+    for name, (_, v) in zip(names, d):
+        acc[name].append(v)
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def copy_kib(db, counter):
+    """Largest reading of `counter` (KiB) over the calibration copy dispatches."""
+    d = _dispatches(db, counter)
+    vals = [v for n, v in d if "copyBuffer" in n or "copy" in n.lower()]
+    return max(vals)
+
+
+def cmd_stats(args):
+    st = kernel_stats(args.db)
+    tot = sum(v["total_ms"] for v in st.values())
+    lines = [f"# Kernel trace: {args.title}", "", "Command:", "", "```", args.cmd, "```", "",
+             "| kernel | calls | avg us | total ms | share |", "|---|---:|---:|---:|---:|"]
+    for k, v in sorted(st.items(), key=lambda kv: -kv[1]["total_ms"]):
+        lines.append(f"| {k} | {v['calls']} | {v['avg_us']:.1f} | {v['total_ms']:.2f} | "
+                     f"{100 * v['total_ms'] / tot:.1f}% |")
+    text = "\n".join(lines) + "\n"
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text)
+
+
+def cmd_traffic(args):
+    # the copy moves 512 MiB each way (bench.py --calibrate-copy)
+    true_kib = 512 * 1024
+    kf = true_kib / copy_kib(args.cal_fetch, "FETCH_SIZE")
+    kw = true_kib / copy_kib(args.cal_write, "WRITE_SIZE")
+    fr = counter_per_launch(args.fetch, "FETCH_SIZE")
+    wr = counter_per_launch(args.write, "WRITE_SIZE")
+    kernels = {}
+    for k in sorted(set(fr) | set(wr)):
+        r = kf * fr.get(k, 0.0) * 1024
+        w = kw * wr.get(k, 0.0) * 1024
+        kernels[k] = {"read_bytes": r, "write_bytes": w, "bytes_per_launch": r + w}
+    data = {}
+    if args.merge and os.path.exists(args.out):
+        with open(args.out) as f:
+            data = json.load(f)
+    from bench import kernel_sources_hash  # noqa: E402  (same hash as bench.py)
+    h = kernel_sources_hash()
+    if data.get("sources_hash") != h:
+        data = {"sources_hash": h, "variants": {}}
+    data["scale"] = {"fetch": kf, "write": kw}
+    data["variants"][args.variant] = kernels
+    with open(args.out, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    print(json.dumps(kernels, indent=1))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd_name", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("db")
+    a.add_argument("--cmd", required=True)
+    a.add_argument("--title", default="")
+    a.add_argument("--out")
+    b = sub.add_parser("traffic")
+    b.add_argument("--variant", required=True)
+    b.add_argument("--fetch", required=True)
+    b.add_argument("--write", required=True)
+    b.add_argument("--cal-fetch", required=True)
+    b.add_argument("--cal-write", required=True)
+    b.add_argument("--out", required=True)
+    b.add_argument("--merge", action="store_true")
+    args = ap.parse_args(argv)
+    if args.cmd_name == "stats":
+        cmd_stats(args)
+    else:
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        sys.path.insert(0, root)
+        cmd_traffic(args)
+
+
+if __name__ == "__main__":
+    main()
