@@ -179,6 +179,23 @@ int mfg_cp_init(mfg_plan_t plan, mfg_state_t* st);
 int mfg_cp_solve(mfg_plan_t plan, mfg_state_t* st, int n_iter, double pcg_rtol,
                  int pcg_maxit, mfg_stats_t* stats);
 
+/* Reverse-mode gradient through n_iter Chambolle-Pock iterations started at
+ * mfg_cp_init: given gy = dJ/dy_N (device primal vector) for a scalar J of the
+ * final primal iterate, writes dJ/dm0 and dJ/dV (device, M values each).
+ * The iteration (eq. pasosChamPock with the Section 5 schedule, the prox of
+ * Section 3 through its implicit-function derivative, the projection eq. CC*)
+ * is differentiated exactly; each reverse step needs one solve with the
+ * symmetric matrix of eq. largeA, done by the same PCG (pcg_rtol, pcg_maxit;
+ * use the forward run's values, so the recomputed forward steps reproduce it).
+ * ckpts[k] must hold the state after k*every iterations (ckpts[0] is the
+ * initial point, as after mfg_cp_init), n_ckpt*every >= n_iter; the
+ * checkpoints are read, not modified. Allocates (every + 6) primal vectors of
+ * workspace for the call. MFG_ERR_NOT_CONVERGED if some solve reached maxit
+ * (outputs still written). */
+int mfg_cp_adjoint(mfg_plan_t plan, const mfg_state_t* ckpts, int n_ckpt, int every, int n_iter,
+                   const double* gy, double pcg_rtol, int pcg_maxit, double* g_m0,
+                   double* g_V);
+
 /* Per-kernel timing: enable != 0 starts recording a HIP event pair on the
  * plan's stream around every kernel launch of the plan (totals reset); 0
  * stops. Recording adds host work per launch but does not change what the

@@ -5,6 +5,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <utility>
 #include <string>
 #include <vector>
@@ -438,6 +439,107 @@ static int run_pcg(Plan& P, const double* b, double* x, double rtol, int maxit, 
   return MFG_OK;
 }
 
+// One Chambolle-Pock iteration (eq. pasosChamPock, Section 5 schedule) on the
+// state; vout (optional) receives the prox input v = y - tau xi'.
+static int cp_step(Plan& P, mfg_state_t* st, double rtol, int maxit, int* its, double* rel,
+                   double* vout) {
+  hipStream_t s = P.stream;
+  launch_rhs(P, st->xi, st->ybar, st->sigma, P.m0, P.b, s);
+  int rc = run_pcg(P, P.b, P.u, rtol, maxit, its, rel, nullptr);
+  if (rc && rc != MFG_ERR_NOT_CONVERGED) return rc;
+  const double theta = 1.0 / std::sqrt(1.0 + 2.0 * P.gamma * st->tau);
+  launch_backproj_prox(P, P.u, st->xi, st->y, st->ybar, st->tau, theta, s, vout);
+  HIP_TRY(hipGetLastError());
+  st->tau *= theta;
+  st->sigma /= theta;
+  st->theta = theta;
+  st->iter += 1;
+  return rc;
+}
+
+// Reverse sweep with recomputation from checkpoints (see adjoint.hip).
+static int run_cp_adjoint(Plan& P, const mfg_state_t* ckpts, int every, int n_iter,
+                          const double* gy_final, double rtol, int maxit, double* g_m0,
+                          double* g_V) {
+  hipStream_t s = P.stream;
+  const long long n = P.g.n;
+  const long long np = n * (1 + P.g.ncomp);
+  const int M = P.g.M;
+  std::vector<void*> mine;
+  auto alloc = [&](double** ptr, long long count) -> int {
+    void* p = nullptr;
+    if (hipMalloc(&p, (size_t)count * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MFG_ERR_OOM, "adjoint workspace allocation failed");
+    }
+    mine.push_back(p);
+    *ptr = static_cast<double*>(p);
+    return MFG_OK;
+  };
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(s);
+    for (void* p : mine) (void)hipFree(p);
+  };
+  double *tape, *sx, *sy, *sb, *gxi, *gy, *gyb, *gVc, *gb;
+  int rc;
+  if ((rc = alloc(&tape, (long long)every * np)) || (rc = alloc(&sx, np)) ||
+      (rc = alloc(&sy, np)) || (rc = alloc(&sb, np)) || (rc = alloc(&gxi, np)) ||
+      (rc = alloc(&gy, np)) || (rc = alloc(&gyb, np)) || (rc = alloc(&gVc, n)) ||
+      (rc = alloc(&gb, n))) {
+    cleanup();
+    return rc;
+  }
+  launch_fill(gxi, np, 0.0, s);
+  launch_fill(gyb, np, 0.0, s);
+  launch_fill(g_m0, M, 0.0, s);
+  launch_fill(g_V, M, 0.0, s);
+  HIP_TRY(hipMemcpyAsync(gy, gy_final, np * sizeof(double), hipMemcpyDeviceToDevice, s));
+  const int nseg = (n_iter + every - 1) / every;
+  std::vector<double> sig(every), ta(every), th(every);
+  int final_rc = MFG_OK;
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int cnt = std::min(every, n_iter - seg * every);
+    // recompute the segment's forward steps from its checkpoint, taping v
+    mfg_state_t st = ckpts[seg];
+    HIP_TRY(hipMemcpyAsync(sx, st.xi, np * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(sy, st.y, np * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(sb, st.ybar, np * sizeof(double), hipMemcpyDeviceToDevice, s));
+    st.xi = sx;
+    st.y = sy;
+    st.ybar = sb;
+    for (int j = 0; j < cnt; ++j) {
+      sig[j] = st.sigma;
+      ta[j] = st.tau;
+      int its;
+      double rel;
+      rc = cp_step(P, &st, rtol, maxit, &its, &rel, tape + (size_t)j * np);
+      if (rc == MFG_ERR_NOT_CONVERGED) final_rc = rc;
+      else if (rc) { cleanup(); return rc; }
+      th[j] = st.theta;
+    }
+    // reverse steps of the segment
+    for (int j = cnt - 1; j >= 0; --j) {
+      launch_adj_prox(P, gy, gyb, tape + (size_t)j * np, ta[j], th[j], gxi, gVc, s);
+      launch_sum_slices(P, gVc, nullptr, g_V, s);
+      launch_apply_C(P, gxi, P.b, s);
+      int its;
+      double rel;
+      rc = run_pcg(P, P.b, gb, rtol, maxit, &its, &rel, nullptr);
+      if (rc == MFG_ERR_NOT_CONVERGED) final_rc = rc;
+      else if (rc) { cleanup(); return rc; }
+      launch_apply_CT(P, gb, gxi, s);
+      launch_axpby(np, sig[j], gxi, 0.0, gyb, s);
+      launch_axpby(M, -sig[j] * P.g.idt, gb, 1.0, g_m0, s);
+    }
+  }
+  // initial point: y_0 = ybar_0 = (m0 at every slice, w = 0)
+  launch_sum_slices(P, gy, gyb, g_m0, s);
+  HIP_TRY(hipGetLastError());
+  cleanup();
+  if (final_rc) return fail(final_rc, "some PCG solve reached maxit");
+  return MFG_OK;
+}
+
 }  // namespace mfg
 
 using mfg::fail;
@@ -553,18 +655,13 @@ int mfg_cp_solve(mfg_plan_t plan, mfg_state_t* st, int n_iter, double pcg_rtol, 
     return fail(MFG_ERR_INVALID_ARG, "bad iteration arguments");
   if (!(st->sigma > 0.0) || !(st->tau > 0.0)) return fail(MFG_ERR_INVALID_ARG, "bad step sizes");
   mfg::Plan& P = plan->P;
-  hipStream_t s = P.stream;
   int final_rc = MFG_OK;
   for (int it = 0; it < n_iter; ++it) {
-    mfg::launch_rhs(P, st->xi, st->ybar, st->sigma, P.m0, P.b, s);
     int its = 0;
     double rel = 0.0;
-    int rc = mfg::run_pcg(P, P.b, P.u, pcg_rtol, pcg_maxit, &its, &rel, nullptr);
+    int rc = mfg::cp_step(P, st, pcg_rtol, pcg_maxit, &its, &rel, nullptr);
     if (rc == MFG_ERR_NOT_CONVERGED) final_rc = rc;
     else if (rc) return rc;
-    const double theta = 1.0 / std::sqrt(1.0 + 2.0 * P.gamma * st->tau);
-    mfg::launch_backproj_prox(P, P.u, st->xi, st->y, st->ybar, st->tau, theta, s);
-    HIP_TRY(hipGetLastError());
     if (stats) {
       if (stats->pcg_iters) stats->pcg_iters[it] = its;
       if (stats->pcg_relres) stats->pcg_relres[it] = rel;
@@ -574,13 +671,24 @@ int mfg_cp_solve(mfg_plan_t plan, mfg_state_t* st, int n_iter, double pcg_rtol, 
         stats->dm[it] = std::sqrt(P.host_scal[mfg::S_DM]);
       }
     }
-    st->tau *= theta;
-    st->sigma /= theta;
-    st->theta = theta;
-    st->iter += 1;
   }
   if (final_rc) return fail(final_rc, "some PCG solve reached maxit");
   return MFG_OK;
+}
+
+int mfg_cp_adjoint(mfg_plan_t plan, const mfg_state_t* ckpts, int n_ckpt, int every, int n_iter,
+                   const double* gy_final, double pcg_rtol, int pcg_maxit, double* g_m0,
+                   double* g_V) {
+  if (!plan || !ckpts || !gy_final || !g_m0 || !g_V)
+    return fail(MFG_ERR_INVALID_ARG, "NULL argument");
+  if (n_iter < 0 || every < 1 || n_ckpt < 1 || (long long)n_ckpt * every < n_iter ||
+      pcg_maxit < 1 || !(pcg_rtol >= 0.0))
+    return fail(MFG_ERR_INVALID_ARG, "bad checkpoint or iteration arguments");
+  for (int k = 0; k < n_ckpt; ++k)
+    if (!ckpts[k].xi || !ckpts[k].y || !ckpts[k].ybar)
+      return fail(MFG_ERR_INVALID_ARG, "checkpoint with NULL vectors");
+  return mfg::run_cp_adjoint(plan->P, ckpts, every, n_iter, gy_final, pcg_rtol, pcg_maxit, g_m0,
+                             g_V);
 }
 
 int mfg_profile(mfg_plan_t plan, int enable) {

@@ -101,8 +101,9 @@ void launch_AAt(const Plan& P, const double* u, double* q, bool reduce_pq, hipSt
 void launch_pdir_AAt(const Plan& P, const double* z, const double* pold, double* pnew, double* q,
                      bool first, hipStream_t s);
 void launch_prox(const Plan& P, const double* v, double tau, double* y, hipStream_t s);
+// vout (optional): stores v = y - tau xi' (the prox input) for the reverse sweep
 void launch_backproj_prox(const Plan& P, const double* u, double* xi, double* y, double* ybar,
-                          double tau, double theta, hipStream_t s);
+                          double tau, double theta, hipStream_t s, double* vout = nullptr);
 // vec.hip
 void launch_pcg_init(const Plan& P, const double* b, double* x, double* r, double rtol,
                      hipStream_t s);
@@ -112,6 +113,12 @@ void launch_residual(const Plan& P, const double* b, const double* Ax, hipStream
 void launch_finish(const Plan& P, int site, int nblocks, int op, hipStream_t s);
 void launch_fill(double* x, long long n, double v, hipStream_t s);
 void launch_cp_init(const Plan& P, double* xi, double* y, double* ybar, hipStream_t s);
+// adjoint.hip
+void launch_adj_prox(const Plan& P, double* gy, const double* gyb, const double* v, double tau,
+                     double theta, double* gxi, double* gVc, hipStream_t s);
+void launch_sum_slices(const Plan& P, const double* in, const double* in2, double* out,
+                       hipStream_t s);
+void launch_axpby(long long n, double a, const double* x, double b, double* y, hipStream_t s);
 // precond.hip
 void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
                     const double* q, hipStream_t s);

@@ -320,7 +320,7 @@ __global__ __launch_bounds__(kThreads) void k_backproj_prox(Geom g, const double
                                                             double* __restrict__ ybar,
                                                             const double* __restrict__ Vpot,
                                                             double tau, double theta,
-                                                            RedBuf rb) {
+                                                            RedBuf rb, double* __restrict__ vout) {
   const long long n = g.n;
   double acc[1] = {0.0};
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
@@ -332,7 +332,12 @@ __global__ __launch_bounds__(kThreads) void k_backproj_prox(Geom g, const double
     CT_cell(g, u, t, i0, i1, x);
     for (int c = 0; c <= g.ncomp; ++c) yo[c] = y[(size_t)c * n + p];
     for (int c = 0; c < g.ncomp; ++c) w[c] = yo[1 + c] - tau * x[1 + c];
-    const double m = prox_cell(yo[0] - tau * x[0], w, g.ncomp, Vpot[rem], tau);
+    const double mbar = yo[0] - tau * x[0];
+    if (vout) {
+      vout[p] = mbar;
+      for (int c = 0; c < g.ncomp; ++c) vout[(size_t)(c + 1) * n + p] = w[c];
+    }
+    const double m = prox_cell(mbar, w, g.ncomp, Vpot[rem], tau);
     for (int c = 0; c <= g.ncomp; ++c) xi[(size_t)c * n + p] = x[c];
     y[p] = m;
     ybar[p] = m + theta * (m - yo[0]);
@@ -420,12 +425,12 @@ void launch_prox(const Plan& P, const double* v, double tau, double* y, hipStrea
 }
 
 void launch_backproj_prox(const Plan& P, const double* u, double* xi, double* y, double* ybar,
-                          double tau, double theta, hipStream_t s) {
+                          double tau, double theta, hipStream_t s, double* vout) {
   const int grid = grid_for(P.g.n, P.red.max_blocks);
   {
     ProfScope ps(P, "backproj_prox", s);
     hipLaunchKernelGGL(k_backproj_prox, dim3(grid), dim3(kThreads), 0, s, P.g, u, xi, y, ybar,
-                       (const double*)P.V, tau, theta, P.red);
+                       (const double*)P.V, tau, theta, P.red, vout);
   }
   launch_finish(P, T_DM, grid, OP_DM, s);
 }

@@ -59,6 +59,8 @@ SIGNATURES = {
                         POINTER(c_double)]),
     "mfg_cp_init": (c_int, [c_void_p, POINTER(State)]),
     "mfg_cp_solve": (c_int, [c_void_p, POINTER(State), c_int, c_double, c_int, POINTER(Stats)]),
+    "mfg_cp_adjoint": (c_int, [c_void_p, POINTER(State), c_int, c_int, c_int, c_void_p, c_double,
+                               c_int, c_void_p, c_void_p]),
     "mfg_profile": (c_int, [c_void_p, c_int]),
     "mfg_profile_report": (c_int, [c_void_p, ctypes.c_char_p, c_int]),
     "mfg_last_error": (c_char_p, []),
@@ -276,6 +278,23 @@ def mfg_cp_solve(plan: Plan, st: CPState, n_iter: int, pcg_rtol: float, pcg_maxi
         out = dict(pcg_iters=list(its), pcg_relres=list(rel), dm=list(dm))
     out["status"] = rc
     return out
+
+
+def mfg_cp_adjoint(plan: Plan, ckpts, every: int, n_iter: int, gy, pcg_rtol: float,
+                   pcg_maxit: int, g_m0, g_V, raise_not_converged: bool = True):
+    """ckpts: list of snapshot dicts (CPState.snapshot()) taken after 0, every,
+    2*every, ... iterations. Writes g_m0 and g_V (float64 CUDA tensors, M values)."""
+    arr = (State * len(ckpts))()
+    for k, c in enumerate(ckpts):
+        arr[k].xi = c["xi"].data_ptr()
+        arr[k].y = c["y"].data_ptr()
+        arr[k].ybar = c["ybar"].data_ptr()
+        arr[k].sigma, arr[k].tau, arr[k].theta, arr[k].iter = (c["sigma"], c["tau"], c["theta"],
+                                                               c["iter"])
+    rc = load().mfg_cp_adjoint(plan.handle, arr, len(ckpts), int(every), int(n_iter), _ptr(gy),
+                               float(pcg_rtol), int(pcg_maxit), _ptr(g_m0), _ptr(g_V))
+    _check(rc, allow=() if raise_not_converged else (3,))
+    return rc
 
 
 def mfg_profile(plan: Plan, enable: bool):
