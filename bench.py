@@ -51,21 +51,23 @@ def algorithmic(kernel, inst, variant):
     (matrix-core bound: 2 N_t flops per element against 16 bytes)."""
     n = inst.n
     nb = 1 + 2 * inst.d  # primal blocks
-    fsz = 8 if variant == "fp64" else 4  # preconditioner intermediate
     flex = variant != "fp64"
     if kernel.startswith("tgemm_f64"):
         return "mfma", 2.0 * inst.nt * inst.nt * inst.M, "fp64"
+    for base in ("rows_fwd", "rows_inv", "rows_solve", "cols_solve"):
+        if kernel in (base + "_f64", base + "_f32"):
+            # one read and one write of the intermediate in the solve's precision
+            return "hbm", 2 * (8 if kernel.endswith("f64") else 4) * n, None
     table = {
         "aat_fused": 4 * 8 * n,      # read z, p_old; write p_new, q
         "aat": 2 * 8 * n,
         "update": 6 * 8 * n,         # read x, r, p, q; write x, r
         "pcg_init": 3 * 8 * n,
         "residual": 2 * 8 * n,
-        "rows_fwd": 2 * fsz * n, "rows_inv": 2 * fsz * n, "rows_solve": 2 * fsz * n,
-        "cols_solve": 2 * fsz * n,
         "rhs": (2 * nb + 1) * 8 * n,             # read xi, ybar; write b
         "backproj_prox": (1 + 4 * nb) * 8 * n,   # read u, y; write xi, y, ybar
         "cp_init": 3 * nb * 8 * n,
+        "adj_prox": (4 * nb + 1) * 8 * n,        # read gy, gybar, v, gxi; write gy, gxi, gV
     }
     if kernel.startswith("tgemm_") and kernel.endswith("_fwd"):
         return "hbm", (8 + 4) * n, None          # read r (f64), write f32

@@ -196,6 +196,42 @@ int mfg_cp_adjoint(mfg_plan_t plan, const mfg_state_t* ckpts, int n_ckpt, int ev
                    const double* gy, double pcg_rtol, int pcg_maxit, double* g_m0,
                    double* g_V);
 
+/* ---- Batches of independent problems -------------------------------------
+ * Many problems solved together (for instance a parameter sweep over nu, V or
+ * m0, or independent problems of different sizes): every phase of a
+ * Chambolle-Pock step runs as ONE kernel launch over all instances, and the
+ * step, up to a fixed number of PCG iterations, is recorded once into a HIP
+ * graph and replayed. Each instance performs exactly the arithmetic of
+ * mfg_cp_solve on its own plan with the same arguments, so its iterates are
+ * bitwise identical to a single-plan run. */
+typedef struct mfg_batch_s* mfg_batch_t;
+
+/* Build a batch of count >= 1 plans. pbs[i], V[i], m0[i] are as for mfg_plan
+ * (V and m0 arrays are host arrays of device pointers). Requirements: d = 2,
+ * N_t <= 128, and one MIXED precision shared by all instances (the
+ * preconditioner of the batched path is the mixed one);
+ * MFG_ERR_UNSUPPORTED otherwise. The instances' plans use `stream`; batched
+ * solves run on an internal stream ordered after and before `stream` with
+ * events. */
+int mfg_plan_batch(const mfg_problem_t* pbs, const double* const* V, const double* const* m0,
+                   int count, hipStream_t stream, mfg_batch_t* out);
+
+/* Plan of instance i (owned by the batch: do not destroy). It accepts every
+ * single-plan call (mfg_cp_init, mfg_cp_solve, mfg_cp_adjoint, ...). */
+int mfg_batch_plan(mfg_batch_t batch, int i, mfg_plan_t* out);
+
+/* Release the batch and its plans. */
+int mfg_batch_destroy(mfg_batch_t batch);
+
+/* n_iter Chambolle-Pock iterations on every instance (states: host array of
+ * count states, each as for mfg_cp_solve). use_graph != 0 replays a recorded
+ * HIP graph for each step after the first one of the batch's life; 0 issues
+ * the same launches eagerly. pcg_iters (host, may be NULL): n_iter * count
+ * entries, [iteration][instance]. Returns MFG_ERR_NOT_CONVERGED (after all
+ * iterations) if some solve reached pcg_maxit. */
+int mfg_batch_cp_solve(mfg_batch_t batch, mfg_state_t* states, int n_iter, double pcg_rtol,
+                       int pcg_maxit, int use_graph, int* pcg_iters);
+
 /* Per-kernel timing: enable != 0 starts recording a HIP event pair on the
  * plan's stream around every kernel launch of the plan (totals reset); 0
  * stops. Recording adds host work per launch but does not change what the

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmfg.so")
-SOURCES = ["api.hip", "stencil.hip", "vec.hip", "precond.hip", "tgemm.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "stencil.hip", "vec.hip", "precond.hip", "tgemm.hip", "adjoint.hip",
+           "batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

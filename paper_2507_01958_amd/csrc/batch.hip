@@ -1,0 +1,549 @@
+// Batched Chambolle-Pock solves: many independent plans advanced together.
+//
+// Every phase of a CP step (right-hand side, PCG initialisation, each PCG
+// iteration's reduced-matrix product, update, preconditioner passes and
+// reductions, back-projection + prox) runs as ONE launch over all instances:
+// the launch takes a device array of per-instance arguments and block offsets
+// and each block runs the single-plan body for its instance (batch_args.h).
+// Instances keep their own launch shapes, so a batched solve performs exactly
+// the arithmetic of solving each plan alone.
+//
+// The step sizes of the Section 5 schedule do not depend on the data: they are
+// computed on the host for every instance and iteration and copied to the
+// device, where a small kernel loads those of the current iteration into each
+// instance's scalar block. With that, a CP step up to a fixed number of PCG
+// iterations contains no host decision and is captured once into a hipGraph
+// and replayed; instances that have converged skip their work through their
+// done flags, and any instance that needs more iterations continues with
+// eager batched launches before the back-projection.
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "batch_args.h"
+#include "plan.h"
+#include "tgemm.h"
+
+namespace mfg {
+
+int fail(int code, const std::string& msg);
+
+namespace {
+
+template <typename A>
+struct Phase {
+  A* args = nullptr;
+  int* off = nullptr;
+  int ninst = 0;
+  int total = 0;
+  size_t shm = 0;
+};
+
+struct GemmGroup {
+  int ntp = 0;
+  Phase<GemmArgs<double, float>> fwd;
+  Phase<GemmArgs<float, double>> inv_init, inv_flex;
+};
+
+}  // namespace
+
+struct Batch {
+  std::vector<mfg_plan_t> plans;
+  int count = 0;
+  int mode = GM_F32;
+  hipStream_t user = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  double* scal_all = nullptr;  // count x S_COUNT scalar blocks (the plans' own)
+  double* host_scal = nullptr;
+  double* tol2 = nullptr;
+  double* sched = nullptr;
+  int sched_cap = 0;
+  std::vector<GemmGroup> groups;
+  Phase<InitArgs> init;
+  Phase<UpdArgs> upd_odd, upd_even;
+  Phase<AatArgs> aat_first, aat_odd, aat_even;
+  Phase<RowsArgs<float>> rows_fwd, rows_inv;
+  Phase<ColsArgs<float>> cols;
+  Phase<RhsArgs> rhs;
+  Phase<BackprojArgs> bp;
+  FinishArgs *f_bb = nullptr, *f_pq = nullptr, *f_rr = nullptr, *f_rz0 = nullptr,
+             *f_rz = nullptr, *f_dm = nullptr;
+  std::vector<const double*> bound;  // state vectors the rhs/bp phases were built for
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_k = 0;
+  std::vector<void*> dev;
+};
+
+}  // namespace mfg
+
+struct mfg_batch_s {
+  mfg::Batch B;
+};
+
+namespace mfg {
+
+namespace {
+
+int dmalloc(Batch& B, void** p, size_t bytes) {
+  if (hipMalloc(p, bytes ? bytes : 16) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MFG_ERR_OOM, "batch allocation failed");
+  }
+  B.dev.push_back(*p);
+  return MFG_OK;
+}
+
+template <typename A>
+int upload_phase(Batch& B, const std::vector<A>& args, const std::vector<int>& blocks,
+                 Phase<A>& ph, size_t shm = 0) {
+  std::vector<int> off(args.size() + 1, 0);
+  for (size_t i = 0; i < args.size(); ++i) off[i + 1] = off[i] + blocks[i];
+  int rc;
+  if (!ph.args) {
+    void *pa, *po;
+    if ((rc = dmalloc(B, &pa, args.size() * sizeof(A))) ||
+        (rc = dmalloc(B, &po, off.size() * sizeof(int))))
+      return rc;
+    ph.args = static_cast<A*>(pa);
+    ph.off = static_cast<int*>(po);
+  }
+  if (hipMemcpy(ph.args, args.data(), args.size() * sizeof(A), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(ph.off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(MFG_ERR_HIP, "batch argument upload failed");
+  ph.ninst = (int)args.size();
+  ph.total = off.back();
+  ph.shm = shm;
+  return MFG_OK;
+}
+
+int upload_finish(Batch& B, const std::vector<FinishArgs>& f, FinishArgs** out) {
+  int rc;
+  if (!*out) {
+    void* p;
+    if ((rc = dmalloc(B, &p, f.size() * sizeof(FinishArgs)))) return rc;
+    *out = static_cast<FinishArgs*>(p);
+  }
+  if (hipMemcpy(*out, f.data(), f.size() * sizeof(FinishArgs), hipMemcpyHostToDevice) !=
+      hipSuccess)
+    return fail(MFG_ERR_HIP, "batch argument upload failed");
+  return MFG_OK;
+}
+
+Plan& plan_of(Batch& B, int i) { return B.plans[i]->P; }
+const double* done_of(Batch& B, int i) { return B.scal_all + (size_t)i * S_COUNT + S_DONE; }
+
+// Build the argument arrays of the PCG phases (state independent).
+int build_pcg_phases(Batch& B) {
+  const int n = B.count;
+  std::vector<InitArgs> init;
+  std::vector<UpdArgs> uo, ue;
+  std::vector<AatArgs> af, ao, ae;
+  std::vector<RowsArgs<float>> rf, ri;
+  std::vector<ColsArgs<float>> cl;
+  std::vector<int> b_init, b_upd, b_aat, b_rows, b_cols;
+  std::vector<FinishArgs> fbb, fpq, frr, frz0, frz;
+  size_t rshm = 0, cshm = 0;
+  for (int i = 0; i < n; ++i) {
+    Plan& P = plan_of(B, i);
+    const double* done = done_of(B, i);
+    float* tmp = reinterpret_cast<float*>(P.tmp);
+    init.push_back(pcg_init_args(P, P.b, P.u, P.r));
+    b_init.push_back(pcg_init_grid(P));
+    UpdArgs u1 = update_args(P, P.u, P.r, P.p, P.q);   // odd k: p_new = p
+    UpdArgs u2 = update_args(P, P.u, P.r, P.p2, P.q);  // even k: p_new = p2
+    u1.done = u2.done = done;
+    uo.push_back(u1);
+    ue.push_back(u2);
+    b_upd.push_back(update_grid(P));
+    int g;
+    af.push_back(aat_args(P, P.z, P.p2, P.p, P.q, true, done, &g));
+    ao.push_back(aat_args(P, P.z, P.p2, P.p, P.q, false, done, &g));
+    ae.push_back(aat_args(P, P.z, P.p, P.p2, P.q, false, done, &g));
+    b_aat.push_back(g);
+    RowsArgs<float> ra, rb;
+    ColsArgs<float> ca;
+    int blk;
+    size_t shm;
+    batch_rows_args(P, tmp, 0, done, &ra, &blk, &shm);
+    batch_rows_args(P, tmp, 1, done, &rb, &blk, &shm);
+    rf.push_back(ra);
+    ri.push_back(rb);
+    b_rows.push_back(blk);
+    rshm = std::max(rshm, shm);
+    batch_cols_args(P, tmp, done, &ca, &blk, &shm);
+    cl.push_back(ca);
+    b_cols.push_back(blk);
+    cshm = std::max(cshm, shm);
+    FinishArgs f = finish_args(P, T_BB, pcg_init_grid(P), OP_BB);
+    fbb.push_back(f);
+    f = finish_args(P, T_PQ, g, OP_PQ);
+    f.done = done;
+    fpq.push_back(f);
+    f = finish_args(P, T_RR, update_grid(P), OP_RR);
+    f.done = done;
+    frr.push_back(f);
+  }
+  int rc;
+  if ((rc = upload_phase(B, init, b_init, B.init)) || (rc = upload_phase(B, uo, b_upd, B.upd_odd)) ||
+      (rc = upload_phase(B, ue, b_upd, B.upd_even)) ||
+      (rc = upload_phase(B, af, b_aat, B.aat_first)) ||
+      (rc = upload_phase(B, ao, b_aat, B.aat_odd)) || (rc = upload_phase(B, ae, b_aat, B.aat_even)) ||
+      (rc = upload_phase(B, rf, b_rows, B.rows_fwd, rshm)) ||
+      (rc = upload_phase(B, ri, b_rows, B.rows_inv, rshm)) ||
+      (rc = upload_phase(B, cl, b_cols, B.cols, cshm)) || (rc = upload_finish(B, fbb, &B.f_bb)) ||
+      (rc = upload_finish(B, fpq, &B.f_pq)) || (rc = upload_finish(B, frr, &B.f_rr)))
+    return rc;
+  // time GEMMs: one launch per N_t padding class
+  std::vector<int> ntps;
+  for (int i = 0; i < n; ++i) ntps.push_back(plan_of(B, i).ntp);
+  std::sort(ntps.begin(), ntps.end());
+  ntps.erase(std::unique(ntps.begin(), ntps.end()), ntps.end());
+  B.groups.assign(ntps.size(), GemmGroup{});
+  std::vector<int> gemm_grid(n, 0);
+  for (size_t gi = 0; gi < ntps.size(); ++gi) {
+    GemmGroup& G = B.groups[gi];
+    G.ntp = ntps[gi];
+    std::vector<GemmArgs<double, float>> fw;
+    std::vector<GemmArgs<float, double>> i0, i1;
+    std::vector<int> blocks;
+    for (int i = 0; i < n; ++i) {
+      Plan& P = plan_of(B, i);
+      if (P.ntp != G.ntp) continue;
+      float* tmp = reinterpret_cast<float*>(P.tmp);
+      int blk;
+      fw.push_back(batch_gemm_args<double, float>(P, B.mode, P.r, tmp, DOT_NONE, nullptr, nullptr,
+                                                  done_of(B, i), &blk));
+      i0.push_back(batch_gemm_args<float, double>(P, B.mode, tmp, P.z, DOT_INIT, P.r, nullptr,
+                                                  done_of(B, i), &blk));
+      i1.push_back(batch_gemm_args<float, double>(P, B.mode, tmp, P.z, DOT_FLEX, P.r, P.q,
+                                                  done_of(B, i), &blk));
+      blocks.push_back(blk);
+      gemm_grid[i] = blk;
+    }
+    if ((rc = upload_phase(B, fw, blocks, G.fwd)) || (rc = upload_phase(B, i0, blocks, G.inv_init)) ||
+        (rc = upload_phase(B, i1, blocks, G.inv_flex)))
+      return rc;
+  }
+  for (int i = 0; i < n; ++i) {
+    Plan& P = plan_of(B, i);
+    FinishArgs f = finish_args(P, T_RZ, gemm_grid[i], OP_RZ_INIT);
+    f.done = done_of(B, i);
+    frz0.push_back(f);
+    f.op = OP_RZ_FLEX;
+    frz.push_back(f);
+  }
+  if ((rc = upload_finish(B, frz0, &B.f_rz0)) || (rc = upload_finish(B, frz, &B.f_rz))) return rc;
+  return MFG_OK;
+}
+
+// Right-hand side and back-projection phases bound to the states' vectors.
+int build_state_phases(Batch& B, mfg_state_t* st) {
+  std::vector<RhsArgs> rh;
+  std::vector<BackprojArgs> bp;
+  std::vector<int> b_rhs, b_bp;
+  std::vector<FinishArgs> fdm;
+  for (int i = 0; i < B.count; ++i) {
+    Plan& P = plan_of(B, i);
+    const double* S = B.scal_all + (size_t)i * S_COUNT;
+    rh.push_back(rhs_args(P, st[i].xi, st[i].ybar, 0.0, S + S_SIGMA, P.b));
+    b_rhs.push_back(rhs_grid(P));
+    bp.push_back(backproj_args(P, P.u, st[i].xi, st[i].y, st[i].ybar, 0.0, 0.0, S + S_TAU,
+                               S + S_THETA, nullptr));
+    b_bp.push_back(backproj_grid(P));
+    fdm.push_back(finish_args(P, T_DM, backproj_grid(P), OP_DM));
+  }
+  int rc;
+  if ((rc = upload_phase(B, rh, b_rhs, B.rhs)) || (rc = upload_phase(B, bp, b_bp, B.bp)) ||
+      (rc = upload_finish(B, fdm, &B.f_dm)))
+    return rc;
+  return MFG_OK;
+}
+
+void precond_phase(Batch& B, bool init, hipStream_t s) {
+  for (auto& G : B.groups)
+    launch_gemm_batch<double, float>(B.mode, G.ntp, G.fwd.args, G.fwd.off, G.fwd.ninst,
+                                     G.fwd.total, s);
+  launch_rows_batch_f32(B.rows_fwd.args, B.rows_fwd.off, B.count, B.rows_fwd.total,
+                        B.rows_fwd.shm, s);
+  launch_cols_batch_f32(B.cols.args, B.cols.off, B.count, B.cols.total, B.cols.shm, s);
+  launch_rows_batch_f32(B.rows_inv.args, B.rows_inv.off, B.count, B.rows_inv.total,
+                        B.rows_inv.shm, s);
+  for (auto& G : B.groups) {
+    const auto& ph = init ? G.inv_init : G.inv_flex;
+    launch_gemm_batch<float, double>(B.mode, G.ntp, ph.args, ph.off, ph.ninst, ph.total, s);
+  }
+  launch_finish_batch(init ? B.f_rz0 : B.f_rz, B.count, s);
+}
+
+// PCG iteration k >= 1 for every instance not yet converged.
+void pcg_iteration(Batch& B, int k, hipStream_t s) {
+  const auto& aat = (k == 1) ? B.aat_first : ((k & 1) ? B.aat_odd : B.aat_even);
+  launch_aat_batch(true, aat.args, aat.off, B.count, aat.total, s);
+  launch_finish_batch(B.f_pq, B.count, s);
+  const auto& upd = (k & 1) ? B.upd_odd : B.upd_even;
+  launch_update_batch(upd.args, upd.off, B.count, upd.total, s);
+  launch_finish_batch(B.f_rr, B.count, s);
+  precond_phase(B, false, s);
+}
+
+// Everything of one CP step before the host looks at convergence: step sizes,
+// right-hand side, PCG initialisation and K iterations.
+void step_head(Batch& B, int K, int maxit_sched, hipStream_t s) {
+  launch_cp_advance_batch(B.scal_all, S_COUNT, B.count, B.sched, maxit_sched, s);
+  launch_rhs_batch(B.rhs.args, B.rhs.off, B.count, B.rhs.total, s);
+  launch_set_scalars_batch(B.scal_all, S_COUNT, B.count, B.tol2, s);
+  launch_pcg_init_batch(B.init.args, B.init.off, B.count, B.init.total, s);
+  launch_finish_batch(B.f_bb, B.count, s);
+  precond_phase(B, true, s);
+  for (int k = 1; k <= K; ++k) pcg_iteration(B, k, s);
+}
+
+int read_all(Batch& B) {
+  if (hipMemcpyAsync(B.host_scal, B.scal_all, (size_t)B.count * S_COUNT * sizeof(double),
+                     hipMemcpyDeviceToHost, B.stream) != hipSuccess ||
+      hipStreamSynchronize(B.stream) != hipSuccess)
+    return fail(MFG_ERR_HIP, "batch scalar readback failed");
+  return MFG_OK;
+}
+
+__global__ void k_batch_set(double* scal, int stride, int ninst, int slot, double v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ninst) scal[(size_t)i * stride + slot] = v;
+}
+
+void release_graph(Batch& B) {
+  if (B.exec) (void)hipGraphExecDestroy(B.exec);
+  if (B.graph) (void)hipGraphDestroy(B.graph);
+  B.exec = nullptr;
+  B.graph = nullptr;
+  B.graph_k = 0;
+}
+
+}  // namespace
+
+int batch_create(Batch& B, const mfg_problem_t* pbs, const double* const* V,
+                 const double* const* m0, int count, hipStream_t stream) {
+  B.count = count;
+  B.user = stream;
+  const int prec = pbs[0].precision;
+  if (prec == MFG_FP64)
+    return fail(MFG_ERR_UNSUPPORTED, "batched solves use a mixed-precision preconditioner");
+  B.mode = prec == MFG_MIXED_FP32 ? GM_F32 : (prec == MFG_MIXED_FP16 ? GM_F16 : GM_BF16);
+  for (int i = 0; i < count; ++i) {
+    if (pbs[i].precision != prec) return fail(MFG_ERR_INVALID_ARG, "mixed precisions in a batch");
+    if (pbs[i].d != 2) return fail(MFG_ERR_UNSUPPORTED, "batched solves need d = 2");
+    if (pbs[i].nt > 128) return fail(MFG_ERR_UNSUPPORTED, "batched solves need N_t <= 128");
+  }
+  if (hipStreamCreateWithFlags(&B.stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&B.ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&B.ev_out, hipEventDisableTiming) != hipSuccess)
+    return fail(MFG_ERR_HIP, "stream creation failed");
+  for (int i = 0; i < count; ++i) {
+    mfg_plan_t h = nullptr;
+    int rc = mfg_plan(&pbs[i], V[i], m0[i], stream, &h);
+    if (rc) return rc;
+    B.plans.push_back(h);
+  }
+  int rc;
+  void* p;
+  if ((rc = dmalloc(B, &p, (size_t)count * S_COUNT * sizeof(double)))) return rc;
+  B.scal_all = static_cast<double*>(p);
+  if (hipMemset(B.scal_all, 0, (size_t)count * S_COUNT * sizeof(double)) != hipSuccess)
+    return fail(MFG_ERR_HIP, "memset failed");
+  for (int i = 0; i < count; ++i) plan_of(B, i).red.scal = B.scal_all + (size_t)i * S_COUNT;
+  if ((rc = dmalloc(B, &p, (size_t)count * sizeof(double)))) return rc;
+  B.tol2 = static_cast<double*>(p);
+  if (hipHostMalloc(&p, (size_t)count * S_COUNT * sizeof(double), hipHostMallocDefault) !=
+      hipSuccess)
+    return fail(MFG_ERR_OOM, "pinned allocation failed");
+  B.host_scal = static_cast<double*>(p);
+  return build_pcg_phases(B);
+}
+
+void batch_release(Batch& B) {
+  if (B.stream) (void)hipStreamSynchronize(B.stream);
+  release_graph(B);
+  for (mfg_plan_t h : B.plans) mfg_destroy(h);
+  B.plans.clear();
+  for (void* p : B.dev) (void)hipFree(p);
+  B.dev.clear();
+  if (B.host_scal) (void)hipHostFree(B.host_scal);
+  B.host_scal = nullptr;
+  if (B.ev_in) (void)hipEventDestroy(B.ev_in);
+  if (B.ev_out) (void)hipEventDestroy(B.ev_out);
+  if (B.stream) (void)hipStreamDestroy(B.stream);
+  B.stream = nullptr;
+}
+
+int batch_cp_solve(Batch& B, mfg_state_t* st, int n_iter, double rtol, int maxit, int use_graph,
+                   int* pcg_iters) {
+  hipStream_t s = B.stream;
+  const int n = B.count;
+  if (n_iter <= 0) return MFG_OK;
+  // host schedule (same arithmetic as the single-plan driver)
+  std::vector<double> sched((size_t)n * n_iter * 3);
+  for (int i = 0; i < n; ++i) {
+    double sigma = st[i].sigma, tau = st[i].tau;
+    const double gamma = plan_of(B, i).gamma;
+    for (int j = 0; j < n_iter; ++j) {
+      const double theta = 1.0 / std::sqrt(1.0 + 2.0 * gamma * tau);
+      double* e = &sched[((size_t)i * n_iter + j) * 3];
+      e[0] = sigma;
+      e[1] = tau;
+      e[2] = theta;
+      tau *= theta;
+      sigma /= theta;
+    }
+  }
+  if (n_iter > B.sched_cap) {
+    void* p;
+    int rc = dmalloc(B, &p, sched.size() * sizeof(double));
+    if (rc) return rc;
+    B.sched = static_cast<double*>(p);
+    B.sched_cap = n_iter;
+    release_graph(B);  // the graph holds the old schedule pointer
+  }
+  std::vector<double> t2(n, rtol * rtol);
+  if (hipMemcpy(B.tol2, t2.data(), n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(MFG_ERR_HIP, "upload failed");
+  // the schedule table is laid out for B.sched_cap iterations per instance
+  std::vector<double> padded((size_t)n * B.sched_cap * 3, 0.0);
+  for (int i = 0; i < n; ++i)
+    std::copy(sched.begin() + (size_t)i * n_iter * 3, sched.begin() + (size_t)(i + 1) * n_iter * 3,
+              padded.begin() + (size_t)i * B.sched_cap * 3);
+  if (hipMemcpy(B.sched, padded.data(), padded.size() * sizeof(double), hipMemcpyHostToDevice) !=
+      hipSuccess)
+    return fail(MFG_ERR_HIP, "upload failed");
+  std::vector<const double*> want;
+  for (int i = 0; i < n; ++i) {
+    want.push_back(st[i].xi);
+    want.push_back(st[i].y);
+    want.push_back(st[i].ybar);
+  }
+  if (want != B.bound) {
+    int rc = build_state_phases(B, st);
+    if (rc) return rc;
+    B.bound = want;
+    release_graph(B);
+  }
+  if (B.graph_k > maxit) release_graph(B);
+  // order after the caller's stream
+  (void)hipEventRecord(B.ev_in, B.user);
+  (void)hipStreamWaitEvent(s, B.ev_in, 0);
+  hipLaunchKernelGGL(k_batch_set, dim3((n + 63) / 64), dim3(64), 0, s, B.scal_all, S_COUNT, n,
+                     (int)S_CPIT, 0.0);
+  int final_rc = MFG_OK;
+  for (int it = 0; it < n_iter; ++it) {
+    int K = std::min(B.graph_k > 0 ? B.graph_k : 8, maxit);
+    if (use_graph && !B.exec && it > 0) {
+      // capture with the iteration count the first steps needed
+      if (hipStreamBeginCapture(s, hipStreamCaptureModeGlobal) != hipSuccess)
+        return fail(MFG_ERR_HIP, "graph capture failed to start");
+      step_head(B, K, B.sched_cap, s);
+      if (hipStreamEndCapture(s, &B.graph) != hipSuccess ||
+          hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0) != hipSuccess) {
+        release_graph(B);
+        return fail(MFG_ERR_HIP, "graph instantiation failed");
+      }
+      B.graph_k = K;
+    }
+    if (use_graph && B.exec) {
+      if (hipGraphLaunch(B.exec, s) != hipSuccess) return fail(MFG_ERR_HIP, "graph launch failed");
+    } else {
+      step_head(B, K, B.sched_cap, s);
+    }
+    int rc = read_all(B);
+    if (rc) return rc;
+    int k = K;
+    int maxits = 0;
+    while (true) {
+      bool all = true;
+      for (int i = 0; i < n; ++i) {
+        const double* S = B.host_scal + (size_t)i * S_COUNT;
+        if (S[S_BAD] == 2.0) return fail(MFG_ERR_NONFINITE, "non-finite value in a batched PCG");
+        if (S[S_BAD] == 1.0) return fail(MFG_ERR_BREAKDOWN, "breakdown in a batched PCG");
+        if (S[S_DONE] == 0.0) all = false;
+      }
+      if (all || k >= maxit) break;
+      ++k;
+      pcg_iteration(B, k, s);
+      if ((rc = read_all(B))) return rc;
+    }
+    for (int i = 0; i < n; ++i) {
+      const double* S = B.host_scal + (size_t)i * S_COUNT;
+      const int its = (int)S[S_ITS];
+      maxits = std::max(maxits, its);
+      if (S[S_DONE] == 0.0) final_rc = MFG_ERR_NOT_CONVERGED;
+      if (pcg_iters) pcg_iters[(size_t)it * n + i] = its;
+    }
+    if (!B.exec && B.graph_k == 0) B.graph_k = std::min(std::max(maxits + 1, 2), maxit);
+    launch_backproj_batch(B.bp.args, B.bp.off, n, B.bp.total, s);
+    launch_finish_batch(B.f_dm, n, s);
+  }
+  (void)hipEventRecord(B.ev_out, s);
+  (void)hipStreamWaitEvent(B.user, B.ev_out, 0);
+  if (hipGetLastError() != hipSuccess) return fail(MFG_ERR_HIP, "batched launch failed");
+  for (int i = 0; i < n; ++i) {
+    const double* e = &sched[((size_t)i * n_iter + (n_iter - 1)) * 3];
+    st[i].theta = e[2];
+    st[i].tau = e[1] * e[2];
+    st[i].sigma = e[0] / e[2];
+    st[i].iter += n_iter;
+  }
+  if (final_rc) return fail(final_rc, "some batched PCG solve reached maxit");
+  return MFG_OK;
+}
+
+}  // namespace mfg
+
+using mfg::fail;
+
+extern "C" {
+
+int mfg_plan_batch(const mfg_problem_t* pbs, const double* const* V, const double* const* m0,
+                   int count, hipStream_t stream, mfg_batch_t* out) {
+  if (!pbs || !V || !m0 || !out || count < 1) return fail(MFG_ERR_INVALID_ARG, "bad arguments");
+  *out = nullptr;
+  mfg_batch_s* h = new (std::nothrow) mfg_batch_s();
+  if (!h) return fail(MFG_ERR_OOM, "host allocation failed");
+  int rc = mfg::batch_create(h->B, pbs, V, m0, count, stream);
+  if (rc) {
+    std::string msg = mfg_last_error();
+    mfg::batch_release(h->B);
+    delete h;
+    fail(rc, msg);
+    return rc;
+  }
+  *out = h;
+  return MFG_OK;
+}
+
+int mfg_batch_destroy(mfg_batch_t b) {
+  if (!b) return MFG_OK;
+  mfg::batch_release(b->B);
+  delete b;
+  return MFG_OK;
+}
+
+int mfg_batch_plan(mfg_batch_t b, int i, mfg_plan_t* out) {
+  if (!b || !out || i < 0 || i >= b->B.count) return fail(MFG_ERR_INVALID_ARG, "bad arguments");
+  *out = b->B.plans[i];
+  return MFG_OK;
+}
+
+int mfg_batch_cp_solve(mfg_batch_t b, mfg_state_t* states, int n_iter, double pcg_rtol,
+                       int pcg_maxit, int use_graph, int* pcg_iters) {
+  if (!b || !states || n_iter < 0 || pcg_maxit < 1 || !(pcg_rtol >= 0.0))
+    return fail(MFG_ERR_INVALID_ARG, "bad arguments");
+  for (int i = 0; i < b->B.count; ++i)
+    if (!states[i].xi || !states[i].y || !states[i].ybar || !(states[i].tau > 0.0) ||
+        !(states[i].sigma > 0.0))
+      return fail(MFG_ERR_INVALID_ARG, "bad state");
+  return mfg::batch_cp_solve(b->B, states, n_iter, pcg_rtol, pcg_maxit, use_graph, pcg_iters);
+}
+
+}  // extern "C"

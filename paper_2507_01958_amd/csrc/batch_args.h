@@ -1,0 +1,173 @@
+// Argument blocks of the kernels that run both for one plan and batched over
+// many plans in one launch. A batched launch takes a device array of these
+// (one per instance) plus block offsets: instance i owns blocks
+// [off[i], off[i+1]) and runs the same body with its local block id, so a
+// batched run performs exactly the arithmetic of the single-plan run.
+#pragma once
+
+#include "mfg_internal.h"
+
+namespace mfg {
+
+// Solve context of Algorithm 2: eigenvalue tables and constants of S.
+struct SolveCtx {
+  const double* lam_t;  // time eigenvalues (eq. eigs)
+  const double* lam0;   // axis-0 eigenvalues / h0^2 (nullptr when absent)
+  const double* lam1;   // axis-1 eigenvalues / h1^2
+  double nu, idt, idt2;
+  double norm;          // 1 / (N0 N1)
+};
+
+// `done` (batched runs only, else null): the instance's converged flag; the
+// PCG-loop bodies return at once when it is set.
+struct InitArgs {
+  long long n;
+  const double* b;
+  double* x;
+  double* r;
+  RedBuf rb;
+};
+
+struct UpdArgs {
+  long long n;
+  double* x;
+  double* r;
+  const double* p;
+  const double* q;
+  RedBuf rb;
+  const double* done;
+};
+
+struct FinishArgs {
+  RedBuf rb;
+  int site, nblocks, op;
+  const double* done;
+};
+
+struct AatArgs {
+  Geom g;
+  const double* src;   // u, or z when forming p = z + beta p_old
+  const double* pold;
+  double* pnew;
+  double* q;
+  RedBuf rb;
+  int tc, first, reduce;
+  const double* done;
+};
+
+// Step sizes either by value or from device memory (pointer non-null).
+struct RhsArgs {
+  Geom g;
+  const double* xi;
+  const double* ybar;
+  double sigma;
+  const double* sigma_dev;
+  const double* m0;
+  double* b;
+};
+
+struct BackprojArgs {
+  Geom g;
+  const double* u;
+  double* xi;
+  double* y;
+  double* ybar;
+  const double* V;
+  double tau, theta;
+  const double* tau_dev;
+  const double* theta_dev;
+  RedBuf rb;
+  double* vout;
+};
+
+template <typename T>
+struct RowsArgs {
+  T* data;
+  int nrows;
+  Axis ax;
+  int mode, lpb;
+  SolveCtx sc;
+  int n0;
+  const double* done;
+};
+
+template <typename T>
+struct ColsArgs {
+  T* data;
+  Geom g;
+  Axis ax;
+  int cw;
+  SolveCtx sc;
+  const double* done;
+};
+
+template <typename TX, typename TY>
+struct GemmArgs {
+  const void* V;   // float64 Vt (chunked kernel) or the padded copy (low precision)
+  const TX* X;
+  TY* Y;
+  int nt, M, ncolblk, dotmode;
+  const double* rvec;
+  const double* qvec;
+  RedBuf rb;
+  const double* done;
+};
+
+// Instance that owns block b of a batched launch (off[0] = 0 <= b < off[ninst]).
+__device__ __forceinline__ int batch_instance(const int* off, int ninst, int b) {
+  int lo = 0, hi = ninst;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// ---- host-side builders and batched launchers (defined next to each kernel) ----
+struct Plan;
+InitArgs pcg_init_args(const Plan& P, const double* b, double* x, double* r);
+int pcg_init_grid(const Plan& P);
+UpdArgs update_args(const Plan& P, double* x, double* r, const double* p, const double* q);
+int update_grid(const Plan& P);
+FinishArgs finish_args(const Plan& P, int site, int nblocks, int op);
+RhsArgs rhs_args(const Plan& P, const double* xi, const double* ybar, double sigma,
+                 const double* sigma_dev, double* b);
+int rhs_grid(const Plan& P);
+BackprojArgs backproj_args(const Plan& P, const double* u, double* xi, double* y, double* ybar,
+                           double tau, double theta, const double* tau_dev,
+                           const double* theta_dev, double* vout);
+int backproj_grid(const Plan& P);
+AatArgs aat_args(const Plan& P, const double* z, const double* pold, double* pnew, double* q,
+                 bool first, const double* done, int* grid);
+void batch_rows_args(const Plan& P, float* data, int mode, const double* done, void* out,
+                     int* blocks, size_t* shm);
+void batch_cols_args(const Plan& P, float* data, const double* done, void* out, int* blocks,
+                     size_t* shm);
+template <typename TX, typename TY>
+GemmArgs<TX, TY> batch_gemm_args(const Plan& P, int mode, const TX* X, TY* Y, int dotmode,
+                                 const double* r, const double* q, const double* done,
+                                 int* blocks);
+
+void launch_pcg_init_batch(const InitArgs* A, const int* off, int ninst, int total,
+                           hipStream_t s);
+void launch_update_batch(const UpdArgs* A, const int* off, int ninst, int total, hipStream_t s);
+void launch_finish_batch(const FinishArgs* F, int ninst, hipStream_t s);
+void launch_set_scalars_batch(double* scal, int stride, int ninst, const double* tol2,
+                              hipStream_t s);
+void launch_cp_advance_batch(double* scal, int stride, int ninst, const double* sched, int maxit,
+                             hipStream_t s);
+void launch_aat_batch(bool has0, const AatArgs* A, const int* off, int ninst, int total,
+                      hipStream_t s);
+void launch_rhs_batch(const RhsArgs* A, const int* off, int ninst, int total, hipStream_t s);
+void launch_backproj_batch(const BackprojArgs* A, const int* off, int ninst, int total,
+                           hipStream_t s);
+void launch_rows_batch_f32(const void* A, const int* off, int ninst, int total, size_t shm,
+                           hipStream_t s);
+void launch_cols_batch_f32(const void* A, const int* off, int ninst, int total, size_t shm,
+                           hipStream_t s);
+template <typename TX, typename TY>
+void launch_gemm_batch(int mode, int ntp, const GemmArgs<TX, TY>* A, const int* off, int ninst,
+                       int total, hipStream_t s);
+
+}  // namespace mfg

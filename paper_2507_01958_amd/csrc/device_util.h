@@ -51,19 +51,21 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
   __syncthreads();
 }
 
-// Store this block's partial sums (slot k of `site` at index blockIdx.x).
+// Store this block's partial sums (slot k of `site` at index bid, the block's
+// id within its instance).
 // A separate single-block finisher kernel sums them in block order after the
 // producing kernel has completed, so no device-scope fence is needed here (on
 // a multi-XCD part such a fence writes back the whole L2 of the XCD).
 template <int NV>
-__device__ __forceinline__ void reduce_store(double (&v)[NV], const RedBuf& rb, int site) {
+__device__ __forceinline__ void reduce_store(double (&v)[NV], const RedBuf& rb, int site,
+                                             int bid) {
   static_assert(NV <= kSlotsPerSite, "too many reduction slots");
   __shared__ double sh[NV * 16];
   block_sum<NV>(v, sh);
   if (threadIdx.x == 0) {
     double* part = rb.partials + (size_t)site * kSlotsPerSite * rb.max_blocks;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) part[(size_t)k * rb.max_blocks + blockIdx.x] = v[k];
+    for (int k = 0; k < NV; ++k) part[(size_t)k * rb.max_blocks + bid] = v[k];
   }
 }
 

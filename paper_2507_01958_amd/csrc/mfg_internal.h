@@ -56,7 +56,12 @@ enum ScalarSlot {
   S_DM = 10,    // ||m' - m||^2 of the last CP step
   S_AUX0 = 11,
   S_AUX1 = 12,
-  S_COUNT = 16
+  S_ITS = 13,   // PCG iterations done (counted by the r.r finisher)
+  S_SIGMA = 14, // CP step sizes of the current iteration (graph-driven runs)
+  S_TAU = 15,
+  S_THETA = 16,
+  S_CPIT = 17,  // CP iterations done (graph-driven runs)
+  S_COUNT = 24
 };
 
 enum ReduceSite { T_BB = 0, T_PQ = 1, T_RR = 2, T_RZ = 3, T_DM = 4, T_AUX = 5, T_COUNT = 8 };

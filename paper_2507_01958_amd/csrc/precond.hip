@@ -13,6 +13,7 @@
 // Neumann axis. Both are computed from one complex FFT per pair of real lines
 // (DCT-II by Makhoul's even/odd reordering), with a mixed-radix (4, 2, 3)
 // Stockham FFT staged in LDS.
+#include "batch_args.h"
 #include "device_util.h"
 #include "plan.h"
 #include "tgemm.h"
@@ -197,13 +198,7 @@ __device__ void stage_tables(const Axis& ax, T* lds, const T*& tw, const T*& ct)
   ct = lds + 2 * N;
 }
 
-struct SolveCtx {
-  const double* lam_t;   // time eigenvalues
-  const double* lam0;    // axis-0 eigenvalues / h0^2 (nullptr when absent)
-  const double* lam1;    // axis-1 eigenvalues / h1^2
-  double nu, idt, idt2;
-  double norm;           // 1 / (N0 N1)
-};
+
 
 __device__ __forceinline__ double shift_symbol(const SolveCtx& sc, double R, double lt) {
   return sc.nu * sc.nu * R * R + 2.0 * R + (sc.nu * lt * sc.idt) * R + lt * sc.idt2;
@@ -212,15 +207,19 @@ __device__ __forceinline__ double shift_symbol(const SolveCtx& sc, double R, dou
 // Transforms along the contiguous axis (length N = ax.N) of nrows rows.
 // mode 0: forward; 1: inverse; 2: forward, divide by S (d = 1), inverse.
 template <typename T>
-__global__ __launch_bounds__(256) void k_rows(T* __restrict__ data, int nrows, Axis ax, int mode,
-                                              int lpb, SolveCtx sc, int n0) {
+__device__ void rows_body(const RowsArgs<T>& a, int bid) {
+  if (a.done && *a.done != 0.0) return;
+  T* __restrict__ data = a.data;
+  const int nrows = a.nrows, mode = a.mode, lpb = a.lpb, n0 = a.n0;
+  const Axis& ax = a.ax;
+  const SolveCtx& sc = a.sc;
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = ax.N;
   C2<T>* A = reinterpret_cast<C2<T>*>(smem);
   C2<T>* B = A + lpb * N;
   const T *tw, *ct;
   stage_tables<T>(ax, reinterpret_cast<T*>(B + lpb * N), tw, ct);
-  const int line0 = blockIdx.x * lpb;
+  const int line0 = bid * lpb;
   int nl = (nrows + 1) / 2 - line0;
   if (nl > lpb) nl = lpb;
   const bool dct = (ax.kind == 1);
@@ -292,8 +291,13 @@ __global__ __launch_bounds__(256) void k_rows(T* __restrict__ data, int nrows, A
 // Transform along axis 0 (stride n1), divide by S, inverse along axis 0, for
 // cw columns of one time slice per block (d = 2).
 template <typename T>
-__global__ __launch_bounds__(256) void k_cols_solve(T* __restrict__ data, Geom g, Axis ax,
-                                                    int cw, SolveCtx sc) {
+__device__ void cols_body(const ColsArgs<T>& a, int bid, int nb) {
+  if (a.done && *a.done != 0.0) return;
+  T* __restrict__ data = a.data;
+  const Geom& g = a.g;
+  const Axis& ax = a.ax;
+  const int cw = a.cw;
+  const SolveCtx& sc = a.sc;
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = ax.N;  // == n0
   const int nlines = cw / 2;
@@ -302,7 +306,7 @@ __global__ __launch_bounds__(256) void k_cols_solve(T* __restrict__ data, Geom g
   const T *tw, *ct;
   stage_tables<T>(ax, reinterpret_cast<T*>(B + nlines * N), tw, ct);
   const int ncb = (g.n1 + cw - 1) / cw;
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int blk = xcd_remap(bid, nb);
   const int t = blk / ncb;
   const int j0 = (blk - t * ncb) * cw;
   const bool dct = (ax.kind == 1);
@@ -365,6 +369,35 @@ __global__ __launch_bounds__(256) void k_cols_solve(T* __restrict__ data, Geom g
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_rows(RowsArgs<T> a) {
+  rows_body<T>(a, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_rows_batch(const RowsArgs<T>* A, const int* off,
+                                                    int ninst) {
+  const int i = batch_instance(off, ninst, blockIdx.x);
+  rows_body<T>(A[i], blockIdx.x - off[i]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cols_solve(ColsArgs<T> a) {
+  cols_body<T>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cols_batch(const ColsArgs<T>* A, const int* off,
+                                                    int ninst) {
+  const int i = batch_instance(off, ninst, blockIdx.x);
+  cols_body<T>(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
+}
+
+struct SpatialShape {
+  int lpb, nrows, rblocks, cw, cblocks;
+  size_t rshm, cshm;
+};
+
 SolveCtx solve_ctx(const Plan& P) {
   SolveCtx sc;
   sc.lam_t = P.lam_t;
@@ -377,10 +410,11 @@ SolveCtx solve_ctx(const Plan& P) {
   return sc;
 }
 
+// Launch shapes of the spatial solves (row transforms and column solves).
 template <typename T>
-void spatial_solves(const Plan& P, T* data, hipStream_t s) {
+SpatialShape spatial_shape(const Plan& P) {
   const Geom& g = P.g;
-  const SolveCtx sc = solve_ctx(P);
+  SpatialShape sh{};
   const int N1 = g.n1;
   int lpb = P.tune.rows_elems / N1;
   if (lpb < 1) lpb = 1;
@@ -392,38 +426,58 @@ void spatial_solves(const Plan& P, T* data, hipStream_t s) {
   const int lpb_max = (int)((65536 - 4 * (size_t)N1 * sizeof(T)) / (2 * (size_t)N1 * sizeof(C2<T>)));
   if (lpb > lpb_max) lpb = lpb_max;
   if (lpb < 1) lpb = 1;
-  const int rblocks = (nlines + lpb - 1) / lpb;
-  // two complex buffers plus the twiddle and DCT tables
-  const size_t rshm = 2 * (size_t)lpb * N1 * sizeof(C2<T>) + 4 * (size_t)N1 * sizeof(T);
+  sh.lpb = lpb;
+  sh.nrows = nrows;
+  sh.rblocks = (nlines + lpb - 1) / lpb;
+  sh.rshm = 2 * (size_t)lpb * N1 * sizeof(C2<T>) + 4 * (size_t)N1 * sizeof(T);
+  if (g.has0) {
+    int lines = P.tune.cols_lines;
+    const int lmax =
+        (int)((65536 - 4 * (size_t)g.n0 * sizeof(T)) / (2 * (size_t)g.n0 * sizeof(C2<T>)));
+    if (lines > lmax) lines = lmax;
+    if (lines < 1) lines = 1;
+    sh.cw = 2 * lines;
+    sh.cblocks = g.nt * ((g.n1 + sh.cw - 1) / sh.cw);
+    sh.cshm = 2 * (size_t)lines * g.n0 * sizeof(C2<T>) + 4 * (size_t)g.n0 * sizeof(T);
+  }
+  return sh;
+}
+
+template <typename T>
+RowsArgs<T> rows_args(const Plan& P, const SpatialShape& sh, T* data, int mode,
+                      const double* done) {
+  return RowsArgs<T>{data, sh.nrows, P.ax1, mode, sh.lpb, solve_ctx(P), P.g.has0 ? P.g.n0 : 1,
+                     done};
+}
+
+template <typename T>
+ColsArgs<T> cols_args(const Plan& P, const SpatialShape& sh, T* data, const double* done) {
+  return ColsArgs<T>{data, P.g, P.ax0, sh.cw, solve_ctx(P), done};
+}
+
+template <typename T>
+void spatial_solves(const Plan& P, T* data, hipStream_t s) {
+  const Geom& g = P.g;
+  const SpatialShape sh = spatial_shape<T>(P);
   if (!g.has0) {
-    ProfScope ps(P, "rows_solve", s);
-    hipLaunchKernelGGL(k_rows<T>, dim3(rblocks), dim3(256), rshm, s, data, nrows, P.ax1, 2, lpb,
-                       sc, 1);
+    ProfScope ps(P, sizeof(T) == 8 ? "rows_solve_f64" : "rows_solve_f32", s);
+    hipLaunchKernelGGL(k_rows<T>, dim3(sh.rblocks), dim3(256), sh.rshm, s,
+                       rows_args<T>(P, sh, data, 2, nullptr));
     return;
   }
   {
-    ProfScope ps(P, "rows_fwd", s);
-    hipLaunchKernelGGL(k_rows<T>, dim3(rblocks), dim3(256), rshm, s, data, nrows, P.ax1, 0, lpb,
-                       sc, g.n0);
+    ProfScope ps(P, sizeof(T) == 8 ? "rows_fwd_f64" : "rows_fwd_f32", s);
+    hipLaunchKernelGGL(k_rows<T>, dim3(sh.rblocks), dim3(256), sh.rshm, s,
+                       rows_args<T>(P, sh, data, 0, nullptr));
   }
-  // columns per block: two real columns per complex line; LDS (two buffers)
-  // kept at or below 64 KB
-  int lines = P.tune.cols_lines;
-  const int lmax =
-      (int)((65536 - 4 * (size_t)g.n0 * sizeof(T)) / (2 * (size_t)g.n0 * sizeof(C2<T>)));
-  if (lines > lmax) lines = lmax;
-  if (lines < 1) lines = 1;
-  const int cw = 2 * lines;
-  const int ncb = (g.n1 + cw - 1) / cw;
-  const size_t cshm = 2 * (size_t)lines * g.n0 * sizeof(C2<T>) + 4 * (size_t)g.n0 * sizeof(T);
   {
-    ProfScope ps(P, "cols_solve", s);
-    hipLaunchKernelGGL(k_cols_solve<T>, dim3(g.nt * ncb), dim3(256), cshm, s, data, g, P.ax0, cw,
-                       sc);
+    ProfScope ps(P, sizeof(T) == 8 ? "cols_solve_f64" : "cols_solve_f32", s);
+    hipLaunchKernelGGL(k_cols_solve<T>, dim3(sh.cblocks), dim3(256), sh.cshm, s,
+                       cols_args<T>(P, sh, data, nullptr));
   }
-  ProfScope ps(P, "rows_inv", s);
-  hipLaunchKernelGGL(k_rows<T>, dim3(rblocks), dim3(256), rshm, s, data, nrows, P.ax1, 1, lpb, sc,
-                     g.n0);
+  ProfScope ps(P, sizeof(T) == 8 ? "rows_inv_f64" : "rows_inv_f32", s);
+  hipLaunchKernelGGL(k_rows<T>, dim3(sh.rblocks), dim3(256), sh.rshm, s,
+                     rows_args<T>(P, sh, data, 1, nullptr));
 }
 
 }  // namespace
@@ -452,6 +506,35 @@ void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
   tgemm<double, float>(P, mode, r, tmp, DOT_NONE, nullptr, nullptr, s, fwd_names[mode]);
   spatial_solves<float>(P, tmp, s);
   tgemm<float, double>(P, mode, tmp, z, dotmode, r, q, s, inv_names[mode]);
+}
+
+// ---- batched spatial solves: float32 data (mixed precision) ----
+void batch_rows_args(const Plan& P, float* data, int mode, const double* done, void* out,
+                     int* blocks, size_t* shm) {
+  const SpatialShape sh = spatial_shape<float>(P);
+  *reinterpret_cast<RowsArgs<float>*>(out) = rows_args<float>(P, sh, data, mode, done);
+  *blocks = sh.rblocks;
+  *shm = sh.rshm;
+}
+
+void batch_cols_args(const Plan& P, float* data, const double* done, void* out, int* blocks,
+                     size_t* shm) {
+  const SpatialShape sh = spatial_shape<float>(P);
+  *reinterpret_cast<ColsArgs<float>*>(out) = cols_args<float>(P, sh, data, done);
+  *blocks = sh.cblocks;
+  *shm = sh.cshm;
+}
+
+void launch_rows_batch_f32(const void* A, const int* off, int ninst, int total, size_t shm,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_rows_batch<float>, dim3(total), dim3(256), shm, s,
+                     reinterpret_cast<const RowsArgs<float>*>(A), off, ninst);
+}
+
+void launch_cols_batch_f32(const void* A, const int* off, int ninst, int total, size_t shm,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_cols_batch<float>, dim3(total), dim3(256), shm, s,
+                     reinterpret_cast<const ColsArgs<float>*>(A), off, ninst);
 }
 
 }  // namespace mfg

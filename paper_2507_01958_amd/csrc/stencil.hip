@@ -15,6 +15,7 @@
 //   (D^1)^T u = u_i - u_{i+1},  (D^2)^T u = u_{i-1} - u_i (both vanish across a
 //        Neumann boundary under the reflection).
 // B = [D^1_x, D^2_x, D^1_y, D^2_y] / h and L = nu K + I/dt (Section 3).
+#include "batch_args.h"
 #include "device_util.h"
 #include "plan.h"
 
@@ -55,13 +56,16 @@ __device__ __forceinline__ double D2w(F f, int i, int n, int neumann) {
 // b = Cr (xi + sigma ybar) - sigma [t==0] m0/dt. With ybar == nullptr this is
 // b = Cr xi (apply_C).
 template <bool HASBAR>
-__global__ __launch_bounds__(kThreads) void k_rhs(Geom g, const double* __restrict__ xi,
-                                                  const double* __restrict__ ybar, double sigma,
-                                                  const double* __restrict__ m0,
-                                                  double* __restrict__ b) {
+__device__ void rhs_body(const RhsArgs& a, int bid, int nb) {
+  const Geom g = a.g;
+  const double* __restrict__ xi = a.xi;
+  const double* __restrict__ ybar = a.ybar;
+  const double* __restrict__ m0 = a.m0;
+  double* __restrict__ b = a.b;
+  const double sigma = a.sigma_dev ? *a.sigma_dev : a.sigma;
   const long long n = g.n;
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-       p += (long long)gridDim.x * blockDim.x) {
+  for (long long p = (long long)bid * blockDim.x + threadIdx.x; p < n;
+       p += (long long)nb * blockDim.x) {
     const int t = (int)(p / g.M);
     const int rem = (int)(p - (long long)t * g.M);
     const int i0 = rem / g.n1, i1 = rem - i0 * g.n1;
@@ -155,18 +159,22 @@ struct Tile {
 };
 
 template <bool HAS0, bool FUSE>
-__global__ __launch_bounds__(kThreads) void k_AAt_tile(Geom g, const double* __restrict__ src,
-                                                       const double* __restrict__ pold,
-                                                       double* __restrict__ pnew,
-                                                       double* __restrict__ q, RedBuf rb, int tc,
-                                                       int first, int reduce) {
+__device__ void aat_body(const AatArgs& a, int bid, int nb) {
+  if (a.done && *a.done != 0.0) return;
   using C = Tile<HAS0>;
+  const Geom g = a.g;
+  const double* __restrict__ src = a.src;
+  const double* __restrict__ pold = a.pold;
+  double* __restrict__ pnew = a.pnew;
+  double* __restrict__ q = a.q;
+  const RedBuf rb = a.rb;
+  const int tc = a.tc, first = a.first, reduce = a.reduce;
   __shared__ double U[3][C::SI * C::SJ];
   __shared__ double G[C::GI * C::GJ];
   const int tiles1 = (g.n1 + kTJ - 1) / kTJ;
   const int tiles0 = HAS0 ? (g.n0 + C::TI - 1) / C::TI : 1;
   const int nchunk = (g.nt + tc - 1) / tc;
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int blk = xcd_remap(bid, nb);
   const int tile = blk / nchunk, chunk = blk - tile * nchunk;
   const int i0 = (tile / tiles1) * C::TI, j0 = (tile % tiles1) * kTJ;
   (void)tiles0;
@@ -258,8 +266,8 @@ __global__ __launch_bounds__(kThreads) void k_AAt_tile(Geom g, const double* __r
     sn = tmp;
   }
   if (reduce) {
-    double a[1] = {acc};
-    reduce_store<1>(a, rb, T_PQ);
+    double v[1] = {acc};
+    reduce_store<1>(v, rb, T_PQ, bid);
   }
 }
 
@@ -314,17 +322,20 @@ __global__ __launch_bounds__(kThreads) void k_prox(Geom g, const double* __restr
 // One CP iteration after the projection solve:
 //   xi' = Cr^T u;  y' = prox_{tau phi}(y - tau xi');  ybar = y' + theta (y' - y);
 // partial ||m' - m||^2 reduced into the device scalar S_DM.
-__global__ __launch_bounds__(kThreads) void k_backproj_prox(Geom g, const double* __restrict__ u,
-                                                            double* __restrict__ xi,
-                                                            double* __restrict__ y,
-                                                            double* __restrict__ ybar,
-                                                            const double* __restrict__ Vpot,
-                                                            double tau, double theta,
-                                                            RedBuf rb, double* __restrict__ vout) {
+__device__ void backproj_body(const BackprojArgs& a, int bid, int nb) {
+  const Geom g = a.g;
+  const double* __restrict__ u = a.u;
+  double* __restrict__ xi = a.xi;
+  double* __restrict__ y = a.y;
+  double* __restrict__ ybar = a.ybar;
+  const double* __restrict__ Vpot = a.V;
+  double* __restrict__ vout = a.vout;
+  const double tau = a.tau_dev ? *a.tau_dev : a.tau;
+  const double theta = a.theta_dev ? *a.theta_dev : a.theta;
   const long long n = g.n;
   double acc[1] = {0.0};
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-       p += (long long)gridDim.x * blockDim.x) {
+  for (long long p = (long long)bid * blockDim.x + threadIdx.x; p < n;
+       p += (long long)nb * blockDim.x) {
     const int t = (int)(p / g.M);
     const int rem = (int)(p - (long long)t * g.M);
     const int i0 = rem / g.n1, i1 = rem - i0 * g.n1;
@@ -348,7 +359,40 @@ __global__ __launch_bounds__(kThreads) void k_backproj_prox(Geom g, const double
     const double dm = m - yo[0];
     acc[0] += dm * dm;
   }
-  reduce_store<1>(acc, rb, T_DM);
+  reduce_store<1>(acc, a.rb, T_DM, bid);
+}
+
+__global__ __launch_bounds__(kThreads) void k_backproj_prox(BackprojArgs a) {
+  backproj_body(a, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(kThreads) void k_backproj_prox_batch(const BackprojArgs* A,
+                                                                  const int* off, int ninst) {
+  const int i = batch_instance(off, ninst, blockIdx.x);
+  backproj_body(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
+}
+
+template <bool HASBAR>
+__global__ __launch_bounds__(kThreads) void k_rhs(RhsArgs a) {
+  rhs_body<HASBAR>(a, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(kThreads) void k_rhs_batch(const RhsArgs* A, const int* off,
+                                                        int ninst) {
+  const int i = batch_instance(off, ninst, blockIdx.x);
+  rhs_body<true>(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
+}
+
+template <bool HAS0, bool FUSE>
+__global__ __launch_bounds__(kThreads) void k_AAt_tile(AatArgs a) {
+  aat_body<HAS0, FUSE>(a, blockIdx.x, gridDim.x);
+}
+
+template <bool HAS0>
+__global__ __launch_bounds__(kThreads) void k_AAt_batch(const AatArgs* A, const int* off,
+                                                        int ninst) {
+  const int i = batch_instance(off, ninst, blockIdx.x);
+  aat_body<HAS0, true>(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
 }
 
 // One thread per node up to `cap` blocks (grid-stride beyond that).
@@ -370,35 +414,49 @@ int aat_chunk(const Geom& g, int ntile, int max_blocks) {
   return (int)tc;
 }
 
-template <bool HAS0, bool FUSE>
-void aat_launch(const Plan& P, const double* src, const double* pold, double* pnew, double* q,
-                bool first, bool reduce, hipStream_t s) {
+template <bool HAS0>
+int aat_shape(const Plan& P, int* tc_out) {
   const Geom& g = P.g;
   const int ntile = ((g.n0 + Tile<HAS0>::TI - 1) / Tile<HAS0>::TI) * ((g.n1 + kTJ - 1) / kTJ);
   const int tc = aat_chunk(g, ntile, P.red.max_blocks);
-  const int nchunk = (g.nt + tc - 1) / tc;
-  const int grid = ntile * nchunk;
+  *tc_out = tc;
+  return ntile * ((g.nt + tc - 1) / tc);
+}
+
+template <bool HAS0, bool FUSE>
+void aat_launch(const Plan& P, const double* src, const double* pold, double* pnew, double* q,
+                bool first, bool reduce, hipStream_t s) {
+  int tc;
+  const int grid = aat_shape<HAS0>(P, &tc);
+  const AatArgs a{P.g, src, pold, pnew, q, P.red, tc, first ? 1 : 0, reduce ? 1 : 0, nullptr};
   {
     ProfScope ps(P, FUSE ? "aat_fused" : "aat", s);
-    hipLaunchKernelGGL((k_AAt_tile<HAS0, FUSE>), dim3(grid), dim3(kThreads), 0, s, g, src, pold,
-                       pnew, q, P.red, tc, first ? 1 : 0, reduce ? 1 : 0);
+    hipLaunchKernelGGL((k_AAt_tile<HAS0, FUSE>), dim3(grid), dim3(kThreads), 0, s, a);
   }
   if (reduce) launch_finish(P, T_PQ, grid, OP_PQ, s);
 }
 
 }  // namespace
 
+RhsArgs rhs_args(const Plan& P, const double* xi, const double* ybar, double sigma,
+                 const double* sigma_dev, double* b) {
+  return RhsArgs{P.g, xi, ybar, sigma, sigma_dev, P.m0, b};
+}
+
+int rhs_grid(const Plan& P) { return grid_for(P.g.n, 1 << 20); }
+
 void launch_rhs(const Plan& P, const double* xi, const double* ybar, double sigma,
                 const double* m0, double* b, hipStream_t s) {
   ProfScope ps(P, "rhs", s);
-  hipLaunchKernelGGL(k_rhs<true>, dim3(grid_for(P.g.n, 1 << 20)), dim3(kThreads), 0, s,
-                     P.g, xi, ybar, sigma, m0, b);
+  RhsArgs a = rhs_args(P, xi, ybar, sigma, nullptr, b);
+  a.m0 = m0;
+  hipLaunchKernelGGL(k_rhs<true>, dim3(rhs_grid(P)), dim3(kThreads), 0, s, a);
 }
 
 void launch_apply_C(const Plan& P, const double* y, double* b, hipStream_t s) {
   ProfScope ps(P, "apply_C", s);
-  hipLaunchKernelGGL(k_rhs<false>, dim3(grid_for(P.g.n, 1 << 20)), dim3(kThreads), 0, s,
-                     P.g, y, (const double*)nullptr, 0.0, (const double*)nullptr, b);
+  const RhsArgs a{P.g, y, nullptr, 0.0, nullptr, nullptr, b};
+  hipLaunchKernelGGL(k_rhs<false>, dim3(rhs_grid(P)), dim3(kThreads), 0, s, a);
 }
 
 void launch_apply_CT(const Plan& P, const double* u, double* y, hipStream_t s) {
@@ -424,15 +482,48 @@ void launch_prox(const Plan& P, const double* v, double tau, double* y, hipStrea
                      v, (const double*)P.V, tau, y);
 }
 
+BackprojArgs backproj_args(const Plan& P, const double* u, double* xi, double* y, double* ybar,
+                           double tau, double theta, const double* tau_dev,
+                           const double* theta_dev, double* vout) {
+  return BackprojArgs{P.g, u, xi, y, ybar, P.V, tau, theta, tau_dev, theta_dev, P.red, vout};
+}
+
+int backproj_grid(const Plan& P) { return grid_for(P.g.n, P.red.max_blocks); }
+
 void launch_backproj_prox(const Plan& P, const double* u, double* xi, double* y, double* ybar,
                           double tau, double theta, hipStream_t s, double* vout) {
-  const int grid = grid_for(P.g.n, P.red.max_blocks);
+  const int grid = backproj_grid(P);
   {
     ProfScope ps(P, "backproj_prox", s);
-    hipLaunchKernelGGL(k_backproj_prox, dim3(grid), dim3(kThreads), 0, s, P.g, u, xi, y, ybar,
-                       (const double*)P.V, tau, theta, P.red, vout);
+    hipLaunchKernelGGL(k_backproj_prox, dim3(grid), dim3(kThreads), 0, s,
+                       backproj_args(P, u, xi, y, ybar, tau, theta, nullptr, nullptr, vout));
   }
   launch_finish(P, T_DM, grid, OP_DM, s);
+}
+
+// ---- batched launches (args / offsets are device arrays, see batch_args.h) ----
+AatArgs aat_args(const Plan& P, const double* z, const double* pold, double* pnew, double* q,
+                 bool first, const double* done, int* grid) {
+  int tc;
+  *grid = P.g.has0 ? aat_shape<true>(P, &tc) : aat_shape<false>(P, &tc);
+  return AatArgs{P.g, z, pold, pnew, q, P.red, tc, first ? 1 : 0, 1, done};
+}
+
+void launch_aat_batch(bool has0, const AatArgs* A, const int* off, int ninst, int total,
+                      hipStream_t s) {
+  if (has0)
+    hipLaunchKernelGGL(k_AAt_batch<true>, dim3(total), dim3(kThreads), 0, s, A, off, ninst);
+  else
+    hipLaunchKernelGGL(k_AAt_batch<false>, dim3(total), dim3(kThreads), 0, s, A, off, ninst);
+}
+
+void launch_rhs_batch(const RhsArgs* A, const int* off, int ninst, int total, hipStream_t s) {
+  hipLaunchKernelGGL(k_rhs_batch, dim3(total), dim3(kThreads), 0, s, A, off, ninst);
+}
+
+void launch_backproj_batch(const BackprojArgs* A, const int* off, int ninst, int total,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_backproj_prox_batch, dim3(total), dim3(kThreads), 0, s, A, off, ninst);
 }
 
 }  // namespace mfg

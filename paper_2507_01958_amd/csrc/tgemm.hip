@@ -13,6 +13,7 @@
 //   and the products are scaled back exactly.
 // V is symmetric (V[k][t] = V[t][k] for the DCT-VIII and the DST-I), which the
 // LDS staging uses to read it with unit stride.
+#include "batch_args.h"
 #include "tgemm.h"
 
 namespace mfg {
@@ -25,17 +26,21 @@ typedef _Float16 v4h __attribute__((ext_vector_type(4)));
 typedef short v4s __attribute__((ext_vector_type(4)));
 
 template <int KB, int CB, typename TX, typename TY>
-__global__ __launch_bounds__(256) void k_tgemm64(const double* __restrict__ Vt,
-                                                 const TX* __restrict__ X, TY* __restrict__ Y,
-                                                 int nt, int M, int ncolblk, int dotmode,
-                                                 const double* __restrict__ rvec,
-                                                 const double* __restrict__ qvec, RedBuf rb) {
+__device__ void tgemm64_body(const GemmArgs<TX, TY>& ga, int bid) {
+  if (ga.done && *ga.done != 0.0) return;
+  const double* __restrict__ Vt = static_cast<const double*>(ga.V);
+  const TX* __restrict__ X = ga.X;
+  TY* __restrict__ Y = ga.Y;
+  const int nt = ga.nt, M = ga.M, ncolblk = ga.ncolblk, dotmode = ga.dotmode;
+  const double* __restrict__ rvec = ga.rvec;
+  const double* __restrict__ qvec = ga.qvec;
+  const RedBuf rb = ga.rb;
   constexpr int KW = KB * 16;
   constexpr int TK = 16;
   constexpr int VPER = TK * KW / 256;
   __shared__ double Vs[TK * KW];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int cbk = blockIdx.x % ncolblk, kc = blockIdx.x / ncolblk;
+  const int cbk = bid % ncolblk, kc = bid / ncolblk;
   const int kbase = kc * KW;
   const int col0 = (cbk * 4 + wave) * CB * 16 + (lane & 15);
   const int kq = lane >> 4;
@@ -109,7 +114,12 @@ __global__ __launch_bounds__(256) void k_tgemm64(const double* __restrict__ Vt,
         }
       }
   }
-  if (dotmode != DOT_NONE) reduce_store<2>(dots, rb, T_RZ);
+  if (dotmode != DOT_NONE) reduce_store<2>(dots, rb, T_RZ, bid);
+}
+
+template <int KB, int CB, typename TX, typename TY>
+__global__ __launch_bounds__(256) void k_tgemm64(GemmArgs<TX, TY> a) {
+  tgemm64_body<KB, CB, TX, TY>(a, blockIdx.x);
 }
 
 __device__ __forceinline__ short f2bf(float f) {
@@ -139,12 +149,16 @@ struct LpTraits<GM_BF16> {
 // NTP: N_t padded to a multiple of 16 (<= 128). The block covers 4 waves x CB
 // blocks of 16 nodes and all N_t output rows.
 template <int MODE, int NTP, int CB, typename TX, typename TY>
-__global__ __launch_bounds__(256) void k_tgemm_lp(const typename LpTraits<MODE>::VT* __restrict__ Vg,
-                                                  const TX* __restrict__ X, TY* __restrict__ Y,
-                                                  int nt, int M, int dotmode,
-                                                  const double* __restrict__ rvec,
-                                                  const double* __restrict__ qvec, RedBuf rb) {
+__device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
+  if (ga.done && *ga.done != 0.0) return;
   using VT = typename LpTraits<MODE>::VT;
+  const VT* __restrict__ Vg = static_cast<const VT*>(ga.V);
+  const TX* __restrict__ X = ga.X;
+  TY* __restrict__ Y = ga.Y;
+  const int nt = ga.nt, M = ga.M, dotmode = ga.dotmode;
+  const double* __restrict__ rvec = ga.rvec;
+  const double* __restrict__ qvec = ga.qvec;
+  const RedBuf rb = ga.rb;
   constexpr int KSTEP = LpTraits<MODE>::KSTEP;
   constexpr int NKS = NTP / KSTEP;  // k-steps
   constexpr int NKB = NTP / 16;     // output row blocks
@@ -153,7 +167,7 @@ __global__ __launch_bounds__(256) void k_tgemm_lp(const typename LpTraits<MODE>:
   __shared__ float smax[4];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int kq = lane >> 4;
-  const int col0 = (blockIdx.x * 4 + wave) * CB * 16 + (lane & 15);
+  const int col0 = (bid * 4 + wave) * CB * 16 + (lane & 15);
   // operands: t = KSTEP*ks + PER*kq + j
   float xs[CB][NKS][PER];
   float amax = 0.0f;
@@ -274,7 +288,19 @@ __global__ __launch_bounds__(256) void k_tgemm_lp(const typename LpTraits<MODE>:
         }
       }
   }
-  if (dotmode != DOT_NONE) reduce_store<2>(dots, rb, T_RZ);
+  if (dotmode != DOT_NONE) reduce_store<2>(dots, rb, T_RZ, bid);
+}
+
+template <int MODE, int NTP, int CB, typename TX, typename TY>
+__global__ __launch_bounds__(256) void k_tgemm_lp(GemmArgs<TX, TY> a) {
+  tgemm_lp_body<MODE, NTP, CB, TX, TY>(a, blockIdx.x);
+}
+
+template <int MODE, int NTP, int CB, typename TX, typename TY>
+__global__ __launch_bounds__(256) void k_tgemm_lp_batch(const GemmArgs<TX, TY>* A, const int* off,
+                                                        int ninst) {
+  const int i = batch_instance(off, ninst, blockIdx.x);
+  tgemm_lp_body<MODE, NTP, CB, TX, TY>(A[i], blockIdx.x - off[i]);
 }
 
 // Persistent form for N_t <= 128 (NTP = N_t rounded up to 16): each block
@@ -464,7 +490,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tgemm_pers(const typename PersTr
       }
     }
   }
-  if (dotmode != DOT_NONE) reduce_store<2>(dots, rb, T_RZ);
+  if (dotmode != DOT_NONE) reduce_store<2>(dots, rb, T_RZ, blockIdx.x);
 }
 
 template <int MODE, int NTP, typename TX, typename TY>
@@ -505,15 +531,18 @@ int pers_dispatch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* 
   }
 }
 
+const void* lp_table(const Plan& P, int mode) {
+  return (mode == GM_F32) ? (const void*)P.Vp32
+         : (mode == GM_F16) ? (const void*)P.Vp16 : (const void*)P.Vpbf;
+}
+
 template <int MODE, int NTP, int CB, typename TX, typename TY>
 int lp_launch_cb(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r, const double* q,
                  hipStream_t s) {
   const int M = P.g.M;
   const int grid = (M + 64 * CB - 1) / (64 * CB);
-  const void* V = (MODE == GM_F32) ? (const void*)P.Vp32
-                  : (MODE == GM_F16) ? (const void*)P.Vp16 : (const void*)P.Vpbf;
-  hipLaunchKernelGGL((k_tgemm_lp<MODE, NTP, CB, TX, TY>), dim3(grid), dim3(256), 0, s,
-                     (const typename LpTraits<MODE>::VT*)V, X, Y, P.g.nt, M, dotmode, r, q, P.red);
+  const GemmArgs<TX, TY> a{lp_table(P, MODE), X, Y, P.g.nt, M, 0, dotmode, r, q, P.red, nullptr};
+  hipLaunchKernelGGL((k_tgemm_lp<MODE, NTP, CB, TX, TY>), dim3(grid), dim3(256), 0, s, a);
   return grid;
 }
 
@@ -546,8 +575,8 @@ int f64_launch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r, 
   const int ncolblk = (M + 64 * CB - 1) / (64 * CB);
   const int nkc = (nt + KB * 16 - 1) / (KB * 16);
   const int grid = ncolblk * nkc;
-  hipLaunchKernelGGL((k_tgemm64<KB, CB, TX, TY>), dim3(grid), dim3(256), 0, s, P.Vt64, X, Y, nt,
-                     M, ncolblk, dotmode, r, q, P.red);
+  const GemmArgs<TX, TY> a{P.Vt64, X, Y, nt, M, ncolblk, dotmode, r, q, P.red, nullptr};
+  hipLaunchKernelGGL((k_tgemm64<KB, CB, TX, TY>), dim3(grid), dim3(256), 0, s, a);
   return grid;
 }
 
@@ -596,5 +625,56 @@ template void tgemm<double, float>(const Plan&, int, const double*, float*, int,
                                     const double*, const double*, hipStream_t, const char*);
 template void tgemm<float, double>(const Plan&, int, const float*, double*, int,
                                     const double*, const double*, hipStream_t, const char*);
+
+// ---- batched low-precision time GEMM (one N_t padding class per launch) ----
+template <typename TX, typename TY>
+GemmArgs<TX, TY> batch_gemm_args(const Plan& P, int mode, const TX* X, TY* Y, int dotmode,
+                                 const double* r, const double* q, const double* done,
+                                 int* blocks) {
+  *blocks = (P.g.M + 127) / 128;  // CB = 2
+  return GemmArgs<TX, TY>{lp_table(P, mode), X, Y, P.g.nt, P.g.M, 0, dotmode, r, q, P.red, done};
+}
+
+template <int MODE, typename TX, typename TY>
+void lp_batch_dispatch(int ntp, const GemmArgs<TX, TY>* A, const int* off, int ninst, int total,
+                       hipStream_t s) {
+#define MFG_LPB(NTPV)                                                                       \
+  case NTPV:                                                                                \
+    hipLaunchKernelGGL((k_tgemm_lp_batch<MODE, NTPV, 2, TX, TY>), dim3(total), dim3(256), 0, \
+                       s, A, off, ninst);                                                   \
+    break;
+  switch (ntp) {
+    MFG_LPB(16)
+    MFG_LPB(32)
+    MFG_LPB(48)
+    MFG_LPB(64)
+    MFG_LPB(80)
+    MFG_LPB(96)
+    MFG_LPB(112)
+    default:
+      hipLaunchKernelGGL((k_tgemm_lp_batch<MODE, 128, 2, TX, TY>), dim3(total), dim3(256), 0, s,
+                         A, off, ninst);
+  }
+#undef MFG_LPB
+}
+
+template <typename TX, typename TY>
+void launch_gemm_batch(int mode, int ntp, const GemmArgs<TX, TY>* A, const int* off, int ninst,
+                       int total, hipStream_t s) {
+  if (mode == GM_F32) lp_batch_dispatch<GM_F32>(ntp, A, off, ninst, total, s);
+  else if (mode == GM_F16) lp_batch_dispatch<GM_F16>(ntp, A, off, ninst, total, s);
+  else lp_batch_dispatch<GM_BF16>(ntp, A, off, ninst, total, s);
+}
+
+template GemmArgs<double, float> batch_gemm_args(const Plan&, int, const double*, float*, int,
+                                                 const double*, const double*, const double*,
+                                                 int*);
+template GemmArgs<float, double> batch_gemm_args(const Plan&, int, const float*, double*, int,
+                                                 const double*, const double*, const double*,
+                                                 int*);
+template void launch_gemm_batch(int, int, const GemmArgs<double, float>*, const int*, int, int,
+                                hipStream_t);
+template void launch_gemm_batch(int, int, const GemmArgs<float, double>*, const int*, int, int,
+                                hipStream_t);
 
 }  // namespace mfg

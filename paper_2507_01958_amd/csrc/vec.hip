@@ -1,6 +1,11 @@
 // Vector kernels of the (flexible) preconditioned conjugate gradient method
 // (Sections 3-4) with device-resident scalars and deterministic two-stage
 // reductions, and the initial Chambolle-Pock point.
+//
+// Each kernel body is a device function of (arguments, block id, block count):
+// the single-instance kernels call it with blockIdx/gridDim, the batched
+// kernels (batch.hip) with the block's place inside its instance.
+#include "batch_args.h"
 #include "device_util.h"
 #include "plan.h"
 
@@ -17,58 +22,45 @@ int grid_for(long long n) {
   return (int)b;
 }
 
+}  // namespace
+
 // x = 0, r = b; partial b.b.
-__global__ __launch_bounds__(kThreads) void k_pcg_init(long long n, const double* __restrict__ b,
-                                                       double* __restrict__ x,
-                                                       double* __restrict__ r, RedBuf rb) {
+__device__ void pcg_init_body(const InitArgs& a, int bid, int nb) {
   double acc[1] = {0.0};
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    const double v = b[i];
-    x[i] = 0.0;
-    r[i] = v;
+  for (long long i = (long long)bid * blockDim.x + threadIdx.x; i < a.n;
+       i += (long long)nb * blockDim.x) {
+    const double v = a.b[i];
+    a.x[i] = 0.0;
+    a.r[i] = v;
     acc[0] += v * v;
   }
-  reduce_store<1>(acc, rb, T_BB);
+  reduce_store<1>(acc, a.rb, T_BB, bid);
 }
 
-// x += alpha p; r -= alpha q; partial r.r.
-__global__ __launch_bounds__(kThreads) void k_update(long long n, double* __restrict__ x,
-                                                     double* __restrict__ r,
-                                                     const double* __restrict__ p,
-                                                     const double* __restrict__ q, RedBuf rb) {
-  const double alpha = rb.scal[S_ALPHA];
+// x += alpha p; r -= alpha q; partial r.r. Skipped once the instance has
+// converged (batched path only: a.done is null otherwise).
+__device__ void update_body(const UpdArgs& a, int bid, int nb) {
+  if (a.done && *a.done != 0.0) return;
+  const double alpha = a.rb.scal[S_ALPHA];
   double acc[1] = {0.0};
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
-    r[i] = ri;
+  for (long long i = (long long)bid * blockDim.x + threadIdx.x; i < a.n;
+       i += (long long)nb * blockDim.x) {
+    a.x[i] += alpha * a.p[i];
+    const double ri = a.r[i] - alpha * a.q[i];
+    a.r[i] = ri;
     acc[0] += ri * ri;
   }
-  reduce_store<1>(acc, rb, T_RR);
+  reduce_store<1>(acc, a.rb, T_RR, bid);
 }
 
-// partials of ||b - Ax||^2 and ||b||^2.
-__global__ __launch_bounds__(kThreads) void k_residual(long long n, const double* __restrict__ b,
-                                                       const double* __restrict__ Ax, RedBuf rb) {
-  double acc[2] = {0.0, 0.0};
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    const double bi = b[i];
-    const double d = bi - Ax[i];
-    acc[0] += d * d;
-    acc[1] += bi * bi;
-  }
-  reduce_store<2>(acc, rb, T_AUX);
-}
-
-// Sum the partials of one site in block order (single block) and apply `op`.
-__global__ __launch_bounds__(256) void k_finish(RedBuf rb, int site, int nblocks, int op) {
+// Sum the partials of one site in block order (one block) and apply `op`.
+__device__ void finish_body(const FinishArgs& f) {
+  const RedBuf& rb = f.rb;
+  if (f.done && *f.done != 0.0) return;
   __shared__ double sh[2 * 16];
-  const double* part = rb.partials + (size_t)site * kSlotsPerSite * rb.max_blocks;
+  const double* part = rb.partials + (size_t)f.site * kSlotsPerSite * rb.max_blocks;
   double v[2] = {0.0, 0.0};
-  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+  for (int b = threadIdx.x; b < f.nblocks; b += blockDim.x) {
     v[0] += part[b];
     v[1] += part[(size_t)rb.max_blocks + b];
   }
@@ -76,7 +68,7 @@ __global__ __launch_bounds__(256) void k_finish(RedBuf rb, int site, int nblocks
   if (threadIdx.x != 0) return;
   double* S = rb.scal;
   const double a = v[0], c = v[1];
-  switch (op) {
+  switch (f.op) {
     case OP_BB:
       S[S_BB] = a;
       S[S_RR] = a;
@@ -97,8 +89,9 @@ __global__ __launch_bounds__(256) void k_finish(RedBuf rb, int site, int nblocks
       break;
     case OP_RR:
       S[S_RR] = a;
+      S[S_ITS] += 1.0;
       if (!finite_d(a)) S[S_BAD] = 2.0;
-      if (a <= S[S_TOL2] * S[S_BB]) S[S_DONE] = 1.0;
+      if (a <= S[S_TOL2] * S[S_BB] || S[S_BAD] != 0.0) S[S_DONE] = 1.0;
       break;
     case OP_RZ_INIT:
     case OP_RZ_STD:
@@ -107,14 +100,15 @@ __global__ __launch_bounds__(256) void k_finish(RedBuf rb, int site, int nblocks
         S[S_BAD] = 2.0;
       } else if (!(a > 0.0)) {
         S[S_BAD] = 1.0;
-      } else if (op == OP_RZ_INIT) {
+      } else if (f.op == OP_RZ_INIT) {
         S[S_RHO] = a;
         S[S_BETA] = 0.0;
       } else {
         const double rho = S[S_RHO];
-        S[S_BETA] = (op == OP_RZ_FLEX) ? -S[S_ALPHA] * c / rho : a / rho;
+        S[S_BETA] = (f.op == OP_RZ_FLEX) ? -S[S_ALPHA] * c / rho : a / rho;
         S[S_RHO] = a;
       }
+      if (S[S_BAD] != 0.0) S[S_DONE] = 1.0;
       break;
     case OP_DM:
       S[S_DM] = a;
@@ -128,6 +122,32 @@ __global__ __launch_bounds__(256) void k_finish(RedBuf rb, int site, int nblocks
   }
 }
 
+namespace {
+
+__global__ __launch_bounds__(kThreads) void k_pcg_init(InitArgs a) {
+  pcg_init_body(a, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(kThreads) void k_update(UpdArgs a) {
+  update_body(a, blockIdx.x, gridDim.x);
+}
+
+// partials of ||b - Ax||^2 and ||b||^2.
+__global__ __launch_bounds__(kThreads) void k_residual(long long n, const double* __restrict__ b,
+                                                       const double* __restrict__ Ax, RedBuf rb) {
+  double acc[2] = {0.0, 0.0};
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double bi = b[i];
+    const double d = bi - Ax[i];
+    acc[0] += d * d;
+    acc[1] += bi * bi;
+  }
+  reduce_store<2>(acc, rb, T_AUX, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_finish(FinishArgs f) { finish_body(f); }
+
 __global__ __launch_bounds__(kThreads) void k_fill(double* __restrict__ x, long long n, double v) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
@@ -139,6 +159,7 @@ __global__ __launch_bounds__(64) void k_set_scalars(double* scal, double tol2) {
     scal[S_TOL2] = tol2;
     scal[S_BAD] = 0.0;
     scal[S_DONE] = 0.0;
+    scal[S_ITS] = 0.0;
   }
 }
 
@@ -159,28 +180,54 @@ __global__ __launch_bounds__(kThreads) void k_cp_init(Geom g, const double* __re
 
 }  // namespace
 
+FinishArgs finish_args(const Plan& P, int site, int nblocks, int op) {
+  FinishArgs f;
+  f.rb = P.red;
+  f.site = site;
+  f.nblocks = nblocks;
+  f.op = op;
+  f.done = nullptr;
+  return f;
+}
+
 void launch_finish(const Plan& P, int site, int nblocks, int op, hipStream_t s) {
   ProfScope ps(P, "finish", s);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, P.red, site, nblocks, op);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, finish_args(P, site, nblocks, op));
+}
+
+InitArgs pcg_init_args(const Plan& P, const double* b, double* x, double* r) {
+  return InitArgs{P.g.n, b, x, r, P.red};
+}
+
+int pcg_init_grid(const Plan& P) { return grid_for(P.g.n); }
+
+void launch_set_scalars(const Plan& P, double rtol, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, P.red.scal, rtol * rtol);
 }
 
 void launch_pcg_init(const Plan& P, const double* b, double* x, double* r, double rtol,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, P.red.scal, rtol * rtol);
-  const int grid = grid_for(P.g.n);
+  launch_set_scalars(P, rtol, s);
+  const int grid = pcg_init_grid(P);
   {
     ProfScope ps(P, "pcg_init", s);
-    hipLaunchKernelGGL(k_pcg_init, dim3(grid), dim3(kThreads), 0, s, P.g.n, b, x, r, P.red);
+    hipLaunchKernelGGL(k_pcg_init, dim3(grid), dim3(kThreads), 0, s, pcg_init_args(P, b, x, r));
   }
   launch_finish(P, T_BB, grid, OP_BB, s);
 }
 
+UpdArgs update_args(const Plan& P, double* x, double* r, const double* p, const double* q) {
+  return UpdArgs{P.g.n, x, r, p, q, P.red, nullptr};
+}
+
+int update_grid(const Plan& P) { return grid_for(P.g.n); }
+
 void launch_update(const Plan& P, double* x, double* r, const double* p, const double* q,
                    hipStream_t s) {
-  const int grid = grid_for(P.g.n);
+  const int grid = update_grid(P);
   {
     ProfScope ps(P, "update", s);
-    hipLaunchKernelGGL(k_update, dim3(grid), dim3(kThreads), 0, s, P.g.n, x, r, p, q, P.red);
+    hipLaunchKernelGGL(k_update, dim3(grid), dim3(kThreads), 0, s, update_args(P, x, r, p, q));
   }
   launch_finish(P, T_RR, grid, OP_RR, s);
 }
@@ -202,6 +249,81 @@ void launch_cp_init(const Plan& P, double* xi, double* y, double* ybar, hipStrea
   ProfScope ps(P, "cp_init", s);
   hipLaunchKernelGGL(k_cp_init, dim3(grid_for(P.g.n * (1 + P.g.ncomp))), dim3(kThreads), 0, s,
                      P.g, (const double*)P.m0, xi, y, ybar);
+}
+
+// ---- batched launches (args / offsets are device arrays, see batch_args.h) ----
+namespace {
+
+__global__ __launch_bounds__(kThreads) void k_pcg_init_batch(const InitArgs* A, const int* off,
+                                                             int ninst) {
+  const int i = batch_instance(off, ninst, blockIdx.x);
+  pcg_init_body(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_update_batch(const UpdArgs* A, const int* off,
+                                                           int ninst) {
+  const int i = batch_instance(off, ninst, blockIdx.x);
+  update_body(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
+}
+
+// one block per instance
+__global__ __launch_bounds__(256) void k_finish_batch(const FinishArgs* F) {
+  finish_body(F[blockIdx.x]);
+}
+
+// Per instance i (scalar block at scal + i * stride): reset the PCG status.
+__global__ __launch_bounds__(64) void k_set_scalars_batch(double* scal, int stride, int ninst,
+                                                          const double* tol2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ninst) return;
+  double* S = scal + (size_t)i * stride;
+  S[S_TOL2] = tol2[i];
+  S[S_BAD] = 0.0;
+  S[S_DONE] = 0.0;
+  S[S_ITS] = 0.0;
+}
+
+// Per instance: load the step sizes of CP iteration S_CPIT from the schedule
+// table sched[(i * maxit + it) * 3 + {sigma, tau, theta}] and advance S_CPIT.
+__global__ __launch_bounds__(64) void k_cp_advance_batch(double* scal, int stride, int ninst,
+                                                         const double* sched, int maxit) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ninst) return;
+  double* S = scal + (size_t)i * stride;
+  int it = (int)S[S_CPIT];
+  if (it >= maxit) it = maxit - 1;
+  const double* e = sched + ((size_t)i * maxit + it) * 3;
+  S[S_SIGMA] = e[0];
+  S[S_TAU] = e[1];
+  S[S_THETA] = e[2];
+  S[S_CPIT] = (double)(it + 1);
+}
+
+}  // namespace
+
+void launch_pcg_init_batch(const InitArgs* A, const int* off, int ninst, int total,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_init_batch, dim3(total), dim3(kThreads), 0, s, A, off, ninst);
+}
+
+void launch_update_batch(const UpdArgs* A, const int* off, int ninst, int total, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_batch, dim3(total), dim3(kThreads), 0, s, A, off, ninst);
+}
+
+void launch_finish_batch(const FinishArgs* F, int ninst, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_batch, dim3(ninst), dim3(256), 0, s, F);
+}
+
+void launch_set_scalars_batch(double* scal, int stride, int ninst, const double* tol2,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_set_scalars_batch, dim3((ninst + 63) / 64), dim3(64), 0, s, scal, stride,
+                     ninst, tol2);
+}
+
+void launch_cp_advance_batch(double* scal, int stride, int ninst, const double* sched, int maxit,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_cp_advance_batch, dim3((ninst + 63) / 64), dim3(64), 0, s, scal, stride,
+                     ninst, sched, maxit);
 }
 
 }  // namespace mfg

@@ -61,6 +61,12 @@ SIGNATURES = {
     "mfg_cp_solve": (c_int, [c_void_p, POINTER(State), c_int, c_double, c_int, POINTER(Stats)]),
     "mfg_cp_adjoint": (c_int, [c_void_p, POINTER(State), c_int, c_int, c_int, c_void_p, c_double,
                                c_int, c_void_p, c_void_p]),
+    "mfg_plan_batch": (c_int, [POINTER(Problem), POINTER(c_void_p), POINTER(c_void_p), c_int,
+                               c_void_p, POINTER(c_void_p)]),
+    "mfg_batch_plan": (c_int, [c_void_p, c_int, POINTER(c_void_p)]),
+    "mfg_batch_destroy": (c_int, [c_void_p]),
+    "mfg_batch_cp_solve": (c_int, [c_void_p, POINTER(State), c_int, c_double, c_int, c_int,
+                                   POINTER(c_int)]),
     "mfg_profile": (c_int, [c_void_p, c_int]),
     "mfg_profile_report": (c_int, [c_void_p, ctypes.c_char_p, c_int]),
     "mfg_last_error": (c_char_p, []),
@@ -132,7 +138,19 @@ def make_problem(d, nx, ny, nt, bc, nu, gamma, l=1, precision="fp64", T=1.0, lo=
 class Plan:
     """Owns an mfg_plan_t; use close() (or a with-block) to release it."""
 
-    def __init__(self, problem: Problem, V, m0, stream=None):
+    def __init__(self, problem: Problem, V, m0, stream=None, _handle=None):
+        self._shape(problem)
+        if _handle is not None:  # borrowed from a batch: not released here
+            self.handle = _handle
+            self._owned = False
+            return
+        h = c_void_p()
+        _check(load().mfg_plan(ctypes.byref(problem), _ptr(V), _ptr(m0), _stream(stream),
+                               ctypes.byref(h)))
+        self.handle = h
+        self._owned = True
+
+    def _shape(self, problem):
         self.problem = problem
         self.d = problem.d
         self.nx, self.ny = problem.n[0], (problem.n[1] if problem.d == 2 else 1)
@@ -140,13 +158,9 @@ class Plan:
         self.M = self.nx * self.ny
         self.n = self.nt * self.M
         self.nprimal = (1 + 2 * self.d) * self.n
-        h = c_void_p()
-        _check(load().mfg_plan(ctypes.byref(problem), _ptr(V), _ptr(m0), _stream(stream),
-                               ctypes.byref(h)))
-        self.handle = h
 
     def close(self):
-        if self.handle is not None and self.handle.value:
+        if self._owned and self.handle is not None and self.handle.value:
             _check(load().mfg_destroy(self.handle))
         self.handle = None
 
@@ -295,6 +309,72 @@ def mfg_cp_adjoint(plan: Plan, ckpts, every: int, n_iter: int, gy, pcg_rtol: flo
                                float(pcg_rtol), int(pcg_maxit), _ptr(g_m0), _ptr(g_V))
     _check(rc, allow=() if raise_not_converged else (3,))
     return rc
+
+
+class Batch:
+    """Owns an mfg_batch_t; `plans[i]` are the instances' (borrowed) plans."""
+
+    def __init__(self, problems, Vs, m0s, stream=None):
+        n = len(problems)
+        arr = (Problem * n)(*problems)
+        vp = (c_void_p * n)(*[_ptr(v).value for v in Vs])
+        mp = (c_void_p * n)(*[_ptr(m).value for m in m0s])
+        h = c_void_p()
+        _check(load().mfg_plan_batch(arr, vp, mp, n, _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        self.count = n
+        self.plans = []
+        for i in range(n):
+            ph = c_void_p()
+            _check(load().mfg_batch_plan(h, i, ctypes.byref(ph)))
+            self.plans.append(Plan(problems[i], None, None, _handle=ph))
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            for p in self.plans:
+                p.handle = None
+            _check(load().mfg_batch_destroy(self.handle))
+        self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mfg_plan_batch(problems, Vs, m0s, stream=None) -> Batch:
+    return Batch(problems, Vs, m0s, stream)
+
+
+def mfg_batch_destroy(batch: Batch):
+    batch.close()
+
+
+def mfg_batch_cp_solve(batch: Batch, states, n_iter: int, pcg_rtol: float, pcg_maxit: int,
+                       use_graph: bool = True, raise_not_converged: bool = True):
+    """Runs n_iter CP iterations on every instance (states: list of CPState);
+    returns the PCG iteration counts as a list of per-iteration lists."""
+    n = batch.count
+    arr = (State * n)()
+    for i, st in enumerate(states):
+        st._sync_ptrs()
+        arr[i] = st.c
+    its = (c_int * max(1, n_iter * n))()
+    rc = load().mfg_batch_cp_solve(batch.handle, arr, int(n_iter), float(pcg_rtol),
+                                   int(pcg_maxit), 1 if use_graph else 0,
+                                   ctypes.cast(its, POINTER(c_int)))
+    for i, st in enumerate(states):
+        st.c.sigma, st.c.tau, st.c.theta, st.c.iter = (arr[i].sigma, arr[i].tau, arr[i].theta,
+                                                      arr[i].iter)
+    _check(rc, allow=() if raise_not_converged else (3,))
+    return [list(its[k * n:(k + 1) * n]) for k in range(n_iter)]
 
 
 def mfg_profile(plan: Plan, enable: bool):

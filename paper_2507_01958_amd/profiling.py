@@ -54,13 +54,18 @@ def classify(seq):
             else:
                 d = "inv" if prev.startswith(("k_rows", "k_cols_solve")) else "fwd"
             out.append(f"tgemm_{mode}_{d}")
+        elif s.startswith(("k_rows_batch", "k_cols_batch", "k_AAt_batch", "k_tgemm_lp_batch")):
+            out.append(s[2:].split("<")[0])
         elif s.startswith("k_rows"):
+            sfx = "_f64" if "<double>" in s else "_f32"
             if nxt.startswith("k_cols_solve"):
-                out.append("rows_fwd")
+                out.append("rows_fwd" + sfx)
             elif prev.startswith("k_cols_solve"):
-                out.append("rows_inv")
+                out.append("rows_inv" + sfx)
             else:
-                out.append("rows_solve")
+                out.append("rows_solve" + sfx)
+        elif s.startswith("k_cols_solve"):
+            out.append("cols_solve" + ("_f64" if "<double>" in s else "_f32"))
         elif s.startswith("k_"):
             out.append(s[2:].split("<")[0])
         else:

@@ -1,0 +1,109 @@
+"""GPU checks of batched solves (mfg_plan_batch / mfg_batch_cp_solve).
+
+A batched run performs, instance by instance, exactly the arithmetic of
+mfg_cp_solve on a single plan: the iterates and the PCG iteration counts must
+agree BITWISE with separate single-plan runs, whether the steps are replayed
+from the recorded HIP graph or launched eagerly, and across several calls
+(the graph is recorded once and replayed, with eager work and host
+synchronisation between the replays). One instance is also compared with the
+oracle (exact projections) as for the single-plan path.
+"""
+import numpy as np
+import pytest
+
+from _gpu import grid_of, host, say
+from oracle import cp as ocp
+from paper_2507_01958_amd import mfg
+from paper_2507_01958_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _instances():
+    # uneven sizes, both boundary conditions, several N_t padding classes
+    return [wl.small_instance(21, 2, 16, 24, 12, "periodic", 0.05),
+            wl.small_instance(22, 2, 32, 18, 20, "neumann", 0.01),
+            wl.small_instance(23, 2, 12, 12, 40, "periodic", 0.5),
+            wl.small_instance(24, 2, 24, 16, 7, "neumann", 0.1)]
+
+
+def _problem(inst, precision):
+    return mfg.make_problem(inst.d, inst.nx, inst.ny, inst.nt, inst.bc, inst.nu, inst.gamma,
+                            l=inst.l, precision=precision, T=inst.T, lo=inst.lo, hi=inst.hi)
+
+
+def _tensors(inst):
+    import torch
+    return torch.from_numpy(inst.V).cuda(), torch.from_numpy(inst.m0).cuda()
+
+
+def _single(inst, precision, chunks, rtol, maxit):
+    V, m0 = _tensors(inst)
+    P = mfg.mfg_plan(_problem(inst, precision), V, m0)
+    st = mfg.CPState(P)
+    mfg.mfg_cp_init(P, st)
+    its = []
+    for k in chunks:
+        its += mfg.mfg_cp_solve(P, st, k, rtol, maxit)["pcg_iters"]
+    out = (host(st.xi), host(st.y), host(st.ybar), st.sigma, st.tau, its)
+    P.close()
+    return out
+
+
+def _batched(insts, precision, chunks, rtol, maxit, use_graph):
+    Vs, m0s = zip(*[_tensors(i) for i in insts])
+    B = mfg.mfg_plan_batch([_problem(i, precision) for i in insts], Vs, m0s)
+    states = [mfg.CPState(p) for p in B.plans]
+    for p, st in zip(B.plans, states):
+        mfg.mfg_cp_init(p, st)
+    its = []
+    for k in chunks:
+        its += mfg.mfg_batch_cp_solve(B, states, k, rtol, maxit, use_graph=use_graph)
+    out = [(host(s.xi), host(s.y), host(s.ybar), s.sigma, s.tau, [row[i] for row in its])
+           for i, s in enumerate(states)]
+    B.close()
+    return out
+
+
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_fp16"])
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_bitwise_equals_single(precision, use_graph):
+    insts = _instances()
+    chunks = [1, 4, 3]  # the graph is recorded in the first call and replayed in later ones
+    rtol, maxit = 1e-10, 300
+    say(f"batch {precision} graph={use_graph} x{len(insts)}")
+    got = _batched(insts, precision, chunks, rtol, maxit, use_graph)
+    for inst, b in zip(insts, got):
+        ref = _single(inst, precision, chunks, rtol, maxit)
+        assert b[5] == ref[5], (inst.name, b[5], ref[5])
+        for name, x, y in zip(["xi", "y", "ybar"], b[:3], ref[:3]):
+            assert np.array_equal(x, y), (inst.name, name, np.abs(x - y).max())
+        assert b[3] == ref[3] and b[4] == ref[4]
+
+
+def test_batch_matches_oracle():
+    insts = _instances()[:2]
+    say("batch vs oracle x25")
+    got = _batched(insts, "mixed_fp32", [25], 1e-12, 400, True)
+    for inst, b in zip(insts, got):
+        g = grid_of(inst)
+        ref, _ = ocp.cp_solve(g, inst.V, inst.m0, 25, method="direct")
+        n = g.n
+        for blk in range(1 + g.ncomp):
+            r = ref.y[blk * n:(blk + 1) * n]
+            err = np.abs(b[1][blk * n:(blk + 1) * n] - r).max() / max(np.abs(r).max(), 1e-300)
+            assert err <= 1e-9, (inst.name, blk, err)
+
+
+def test_batch_rejects_unsupported():
+    import torch
+    inst = _instances()[0]
+    V, m0 = _tensors(inst)
+    with pytest.raises(mfg.MFGError) as e:
+        mfg.mfg_plan_batch([_problem(inst, "fp64")], [V], [m0])
+    assert e.value.code == 2
+    with pytest.raises(mfg.MFGError) as e:
+        mfg.mfg_plan_batch([_problem(inst, "mixed_fp32"), _problem(inst, "mixed_fp16")],
+                           [V, V], [m0, m0])
+    assert e.value.code == 1
+    torch.cuda.synchronize()
