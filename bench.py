@@ -146,6 +146,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--nt", type=int, default=128)
+    ap.add_argument("--workload", default="neumann256", choices=["neumann256", "batch", "grad"],
+                    help="neumann256: the headline line; batch: 32 uneven periodic instances, "
+                         "batched vs one plan at a time; grad: gradient through 50 CP iterations")
+    ap.add_argument("--batch", type=int, default=32, help="instances of the batch workload")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes instead of tuning them first")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 512 MiB device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -165,6 +171,132 @@ def calibrate_copy():
                       "repeats": 4}))
 
 
+def _problem(inst, precision):
+    from paper_2507_01958_amd import mfg
+    return mfg.make_problem(inst.d, inst.nx, inst.ny, inst.nt, inst.bc, inst.nu, inst.gamma,
+                            l=inst.l, precision=precision, T=inst.T, lo=inst.lo, hi=inst.hi)
+
+
+def bench_batch(args):
+    """Uneven batch of independent periodic problems (sizes 64^2..256^2, N_t 32..128,
+    nu log-uniform in [1e-3, 1]): instance-CP-iterations per second of the
+    batched path (one launch per phase over all instances, steps replayed from a
+    HIP graph) against running the same instances one plan at a time."""
+    import numpy as np
+    import torch
+
+    from paper_2507_01958_amd import mfg
+    from paper_2507_01958_amd import workloads as wl
+
+    insts = [wl.batch_instance(i) for i in range(args.batch)]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    Vs = [torch.from_numpy(i.V).to(dev) for i in insts]
+    m0s = [torch.from_numpy(i.m0).to(dev) for i in insts]
+    prec = "mixed_fp32"
+    B = mfg.mfg_plan_batch([_problem(i, prec) for i in insts], Vs, m0s, stream)
+    if not args.no_autotune:
+        mfg.mfg_batch_autotune(B, 1)
+    states = [mfg.CPState(p) for p in B.plans]
+    for p, st in zip(B.plans, states):
+        mfg.mfg_cp_init(p, st)
+    mfg.mfg_batch_cp_solve(B, states, args.warmup, RTOL, PCG_MAXIT)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = mfg.mfg_batch_cp_solve(B, states, args.steps, RTOL, PCG_MAXIT)
+    torch.cuda.synchronize()
+    dt_batch = time.perf_counter() - t0
+    B.close()
+    del states
+    rate_batch = len(insts) * args.steps / dt_batch
+    seq = {}
+    for variant in ("fp64", prec):
+        total = 0.0
+        for inst, V, m0 in zip(insts, Vs, m0s):
+            P = mfg.mfg_plan(_problem(inst, variant), V, m0, stream)
+            if not args.no_autotune:
+                mfg.mfg_autotune(P, 1)
+            st = mfg.CPState(P)
+            mfg.mfg_cp_init(P, st)
+            mfg.mfg_cp_solve(P, st, args.warmup, RTOL, PCG_MAXIT, stats=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mfg.mfg_cp_solve(P, st, args.steps, RTOL, PCG_MAXIT, stats=False)
+            torch.cuda.synchronize()
+            total += time.perf_counter() - t0
+            P.close()
+        seq[variant] = len(insts) * args.steps / total
+    n_total = sum(i.n for i in insts)
+    out = {
+        "metric": "instance CP iters/s, batch of independent 2D periodic problems",
+        "value": rate_batch,
+        "unit": "instance CP iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt_batch / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+fp32", "data": "synthetic (seeded)",
+        "config": {"workload": f"batch{len(insts)}_periodic_uneven", "pcg_rtol": RTOL,
+                   "instances": [i.name for i in insts], "sum_n": n_total,
+                   "variant": prec},
+        "sequential_instance_cp_iters_per_s": seq,
+        "speedup_vs_sequential": {k: rate_batch / v for k, v in seq.items()},
+        "mean_pcg_iters": float(np.mean(its)), "max_pcg_iters": int(np.max(its)),
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
+def bench_grad(args):
+    """dJ/dm0 and dJ/dV of J = 1/2 ||m(., T) - m_target||^2 through 50 CP
+    iterations (PCG rtol 1e-10, checkpoint every 10) on the 2-D torus 256^2 x 100,
+    nu = 5e-2: gradient evaluations (forward + reverse sweep) per second."""
+    import torch
+
+    from paper_2507_01958_amd import autograd as mad
+    from paper_2507_01958_amd import workloads as wl
+
+    inst, mt = wl.gradient_instance()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    pb = _problem(inst, "fp64")
+    target = torch.from_numpy(mt).to(dev)
+    n_iter, every, rtol = 50, 10, 1e-10
+    fwd, bwd = [], []
+    for rep in range(args.warmup + args.steps):
+        m0 = torch.from_numpy(inst.m0).to(dev).requires_grad_(True)
+        V = torch.from_numpy(inst.V).to(dev).requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        y = mad.cp_solve(pb, m0, V, n_iter, rtol=rtol, maxit=1000, every=every)
+        J = 0.5 * ((mad.terminal_m(pb, y) - target) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if rep >= args.warmup:
+            fwd.append(t1 - t0)
+            bwd.append(t2 - t1)
+    tot = sum(fwd) + sum(bwd)
+    out = {
+        "metric": "gradient evaluations/s through 50 CP iterations (d=2 periodic 256^2x100)",
+        "value": args.steps / tot,
+        "unit": "gradients/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * tot / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic (seeded)",
+        "config": {"workload": f"grad_periodic{inst.nx}x{inst.ny}x{inst.nt}_nu{inst.nu:g}",
+                   "cp_iters": n_iter, "checkpoint_every": every, "pcg_rtol": rtol},
+        "forward_ms": 1e3 * sum(fwd) / args.steps, "reverse_ms": 1e3 * sum(bwd) / args.steps,
+        "J": float(J.detach().cpu()),
+        "grad_norms": {"m0": float(m0.grad.norm().cpu()), "V": float(V.grad.norm().cpu())},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -174,6 +306,12 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        bench_batch(args)
+        return
+    if args.workload == "grad":
+        bench_grad(args)
+        return
     import numpy as np
     import torch
 
@@ -192,6 +330,8 @@ def main():
         pb = mfg.make_problem(2, inst.nx, inst.ny, inst.nt, inst.bc, inst.nu, inst.gamma, l=1,
                               precision=variant)
         P = mfg.mfg_plan(pb, V, m0, stream)
+        if not args.no_autotune:
+            mfg.mfg_autotune(P, 1)  # launch shapes for this workload (setup, not timed)
         st = mfg.CPState(P)
         mfg.mfg_cp_init(P, st)
         # warmup

@@ -196,6 +196,18 @@ int mfg_cp_adjoint(mfg_plan_t plan, const mfg_state_t* ckpts, int n_ckpt, int ev
                    const double* gy, double pcg_rtol, int pcg_maxit, double* g_m0,
                    double* g_V);
 
+/* Autotune the plan's launch shapes (how the preconditioner passes split
+ * work among thread blocks: rows per block of the row transforms, column
+ * pairs per block of the column solves, column blocks per wave and the
+ * persistent form of the time GEMM), timing candidates with HIP events on the
+ * plan's stream; results are unchanged up to the summation order of the dot
+ * products. effort 1: use the choice cached for this (d, grid, N_t, bc,
+ * precision, l, GPU architecture) if any, else measure; 2: measure again.
+ * The choice is cached for the process and applied to later plans of the
+ * same key; if the environment variable MFG_TUNE_CACHE names a file it is
+ * read from and appended to. Overwrites the plan's workspace; synchronises. */
+int mfg_autotune(mfg_plan_t plan, int effort);
+
 /* ---- Batches of independent problems -------------------------------------
  * Many problems solved together (for instance a parameter sweep over nu, V or
  * m0, or independent problems of different sizes): every phase of a
@@ -219,6 +231,10 @@ int mfg_plan_batch(const mfg_problem_t* pbs, const double* const* V, const doubl
 /* Plan of instance i (owned by the batch: do not destroy). It accepts every
  * single-plan call (mfg_cp_init, mfg_cp_solve, mfg_cp_adjoint, ...). */
 int mfg_batch_plan(mfg_batch_t batch, int i, mfg_plan_t* out);
+
+/* mfg_autotune for every instance (the persistent time GEMM excluded), then
+ * rebuild the batched launches. */
+int mfg_batch_autotune(mfg_batch_t batch, int effort);
 
 /* Release the batch and its plans. */
 int mfg_batch_destroy(mfg_batch_t batch);

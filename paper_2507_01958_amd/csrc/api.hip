@@ -195,7 +195,6 @@ static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const d
 
   P.pb = *pb;
   P.stream = stream;
-  read_tune_env(P.tune);
   HIP_TRY(hipGetDevice(&P.device));
   {
     int ncu = 0;
@@ -333,6 +332,13 @@ static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const d
   HIP_TRY(hipHostMalloc(&hs, S_COUNT * sizeof(double), hipHostMallocDefault));
   P.host_allocs.push_back(hs);
   P.host_scal = static_cast<double*>(hs);
+  // launch shapes: defaults, then a tuned choice cached for this key, then
+  // explicit MFG_TUNE overrides
+  {
+    Tune t;
+    if (tune_lookup(P, &t)) P.tune = t;
+  }
+  read_tune_env(P.tune);
   HIP_TRY(hipDeviceSynchronize());
   return MFG_OK;
 }
@@ -717,6 +723,11 @@ int mfg_profile_report(mfg_plan_t plan, char* buf, int len) {
   if ((int)out.size() + 1 > len) return fail(MFG_ERR_INVALID_ARG, "buffer too small");
   std::memcpy(buf, out.c_str(), out.size() + 1);
   return MFG_OK;
+}
+
+int mfg_autotune(mfg_plan_t plan, int effort) {
+  if (!plan || (effort != 1 && effort != 2)) return fail(MFG_ERR_INVALID_ARG, "bad arguments");
+  return mfg::autotune(plan->P, effort, true);
 }
 
 const char* mfg_last_error(void) { return mfg::g_last_error.c_str(); }

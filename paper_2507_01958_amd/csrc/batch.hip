@@ -41,7 +41,7 @@ struct Phase {
 };
 
 struct GemmGroup {
-  int ntp = 0;
+  int ntp = 0, cb = 2;
   Phase<GemmArgs<double, float>> fwd;
   Phase<GemmArgs<float, double>> inv_init, inv_flex;
 };
@@ -197,22 +197,24 @@ int build_pcg_phases(Batch& B) {
       (rc = upload_phase(B, cl, b_cols, B.cols, cshm)) || (rc = upload_finish(B, fbb, &B.f_bb)) ||
       (rc = upload_finish(B, fpq, &B.f_pq)) || (rc = upload_finish(B, frr, &B.f_rr)))
     return rc;
-  // time GEMMs: one launch per N_t padding class
-  std::vector<int> ntps;
-  for (int i = 0; i < n; ++i) ntps.push_back(plan_of(B, i).ntp);
-  std::sort(ntps.begin(), ntps.end());
-  ntps.erase(std::unique(ntps.begin(), ntps.end()), ntps.end());
-  B.groups.assign(ntps.size(), GemmGroup{});
+  // time GEMMs: one launch per (N_t padding class, column blocks per wave)
+  std::vector<std::pair<int, int>> classes;
+  for (int i = 0; i < n; ++i)
+    classes.emplace_back(plan_of(B, i).ntp, plan_of(B, i).tune.lp_cb == 1 ? 1 : 2);
+  std::sort(classes.begin(), classes.end());
+  classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
+  B.groups.assign(classes.size(), GemmGroup{});
   std::vector<int> gemm_grid(n, 0);
-  for (size_t gi = 0; gi < ntps.size(); ++gi) {
+  for (size_t gi = 0; gi < classes.size(); ++gi) {
     GemmGroup& G = B.groups[gi];
-    G.ntp = ntps[gi];
+    G.ntp = classes[gi].first;
+    G.cb = classes[gi].second;
     std::vector<GemmArgs<double, float>> fw;
     std::vector<GemmArgs<float, double>> i0, i1;
     std::vector<int> blocks;
     for (int i = 0; i < n; ++i) {
       Plan& P = plan_of(B, i);
-      if (P.ntp != G.ntp) continue;
+      if (P.ntp != G.ntp || (P.tune.lp_cb == 1 ? 1 : 2) != G.cb) continue;
       float* tmp = reinterpret_cast<float*>(P.tmp);
       int blk;
       fw.push_back(batch_gemm_args<double, float>(P, B.mode, P.r, tmp, DOT_NONE, nullptr, nullptr,
@@ -265,7 +267,7 @@ int build_state_phases(Batch& B, mfg_state_t* st) {
 
 void precond_phase(Batch& B, bool init, hipStream_t s) {
   for (auto& G : B.groups)
-    launch_gemm_batch<double, float>(B.mode, G.ntp, G.fwd.args, G.fwd.off, G.fwd.ninst,
+    launch_gemm_batch<double, float>(B.mode, G.ntp, G.cb, G.fwd.args, G.fwd.off, G.fwd.ninst,
                                      G.fwd.total, s);
   launch_rows_batch_f32(B.rows_fwd.args, B.rows_fwd.off, B.count, B.rows_fwd.total,
                         B.rows_fwd.shm, s);
@@ -274,7 +276,8 @@ void precond_phase(Batch& B, bool init, hipStream_t s) {
                         B.rows_inv.shm, s);
   for (auto& G : B.groups) {
     const auto& ph = init ? G.inv_init : G.inv_flex;
-    launch_gemm_batch<float, double>(B.mode, G.ntp, ph.args, ph.off, ph.ninst, ph.total, s);
+    launch_gemm_batch<float, double>(B.mode, G.ntp, G.cb, ph.args, ph.off, ph.ninst, ph.total,
+                                     s);
   }
   launch_finish_batch(init ? B.f_rz0 : B.f_rz, B.count, s);
 }
@@ -347,6 +350,7 @@ int batch_create(Batch& B, const mfg_problem_t* pbs, const double* const* V,
     int rc = mfg_plan(&pbs[i], V[i], m0[i], stream, &h);
     if (rc) return rc;
     B.plans.push_back(h);
+    h->P.tune.tgemm_pers = 0;  // batched launches use the blocked time GEMM
   }
   int rc;
   void* p;
@@ -379,11 +383,24 @@ void batch_release(Batch& B) {
   B.stream = nullptr;
 }
 
+int batch_autotune(Batch& B, int effort) {
+  if (hipStreamSynchronize(B.stream) != hipSuccess) return fail(MFG_ERR_HIP, "stream sync failed");
+  for (int i = 0; i < B.count; ++i) {
+    int rc = autotune(plan_of(B, i), effort, false);
+    if (rc) return rc;
+  }
+  // launch shapes changed: rebuild the argument arrays, drop the graph
+  release_graph(B);
+  return build_pcg_phases(B);
+}
+
 int batch_cp_solve(Batch& B, mfg_state_t* st, int n_iter, double rtol, int maxit, int use_graph,
                    int* pcg_iters) {
   hipStream_t s = B.stream;
   const int n = B.count;
   if (n_iter <= 0) return MFG_OK;
+  // the previous call's last launches may still read the argument arrays
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(MFG_ERR_HIP, "stream sync failed");
   // host schedule (same arithmetic as the single-plan driver)
   std::vector<double> sched((size_t)n * n_iter * 3);
   for (int i = 0; i < n; ++i) {
@@ -533,6 +550,11 @@ int mfg_batch_plan(mfg_batch_t b, int i, mfg_plan_t* out) {
   if (!b || !out || i < 0 || i >= b->B.count) return fail(MFG_ERR_INVALID_ARG, "bad arguments");
   *out = b->B.plans[i];
   return MFG_OK;
+}
+
+int mfg_batch_autotune(mfg_batch_t b, int effort) {
+  if (!b || (effort != 1 && effort != 2)) return fail(MFG_ERR_INVALID_ARG, "bad arguments");
+  return mfg::batch_autotune(b->B, effort);
 }
 
 int mfg_batch_cp_solve(mfg_batch_t b, mfg_state_t* states, int n_iter, double pcg_rtol,

@@ -18,7 +18,6 @@ struct Tune {
   int lp_cb = 2;     // time GEMM (low precision): column blocks per wave
   int rows_elems = 1024;  // row transforms: complex elements per block
   int cols_lines = 4;     // column solves: complex lines (column pairs) per block
-  int aat_ti = 16;        // A kernel tile rows (d = 2)
   int tgemm_pers = 0;     // persistent time GEMM (whole V in LDS) when N_t <= 128
 };
 
@@ -92,6 +91,12 @@ struct ProfScope {
   ProfScope(const Plan& p, const char* name, hipStream_t st) : P(p), s(st), id(prof_begin(p, name, st)) {}
   ~ProfScope() { prof_end(P, id, s); }
 };
+
+// Launch-shape autotuner (tune.hip): cached choice for the plan's key, and
+// measurement of the candidates (allow_pers = false excludes the persistent
+// time GEMM, which batched launches do not use).
+bool tune_lookup(const Plan& P, Tune* out);
+int autotune(Plan& P, int effort, bool allow_pers);
 
 }  // namespace mfg
 

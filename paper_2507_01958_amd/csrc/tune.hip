@@ -1,0 +1,177 @@
+// Autotuner of the launch shapes (struct Tune) of the preconditioner passes.
+//
+// The choices change how work is split among blocks (rows per block of the
+// row transforms, column pairs per block of the column solves, column blocks
+// per wave and the persistent form of the time GEMM), never what a line or a
+// column computes. They are measured with HIP events on the plan's stream:
+// each candidate times a few applications of the preconditioner to a fixed
+// vector, the best (minimum over trials) is kept, one parameter at a time.
+// Results are cached per (d, grid, N_t, boundary, precision, l, GPU
+// architecture) for the process, applied to every later plan of that key,
+// and, when MFG_TUNE_CACHE names a file, read from and appended to it.
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "plan.h"
+
+namespace mfg {
+
+int fail(int code, const std::string& msg);
+
+namespace {
+
+using Key = std::tuple<int, int, int, int, int, int, int, std::string>;
+
+std::mutex g_mu;
+std::map<Key, Tune> g_cache;
+bool g_file_loaded = false;
+
+std::string arch_of(int device) {
+  static std::map<int, std::string> names;
+  auto it = names.find(device);
+  if (it != names.end()) return it->second;
+  hipDeviceProp_t prop;
+  std::string name = "unknown";
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    name = prop.gcnArchName;
+    const size_t colon = name.find(':');
+    if (colon != std::string::npos) name = name.substr(0, colon);
+  }
+  names[device] = name;
+  return name;
+}
+
+Key key_of(const Plan& P) {
+  return Key{P.pb.d, P.g.n0, P.g.n1, P.g.nt, P.pb.bc, P.precision, P.l, arch_of(P.device)};
+}
+
+// One cache line: "d n0 n1 nt bc precision l arch f64_cb lp_cb rows_elems cols_lines pers".
+void load_file_locked() {
+  if (g_file_loaded) return;
+  g_file_loaded = true;
+  const char* path = std::getenv("MFG_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char arch[64];
+  int d, n0, n1, nt, bc, prec, l;
+  Tune t;
+  while (std::fscanf(f, "%d %d %d %d %d %d %d %63s %d %d %d %d %d", &d, &n0, &n1, &nt, &bc, &prec,
+                     &l, arch, &t.f64_cb, &t.lp_cb, &t.rows_elems, &t.cols_lines,
+                     &t.tgemm_pers) == 13)
+    g_cache[Key{d, n0, n1, nt, bc, prec, l, arch}] = t;
+  std::fclose(f);
+}
+
+void store(const Plan& P, const Tune& t) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  load_file_locked();
+  const Key k = key_of(P);
+  g_cache[k] = t;
+  const char* path = std::getenv("MFG_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%d %d %d %d %d %d %d %s %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k),
+               std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k),
+               std::get<7>(k).c_str(), t.f64_cb, t.lp_cb, t.rows_elems, t.cols_lines,
+               t.tgemm_pers);
+  std::fclose(f);
+}
+
+// Mean time (ms) of `reps` preconditioner applications, best of `trials`.
+int time_precond(Plan& P, hipEvent_t a, hipEvent_t b, int reps, int trials, float* best) {
+  hipStream_t s = P.stream;
+  launch_precond(P, P.r, P.z, false, nullptr, s);  // warm caches and code
+  *best = 1e30f;
+  for (int t = 0; t < trials; ++t) {
+    if (hipEventRecord(a, s) != hipSuccess) return fail(MFG_ERR_HIP, "event record failed");
+    for (int i = 0; i < reps; ++i) launch_precond(P, P.r, P.z, false, nullptr, s);
+    if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess)
+      return fail(MFG_ERR_HIP, "event record failed");
+    if (hipGetLastError() != hipSuccess) return fail(MFG_ERR_HIP, "launch failed while tuning");
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return fail(MFG_ERR_HIP, "event timing failed");
+    if (ms / reps < *best) *best = ms / reps;
+  }
+  return MFG_OK;
+}
+
+}  // namespace
+
+bool tune_lookup(const Plan& P, Tune* out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  load_file_locked();
+  auto it = g_cache.find(key_of(P));
+  if (it == g_cache.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+// allow_pers = false keeps the time GEMM in the form the batched launches use.
+int autotune(Plan& P, int effort, bool allow_pers) {
+  if (effort < 2) {
+    Tune t;
+    if (tune_lookup(P, &t)) {
+      if (!allow_pers) t.tgemm_pers = 0;
+      P.tune = t;
+      return MFG_OK;
+    }
+  }
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return fail(MFG_ERR_HIP, "event creation failed");
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail(MFG_ERR_HIP, "event creation failed");
+  }
+  // input: a constant vector (the passes take the same time for any values)
+  launch_fill(P.r, P.g.n, 1.0, P.stream);
+  const long long work = P.g.n;
+  const int reps = work >= (1LL << 22) ? 3 : (work >= (1LL << 18) ? 10 : 40);
+  const int trials = 3;
+  struct Param {
+    int Tune::*field;
+    std::vector<int> values;
+  };
+  std::vector<Param> params;
+  if (P.precision == MFG_FP64) params.push_back({&Tune::f64_cb, {1, 2}});
+  else params.push_back({&Tune::lp_cb, {1, 2}});
+  if (P.ntp > 0 && allow_pers) params.push_back({&Tune::tgemm_pers, {0, 1}});
+  params.push_back({&Tune::rows_elems, {256, 512, 1024, 2048, 4096}});
+  if (P.g.has0) params.push_back({&Tune::cols_lines, {1, 2, 4, 8, 16}});
+  if (!allow_pers) P.tune.tgemm_pers = 0;
+  int rc = MFG_OK;
+  float cur = 0.0f;
+  rc = time_precond(P, a, b, reps, trials, &cur);
+  const int passes = effort >= 2 ? 2 : 1;
+  for (int pass = 0; pass < passes && !rc; ++pass) {
+    for (const Param& prm : params) {
+      const int keep = P.tune.*(prm.field);
+      int best_v = keep;
+      for (int v : prm.values) {
+        if (v == keep) continue;
+        P.tune.*(prm.field) = v;
+        float ms;
+        if ((rc = time_precond(P, a, b, reps, trials, &ms))) break;
+        if (ms < 0.97f * cur) {  // switch only on a clear gain
+          cur = ms;
+          best_v = v;
+        }
+      }
+      P.tune.*(prm.field) = best_v;
+      if (rc) break;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc) return rc;
+  store(P, P.tune);
+  return MFG_OK;
+}
+
+}  // namespace mfg

@@ -61,6 +61,8 @@ SIGNATURES = {
     "mfg_cp_solve": (c_int, [c_void_p, POINTER(State), c_int, c_double, c_int, POINTER(Stats)]),
     "mfg_cp_adjoint": (c_int, [c_void_p, POINTER(State), c_int, c_int, c_int, c_void_p, c_double,
                                c_int, c_void_p, c_void_p]),
+    "mfg_autotune": (c_int, [c_void_p, c_int]),
+    "mfg_batch_autotune": (c_int, [c_void_p, c_int]),
     "mfg_plan_batch": (c_int, [POINTER(Problem), POINTER(c_void_p), POINTER(c_void_p), c_int,
                                c_void_p, POINTER(c_void_p)]),
     "mfg_batch_plan": (c_int, [c_void_p, c_int, POINTER(c_void_p)]),
@@ -351,6 +353,14 @@ class Batch:
 
 def mfg_plan_batch(problems, Vs, m0s, stream=None) -> Batch:
     return Batch(problems, Vs, m0s, stream)
+
+
+def mfg_autotune(plan: Plan, effort: int = 1):
+    _check(load().mfg_autotune(plan.handle, int(effort)))
+
+
+def mfg_batch_autotune(batch: Batch, effort: int = 1):
+    _check(load().mfg_batch_autotune(batch.handle, int(effort)))
 
 
 def mfg_batch_destroy(batch: Batch):

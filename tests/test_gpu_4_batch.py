@@ -107,3 +107,55 @@ def test_batch_rejects_unsupported():
                            [V, V], [m0, m0])
     assert e.value.code == 1
     torch.cuda.synchronize()
+
+
+def test_autotune_keeps_results_and_caches(tmp_path, monkeypatch):
+    """The tuned launch shapes change only how work is split: the tuned
+    preconditioner agrees with the untuned one to rounding (the dot products'
+    summation order may change), and the choice is written to MFG_TUNE_CACHE."""
+    import torch
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("MFG_TUNE_CACHE", str(cache))
+    inst = wl.small_instance(25, 2, 48, 36, 24, "neumann", 0.02)
+    say("autotune 48x36x24")
+    V, m0 = _tensors(inst)
+    r = torch.from_numpy(wl.random_vector(5, inst.n)).cuda()
+    for precision in ["fp64", "mixed_fp32"]:
+        P0 = mfg.mfg_plan(_problem(inst, precision), V, m0)
+        z0 = torch.empty_like(r)
+        mfg.mfg_precond(P0, r, z0)
+        mfg.mfg_autotune(P0, 2)
+        z1 = torch.empty_like(r)
+        mfg.mfg_precond(P0, r, z1)
+        a, b = host(z0), host(z1)
+        # float64: identical per-element arithmetic; float32: the persistent
+        # and blocked GEMMs may accumulate in a different order
+        tol = 1e-13 if precision == "fp64" else 1e-5
+        assert np.abs(a - b).max() <= tol * np.abs(a).max(), precision
+        P0.close()
+    lines = cache.read_text().split("\n")
+    rows = [ln.split() for ln in lines if ln.strip()]
+    assert len(rows) == 2 and all(len(x) == 13 for x in rows)
+    assert rows[0][:7] == ["2", "48", "36", "24", "1", "0", "1"] and rows[0][7].startswith("gfx")
+    assert rows[1][5] == "1"
+
+
+def test_batch_autotuned_bitwise_equals_single():
+    """After mfg_batch_autotune the tuned shapes are cached; single plans made
+    afterwards take the same shapes, so batched and single runs still agree
+    bitwise."""
+    insts = _instances()
+    B_args = ([_problem(i, "mixed_fp32") for i in insts],) + tuple(zip(*[_tensors(i) for i in insts]))
+    say("batch autotuned x4")
+    B = mfg.mfg_plan_batch(*B_args)
+    mfg.mfg_batch_autotune(B, 2)
+    states = [mfg.CPState(p) for p in B.plans]
+    for p, st in zip(B.plans, states):
+        mfg.mfg_cp_init(p, st)
+    its = mfg.mfg_batch_cp_solve(B, states, 5, 1e-10, 300)
+    got = [(host(s.y), [row[i] for row in its]) for i, s in enumerate(states)]
+    B.close()
+    for inst, (y, it) in zip(insts, got):
+        ref = _single(inst, "mixed_fp32", [5], 1e-10, 300)
+        assert it == ref[5]
+        assert np.array_equal(y, ref[1]), inst.name
