@@ -165,6 +165,7 @@ static void read_tune_env(Tune& t) {
       else if (k == "rows_elems" && v >= 64 && v <= 8192) t.rows_elems = v;
       else if (k == "cols_lines" && v >= 1 && v <= 16) t.cols_lines = v;
       else if (k == "tgemm_pers" && (v == 0 || v == 1)) t.tgemm_pers = v;
+      else if (k == "fft_reg" && (v == 0 || v == 1)) t.fft_reg = v;
     }
     pos = end + 1;
   }

@@ -40,6 +40,16 @@ struct Phase {
   size_t shm = 0;
 };
 
+// Spatial launches of one FFT size class (0: LDS path, else the axis length).
+struct SpatialGroup {
+  int cls = 0;
+  Phase<RowsArgs<float>> rows_fwd, rows_inv;
+};
+struct ColsGroup {
+  int cls = 0;
+  Phase<ColsArgs<float>> cols;
+};
+
 struct GemmGroup {
   int ntp = 0, cb = 2;
   Phase<GemmArgs<double, float>> fwd;
@@ -64,8 +74,8 @@ struct Batch {
   Phase<InitArgs> init;
   Phase<UpdArgs> upd_odd, upd_even;
   Phase<AatArgs> aat_first, aat_odd, aat_even;
-  Phase<RowsArgs<float>> rows_fwd, rows_inv;
-  Phase<ColsArgs<float>> cols;
+  std::vector<SpatialGroup> rows;
+  std::vector<ColsGroup> cols;
   Phase<RhsArgs> rhs;
   Phase<BackprojArgs> bp;
   FinishArgs *f_bb = nullptr, *f_pq = nullptr, *f_rr = nullptr, *f_rz0 = nullptr,
@@ -142,11 +152,14 @@ int build_pcg_phases(Batch& B) {
   std::vector<InitArgs> init;
   std::vector<UpdArgs> uo, ue;
   std::vector<AatArgs> af, ao, ae;
-  std::vector<RowsArgs<float>> rf, ri;
-  std::vector<ColsArgs<float>> cl;
-  std::vector<int> b_init, b_upd, b_aat, b_rows, b_cols;
+  std::vector<int> b_init, b_upd, b_aat;
   std::vector<FinishArgs> fbb, fpq, frr, frz0, frz;
-  size_t rshm = 0, cshm = 0;
+  // spatial launches grouped by size class
+  std::vector<int> rcls(n), ccls(n);
+  std::vector<RowsArgs<float>> rf(n), ri(n);
+  std::vector<ColsArgs<float>> cl(n);
+  std::vector<int> b_rows(n), b_cols(n);
+  std::vector<size_t> rshm(n), cshm(n);
   for (int i = 0; i < n; ++i) {
     Plan& P = plan_of(B, i);
     const double* done = done_of(B, i);
@@ -164,20 +177,9 @@ int build_pcg_phases(Batch& B) {
     ao.push_back(aat_args(P, P.z, P.p2, P.p, P.q, false, done, &g));
     ae.push_back(aat_args(P, P.z, P.p, P.p2, P.q, false, done, &g));
     b_aat.push_back(g);
-    RowsArgs<float> ra, rb;
-    ColsArgs<float> ca;
-    int blk;
-    size_t shm;
-    batch_rows_args(P, tmp, 0, done, &ra, &blk, &shm);
-    batch_rows_args(P, tmp, 1, done, &rb, &blk, &shm);
-    rf.push_back(ra);
-    ri.push_back(rb);
-    b_rows.push_back(blk);
-    rshm = std::max(rshm, shm);
-    batch_cols_args(P, tmp, done, &ca, &blk, &shm);
-    cl.push_back(ca);
-    b_cols.push_back(blk);
-    cshm = std::max(cshm, shm);
+    rcls[i] = batch_rows_args(P, tmp, 0, done, &rf[i], &b_rows[i], &rshm[i]);
+    batch_rows_args(P, tmp, 1, done, &ri[i], &b_rows[i], &rshm[i]);
+    ccls[i] = batch_cols_args(P, tmp, done, &cl[i], &b_cols[i], &cshm[i]);
     FinishArgs f = finish_args(P, T_BB, pcg_init_grid(P), OP_BB);
     fbb.push_back(f);
     f = finish_args(P, T_PQ, g, OP_PQ);
@@ -192,11 +194,48 @@ int build_pcg_phases(Batch& B) {
       (rc = upload_phase(B, ue, b_upd, B.upd_even)) ||
       (rc = upload_phase(B, af, b_aat, B.aat_first)) ||
       (rc = upload_phase(B, ao, b_aat, B.aat_odd)) || (rc = upload_phase(B, ae, b_aat, B.aat_even)) ||
-      (rc = upload_phase(B, rf, b_rows, B.rows_fwd, rshm)) ||
-      (rc = upload_phase(B, ri, b_rows, B.rows_inv, rshm)) ||
-      (rc = upload_phase(B, cl, b_cols, B.cols, cshm)) || (rc = upload_finish(B, fbb, &B.f_bb)) ||
+      (rc = upload_finish(B, fbb, &B.f_bb)) ||
       (rc = upload_finish(B, fpq, &B.f_pq)) || (rc = upload_finish(B, frr, &B.f_rr)))
     return rc;
+  {
+    std::vector<int> classes(rcls);
+    std::sort(classes.begin(), classes.end());
+    classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
+    B.rows.assign(classes.size(), SpatialGroup{});
+    for (size_t c = 0; c < classes.size(); ++c) {
+      std::vector<RowsArgs<float>> f, v;
+      std::vector<int> blocks;
+      size_t shm = 0;
+      for (int i = 0; i < n; ++i)
+        if (rcls[i] == classes[c]) {
+          f.push_back(rf[i]);
+          v.push_back(ri[i]);
+          blocks.push_back(b_rows[i]);
+          shm = std::max(shm, rshm[i]);
+        }
+      B.rows[c].cls = classes[c];
+      if ((rc = upload_phase(B, f, blocks, B.rows[c].rows_fwd, shm)) ||
+          (rc = upload_phase(B, v, blocks, B.rows[c].rows_inv, shm)))
+        return rc;
+    }
+    classes = ccls;
+    std::sort(classes.begin(), classes.end());
+    classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
+    B.cols.assign(classes.size(), ColsGroup{});
+    for (size_t c = 0; c < classes.size(); ++c) {
+      std::vector<ColsArgs<float>> f;
+      std::vector<int> blocks;
+      size_t shm = 0;
+      for (int i = 0; i < n; ++i)
+        if (ccls[i] == classes[c]) {
+          f.push_back(cl[i]);
+          blocks.push_back(b_cols[i]);
+          shm = std::max(shm, cshm[i]);
+        }
+      B.cols[c].cls = classes[c];
+      if ((rc = upload_phase(B, f, blocks, B.cols[c].cols, shm))) return rc;
+    }
+  }
   // time GEMMs: one launch per (N_t padding class, column blocks per wave)
   std::vector<std::pair<int, int>> classes;
   for (int i = 0; i < n; ++i)
@@ -269,11 +308,15 @@ void precond_phase(Batch& B, bool init, hipStream_t s) {
   for (auto& G : B.groups)
     launch_gemm_batch<double, float>(B.mode, G.ntp, G.cb, G.fwd.args, G.fwd.off, G.fwd.ninst,
                                      G.fwd.total, s);
-  launch_rows_batch_f32(B.rows_fwd.args, B.rows_fwd.off, B.count, B.rows_fwd.total,
-                        B.rows_fwd.shm, s);
-  launch_cols_batch_f32(B.cols.args, B.cols.off, B.count, B.cols.total, B.cols.shm, s);
-  launch_rows_batch_f32(B.rows_inv.args, B.rows_inv.off, B.count, B.rows_inv.total,
-                        B.rows_inv.shm, s);
+  for (const auto& G : B.rows)
+    launch_rows_batch_f32(G.cls, G.rows_fwd.args, G.rows_fwd.off, G.rows_fwd.ninst,
+                          G.rows_fwd.total, G.rows_fwd.shm, s);
+  for (const auto& G : B.cols)
+    launch_cols_batch_f32(G.cls, G.cols.args, G.cols.off, G.cols.ninst, G.cols.total, G.cols.shm,
+                          s);
+  for (const auto& G : B.rows)
+    launch_rows_batch_f32(G.cls, G.rows_inv.args, G.rows_inv.off, G.rows_inv.ninst,
+                          G.rows_inv.total, G.rows_inv.shm, s);
   for (auto& G : B.groups) {
     const auto& ph = init ? G.inv_init : G.inv_flex;
     launch_gemm_batch<float, double>(B.mode, G.ntp, G.cb, ph.args, ph.off, ph.ninst, ph.total,

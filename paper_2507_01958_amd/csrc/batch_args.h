@@ -89,6 +89,7 @@ struct RowsArgs {
   SolveCtx sc;
   int n0;
   const double* done;
+  int reg;  // register path (fft_reg.h) for axis lengths 64, 128, 256
 };
 
 template <typename T>
@@ -99,6 +100,7 @@ struct ColsArgs {
   int cw;
   SolveCtx sc;
   const double* done;
+  int reg;
 };
 
 template <typename TX, typename TY>
@@ -140,10 +142,11 @@ BackprojArgs backproj_args(const Plan& P, const double* u, double* xi, double* y
 int backproj_grid(const Plan& P);
 AatArgs aat_args(const Plan& P, const double* z, const double* pold, double* pnew, double* q,
                  bool first, const double* done, int* grid);
-void batch_rows_args(const Plan& P, float* data, int mode, const double* done, void* out,
-                     int* blocks, size_t* shm);
-void batch_cols_args(const Plan& P, float* data, const double* done, void* out, int* blocks,
-                     size_t* shm);
+// return the size class of the instance's launch (0: LDS path, else N)
+int batch_rows_args(const Plan& P, float* data, int mode, const double* done, void* out,
+                    int* blocks, size_t* shm);
+int batch_cols_args(const Plan& P, float* data, const double* done, void* out, int* blocks,
+                    size_t* shm);
 template <typename TX, typename TY>
 GemmArgs<TX, TY> batch_gemm_args(const Plan& P, int mode, const TX* X, TY* Y, int dotmode,
                                  const double* r, const double* q, const double* done,
@@ -162,10 +165,10 @@ void launch_aat_batch(bool has0, const AatArgs* A, const int* off, int ninst, in
 void launch_rhs_batch(const RhsArgs* A, const int* off, int ninst, int total, hipStream_t s);
 void launch_backproj_batch(const BackprojArgs* A, const int* off, int ninst, int total,
                            hipStream_t s);
-void launch_rows_batch_f32(const void* A, const int* off, int ninst, int total, size_t shm,
-                           hipStream_t s);
-void launch_cols_batch_f32(const void* A, const int* off, int ninst, int total, size_t shm,
-                           hipStream_t s);
+void launch_rows_batch_f32(int cls, const void* A, const int* off, int ninst, int total,
+                           size_t shm, hipStream_t s);
+void launch_cols_batch_f32(int cls, const void* A, const int* off, int ninst, int total,
+                           size_t shm, hipStream_t s);
 template <typename TX, typename TY>
 void launch_gemm_batch(int mode, int ntp, int cb, const GemmArgs<TX, TY>* A, const int* off,
                        int ninst, int total, hipStream_t s);

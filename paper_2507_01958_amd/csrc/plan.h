@@ -19,6 +19,7 @@ struct Tune {
   int rows_elems = 1024;  // row transforms: complex elements per block
   int cols_lines = 4;     // column solves: complex lines (column pairs) per block
   int tgemm_pers = 0;     // persistent time GEMM (whole V in LDS) when N_t <= 128
+  int fft_reg = 1;        // register-resident FFTs for axis lengths 64, 128, 256
 };
 
 // Optional per-kernel timing with HIP events recorded on the plan's stream

@@ -15,17 +15,13 @@
 // Stockham FFT staged in LDS.
 #include "batch_args.h"
 #include "device_util.h"
+#include "fft_reg.h"
 #include "plan.h"
 #include "tgemm.h"
 
 namespace mfg {
 
 namespace {
-
-template <typename T>
-struct C2 {
-  T x, y;
-};
 
 constexpr int kLoadBatch = 8;  // global loads per thread issued before their LDS stores
 
@@ -369,6 +365,202 @@ __device__ void cols_body(const ColsArgs<T>& a, int bid, int nb) {
   }
 }
 
+// ---- register path (axis length 64, 128 or 256; see fft_reg.h) ----
+// A complex line packs two real lines (real and imaginary parts); thread p of
+// line l holds the elements p + N2 m. Threads of lines past the end take part
+// in the barriers with zeros and store nothing.
+
+template <typename T>
+using V2 = T __attribute__((ext_vector_type(2)));
+
+// Forward real transform along the contiguous axis: DHT (periodic) or DCT-II
+// (Neumann, input read in Makhoul order), spectra stored in natural order.
+template <typename T, int N>
+__device__ void rows_fwd_reg(const RowsArgs<T>& a, int bid, C2<T>* lds) {
+  using Sh = fftr::Shape<T, N>;
+  const int l = threadIdx.x / Sh::N2, p = threadIdx.x % Sh::N2;
+  const int line = bid * Sh::LPB + l;
+  const int ra = 2 * line, rb = ra + 1;
+  const bool hasa = ra < a.nrows, hasb = rb < a.nrows;
+  const bool dct = a.ax.kind == 1;
+  T* __restrict__ data = a.data;
+  const T* __restrict__ tw = tw_table<T>(a.ax);
+  C2<T> v[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) {
+    const int n = p + Sh::N2 * n1;
+    const int src = dct ? dct_perm(n, N) : n;
+    v[n1].x = hasa ? data[(size_t)ra * N + src] : (T)0;
+    v[n1].y = hasb ? data[(size_t)rb * N + src] : (T)0;
+  }
+  fftr::fft4<T, N, -1>(v, lds + l * Sh::L, p, tw);
+  __syncthreads();
+  C2<T>* zb = lds + l * Sh::L2;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) zb[p + Sh::N2 * m] = v[m];
+  __syncthreads();
+  const T* __restrict__ ct = ct_table<T>(a.ax);
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int k = p + Sh::N2 * m;
+    const int kr = k ? N - k : 0;
+    const C2<T> z = v[m], zr = zb[kr];
+    const T pp = z.x, q = z.y, r = zr.x, s = zr.y;
+    T oa, ob;
+    if (!dct) {
+      oa = (T)0.5 * ((pp + r) - (q - s));
+      ob = (T)0.5 * ((q + s) + (pp - r));
+    } else {
+      const T c = ct[2 * k], sn = ct[2 * k + 1];
+      oa = (T)0.5 * (c * (pp + r) + sn * (q - s));
+      ob = (T)0.5 * (c * (q + s) + sn * (r - pp));
+    }
+    if (hasa) data[(size_t)ra * N + k] = oa;
+    if (hasb) data[(size_t)rb * N + k] = ob;
+  }
+}
+
+// Inverse real transform along the contiguous axis (times N): spectra in,
+// lines out in natural order. The complex input of the inverse FFT is formed
+// from the pair (k, N - k) read directly: DHT: Re F = (H[k] + H[N-k])/2,
+// Im F = (H[N-k] - H[k])/2; DCT-II: V[k] = exp(i pi k/(2N)) (C[k] - i C[N-k]).
+template <typename T, int N>
+__device__ void rows_inv_reg(const RowsArgs<T>& a, int bid, C2<T>* lds) {
+  using Sh = fftr::Shape<T, N>;
+  const int l = threadIdx.x / Sh::N2, p = threadIdx.x % Sh::N2;
+  const int line = bid * Sh::LPB + l;
+  const int ra = 2 * line, rb = ra + 1;
+  const bool hasa = ra < a.nrows, hasb = rb < a.nrows;
+  const bool dct = a.ax.kind == 1;
+  T* __restrict__ data = a.data;
+  const T* __restrict__ tw = tw_table<T>(a.ax);
+  const T* __restrict__ ct = ct_table<T>(a.ax);
+  C2<T> v[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int k = p + Sh::N2 * m;
+    const int kr = k ? N - k : 0;
+    const T ca = hasa ? data[(size_t)ra * N + k] : (T)0;
+    const T cb = hasb ? data[(size_t)rb * N + k] : (T)0;
+    T ra_ = hasa ? data[(size_t)ra * N + kr] : (T)0;
+    T rb_ = hasb ? data[(size_t)rb * N + kr] : (T)0;
+    if (!dct) {
+      const T fa_re = (T)0.5 * (ca + ra_), fa_im = (T)0.5 * (ra_ - ca);
+      const T fb_re = (T)0.5 * (cb + rb_), fb_im = (T)0.5 * (rb_ - cb);
+      v[m] = C2<T>{fa_re - fb_im, fa_im + fb_re};
+    } else {
+      if (k == 0) {
+        ra_ = (T)0;
+        rb_ = (T)0;
+      }
+      const T c = ct[2 * k], sn = ct[2 * k + 1];
+      v[m].x = c * ca + sn * ra_ - (sn * cb - c * rb_);
+      v[m].y = (sn * ca - c * ra_) + c * cb + sn * rb_;
+    }
+  }
+  fftr::fft4<T, N, +1>(v, lds + l * Sh::L, p, tw);
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int n = p + Sh::N2 * m;
+    const int dst = dct ? dct_perm(n, N) : n;
+    if (hasa) data[(size_t)ra * N + dst] = v[m].x;
+    if (hasb) data[(size_t)rb * N + dst] = v[m].y;
+  }
+}
+
+// Column solve along axis 0 (length N = n0, stride n1) of one time slice:
+// forward transform, division by S, inverse transform; two real columns per
+// complex line. Periodic: DFT with the two columns' spectra separated by
+// Z_a = (Z[k] + conj Z[N-k])/2, Z_b = (Z[k] - conj Z[N-k])/(2i) (S is even in
+// k). Neumann: DCT-II via Makhoul's reordering; both C[k] and C[N-k] are
+// formed from the pair (Z[k], Z[N-k]) so the inverse input needs no second
+// exchange.
+template <typename T, int N>
+__device__ void cols_reg(const ColsArgs<T>& a, int bid, int nb, C2<T>* lds) {
+  using Sh = fftr::Shape<T, N>;
+  const Geom& g = a.g;
+  const SolveCtx& sc = a.sc;
+  const int l = threadIdx.x / Sh::N2, p = threadIdx.x % Sh::N2;
+  const int cw = 2 * Sh::LPB;
+  const int ncb = (g.n1 + cw - 1) / cw;
+  const int blk = xcd_remap(bid, nb);
+  const int t = blk / ncb;
+  const int ja = (blk - t * ncb) * cw + 2 * l, jb = ja + 1;
+  const bool hasa = ja < g.n1, hasb = jb < g.n1;
+  const bool pair_ld = hasb && ((g.n1 & 1) == 0);  // 2-element aligned vector access
+  const bool dct = a.ax.kind == 1;
+  T* __restrict__ slice = a.data + (size_t)t * g.M;
+  const T* __restrict__ tw = tw_table<T>(a.ax);
+  C2<T> v[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) {
+    const int n = p + Sh::N2 * n1;
+    const int i = dct ? dct_perm(n, N) : n;
+    const size_t o = (size_t)i * g.n1 + ja;
+    if (pair_ld) {
+      const V2<T> w = *reinterpret_cast<const V2<T>*>(slice + o);
+      v[n1] = C2<T>{w.x, w.y};
+    } else {
+      v[n1].x = hasa ? slice[o] : (T)0;
+      v[n1].y = hasb ? slice[o + 1] : (T)0;
+    }
+  }
+  fftr::fft4<T, N, -1>(v, lds + l * Sh::L, p, tw);
+  __syncthreads();
+  C2<T>* zb = lds + l * Sh::L2;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) zb[p + Sh::N2 * m] = v[m];
+  __syncthreads();
+  const double lt = sc.lam_t[t];
+  const double l1a = hasa ? sc.lam1[ja] : 0.0, l1b = hasb ? sc.lam1[jb] : 0.0;
+  const T* __restrict__ ct = ct_table<T>(a.ax);
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int k = p + Sh::N2 * m;
+    const int kr = k ? N - k : 0;
+    const C2<T> z = v[m], zr = zb[kr];
+    const double R0 = sc.lam0[k];
+    const T ia = (T)(sc.norm / shift_symbol(sc, R0 + l1a, lt));
+    const T ib = (T)(sc.norm / shift_symbol(sc, R0 + l1b, lt));
+    if (!dct) {
+      // W = Z_a ia + i Z_b ib = (Z + conj Zr)/2 ia + (Z - conj Zr)/2 ib
+      const C2<T> sp = {(T)0.5 * (z.x + zr.x), (T)0.5 * (z.y - zr.y)};
+      const C2<T> sm = {(T)0.5 * (z.x - zr.x), (T)0.5 * (z.y + zr.y)};
+      v[m] = C2<T>{sp.x * ia + sm.x * ib, sp.y * ia + sm.y * ib};
+    } else {
+      const T pp = z.x, q = z.y, r = zr.x, s = zr.y;
+      const T c = ct[2 * k], sn = ct[2 * k + 1];
+      const T ca = (T)0.5 * (c * (pp + r) + sn * (q - s)) * ia;
+      const T cb = (T)0.5 * (c * (q + s) + sn * (r - pp)) * ib;
+      T rca = (T)0, rcb = (T)0;
+      if (k) {
+        const double Rr = sc.lam0[kr];
+        const T ira = (T)(sc.norm / shift_symbol(sc, Rr + l1a, lt));
+        const T irb = (T)(sc.norm / shift_symbol(sc, Rr + l1b, lt));
+        const T cr = ct[2 * kr], snr = ct[2 * kr + 1];
+        rca = (T)0.5 * (cr * (r + pp) + snr * (s - q)) * ira;
+        rcb = (T)0.5 * (cr * (s + q) + snr * (pp - r)) * irb;
+      }
+      v[m].x = c * ca + sn * rca - (sn * cb - c * rcb);
+      v[m].y = (sn * ca - c * rca) + c * cb + sn * rcb;
+    }
+  }
+  __syncthreads();
+  fftr::fft4<T, N, +1>(v, lds + l * Sh::L, p, tw);
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int n = p + Sh::N2 * m;
+    const int i = dct ? dct_perm(n, N) : n;
+    const size_t o = (size_t)i * g.n1 + ja;
+    if (pair_ld) {
+      *reinterpret_cast<V2<T>*>(slice + o) = V2<T>{v[m].x, v[m].y};
+    } else {
+      if (hasa) slice[o] = v[m].x;
+      if (hasb) slice[o + 1] = v[m].y;
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_rows(RowsArgs<T> a) {
   rows_body<T>(a, blockIdx.x);
@@ -393,8 +585,75 @@ __global__ __launch_bounds__(256) void k_cols_batch(const ColsArgs<T>* A, const 
   cols_body<T>(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
 }
 
+// Register path, one kernel per axis length (mode 0: forward, 1: inverse).
+template <typename T, int N>
+__device__ __forceinline__ void rows_reg(const RowsArgs<T>& a, int bid) {
+  if (a.done && *a.done != 0.0) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C2<T>* lds = reinterpret_cast<C2<T>*>(smem);
+  if (a.mode == 0) rows_fwd_reg<T, N>(a, bid, lds);
+  else rows_inv_reg<T, N>(a, bid, lds);
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void cols_reg_entry(const ColsArgs<T>& a, int bid, int nb) {
+  if (a.done && *a.done != 0.0) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cols_reg<T, N>(a, bid, nb, reinterpret_cast<C2<T>*>(smem));
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_rows_reg(RowsArgs<T> a) {
+  rows_reg<T, N>(a, blockIdx.x);
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_rows_reg_batch(const RowsArgs<T>* A, const int* off,
+                                                        int ninst) {
+  const int i = batch_instance(off, ninst, blockIdx.x);
+  rows_reg<T, N>(A[i], blockIdx.x - off[i]);
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_cols_reg(ColsArgs<T> a) {
+  cols_reg_entry<T, N>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_cols_reg_batch(const ColsArgs<T>* A, const int* off,
+                                                        int ninst) {
+  const int i = batch_instance(off, ninst, blockIdx.x);
+  cols_reg_entry<T, N>(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
+}
+
+// Launch the row / column kernels of size class cls (0: LDS Stockham path,
+// else the register path of that axis length).
+template <typename T>
+void launch_rows_cls(int cls, dim3 grid, dim3 block, size_t shm, hipStream_t s,
+                     const RowsArgs<T>& a) {
+  switch (cls) {
+    case 64: hipLaunchKernelGGL((k_rows_reg<T, 64>), grid, block, shm, s, a); break;
+    case 128: hipLaunchKernelGGL((k_rows_reg<T, 128>), grid, block, shm, s, a); break;
+    case 256: hipLaunchKernelGGL((k_rows_reg<T, 256>), grid, block, shm, s, a); break;
+    default: hipLaunchKernelGGL(k_rows<T>, grid, block, shm, s, a);
+  }
+}
+
+template <typename T>
+void launch_cols_cls(int cls, dim3 grid, dim3 block, size_t shm, hipStream_t s,
+                     const ColsArgs<T>& a) {
+  switch (cls) {
+    case 64: hipLaunchKernelGGL((k_cols_reg<T, 64>), grid, block, shm, s, a); break;
+    case 128: hipLaunchKernelGGL((k_cols_reg<T, 128>), grid, block, shm, s, a); break;
+    case 256: hipLaunchKernelGGL((k_cols_reg<T, 256>), grid, block, shm, s, a); break;
+    default: hipLaunchKernelGGL(k_cols_solve<T>, grid, block, shm, s, a);
+  }
+}
+
 struct SpatialShape {
   int lpb, nrows, rblocks, cw, cblocks;
+  int rreg, creg;          // size class: 0 (LDS path) or the axis length (register path)
+  int rthreads, cthreads;  // block sizes
   size_t rshm, cshm;
 };
 
@@ -416,29 +675,60 @@ SpatialShape spatial_shape(const Plan& P) {
   const Geom& g = P.g;
   SpatialShape sh{};
   const int N1 = g.n1;
-  int lpb = P.tune.rows_elems / N1;
-  if (lpb < 1) lpb = 1;
-  if (lpb > 32) lpb = 32;
   const int nrows = g.nt * g.n0;
   const int nlines = (nrows + 1) / 2;
-  if (lpb > nlines) lpb = nlines;
-  // keep dynamic LDS (two buffers + tables) within 64 KB
-  const int lpb_max = (int)((65536 - 4 * (size_t)N1 * sizeof(T)) / (2 * (size_t)N1 * sizeof(C2<T>)));
-  if (lpb > lpb_max) lpb = lpb_max;
-  if (lpb < 1) lpb = 1;
-  sh.lpb = lpb;
   sh.nrows = nrows;
-  sh.rblocks = (nlines + lpb - 1) / lpb;
-  sh.rshm = 2 * (size_t)lpb * N1 * sizeof(C2<T>) + 4 * (size_t)N1 * sizeof(T);
+  const bool use_reg = P.tune.fft_reg != 0;
+  sh.rreg = (use_reg && g.has0 && fftr::has_reg_path(N1)) ? N1 : 0;
+  if (sh.rreg) {
+    int lpb = 0, buf = 0;
+    switch (N1) {
+      case 64: lpb = fftr::Shape<T, 64>::LPB; buf = fftr::Shape<T, 64>::BUF; break;
+      case 128: lpb = fftr::Shape<T, 128>::LPB; buf = fftr::Shape<T, 128>::BUF; break;
+      default: lpb = fftr::Shape<T, 256>::LPB; buf = fftr::Shape<T, 256>::BUF; break;
+    }
+    sh.lpb = lpb;
+    sh.rblocks = (nlines + lpb - 1) / lpb;
+    sh.rthreads = fftr::Shape<T, 64>::NT;
+    sh.rshm = (size_t)buf * sizeof(C2<T>);
+  } else {
+    int lpb = P.tune.rows_elems / N1;
+    if (lpb < 1) lpb = 1;
+    if (lpb > 32) lpb = 32;
+    if (lpb > nlines) lpb = nlines;
+    // keep dynamic LDS (two buffers + tables) within 64 KB
+    const int lpb_max =
+        (int)((65536 - 4 * (size_t)N1 * sizeof(T)) / (2 * (size_t)N1 * sizeof(C2<T>)));
+    if (lpb > lpb_max) lpb = lpb_max;
+    if (lpb < 1) lpb = 1;
+    sh.lpb = lpb;
+    sh.rblocks = (nlines + lpb - 1) / lpb;
+    sh.rthreads = 256;
+    sh.rshm = 2 * (size_t)lpb * N1 * sizeof(C2<T>) + 4 * (size_t)N1 * sizeof(T);
+  }
   if (g.has0) {
-    int lines = P.tune.cols_lines;
-    const int lmax =
-        (int)((65536 - 4 * (size_t)g.n0 * sizeof(T)) / (2 * (size_t)g.n0 * sizeof(C2<T>)));
-    if (lines > lmax) lines = lmax;
-    if (lines < 1) lines = 1;
-    sh.cw = 2 * lines;
+    sh.creg = (use_reg && fftr::has_reg_path(g.n0)) ? g.n0 : 0;
+    if (sh.creg) {
+      int lines = 0, buf = 0;
+      switch (g.n0) {
+        case 64: lines = fftr::Shape<T, 64>::LPB; buf = fftr::Shape<T, 64>::BUF; break;
+        case 128: lines = fftr::Shape<T, 128>::LPB; buf = fftr::Shape<T, 128>::BUF; break;
+        default: lines = fftr::Shape<T, 256>::LPB; buf = fftr::Shape<T, 256>::BUF; break;
+      }
+      sh.cw = 2 * lines;
+      sh.cthreads = fftr::Shape<T, 64>::NT;
+      sh.cshm = (size_t)buf * sizeof(C2<T>);
+    } else {
+      int lines = P.tune.cols_lines;
+      const int lmax =
+          (int)((65536 - 4 * (size_t)g.n0 * sizeof(T)) / (2 * (size_t)g.n0 * sizeof(C2<T>)));
+      if (lines > lmax) lines = lmax;
+      if (lines < 1) lines = 1;
+      sh.cw = 2 * lines;
+      sh.cthreads = 256;
+      sh.cshm = 2 * (size_t)lines * g.n0 * sizeof(C2<T>) + 4 * (size_t)g.n0 * sizeof(T);
+    }
     sh.cblocks = g.nt * ((g.n1 + sh.cw - 1) / sh.cw);
-    sh.cshm = 2 * (size_t)lines * g.n0 * sizeof(C2<T>) + 4 * (size_t)g.n0 * sizeof(T);
   }
   return sh;
 }
@@ -446,13 +736,13 @@ SpatialShape spatial_shape(const Plan& P) {
 template <typename T>
 RowsArgs<T> rows_args(const Plan& P, const SpatialShape& sh, T* data, int mode,
                       const double* done) {
-  return RowsArgs<T>{data, sh.nrows, P.ax1, mode, sh.lpb, solve_ctx(P), P.g.has0 ? P.g.n0 : 1,
-                     done};
+  return RowsArgs<T>{data,        sh.nrows, P.ax1, mode, sh.lpb, solve_ctx(P),
+                     P.g.has0 ? P.g.n0 : 1, done, (mode != 2) ? sh.rreg : 0};
 }
 
 template <typename T>
 ColsArgs<T> cols_args(const Plan& P, const SpatialShape& sh, T* data, const double* done) {
-  return ColsArgs<T>{data, P.g, P.ax0, sh.cw, solve_ctx(P), done};
+  return ColsArgs<T>{data, P.g, P.ax0, sh.cw, solve_ctx(P), done, sh.creg};
 }
 
 template <typename T>
@@ -467,16 +757,16 @@ void spatial_solves(const Plan& P, T* data, hipStream_t s) {
   }
   {
     ProfScope ps(P, sizeof(T) == 8 ? "rows_fwd_f64" : "rows_fwd_f32", s);
-    hipLaunchKernelGGL(k_rows<T>, dim3(sh.rblocks), dim3(256), sh.rshm, s,
+    launch_rows_cls<T>(sh.rreg, dim3(sh.rblocks), dim3(sh.rthreads), sh.rshm, s,
                        rows_args<T>(P, sh, data, 0, nullptr));
   }
   {
     ProfScope ps(P, sizeof(T) == 8 ? "cols_solve_f64" : "cols_solve_f32", s);
-    hipLaunchKernelGGL(k_cols_solve<T>, dim3(sh.cblocks), dim3(256), sh.cshm, s,
+    launch_cols_cls<T>(sh.creg, dim3(sh.cblocks), dim3(sh.cthreads), sh.cshm, s,
                        cols_args<T>(P, sh, data, nullptr));
   }
   ProfScope ps(P, sizeof(T) == 8 ? "rows_inv_f64" : "rows_inv_f32", s);
-  hipLaunchKernelGGL(k_rows<T>, dim3(sh.rblocks), dim3(256), sh.rshm, s,
+  launch_rows_cls<T>(sh.rreg, dim3(sh.rblocks), dim3(sh.rthreads), sh.rshm, s,
                      rows_args<T>(P, sh, data, 1, nullptr));
 }
 
@@ -509,32 +799,47 @@ void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
 }
 
 // ---- batched spatial solves: float32 data (mixed precision) ----
-void batch_rows_args(const Plan& P, float* data, int mode, const double* done, void* out,
-                     int* blocks, size_t* shm) {
+int batch_rows_args(const Plan& P, float* data, int mode, const double* done, void* out,
+                    int* blocks, size_t* shm) {
   const SpatialShape sh = spatial_shape<float>(P);
   *reinterpret_cast<RowsArgs<float>*>(out) = rows_args<float>(P, sh, data, mode, done);
   *blocks = sh.rblocks;
   *shm = sh.rshm;
+  return sh.rreg;
 }
 
-void batch_cols_args(const Plan& P, float* data, const double* done, void* out, int* blocks,
-                     size_t* shm) {
+int batch_cols_args(const Plan& P, float* data, const double* done, void* out, int* blocks,
+                    size_t* shm) {
   const SpatialShape sh = spatial_shape<float>(P);
   *reinterpret_cast<ColsArgs<float>*>(out) = cols_args<float>(P, sh, data, done);
   *blocks = sh.cblocks;
   *shm = sh.cshm;
+  return sh.creg;
 }
 
-void launch_rows_batch_f32(const void* A, const int* off, int ninst, int total, size_t shm,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_rows_batch<float>, dim3(total), dim3(256), shm, s,
-                     reinterpret_cast<const RowsArgs<float>*>(A), off, ninst);
+// float32 blocks have 256 threads on both paths
+void launch_rows_batch_f32(int cls, const void* A, const int* off, int ninst, int total,
+                           size_t shm, hipStream_t s) {
+  const auto* a = reinterpret_cast<const RowsArgs<float>*>(A);
+  const dim3 g(total), b(256);
+  switch (cls) {
+    case 64: hipLaunchKernelGGL((k_rows_reg_batch<float, 64>), g, b, shm, s, a, off, ninst); break;
+    case 128: hipLaunchKernelGGL((k_rows_reg_batch<float, 128>), g, b, shm, s, a, off, ninst); break;
+    case 256: hipLaunchKernelGGL((k_rows_reg_batch<float, 256>), g, b, shm, s, a, off, ninst); break;
+    default: hipLaunchKernelGGL(k_rows_batch<float>, g, b, shm, s, a, off, ninst);
+  }
 }
 
-void launch_cols_batch_f32(const void* A, const int* off, int ninst, int total, size_t shm,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_cols_batch<float>, dim3(total), dim3(256), shm, s,
-                     reinterpret_cast<const ColsArgs<float>*>(A), off, ninst);
+void launch_cols_batch_f32(int cls, const void* A, const int* off, int ninst, int total,
+                           size_t shm, hipStream_t s) {
+  const auto* a = reinterpret_cast<const ColsArgs<float>*>(A);
+  const dim3 g(total), b(256);
+  switch (cls) {
+    case 64: hipLaunchKernelGGL((k_cols_reg_batch<float, 64>), g, b, shm, s, a, off, ninst); break;
+    case 128: hipLaunchKernelGGL((k_cols_reg_batch<float, 128>), g, b, shm, s, a, off, ninst); break;
+    case 256: hipLaunchKernelGGL((k_cols_reg_batch<float, 256>), g, b, shm, s, a, off, ninst); break;
+    default: hipLaunchKernelGGL(k_cols_batch<float>, g, b, shm, s, a, off, ninst);
+  }
 }
 
 }  // namespace mfg

@@ -2,8 +2,8 @@
 //
 // The choices change how work is split among blocks (rows per block of the
 // row transforms, column pairs per block of the column solves, column blocks
-// per wave and the persistent form of the time GEMM), never what a line or a
-// column computes. They are measured with HIP events on the plan's stream:
+// per wave and the persistent form of the time GEMM) and which FFT form runs
+// (register-resident or LDS-staged), never what is computed beyond rounding. They are measured with HIP events on the plan's stream:
 // each candidate times a few applications of the preconditioner to a fixed
 // vector, the best (minimum over trials) is kept, one parameter at a time.
 // Results are cached per (d, grid, N_t, boundary, precision, l, GPU
@@ -50,7 +50,8 @@ Key key_of(const Plan& P) {
   return Key{P.pb.d, P.g.n0, P.g.n1, P.g.nt, P.pb.bc, P.precision, P.l, arch_of(P.device)};
 }
 
-// One cache line: "d n0 n1 nt bc precision l arch f64_cb lp_cb rows_elems cols_lines pers".
+// One cache line: "d n0 n1 nt bc precision l arch f64_cb lp_cb rows_elems cols_lines pers
+// fft_reg".
 void load_file_locked() {
   if (g_file_loaded) return;
   g_file_loaded = true;
@@ -61,9 +62,9 @@ void load_file_locked() {
   char arch[64];
   int d, n0, n1, nt, bc, prec, l;
   Tune t;
-  while (std::fscanf(f, "%d %d %d %d %d %d %d %63s %d %d %d %d %d", &d, &n0, &n1, &nt, &bc, &prec,
-                     &l, arch, &t.f64_cb, &t.lp_cb, &t.rows_elems, &t.cols_lines,
-                     &t.tgemm_pers) == 13)
+  while (std::fscanf(f, "%d %d %d %d %d %d %d %63s %d %d %d %d %d %d", &d, &n0, &n1, &nt, &bc,
+                     &prec, &l, arch, &t.f64_cb, &t.lp_cb, &t.rows_elems, &t.cols_lines,
+                     &t.tgemm_pers, &t.fft_reg) == 14)
     g_cache[Key{d, n0, n1, nt, bc, prec, l, arch}] = t;
   std::fclose(f);
 }
@@ -77,10 +78,10 @@ void store(const Plan& P, const Tune& t) {
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%d %d %d %d %d %d %d %s %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k),
-               std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k),
-               std::get<7>(k).c_str(), t.f64_cb, t.lp_cb, t.rows_elems, t.cols_lines,
-               t.tgemm_pers);
+  std::fprintf(f, "%d %d %d %d %d %d %d %s %d %d %d %d %d %d\n", std::get<0>(k),
+               std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k),
+               std::get<6>(k), std::get<7>(k).c_str(), t.f64_cb, t.lp_cb, t.rows_elems,
+               t.cols_lines, t.tgemm_pers, t.fft_reg);
   std::fclose(f);
 }
 
@@ -142,6 +143,7 @@ int autotune(Plan& P, int effort, bool allow_pers) {
   if (P.precision == MFG_FP64) params.push_back({&Tune::f64_cb, {1, 2}});
   else params.push_back({&Tune::lp_cb, {1, 2}});
   if (P.ntp > 0 && allow_pers) params.push_back({&Tune::tgemm_pers, {0, 1}});
+  params.push_back({&Tune::fft_reg, {1, 0}});
   params.push_back({&Tune::rows_elems, {256, 512, 1024, 2048, 4096}});
   if (P.g.has0) params.push_back({&Tune::cols_lines, {1, 2, 4, 8, 16}});
   if (!allow_pers) P.tune.tgemm_pers = 0;

@@ -32,6 +32,21 @@ CASES = [
 ]
 
 
+# Axis lengths 64, 128, 256 take the register-resident FFT path; the others
+# the LDS one. Ragged cases: a partial last block of lines (9 x 64 rows, 18 x
+# 256), an odd number of rows (3 x 9), an odd column count (27), fewer columns
+# than one block covers (18).
+FFT_CASES = [
+    (2, 128, 256, 5, "neumann", 0.02),
+    (2, 256, 128, 3, "periodic", 0.3),
+    (2, 64, 64, 7, "periodic", 0.1),
+    (2, 9, 64, 3, "neumann", 0.2),
+    (2, 18, 256, 5, "periodic", 0.01),
+    (2, 256, 27, 3, "periodic", 0.1),
+    (2, 128, 18, 4, "neumann", 0.05),
+]
+
+
 def _inst(case, seed=0, l=1):
     d, nx, ny, nt, bc, nu = case
     return wl.small_instance(100 + seed, d, nx, ny, nt, bc, nu, l=l)
@@ -99,7 +114,7 @@ def test_prox(case):
 
 
 @pytest.mark.parametrize("l", [1, 2])
-@pytest.mark.parametrize("case", CASES, ids=_ids)
+@pytest.mark.parametrize("case", CASES + FFT_CASES, ids=_ids)
 def test_precond(case, l):
     inst = _inst(case, l=l)
     g = grid_of(inst, l=l)
@@ -148,7 +163,7 @@ MIXED_TOL = {"mixed_fp32": 2e-5, "mixed_fp16": 1e-2, "mixed_bf16": 5e-2}
 
 
 @pytest.mark.parametrize("precision", list(MIXED_TOL))
-@pytest.mark.parametrize("case", [CASES[0], CASES[4], CASES[5], CASES[7]], ids=_ids)
+@pytest.mark.parametrize("case", [CASES[0], CASES[4], CASES[5], CASES[7]] + FFT_CASES, ids=_ids)
 def test_precond_mixed(case, precision):
     inst = _inst(case)
     g = grid_of(inst)
