@@ -58,10 +58,12 @@ typedef enum { MFG_BC_PERIODIC = 0, MFG_BC_NEUMANN = 1 } mfg_bc_t;
 
 /* Arithmetic of the preconditioner inside PCG. The outer PCG recurrences,
  * the reduced-matrix products, the right-hand side and the prox are float64
- * in every mode. MIXED modes run the spatial solves (Algorithm 2) in float32,
- * the time transform (Algorithm 1) on the matrix cores with float16/bfloat16
- * (or float32) inputs and float32 accumulation, and switch PCG to its
- * flexible form. */
+ * in every mode. MIXED modes run the spatial solves (Algorithm 2) in float32
+ * and the time transform (Algorithm 1) on the matrix cores with float16/
+ * bfloat16 (or float32) inputs and float32 accumulation. With float16 and
+ * bfloat16 PCG takes its flexible (Polak-Ribiere) form; with float32 the
+ * preconditioner is symmetric to float32 rounding and PCG keeps the standard
+ * form. */
 typedef enum {
   MFG_FP64 = 0,
   MFG_MIXED_FP32 = 1,  /* time transform fp32 inputs, spatial solves fp32 */
@@ -135,7 +137,7 @@ int mfg_precond(mfg_plan_t plan, const double* r, double* z);
 
 /* Preconditioned CG on A u = b from u = 0 (Sections 3-4): stops when the
  * recursively updated residual satisfies ||r||_2 <= rtol ||b||_2 or after
- * maxit iterations. MIXED modes use the flexible (Polak-Ribiere) update.
+ * maxit iterations (flexible update with the float16/bfloat16 preconditioner).
  * b, u: n-vectors (must not alias). iters (host, may be NULL): iterations
  * done. relres (host, may be NULL): if non-NULL, the TRUE float64 relative
  * residual ||b - A u|| / ||b|| is computed (one extra product) and stored.

@@ -166,6 +166,7 @@ static void read_tune_env(Tune& t) {
       else if (k == "cols_lines" && v >= 1 && v <= 16) t.cols_lines = v;
       else if (k == "tgemm_pers" && (v == 0 || v == 1)) t.tgemm_pers = v;
       else if (k == "fft_reg" && (v == 0 || v == 1)) t.fft_reg = v;
+      else if (k == "flex" && (v >= -1 && v <= 1)) t.flex = v;
     }
     pos = end + 1;
   }
@@ -337,7 +338,10 @@ static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const d
   // explicit MFG_TUNE overrides
   {
     Tune t;
-    if (tune_lookup(P, &t)) P.tune = t;
+    if (tune_lookup(P, &t)) {
+      t.flex = P.tune.flex;
+      P.tune = t;
+    }
   }
   read_tune_env(P.tune);
   HIP_TRY(hipDeviceSynchronize());
@@ -397,43 +401,51 @@ static int read_scalars(Plan& P) {
   return MFG_OK;
 }
 
-// Preconditioned CG (flexible in the mixed modes) from x = 0.
+// PCG from x = 0 (flexible form where pcg_flexible says so). Iterations are
+// launched in chunks without a host round trip: every kernel of an iteration
+// tests the device `done` flag (set by the r.r finisher on convergence,
+// breakdown or a non-finite value) and returns at once when it is set, so
+// launching past convergence only costs launch latency. The first chunk is as
+// long as the previous solve on this plan; later ones are single iterations.
 static int run_pcg(Plan& P, const double* b, double* x, double rtol, int maxit, int* iters_out,
                    double* relres_rec, double* relres_true) {
   hipStream_t s = P.stream;
-  const bool flex = P.precision != MFG_FP64;
+  P.pcg_done = P.red.scal + S_DONE;
   launch_pcg_init(P, b, x, P.r, rtol, s);
-  HIP_TRY(hipGetLastError());
-  int rc = read_scalars(P);
-  if (rc) return rc;
-  if (P.host_scal[S_BAD] != 0.0) return fail(MFG_ERR_NONFINITE, "right-hand side is not finite");
-  const double bb = P.host_scal[S_BB];
-  int k = 0;
-  bool conv = (bb == 0.0);
-  if (!conv) {
-    launch_precond(P, P.r, P.z, true, nullptr, s);
-    double* pold = P.p2;
-    double* pnew = P.p;
-    for (k = 1; k <= maxit; ++k) {
+  launch_precond(P, P.r, P.z, true, nullptr, s);
+  double* pold = P.p2;
+  double* pnew = P.p;
+  int k = 0, rc = MFG_OK;
+  int chunk = std::max(1, P.last_pcg_its);
+  while (true) {
+    const int todo = std::min(chunk, maxit - k);
+    for (int j = 0; j < todo; ++j) {
+      ++k;
       launch_pdir_AAt(P, P.z, pold, pnew, P.q, k == 1, s);
-      launch_update(P, x, P.r, pnew, P.q, s);
+      launch_update_precond(P, x, P.r, pnew, P.q, P.z, s);
       std::swap(pold, pnew);
-      HIP_TRY(hipGetLastError());
-      if ((rc = read_scalars(P))) return rc;
-      const double bad = P.host_scal[S_BAD];
-      if (bad == 2.0) return fail(MFG_ERR_NONFINITE, "non-finite value in PCG");
-      if (bad == 1.0) return fail(MFG_ERR_BREAKDOWN, "PCG breakdown (p.Ap or r.z not positive)");
-      if (P.host_scal[S_DONE] != 0.0) {
-        conv = true;
-        break;
-      }
-      if (k == maxit) break;
-      launch_precond(P, P.r, P.z, true, P.q, s);
     }
-    (void)flex;
+    const hipError_t le = hipGetLastError();
+    if (le != hipSuccess) {
+      P.pcg_done = nullptr;
+      return fail(MFG_ERR_HIP, std::string("PCG launch failed: ") + hipGetErrorString(le));
+    }
+    if ((rc = read_scalars(P))) {
+      P.pcg_done = nullptr;
+      return rc;
+    }
+    if (P.host_scal[S_DONE] != 0.0 || k >= maxit) break;
+    chunk = 1;
   }
-  if (k > maxit) k = maxit;
-  if (iters_out) *iters_out = k;
+  P.pcg_done = nullptr;
+  const double bad = P.host_scal[S_BAD];
+  if (bad == 2.0) return fail(MFG_ERR_NONFINITE, "non-finite value in PCG");
+  if (bad == 1.0) return fail(MFG_ERR_BREAKDOWN, "PCG breakdown (p.Ap or r.z not positive)");
+  const bool conv = P.host_scal[S_DONE] != 0.0;
+  const int its = (int)P.host_scal[S_ITS];
+  const double bb = P.host_scal[S_BB];
+  P.last_pcg_its = its;
+  if (iters_out) *iters_out = its;
   if (relres_rec) *relres_rec = (bb > 0.0) ? std::sqrt(P.host_scal[S_RR] / bb) : 0.0;
   if (relres_true) {
     launch_AAt(P, x, P.p, false, s);

@@ -53,7 +53,7 @@ struct ColsGroup {
 struct GemmGroup {
   int ntp = 0, cb = 2;
   Phase<GemmArgs<double, float>> fwd;
-  Phase<GemmArgs<float, double>> inv_init, inv_flex;
+  Phase<GemmArgs<float, double>> inv_init, inv_iter;
 };
 
 }  // namespace
@@ -260,13 +260,14 @@ int build_pcg_phases(Batch& B) {
                                                   done_of(B, i), &blk));
       i0.push_back(batch_gemm_args<float, double>(P, B.mode, tmp, P.z, DOT_INIT, P.r, nullptr,
                                                   done_of(B, i), &blk));
-      i1.push_back(batch_gemm_args<float, double>(P, B.mode, tmp, P.z, DOT_FLEX, P.r, P.q,
+      i1.push_back(batch_gemm_args<float, double>(P, B.mode, tmp, P.z,
+                                                  pcg_flexible(P) ? DOT_FLEX : DOT_STD, P.r, P.q,
                                                   done_of(B, i), &blk));
       blocks.push_back(blk);
       gemm_grid[i] = blk;
     }
     if ((rc = upload_phase(B, fw, blocks, G.fwd)) || (rc = upload_phase(B, i0, blocks, G.inv_init)) ||
-        (rc = upload_phase(B, i1, blocks, G.inv_flex)))
+        (rc = upload_phase(B, i1, blocks, G.inv_iter)))
       return rc;
   }
   for (int i = 0; i < n; ++i) {
@@ -274,7 +275,7 @@ int build_pcg_phases(Batch& B) {
     FinishArgs f = finish_args(P, T_RZ, gemm_grid[i], OP_RZ_INIT);
     f.done = done_of(B, i);
     frz0.push_back(f);
-    f.op = OP_RZ_FLEX;
+    f.op = pcg_flexible(P) ? OP_RZ_FLEX : OP_RZ_STD;
     frz.push_back(f);
   }
   if ((rc = upload_finish(B, frz0, &B.f_rz0)) || (rc = upload_finish(B, frz, &B.f_rz))) return rc;
@@ -318,7 +319,7 @@ void precond_phase(Batch& B, bool init, hipStream_t s) {
     launch_rows_batch_f32(G.cls, G.rows_inv.args, G.rows_inv.off, G.rows_inv.ninst,
                           G.rows_inv.total, G.rows_inv.shm, s);
   for (auto& G : B.groups) {
-    const auto& ph = init ? G.inv_init : G.inv_flex;
+    const auto& ph = init ? G.inv_init : G.inv_iter;
     launch_gemm_batch<float, double>(B.mode, G.ntp, G.cb, ph.args, ph.off, ph.ninst, ph.total,
                                      s);
   }

@@ -125,6 +125,8 @@ void launch_sum_slices(const Plan& P, const double* in, const double* in2, doubl
                        hipStream_t s);
 void launch_axpby(long long n, double a, const double* x, double b, double* y, hipStream_t s);
 // precond.hip
+void launch_update_precond(const Plan& P, double* x, double* r, const double* p,
+                           const double* q, double* z, hipStream_t s);
 void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
                     const double* q, hipStream_t s);
 

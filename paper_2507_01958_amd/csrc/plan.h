@@ -20,6 +20,11 @@ struct Tune {
   int cols_lines = 4;     // column solves: complex lines (column pairs) per block
   int tgemm_pers = 0;     // persistent time GEMM (whole V in LDS) when N_t <= 128
   int fft_reg = 1;        // register-resident FFTs for axis lengths 64, 128, 256
+  // PCG update with the mixed-precision preconditioner: 1 flexible
+  // (Polak-Ribiere), 0 standard, -1 by precision (standard for float32, whose
+  // preconditioner is symmetric to float32 rounding; flexible for float16 and
+  // bfloat16)
+  int flex = -1;
 };
 
 // Optional per-kernel timing with HIP events recorded on the plan's stream
@@ -40,6 +45,10 @@ struct Plan {
   mfg_problem_t pb{};
   Tune tune{};
   mutable Profiler prof;
+  // Device flag that the kernels of a PCG loop test to skip their work once
+  // the solve has converged (set only while mfg_pcg / a CP step iterates).
+  const double* pcg_done = nullptr;
+  int last_pcg_its = 0;  // iterations of the previous solve (launch chunking)
   Geom g{};
   int precision = MFG_FP64;
   int l = 1;
@@ -92,6 +101,13 @@ struct ProfScope {
   ProfScope(const Plan& p, const char* name, hipStream_t st) : P(p), s(st), id(prof_begin(p, name, st)) {}
   ~ProfScope() { prof_end(P, id, s); }
 };
+
+// Whether PCG takes the flexible update on this plan.
+inline bool pcg_flexible(const Plan& P) {
+  if (P.precision == MFG_FP64) return false;
+  if (P.tune.flex >= 0) return P.tune.flex != 0;
+  return P.precision != MFG_MIXED_FP32;
+}
 
 // Launch-shape autotuner (tune.hip): cached choice for the plan's key, and
 // measurement of the candidates (allow_pers = false excludes the persistent

@@ -752,22 +752,22 @@ void spatial_solves(const Plan& P, T* data, hipStream_t s) {
   if (!g.has0) {
     ProfScope ps(P, sizeof(T) == 8 ? "rows_solve_f64" : "rows_solve_f32", s);
     hipLaunchKernelGGL(k_rows<T>, dim3(sh.rblocks), dim3(256), sh.rshm, s,
-                       rows_args<T>(P, sh, data, 2, nullptr));
+                       rows_args<T>(P, sh, data, 2, P.pcg_done));
     return;
   }
   {
     ProfScope ps(P, sizeof(T) == 8 ? "rows_fwd_f64" : "rows_fwd_f32", s);
     launch_rows_cls<T>(sh.rreg, dim3(sh.rblocks), dim3(sh.rthreads), sh.rshm, s,
-                       rows_args<T>(P, sh, data, 0, nullptr));
+                       rows_args<T>(P, sh, data, 0, P.pcg_done));
   }
   {
     ProfScope ps(P, sizeof(T) == 8 ? "cols_solve_f64" : "cols_solve_f32", s);
     launch_cols_cls<T>(sh.creg, dim3(sh.cblocks), dim3(sh.cthreads), sh.cshm, s,
-                       cols_args<T>(P, sh, data, nullptr));
+                       cols_args<T>(P, sh, data, P.pcg_done));
   }
   ProfScope ps(P, sizeof(T) == 8 ? "rows_inv_f64" : "rows_inv_f32", s);
   launch_rows_cls<T>(sh.rreg, dim3(sh.rblocks), dim3(sh.rthreads), sh.rshm, s,
-                     rows_args<T>(P, sh, data, 1, nullptr));
+                     rows_args<T>(P, sh, data, 1, P.pcg_done));
 }
 
 }  // namespace
@@ -776,7 +776,7 @@ void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
                     const double* q, hipStream_t s) {
   int dotmode = DOT_NONE;
   if (fused_dots)
-    dotmode = (q == nullptr) ? DOT_INIT : (P.precision == MFG_FP64 ? DOT_STD : DOT_FLEX);
+    dotmode = (q == nullptr) ? DOT_INIT : (pcg_flexible(P) ? DOT_FLEX : DOT_STD);
   if (P.precision == MFG_FP64) {
     double* tmp = P.tmp;
     tgemm<double, double>(P, GM_F64, r, tmp, DOT_NONE, nullptr, nullptr, s, "tgemm_f64_fwd");
@@ -796,6 +796,14 @@ void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
   tgemm<double, float>(P, mode, r, tmp, DOT_NONE, nullptr, nullptr, s, fwd_names[mode]);
   spatial_solves<float>(P, tmp, s);
   tgemm<float, double>(P, mode, tmp, z, dotmode, r, q, s, inv_names[mode]);
+}
+
+// One PCG iteration's update and preconditioning: x += alpha p, r -= alpha q
+// (r.r finisher), then z = P^{-1} r with the fused r.z (and z.q) partials.
+void launch_update_precond(const Plan& P, double* x, double* r, const double* p,
+                           const double* q, double* z, hipStream_t s) {
+  launch_update(P, x, r, p, q, s);
+  launch_precond(P, r, z, true, q, s);
 }
 
 // ---- batched spatial solves: float32 data (mixed precision) ----

@@ -428,7 +428,7 @@ void aat_launch(const Plan& P, const double* src, const double* pold, double* pn
                 bool first, bool reduce, hipStream_t s) {
   int tc;
   const int grid = aat_shape<HAS0>(P, &tc);
-  const AatArgs a{P.g, src, pold, pnew, q, P.red, tc, first ? 1 : 0, reduce ? 1 : 0, nullptr};
+  const AatArgs a{P.g, src, pold, pnew, q, P.red, tc, first ? 1 : 0, reduce ? 1 : 0, P.pcg_done};
   {
     ProfScope ps(P, FUSE ? "aat_fused" : "aat", s);
     hipLaunchKernelGGL((k_AAt_tile<HAS0, FUSE>), dim3(grid), dim3(kThreads), 0, s, a);

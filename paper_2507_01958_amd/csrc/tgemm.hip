@@ -122,6 +122,33 @@ __global__ __launch_bounds__(256) void k_tgemm64(GemmArgs<TX, TY> a) {
   tgemm64_body<KB, CB, TX, TY>(a, blockIdx.x);
 }
 
+constexpr int pow2_floor(int c) {
+  int m = 1;
+  while (m * 2 <= c) m *= 2;
+  return m;
+}
+
+// LDS copy of the low-precision V (row r = output row k, V[r][t] for
+// t < NTP): the 16-byte chunks c < P of row r (P the largest power of two
+// <= chunks per row) are stored at c ^ (r & (P - 1)), a permutation within the
+// row, so that the 16 lanes of a matrix-core A-operand read (16 consecutive
+// rows, the same chunk) fall on distinct banks instead of one.
+template <int NTP, typename VT>
+struct VsLayout {
+  static constexpr int EPC = 16 / (int)sizeof(VT);  // elements per chunk
+  static constexpr int C = NTP / EPC;                // chunks per row
+  static constexpr int P = pow2_floor(C);
+  __device__ static __forceinline__ int swz(int r, int c) { return c < P ? (c ^ (r & (P - 1))) : c; }
+  __device__ static __forceinline__ int idx(int r, int t) {
+    return r * NTP + swz(r, t / EPC) * EPC + (t % EPC);
+  }
+  // destination chunk of source chunk i of the row-major copy
+  __device__ static __forceinline__ int chunk(int i) {
+    const int r = i / C;
+    return r * C + swz(r, i - r * C);
+  }
+};
+
 __device__ __forceinline__ short f2bf(float f) {
   unsigned u = __float_as_uint(f);
   u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
@@ -200,7 +227,7 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
 #pragma unroll
     for (int e = 0; e < PERT; ++e) {
       const int i = threadIdx.x + 256 * e;
-      if (i < NV16) dst[i] = tmp[e];
+      if (i < NV16) dst[VsLayout<NTP, VT>::chunk(i)] = tmp[e];
     }
   }
   float scale = 1.0f, unscale = 1.0f;
@@ -230,7 +257,7 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
     if constexpr (MODE == GM_F32) {
 #pragma unroll
       for (int kb = 0; kb < NKB; ++kb) {
-        const float a = Vs[(kb * 16 + (lane & 15)) * NTP + KSTEP * ks + PER * kq];
+        const float a = Vs[VsLayout<NTP, VT>::idx(kb * 16 + (lane & 15), KSTEP * ks + PER * kq)];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
           acc[cb][kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xs[cb][ks][0], acc[cb][kb], 0, 0, 0);
@@ -244,7 +271,7 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
 #pragma unroll
       for (int kb = 0; kb < NKB; ++kb) {
         const v4h a = *reinterpret_cast<const v4h*>(
-            &Vs[(kb * 16 + (lane & 15)) * NTP + KSTEP * ks + PER * kq]);
+            &Vs[VsLayout<NTP, VT>::idx(kb * 16 + (lane & 15), KSTEP * ks + PER * kq)]);
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
           acc[cb][kb] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b[cb], acc[cb][kb], 0, 0, 0);
@@ -258,7 +285,7 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
 #pragma unroll
       for (int kb = 0; kb < NKB; ++kb) {
         const v4s a = *reinterpret_cast<const v4s*>(
-            &Vs[(kb * 16 + (lane & 15)) * NTP + KSTEP * ks + PER * kq]);
+            &Vs[VsLayout<NTP, VT>::idx(kb * 16 + (lane & 15), KSTEP * ks + PER * kq)]);
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
           acc[cb][kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[cb], acc[cb][kb], 0, 0, 0);
@@ -366,7 +393,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tgemm_pers(const typename PersTr
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int i = base + threadIdx.x + NT * e;
-        if (i < NV16) dst[i] = tmp[e];
+        if (i < NV16) dst[MODE == GM_F64 ? i : VsLayout<NTP, VT>::chunk(i)] = tmp[e];
       }
     }
   }
@@ -449,14 +476,15 @@ __global__ __launch_bounds__(WAVES * 64) void k_tgemm_pers(const typename PersTr
 #pragma unroll
           for (int kb = 0; kb < NKB; ++kb)
             acc[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                Vs[(kb * 16 + cl) * NTP + 4 * ks + kq], xc[ks], acc[kb], 0, 0, 0);
+                Vs[VsLayout<NTP, VT>::idx(kb * 16 + cl, 4 * ks + kq)], xc[ks], acc[kb], 0, 0, 0);
         } else if constexpr (MODE == GM_F16) {
           v4h b;
 #pragma unroll
           for (int j = 0; j < 4; ++j) b[j] = (_Float16)(xc[ks * 4 + j] * scale);
 #pragma unroll
           for (int kb = 0; kb < NKB; ++kb) {
-            const v4h a = *reinterpret_cast<const v4h*>(&Vs[(kb * 16 + cl) * NTP + 16 * ks + 4 * kq]);
+            const v4h a = *reinterpret_cast<const v4h*>(
+                &Vs[VsLayout<NTP, VT>::idx(kb * 16 + cl, 16 * ks + 4 * kq)]);
             acc[kb] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc[kb], 0, 0, 0);
           }
         } else {
@@ -465,7 +493,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_tgemm_pers(const typename PersTr
           for (int j = 0; j < 4; ++j) b[j] = f2bf(xc[ks * 4 + j]);
 #pragma unroll
           for (int kb = 0; kb < NKB; ++kb) {
-            const v4s a = *reinterpret_cast<const v4s*>(&Vs[(kb * 16 + cl) * NTP + 16 * ks + 4 * kq]);
+            const v4s a = *reinterpret_cast<const v4s*>(
+                &Vs[VsLayout<NTP, VT>::idx(kb * 16 + cl, 16 * ks + 4 * kq)]);
             acc[kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[kb], 0, 0, 0);
           }
         }
@@ -541,7 +570,8 @@ int lp_launch_cb(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r
                  hipStream_t s) {
   const int M = P.g.M;
   const int grid = (M + 64 * CB - 1) / (64 * CB);
-  const GemmArgs<TX, TY> a{lp_table(P, MODE), X, Y, P.g.nt, M, 0, dotmode, r, q, P.red, nullptr};
+  const GemmArgs<TX, TY> a{lp_table(P, MODE), X, Y, P.g.nt, M, 0, dotmode, r, q, P.red,
+                           P.pcg_done};
   hipLaunchKernelGGL((k_tgemm_lp<MODE, NTP, CB, TX, TY>), dim3(grid), dim3(256), 0, s, a);
   return grid;
 }
@@ -575,7 +605,7 @@ int f64_launch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r, 
   const int ncolblk = (M + 64 * CB - 1) / (64 * CB);
   const int nkc = (nt + KB * 16 - 1) / (KB * 16);
   const int grid = ncolblk * nkc;
-  const GemmArgs<TX, TY> a{P.Vt64, X, Y, nt, M, ncolblk, dotmode, r, q, P.red, nullptr};
+  const GemmArgs<TX, TY> a{P.Vt64, X, Y, nt, M, ncolblk, dotmode, r, q, P.red, P.pcg_done};
   hipLaunchKernelGGL((k_tgemm64<KB, CB, TX, TY>), dim3(grid), dim3(256), 0, s, a);
   return grid;
 }

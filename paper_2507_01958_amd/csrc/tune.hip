@@ -120,6 +120,7 @@ int autotune(Plan& P, int effort, bool allow_pers) {
     Tune t;
     if (tune_lookup(P, &t)) {
       if (!allow_pers) t.tgemm_pers = 0;
+      t.flex = P.tune.flex;  // a choice of method, not a launch shape
       P.tune = t;
       return MFG_OK;
     }

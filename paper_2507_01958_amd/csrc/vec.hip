@@ -186,7 +186,7 @@ FinishArgs finish_args(const Plan& P, int site, int nblocks, int op) {
   f.site = site;
   f.nblocks = nblocks;
   f.op = op;
-  f.done = nullptr;
+  f.done = P.pcg_done;
   return f;
 }
 
@@ -217,7 +217,7 @@ void launch_pcg_init(const Plan& P, const double* b, double* x, double* r, doubl
 }
 
 UpdArgs update_args(const Plan& P, double* x, double* r, const double* p, const double* q) {
-  return UpdArgs{P.g.n, x, r, p, q, P.red, nullptr};
+  return UpdArgs{P.g.n, x, r, p, q, P.red, P.pcg_done};
 }
 
 int update_grid(const Plan& P) { return grid_for(P.g.n); }
