@@ -11,10 +11,11 @@
 // unnormalised.
 //
 // LDS layout of the exchange: per line, element (k1, n2) at k1 * S + n2 with
-// row stride S = N2 + 1 and line stride L; the pairing buffer (element k of a
-// line at k, line stride L2). Both were chosen, by exhaustive count over the
-// lanes of each access, to be free of bank conflicts for 16-byte (float64
-// complex) and 8-byte (float32 complex) accesses with lanes p fastest.
+// row stride S and line stride L; the pairing buffer (element k of a line at
+// k, line stride L2). They were chosen, by exhaustive count over the lanes of
+// each access, to be free of bank conflicts for 16-byte (float64 complex) and
+// 8-byte (float32 complex) accesses with 64 banks of 4 bytes (with 32 banks,
+// the line-fastest N = 256 layout has 2-way conflicts, the others none).
 #pragma once
 
 #include "mfg_internal.h"
@@ -101,16 +102,24 @@ __device__ __forceinline__ void dft(C2<T>* v) {
   }
 }
 
-template <typename T, int N>
+// LF selects the thread mapping: false, p fastest (thread = line * N2 + p; the
+// row transforms, where a line is contiguous in memory); true, line fastest
+// (thread = p * LPB + line; the column solves, where the lines of a block are
+// adjacent columns, so one load instruction covers whole 128-byte row
+// segments). Each mapping has its own conflict-free strides.
+template <typename T, int N, bool LF = false>
 struct Shape {
   static constexpr int N1 = 16;
   static constexpr int N2 = N / 16;          // threads per line
   static constexpr int NT = sizeof(T) == 8 ? 128 : 256;  // threads per block
   static constexpr int LPB = NT / N2;        // complex lines per block
-  static constexpr int S = N2 + 1;
-  static constexpr int L = 16 * S + (N2 == 16 ? 0 : N2);
-  static constexpr int L2 = N + ((N2 == 16 && sizeof(T) == 8) ? 0 : N2);
+  static constexpr int S = LF ? (N2 == 16 ? 17 : N2) : N2 + 1;
+  static constexpr int L = LF ? (N2 == 16 ? 274 : N + 1) : 16 * S + (N2 == 16 ? 0 : N2);
+  static constexpr int L2 =
+      LF ? (N2 == 16 ? 258 : N + 1) : N + ((N2 == 16 && sizeof(T) == 8) ? 0 : N2);
   static constexpr int BUF = LPB * (L > L2 ? L : L2);  // complex elements of LDS
+  __device__ static __forceinline__ int line(int tid) { return LF ? tid % LPB : tid / N2; }
+  __device__ static __forceinline__ int pos(int tid) { return LF ? tid / LPB : tid % N2; }
 };
 
 // True for the axis lengths with a register path.
@@ -120,9 +129,9 @@ __host__ __device__ constexpr bool has_reg_path(int N) { return N == 64 || N == 
 // lds: this line's exchange area (Shape::L complex elements); tw: cos/sin of
 // 2 pi m / N, m = 0..N-1 (interleaved). Called by every thread of the block
 // (contains a barrier); the caller synchronises before reusing lds.
-template <typename T, int N, int SIGN>
+template <typename T, int N, int SIGN, bool LF = false>
 __device__ __forceinline__ void fft4(C2<T>* v, C2<T>* lds, int p, const T* __restrict__ tw) {
-  using Sh = Shape<T, N>;
+  using Sh = Shape<T, N, LF>;
   dft<16, SIGN>(v);
 #pragma unroll
   for (int k1 = 1; k1 < 16; ++k1) {

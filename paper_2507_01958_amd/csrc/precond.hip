@@ -468,6 +468,38 @@ __device__ void rows_inv_reg(const RowsArgs<T>& a, int bid, C2<T>* lds) {
   }
 }
 
+// 1/x from the hardware reciprocal refined by Newton steps (two in float64,
+// one in float32): within an ulp of the correctly rounded quotient.
+template <typename T>
+__device__ __forceinline__ T recip(T x);
+template <>
+__device__ __forceinline__ double recip<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+template <>
+__device__ __forceinline__ float recip<float>(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+// The shifted symbol of Algorithm 2 for one time slice as a polynomial in R:
+// S = nu^2 R^2 + (2 + nu lambda_t/dt) R + lambda_t/dt^2 (> 0), and the scale
+// norm / S applied to a spectral coefficient.
+template <typename T>
+struct SliceSymbol {
+  T a2, b, c, norm;
+  __device__ SliceSymbol(const SolveCtx& sc, double lt)
+      : a2((T)(sc.nu * sc.nu)), b((T)(2.0 + sc.nu * lt * sc.idt)), c((T)(lt * sc.idt2)),
+        norm((T)sc.norm) {}
+  __device__ __forceinline__ T inv(T R) const {
+    return norm * recip<T>(fma(fma(a2, R, b), R, c));
+  }
+};
+
 // Column solve along axis 0 (length N = n0, stride n1) of one time slice:
 // forward transform, division by S, inverse transform; two real columns per
 // complex line. Periodic: DFT with the two columns' spectra separated by
@@ -477,10 +509,10 @@ __device__ void rows_inv_reg(const RowsArgs<T>& a, int bid, C2<T>* lds) {
 // exchange.
 template <typename T, int N>
 __device__ void cols_reg(const ColsArgs<T>& a, int bid, int nb, C2<T>* lds) {
-  using Sh = fftr::Shape<T, N>;
+  using Sh = fftr::Shape<T, N, true>;
   const Geom& g = a.g;
   const SolveCtx& sc = a.sc;
-  const int l = threadIdx.x / Sh::N2, p = threadIdx.x % Sh::N2;
+  const int l = Sh::line(threadIdx.x), p = Sh::pos(threadIdx.x);
   const int cw = 2 * Sh::LPB;
   const int ncb = (g.n1 + cw - 1) / cw;
   const int blk = xcd_remap(bid, nb);
@@ -505,23 +537,23 @@ __device__ void cols_reg(const ColsArgs<T>& a, int bid, int nb, C2<T>* lds) {
       v[n1].y = hasb ? slice[o + 1] : (T)0;
     }
   }
-  fftr::fft4<T, N, -1>(v, lds + l * Sh::L, p, tw);
+  fftr::fft4<T, N, -1, true>(v, lds + l * Sh::L, p, tw);
   __syncthreads();
   C2<T>* zb = lds + l * Sh::L2;
 #pragma unroll
   for (int m = 0; m < 16; ++m) zb[p + Sh::N2 * m] = v[m];
   __syncthreads();
-  const double lt = sc.lam_t[t];
-  const double l1a = hasa ? sc.lam1[ja] : 0.0, l1b = hasb ? sc.lam1[jb] : 0.0;
+  const SliceSymbol<T> sym(sc, sc.lam_t[t]);
+  const T l1a = hasa ? (T)sc.lam1[ja] : (T)0, l1b = hasb ? (T)sc.lam1[jb] : (T)0;
   const T* __restrict__ ct = ct_table<T>(a.ax);
 #pragma unroll
   for (int m = 0; m < 16; ++m) {
     const int k = p + Sh::N2 * m;
     const int kr = k ? N - k : 0;
     const C2<T> z = v[m], zr = zb[kr];
-    const double R0 = sc.lam0[k];
-    const T ia = (T)(sc.norm / shift_symbol(sc, R0 + l1a, lt));
-    const T ib = (T)(sc.norm / shift_symbol(sc, R0 + l1b, lt));
+    const T R0 = (T)sc.lam0[k];
+    const T ia = sym.inv(R0 + l1a);
+    const T ib = sym.inv(R0 + l1b);
     if (!dct) {
       // W = Z_a ia + i Z_b ib = (Z + conj Zr)/2 ia + (Z - conj Zr)/2 ib
       const C2<T> sp = {(T)0.5 * (z.x + zr.x), (T)0.5 * (z.y - zr.y)};
@@ -534,9 +566,9 @@ __device__ void cols_reg(const ColsArgs<T>& a, int bid, int nb, C2<T>* lds) {
       const T cb = (T)0.5 * (c * (q + s) + sn * (r - pp)) * ib;
       T rca = (T)0, rcb = (T)0;
       if (k) {
-        const double Rr = sc.lam0[kr];
-        const T ira = (T)(sc.norm / shift_symbol(sc, Rr + l1a, lt));
-        const T irb = (T)(sc.norm / shift_symbol(sc, Rr + l1b, lt));
+        const T Rr = (T)sc.lam0[kr];
+        const T ira = sym.inv(Rr + l1a);
+        const T irb = sym.inv(Rr + l1b);
         const T cr = ct[2 * kr], snr = ct[2 * kr + 1];
         rca = (T)0.5 * (cr * (r + pp) + snr * (s - q)) * ira;
         rcb = (T)0.5 * (cr * (s + q) + snr * (pp - r)) * irb;
@@ -546,7 +578,7 @@ __device__ void cols_reg(const ColsArgs<T>& a, int bid, int nb, C2<T>* lds) {
     }
   }
   __syncthreads();
-  fftr::fft4<T, N, +1>(v, lds + l * Sh::L, p, tw);
+  fftr::fft4<T, N, +1, true>(v, lds + l * Sh::L, p, tw);
 #pragma unroll
   for (int m = 0; m < 16; ++m) {
     const int n = p + Sh::N2 * m;
@@ -711,9 +743,9 @@ SpatialShape spatial_shape(const Plan& P) {
     if (sh.creg) {
       int lines = 0, buf = 0;
       switch (g.n0) {
-        case 64: lines = fftr::Shape<T, 64>::LPB; buf = fftr::Shape<T, 64>::BUF; break;
-        case 128: lines = fftr::Shape<T, 128>::LPB; buf = fftr::Shape<T, 128>::BUF; break;
-        default: lines = fftr::Shape<T, 256>::LPB; buf = fftr::Shape<T, 256>::BUF; break;
+        case 64: lines = fftr::Shape<T, 64, true>::LPB; buf = fftr::Shape<T, 64, true>::BUF; break;
+        case 128: lines = fftr::Shape<T, 128, true>::LPB; buf = fftr::Shape<T, 128, true>::BUF; break;
+        default: lines = fftr::Shape<T, 256, true>::LPB; buf = fftr::Shape<T, 256, true>::BUF; break;
       }
       sh.cw = 2 * lines;
       sh.cthreads = fftr::Shape<T, 64>::NT;

@@ -405,10 +405,11 @@ int grid_for(long long n, int cap = kStreamGrid) {
 
 // Time-chunk length of the tiled A kernel: enough blocks to fill the chip.
 // The grid also stays within the reduction's partial-sum capacity.
-int aat_chunk(const Geom& g, int ntile, int max_blocks) {
+int aat_chunk(const Geom& g, int ntile, int max_blocks, int want) {
   long long tc = ((long long)g.nt * ntile) / 1024;
+  if (want > 0) tc = want;  // tuned
   if (tc < 1) tc = 1;
-  if (tc > 16) tc = 16;
+  if (tc > 64) tc = 64;
   const long long need = ((long long)g.nt * ntile + max_blocks - 1) / max_blocks;
   if (tc < need) tc = need;
   return (int)tc;
@@ -418,7 +419,7 @@ template <bool HAS0>
 int aat_shape(const Plan& P, int* tc_out) {
   const Geom& g = P.g;
   const int ntile = ((g.n0 + Tile<HAS0>::TI - 1) / Tile<HAS0>::TI) * ((g.n1 + kTJ - 1) / kTJ);
-  const int tc = aat_chunk(g, ntile, P.red.max_blocks);
+  const int tc = aat_chunk(g, ntile, P.red.max_blocks, P.tune.aat_tc);
   *tc_out = tc;
   return ntile * ((g.nt + tc - 1) / tc);
 }

@@ -159,8 +159,11 @@ template <int MODE>
 struct LpTraits;
 template <>
 struct LpTraits<GM_F32> {
+  // 16 t per step like the 16-bit types: lane group kq holds t = 16 ks + 4 kq + j
+  // (j < 4), and the four float32 products of a step take k-slice j each, so a
+  // lane's four A values are contiguous (one 16-byte LDS read).
   using VT = float;
-  static constexpr int KSTEP = 4;
+  static constexpr int KSTEP = 16;
 };
 template <>
 struct LpTraits<GM_F16> {
@@ -215,20 +218,9 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
   // loads are in flight: an unrolled 16-byte copy
   {
     constexpr int NV16 = NTP * NTP * (int)sizeof(VT) / 16;
-    constexpr int PERT = (NV16 + 255) / 256;
     const uint4* src = reinterpret_cast<const uint4*>(Vg);
     uint4* dst = reinterpret_cast<uint4*>(Vs);
-    uint4 tmp[PERT];
-#pragma unroll
-    for (int e = 0; e < PERT; ++e) {
-      const int i = threadIdx.x + 256 * e;
-      if (i < NV16) tmp[e] = src[i];
-    }
-#pragma unroll
-    for (int e = 0; e < PERT; ++e) {
-      const int i = threadIdx.x + 256 * e;
-      if (i < NV16) dst[VsLayout<NTP, VT>::chunk(i)] = tmp[e];
-    }
+    for (int i = threadIdx.x; i < NV16; i += 256) dst[VsLayout<NTP, VT>::chunk(i)] = src[i];
   }
   float scale = 1.0f, unscale = 1.0f;
   if (MODE == GM_F16) {
@@ -257,10 +249,14 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
     if constexpr (MODE == GM_F32) {
 #pragma unroll
       for (int kb = 0; kb < NKB; ++kb) {
-        const float a = Vs[VsLayout<NTP, VT>::idx(kb * 16 + (lane & 15), KSTEP * ks + PER * kq)];
+        const v4f a = *reinterpret_cast<const v4f*>(
+            &Vs[VsLayout<NTP, VT>::idx(kb * 16 + (lane & 15), KSTEP * ks + PER * kq)]);
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
-          acc[cb][kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xs[cb][ks][0], acc[cb][kb], 0, 0, 0);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[cb][kb] =
+                __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], xs[cb][ks][j], acc[cb][kb], 0, 0, 0);
       }
     } else if constexpr (MODE == GM_F16) {
       v4h b[CB];
@@ -383,19 +379,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_tgemm_pers(const typename PersTr
     constexpr int NV16 = NTP * NTP * (int)sizeof(VT) / 16;
     const uint4* src = reinterpret_cast<const uint4*>(Vg);
     uint4* dst = reinterpret_cast<uint4*>(Vs);
-    for (int base = 0; base < NV16; base += 8 * NT) {
-      uint4 tmp[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int i = base + threadIdx.x + NT * e;
-        if (i < NV16) tmp[e] = src[i];
-      }
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int i = base + threadIdx.x + NT * e;
-        if (i < NV16) dst[MODE == GM_F64 ? i : VsLayout<NTP, VT>::chunk(i)] = tmp[e];
-      }
-    }
+    for (int i = threadIdx.x; i < NV16; i += NT)
+      dst[MODE == GM_F64 ? i : VsLayout<NTP, VT>::chunk(i)] = src[i];
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;

@@ -1,4 +1,5 @@
-// Autotuner of the launch shapes (struct Tune) of the preconditioner passes.
+// Autotuner of the launch shapes (struct Tune) of the preconditioner passes
+// and the A kernel.
 //
 // The choices change how work is split among blocks (rows per block of the
 // row transforms, column pairs per block of the column solves, column blocks
@@ -51,7 +52,7 @@ Key key_of(const Plan& P) {
 }
 
 // One cache line: "d n0 n1 nt bc precision l arch f64_cb lp_cb rows_elems cols_lines pers
-// fft_reg".
+// fft_reg aat_tc".
 void load_file_locked() {
   if (g_file_loaded) return;
   g_file_loaded = true;
@@ -62,9 +63,9 @@ void load_file_locked() {
   char arch[64];
   int d, n0, n1, nt, bc, prec, l;
   Tune t;
-  while (std::fscanf(f, "%d %d %d %d %d %d %d %63s %d %d %d %d %d %d", &d, &n0, &n1, &nt, &bc,
-                     &prec, &l, arch, &t.f64_cb, &t.lp_cb, &t.rows_elems, &t.cols_lines,
-                     &t.tgemm_pers, &t.fft_reg) == 14)
+  while (std::fscanf(f, "%d %d %d %d %d %d %d %63s %d %d %d %d %d %d %d", &d, &n0, &n1, &nt,
+                     &bc, &prec, &l, arch, &t.f64_cb, &t.lp_cb, &t.rows_elems, &t.cols_lines,
+                     &t.tgemm_pers, &t.fft_reg, &t.aat_tc) == 15)
     g_cache[Key{d, n0, n1, nt, bc, prec, l, arch}] = t;
   std::fclose(f);
 }
@@ -78,21 +79,29 @@ void store(const Plan& P, const Tune& t) {
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%d %d %d %d %d %d %d %s %d %d %d %d %d %d\n", std::get<0>(k),
+  std::fprintf(f, "%d %d %d %d %d %d %d %s %d %d %d %d %d %d %d\n", std::get<0>(k),
                std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k),
                std::get<6>(k), std::get<7>(k).c_str(), t.f64_cb, t.lp_cb, t.rows_elems,
-               t.cols_lines, t.tgemm_pers, t.fft_reg);
+               t.cols_lines, t.tgemm_pers, t.fft_reg, t.aat_tc);
   std::fclose(f);
 }
 
-// Mean time (ms) of `reps` preconditioner applications, best of `trials`.
+// One timed unit: a preconditioner application plus a fused A apply (the
+// PCG direction update p = z + beta p_old with q = A p), the two parts whose
+// launch shapes are tuned.
+void tune_unit(Plan& P, hipStream_t s) {
+  launch_precond(P, P.r, P.z, false, nullptr, s);
+  launch_pdir_AAt(P, P.z, P.r, P.p, P.q, true, s);
+}
+
+// Mean time (ms) of `reps` units, best of `trials`.
 int time_precond(Plan& P, hipEvent_t a, hipEvent_t b, int reps, int trials, float* best) {
   hipStream_t s = P.stream;
-  launch_precond(P, P.r, P.z, false, nullptr, s);  // warm caches and code
+  tune_unit(P, s);  // warm caches and code
   *best = 1e30f;
   for (int t = 0; t < trials; ++t) {
     if (hipEventRecord(a, s) != hipSuccess) return fail(MFG_ERR_HIP, "event record failed");
-    for (int i = 0; i < reps; ++i) launch_precond(P, P.r, P.z, false, nullptr, s);
+    for (int i = 0; i < reps; ++i) tune_unit(P, s);
     if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess)
       return fail(MFG_ERR_HIP, "event record failed");
     if (hipGetLastError() != hipSuccess) return fail(MFG_ERR_HIP, "launch failed while tuning");
@@ -147,6 +156,7 @@ int autotune(Plan& P, int effort, bool allow_pers) {
   params.push_back({&Tune::fft_reg, {1, 0}});
   params.push_back({&Tune::rows_elems, {256, 512, 1024, 2048, 4096}});
   if (P.g.has0) params.push_back({&Tune::cols_lines, {1, 2, 4, 8, 16}});
+  params.push_back({&Tune::aat_tc, {0, 4, 8, 16, 32}});
   if (!allow_pers) P.tune.tgemm_pers = 0;
   int rc = MFG_OK;
   float cur = 0.0f;
