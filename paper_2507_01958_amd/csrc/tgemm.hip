@@ -13,6 +13,8 @@
 //   and the products are scaled back exactly.
 // V is symmetric (V[k][t] = V[t][k] for the DCT-VIII and the DST-I), which the
 // LDS staging uses to read it with unit stride.
+#include <type_traits>
+
 #include "batch_args.h"
 #include "tgemm.h"
 
@@ -326,58 +328,209 @@ __global__ __launch_bounds__(256) void k_tgemm_lp_batch(const GemmArgs<TX, TY>* 
   tgemm_lp_body<MODE, NTP, CB, TX, TY>(A[i], blockIdx.x - off[i]);
 }
 
-// Persistent form for N_t <= 128 (NTP = N_t rounded up to 16): each block
-// stages all of V in LDS once, then every wave independently streams 16-node
-// column tiles (tile c, c + #waves, ...), fetching the next tile's operands into
-// registers while it multiplies the current one. float16 operands are scaled
-// per wave tile (16 columns) by a power of two; the scaling is exact per column.
-// LDS layout: float64 Vs[t][k] (the f64 A operand is one k per lane); low
-// precision Vs[k][t] (four consecutive t per lane).
+// Streaming persistent form for N_t <= 128 (NTP = N_t rounded up to 16):
+// each block stages all of V in LDS once; each wave then streams 16-node
+// column tiles (tile w, w + #waves, ...) with two operand register sets, so
+// the global loads of the next tile are in flight while the current one is
+// multiplied and stored. float16 / bfloat16 operands are scaled per tile by a
+// power of two from the tile's largest magnitude (a wave-level reduction).
+// LDS layout: float64 Vs[t][k] (V is symmetric; the f64 A operand is one k
+// per lane); low precision the swizzled row-major copy of VsLayout.
 template <int MODE>
-struct PersTraits;
+struct StreamTraits;
 template <>
-struct PersTraits<GM_F64> {
+struct StreamTraits<GM_F64> {
   using VT = double;
-  using XT = double;  // register type of a fetched operand
   static constexpr int KSTEP = 4;
 };
 template <>
-struct PersTraits<GM_F32> {
+struct StreamTraits<GM_F32> {
   using VT = float;
-  using XT = float;
-  static constexpr int KSTEP = 4;
-};
-template <>
-struct PersTraits<GM_F16> {
-  using VT = _Float16;
-  using XT = float;
   static constexpr int KSTEP = 16;
 };
 template <>
-struct PersTraits<GM_BF16> {
+struct StreamTraits<GM_F16> {
+  using VT = _Float16;
+  static constexpr int KSTEP = 16;
+};
+template <>
+struct StreamTraits<GM_BF16> {
   using VT = unsigned short;
-  using XT = float;
   static constexpr int KSTEP = 16;
 };
 
+template <int MODE, int NTP>
+struct StreamShape {
+  static constexpr int KSTEP = StreamTraits<MODE>::KSTEP;
+  static constexpr int PER = KSTEP / 4;   // operand values per lane per step
+  static constexpr int NKS = NTP / KSTEP;  // steps
+  static constexpr int NKB = NTP / 16;     // 16-row output blocks
+  static constexpr int NX = NKS * PER;     // operand values per lane per tile
+};
+
+// Operands of one 16-column tile: x[ks * PER + j] = X[t][col], t = KSTEP ks +
+// PER kq + j (zero outside the matrix).
+template <int MODE, int NTP, typename TX, int NXA>
+__device__ __forceinline__ void stream_load(TX (&x)[NXA], const TX* __restrict__ X, int tile,
+                                            int nt, int M, int kq, int cl) {
+  using Sh = StreamShape<MODE, NTP>;
+  const int col = tile * 16 + cl;
+  const bool cv = col < M;
+#pragma unroll
+  for (int ks = 0; ks < Sh::NKS; ++ks)
+#pragma unroll
+    for (int j = 0; j < Sh::PER; ++j) {
+      const int t = Sh::KSTEP * ks + Sh::PER * kq + j;
+      x[ks * Sh::PER + j] = (cv && t < nt) ? X[(size_t)t * M + col] : (TX)0;
+    }
+}
+
+// Multiply one tile, store it and accumulate the dot products.
+template <int MODE, int NTP, typename TX, typename TY, int NXA>
+__device__ __forceinline__ void stream_tile(const TX (&x)[NXA],
+                                            const typename StreamTraits<MODE>::VT* Vs, int tile,
+                                            const GemmArgs<TX, TY>& ga, int lane,
+                                            double (&dots)[2]) {
+  using Sh = StreamShape<MODE, NTP>;
+  using VT = typename StreamTraits<MODE>::VT;
+  const int nt = ga.nt, M = ga.M, dotmode = ga.dotmode;
+  const int kq = lane >> 4, cl = lane & 15;
+  const int col = tile * 16 + cl;
+  // The A operands of step ks + 1 are read from LDS while step ks multiplies;
+  // a scheduling barrier per step keeps the compiler from hoisting every
+  // step's reads (which would exhaust the register file).
+  if constexpr (MODE == GM_F64) {
+    v4d acc[Sh::NKB];
+#pragma unroll
+    for (int kb = 0; kb < Sh::NKB; ++kb) acc[kb] = (v4d){0.0, 0.0, 0.0, 0.0};
+    double a[2][Sh::NKB];
+#pragma unroll
+    for (int kb = 0; kb < Sh::NKB; ++kb) a[0][kb] = Vs[kq * NTP + kb * 16 + cl];
+#pragma unroll
+    for (int ks = 0; ks < Sh::NKS; ++ks) {
+      if (ks + 1 < Sh::NKS) {
+#pragma unroll
+        for (int kb = 0; kb < Sh::NKB; ++kb)
+          a[(ks + 1) & 1][kb] = Vs[(4 * (ks + 1) + kq) * NTP + kb * 16 + cl];
+      }
+#pragma unroll
+      for (int kb = 0; kb < Sh::NKB; ++kb)
+        acc[kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks & 1][kb], (double)x[ks], acc[kb], 0,
+                                                       0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (col < M) {
+#pragma unroll
+      for (int kb = 0; kb < Sh::NKB; ++kb)
+#pragma unroll
+        for (int jr = 0; jr < 4; ++jr) {
+          // f64 result layout: row (l / 16) + 4 jr, column l % 16
+          const int k = kb * 16 + kq + 4 * jr;
+          if (k < nt) {
+            const size_t o = (size_t)k * M + col;
+            const double v = acc[kb][jr];
+            ga.Y[o] = (TY)v;
+            if (dotmode != DOT_NONE) {
+              dots[0] += ga.rvec[o] * v;
+              if (dotmode == DOT_FLEX) dots[1] += ga.qvec[o] * v;
+            }
+          }
+        }
+    }
+  } else {
+    float scale = 1.0f, unscale = 1.0f;
+    if constexpr (MODE == GM_F16) {
+      float amax = 0.0f;
+#pragma unroll
+      for (int i = 0; i < Sh::NX; ++i) amax = fmaxf(amax, fabsf((float)x[i]));
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
+      if (amax > 0.0f && __builtin_isfinite(amax)) {
+        int e;
+        frexpf(amax, &e);
+        e = e < -100 ? -100 : e;
+        scale = ldexpf(1.0f, 14 - e);
+        unscale = ldexpf(1.0f, e - 14);
+      }
+    }
+    v4f acc[Sh::NKB];
+#pragma unroll
+    for (int kb = 0; kb < Sh::NKB; ++kb) acc[kb] = (v4f){0.f, 0.f, 0.f, 0.f};
+    // 16 bytes of A per lane and step: 4 floats, or 4 x 16 bits (low half used)
+    using AT = typename std::conditional<MODE == GM_F32, v4f, uint2>::type;
+    AT a[2][Sh::NKB];
+#pragma unroll
+    for (int kb = 0; kb < Sh::NKB; ++kb)
+      a[0][kb] = *reinterpret_cast<const AT*>(&Vs[VsLayout<NTP, VT>::idx(kb * 16 + cl, 4 * kq)]);
+#pragma unroll
+    for (int ks = 0; ks < Sh::NKS; ++ks) {
+      if (ks + 1 < Sh::NKS) {
+#pragma unroll
+        for (int kb = 0; kb < Sh::NKB; ++kb)
+          a[(ks + 1) & 1][kb] = *reinterpret_cast<const AT*>(
+              &Vs[VsLayout<NTP, VT>::idx(kb * 16 + cl, Sh::KSTEP * (ks + 1) + 4 * kq)]);
+      }
+      if constexpr (MODE == GM_F32) {
+#pragma unroll
+        for (int kb = 0; kb < Sh::NKB; ++kb)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks & 1][kb][j], (float)x[ks * 4 + j],
+                                                           acc[kb], 0, 0, 0);
+      } else if constexpr (MODE == GM_F16) {
+        v4h b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = (_Float16)((float)x[ks * 4 + j] * scale);
+#pragma unroll
+        for (int kb = 0; kb < Sh::NKB; ++kb) {
+          v4h av;
+          __builtin_memcpy(&av, &a[ks & 1][kb], sizeof(av));
+          acc[kb] = __builtin_amdgcn_mfma_f32_16x16x16f16(av, b, acc[kb], 0, 0, 0);
+        }
+      } else {
+        v4s b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = f2bf((float)x[ks * 4 + j]);
+#pragma unroll
+        for (int kb = 0; kb < Sh::NKB; ++kb) {
+          v4s av;
+          __builtin_memcpy(&av, &a[ks & 1][kb], sizeof(av));
+          acc[kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, b, acc[kb], 0, 0, 0);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (col < M) {
+#pragma unroll
+      for (int kb = 0; kb < Sh::NKB; ++kb)
+#pragma unroll
+        for (int jr = 0; jr < 4; ++jr) {
+          // float32-accumulating 16x16 results: row 4 (l / 16) + jr, column l % 16
+          const int k = kb * 16 + 4 * kq + jr;
+          if (k < nt) {
+            const size_t o = (size_t)k * M + col;
+            const double v = (double)(acc[kb][jr] * unscale);
+            ga.Y[o] = (TY)v;
+            if (dotmode != DOT_NONE) {
+              dots[0] += ga.rvec[o] * v;
+              if (dotmode == DOT_FLEX) dots[1] += ga.qvec[o] * v;
+            }
+          }
+        }
+    }
+  }
+}
+
 template <int MODE, int NTP, int WAVES, typename TX, typename TY>
-__global__ __launch_bounds__(WAVES * 64) void k_tgemm_pers(const typename PersTraits<MODE>::VT* __restrict__ Vg,
-                                                    const TX* __restrict__ X, TY* __restrict__ Y,
-                                                    int nt, int M, int dotmode,
-                                                    const double* __restrict__ rvec,
-                                                    const double* __restrict__ qvec, RedBuf rb) {
-  using VT = typename PersTraits<MODE>::VT;
-  using XT = typename PersTraits<MODE>::XT;
-  constexpr int KSTEP = PersTraits<MODE>::KSTEP;
-  constexpr int PER = KSTEP / 4;
-  constexpr int NKS = NTP / KSTEP;
-  constexpr int NKB = NTP / 16;
-  constexpr int NX = NKS * PER;  // operand values per lane per tile
+__global__ __launch_bounds__(WAVES * 64) void k_tgemm_stream(GemmArgs<TX, TY> ga) {
+  if (ga.done && *ga.done != 0.0) return;
+  using VT = typename StreamTraits<MODE>::VT;
+  using Sh = StreamShape<MODE, NTP>;
+  constexpr int NT = WAVES * 64;
   __shared__ __align__(16) VT Vs[NTP * NTP];
   {
-    constexpr int NT = WAVES * 64;
     constexpr int NV16 = NTP * NTP * (int)sizeof(VT) / 16;
-    const uint4* src = reinterpret_cast<const uint4*>(Vg);
+    const uint4* src = reinterpret_cast<const uint4*>(ga.V);
     uint4* dst = reinterpret_cast<uint4*>(Vs);
     for (int i = threadIdx.x; i < NV16; i += NT)
       dst[MODE == GM_F64 ? i : VsLayout<NTP, VT>::chunk(i)] = src[i];
@@ -385,148 +538,45 @@ __global__ __launch_bounds__(WAVES * 64) void k_tgemm_pers(const typename PersTr
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int kq = lane >> 4, cl = lane & 15;
-  const int nw = gridDim.x * WAVES;
-  const int ncb = (M + 15) / 16;
-  XT xn[NX];
-  auto fetch = [&](int cb) {
-    const int col = cb * 16 + cl;
-    const bool cv = col < M;
-#pragma unroll
-    for (int ks = 0; ks < NKS; ++ks)
-#pragma unroll
-      for (int j = 0; j < PER; ++j) {
-        const int t = KSTEP * ks + PER * kq + j;
-        xn[ks * PER + j] = (cv && t < nt) ? (XT)X[(size_t)t * M + col] : (XT)0;
-      }
-  };
+  const int ntiles = (ga.M + 15) / 16;
+  const int stride = gridDim.x * WAVES;
   double dots[2] = {0.0, 0.0};
-  int cb = blockIdx.x * WAVES + wave;
-  if (cb < ncb) fetch(cb);
-  for (; cb < ncb; cb += nw) {
-    XT xc[NX];
-#pragma unroll
-    for (int i = 0; i < NX; ++i) xc[i] = xn[i];
-    if (cb + nw < ncb) fetch(cb + nw);
-    const int col = cb * 16 + cl;
-    if constexpr (MODE == GM_F64) {
-      v4d acc[NKB];
-#pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) acc[kb] = (v4d){0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-      for (int ks = 0; ks < NKS; ++ks)
-#pragma unroll
-        for (int kb = 0; kb < NKB; ++kb)
-          acc[kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[(4 * ks + kq) * NTP + kb * 16 + cl],
-                                                         xc[ks], acc[kb], 0, 0, 0);
-      if (col < M) {
-#pragma unroll
-        for (int kb = 0; kb < NKB; ++kb)
-#pragma unroll
-          for (int jr = 0; jr < 4; ++jr) {
-            // f64 result layout: row (l / 16) + 4 jr
-            const int k = kb * 16 + kq + 4 * jr;
-            if (k < nt) {
-              const size_t o = (size_t)k * M + col;
-              const double v = acc[kb][jr];
-              Y[o] = (TY)v;
-              if (dotmode != DOT_NONE) {
-                dots[0] += rvec[o] * v;
-                if (dotmode == DOT_FLEX) dots[1] += qvec[o] * v;
-              }
-            }
-          }
-      }
-    } else {
-      float scale = 1.0f, unscale = 1.0f;
-      if constexpr (MODE == GM_F16) {
-        float amax = 0.0f;
-#pragma unroll
-        for (int i = 0; i < NX; ++i) amax = fmaxf(amax, fabsf(xc[i]));
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
-        if (amax > 0.0f && __builtin_isfinite(amax)) {
-          int e;
-          frexpf(amax, &e);
-          e = e < -100 ? -100 : e;
-          scale = ldexpf(1.0f, 14 - e);
-          unscale = ldexpf(1.0f, e - 14);
-        }
-      }
-      v4f acc[NKB];
-#pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) acc[kb] = (v4f){0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-      for (int ks = 0; ks < NKS; ++ks) {
-        if constexpr (MODE == GM_F32) {
-#pragma unroll
-          for (int kb = 0; kb < NKB; ++kb)
-            acc[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                Vs[VsLayout<NTP, VT>::idx(kb * 16 + cl, 4 * ks + kq)], xc[ks], acc[kb], 0, 0, 0);
-        } else if constexpr (MODE == GM_F16) {
-          v4h b;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) b[j] = (_Float16)(xc[ks * 4 + j] * scale);
-#pragma unroll
-          for (int kb = 0; kb < NKB; ++kb) {
-            const v4h a = *reinterpret_cast<const v4h*>(
-                &Vs[VsLayout<NTP, VT>::idx(kb * 16 + cl, 16 * ks + 4 * kq)]);
-            acc[kb] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc[kb], 0, 0, 0);
-          }
-        } else {
-          v4s b;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) b[j] = f2bf(xc[ks * 4 + j]);
-#pragma unroll
-          for (int kb = 0; kb < NKB; ++kb) {
-            const v4s a = *reinterpret_cast<const v4s*>(
-                &Vs[VsLayout<NTP, VT>::idx(kb * 16 + cl, 16 * ks + 4 * kq)]);
-            acc[kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[kb], 0, 0, 0);
-          }
-        }
-      }
-      if (col < M) {
-#pragma unroll
-        for (int kb = 0; kb < NKB; ++kb)
-#pragma unroll
-          for (int jr = 0; jr < 4; ++jr) {
-            // f32-accumulating result layout: row 4 (l / 16) + jr
-            const int k = kb * 16 + 4 * kq + jr;
-            if (k < nt) {
-              const size_t o = (size_t)k * M + col;
-              const double v = (double)(acc[kb][jr] * unscale);
-              Y[o] = (TY)v;
-              if (dotmode != DOT_NONE) {
-                dots[0] += rvec[o] * v;
-                if (dotmode == DOT_FLEX) dots[1] += qvec[o] * v;
-              }
-            }
-          }
-      }
-    }
+  TX xa[Sh::NX], xb[Sh::NX];
+  int tile = blockIdx.x * WAVES + wave;
+  if (tile < ntiles) stream_load<MODE, NTP>(xa, ga.X, tile, ga.nt, ga.M, kq, cl);
+  while (tile < ntiles) {
+    int next = tile + stride;
+    if (next < ntiles) stream_load<MODE, NTP>(xb, ga.X, next, ga.nt, ga.M, kq, cl);
+    stream_tile<MODE, NTP>(xa, Vs, tile, ga, lane, dots);
+    tile = next;
+    if (tile >= ntiles) break;
+    next = tile + stride;
+    if (next < ntiles) stream_load<MODE, NTP>(xa, ga.X, next, ga.nt, ga.M, kq, cl);
+    stream_tile<MODE, NTP>(xb, Vs, tile, ga, lane, dots);
+    tile = next;
   }
-  if (dotmode != DOT_NONE) reduce_store<2>(dots, rb, T_RZ, blockIdx.x);
+  if (ga.dotmode != DOT_NONE) reduce_store<2>(dots, ga.rb, T_RZ, blockIdx.x);
 }
 
 template <int MODE, int NTP, typename TX, typename TY>
-int pers_launch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r, const double* q,
-                hipStream_t s) {
-  using VT = typename PersTraits<MODE>::VT;
+int stream_launch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r,
+                  const double* q, hipStream_t s) {
   const int M = P.g.M;
-  const int ncb = (M + 15) / 16;
-  // float64: 4 waves (one per SIMD, the full register file each) and one
-  // block per CU (up to 128 KB of V in LDS); low precision: 8 waves, two
-  // blocks per CU
-  constexpr int WAVES = (MODE == GM_F64) ? 4 : 8;
+  const int ntiles = (M + 15) / 16;
+  // 4 waves a block; float64: one block per CU (V takes up to 128 KB of LDS,
+  // each wave has a SIMD's whole register file); low precision: two blocks
+  constexpr int WAVES = 4;
   const int per_cu = (MODE == GM_F64) ? 1 : 2;
   int grid = P.num_cus * per_cu;
-  const int need = (ncb + WAVES - 1) / WAVES;
+  const int need = (ntiles + WAVES - 1) / WAVES;
   if (grid > need) grid = need;
   if (grid < 1) grid = 1;
   const void* V = (MODE == GM_F64) ? (const void*)P.Vp64
                   : (MODE == GM_F32) ? (const void*)P.Vp32
                   : (MODE == GM_F16) ? (const void*)P.Vp16 : (const void*)P.Vpbf;
-  hipLaunchKernelGGL((k_tgemm_pers<MODE, NTP, WAVES, TX, TY>), dim3(grid), dim3(WAVES * 64), 0, s,
-                     (const VT*)V, X, Y, P.g.nt, M, dotmode, r, q, P.red);
+  const GemmArgs<TX, TY> a{V, X, Y, P.g.nt, M, 0, dotmode, r, q, P.red, P.pcg_done};
+  hipLaunchKernelGGL((k_tgemm_stream<MODE, NTP, WAVES, TX, TY>), dim3(grid), dim3(WAVES * 64), 0,
+                     s, a);
   return grid;
 }
 
@@ -534,14 +584,14 @@ template <int MODE, typename TX, typename TY>
 int pers_dispatch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r,
                   const double* q, hipStream_t s) {
   switch (P.ntp) {
-    case 16: return pers_launch<MODE, 16>(P, X, Y, dotmode, r, q, s);
-    case 32: return pers_launch<MODE, 32>(P, X, Y, dotmode, r, q, s);
-    case 48: return pers_launch<MODE, 48>(P, X, Y, dotmode, r, q, s);
-    case 64: return pers_launch<MODE, 64>(P, X, Y, dotmode, r, q, s);
-    case 80: return pers_launch<MODE, 80>(P, X, Y, dotmode, r, q, s);
-    case 96: return pers_launch<MODE, 96>(P, X, Y, dotmode, r, q, s);
-    case 112: return pers_launch<MODE, 112>(P, X, Y, dotmode, r, q, s);
-    default: return pers_launch<MODE, 128>(P, X, Y, dotmode, r, q, s);
+    case 16: return stream_launch<MODE, 16>(P, X, Y, dotmode, r, q, s);
+    case 32: return stream_launch<MODE, 32>(P, X, Y, dotmode, r, q, s);
+    case 48: return stream_launch<MODE, 48>(P, X, Y, dotmode, r, q, s);
+    case 64: return stream_launch<MODE, 64>(P, X, Y, dotmode, r, q, s);
+    case 80: return stream_launch<MODE, 80>(P, X, Y, dotmode, r, q, s);
+    case 96: return stream_launch<MODE, 96>(P, X, Y, dotmode, r, q, s);
+    case 112: return stream_launch<MODE, 112>(P, X, Y, dotmode, r, q, s);
+    default: return stream_launch<MODE, 128>(P, X, Y, dotmode, r, q, s);
   }
 }
 

@@ -86,22 +86,25 @@ void store(const Plan& P, const Tune& t) {
   std::fclose(f);
 }
 
-// One timed unit: a preconditioner application plus a fused A apply (the
-// PCG direction update p = z + beta p_old with q = A p), the two parts whose
-// launch shapes are tuned.
-void tune_unit(Plan& P, hipStream_t s) {
-  launch_precond(P, P.r, P.z, false, nullptr, s);
-  launch_pdir_AAt(P, P.z, P.r, P.p, P.q, true, s);
+// Timed units: the preconditioner as PCG applies it (with its fused dot
+// products and finisher), and the fused A apply (PCG direction update
+// p = z + beta p_old with q = A p), each tuned on its own launch shapes.
+enum Unit { U_PRECOND = 0, U_AAT = 1 };
+
+void tune_unit(Plan& P, int unit, hipStream_t s) {
+  if (unit == U_PRECOND) launch_precond(P, P.r, P.z, true, P.q, s);
+  else launch_pdir_AAt(P, P.z, P.r, P.p, P.q, false, s);
 }
 
 // Mean time (ms) of `reps` units, best of `trials`.
-int time_precond(Plan& P, hipEvent_t a, hipEvent_t b, int reps, int trials, float* best) {
+int time_unit(Plan& P, int unit, hipEvent_t a, hipEvent_t b, int reps, int trials,
+              float* best) {
   hipStream_t s = P.stream;
-  tune_unit(P, s);  // warm caches and code
+  tune_unit(P, unit, s);  // warm caches and code
   *best = 1e30f;
   for (int t = 0; t < trials; ++t) {
     if (hipEventRecord(a, s) != hipSuccess) return fail(MFG_ERR_HIP, "event record failed");
-    for (int i = 0; i < reps; ++i) tune_unit(P, s);
+    for (int i = 0; i < reps; ++i) tune_unit(P, unit, s);
     if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess)
       return fail(MFG_ERR_HIP, "event record failed");
     if (hipGetLastError() != hipSuccess) return fail(MFG_ERR_HIP, "launch failed while tuning");
@@ -140,27 +143,30 @@ int autotune(Plan& P, int effort, bool allow_pers) {
     (void)hipEventDestroy(a);
     return fail(MFG_ERR_HIP, "event creation failed");
   }
-  // input: a constant vector (the passes take the same time for any values)
+  // inputs: constant vectors (the passes take the same time for any values)
   launch_fill(P.r, P.g.n, 1.0, P.stream);
+  launch_fill(P.q, P.g.n, 1.0, P.stream);
   const long long work = P.g.n;
-  const int reps = work >= (1LL << 22) ? 3 : (work >= (1LL << 18) ? 10 : 40);
+  const int reps = work >= (1LL << 22) ? 5 : (work >= (1LL << 18) ? 10 : 40);
   const int trials = 3;
   struct Param {
+    int unit;
     int Tune::*field;
     std::vector<int> values;
   };
   std::vector<Param> params;
-  if (P.precision == MFG_FP64) params.push_back({&Tune::f64_cb, {1, 2}});
-  else params.push_back({&Tune::lp_cb, {1, 2}});
-  if (P.ntp > 0 && allow_pers) params.push_back({&Tune::tgemm_pers, {0, 1}});
-  params.push_back({&Tune::fft_reg, {1, 0}});
-  params.push_back({&Tune::rows_elems, {256, 512, 1024, 2048, 4096}});
-  if (P.g.has0) params.push_back({&Tune::cols_lines, {1, 2, 4, 8, 16}});
-  params.push_back({&Tune::aat_tc, {0, 4, 8, 16, 32}});
+  if (P.precision == MFG_FP64) params.push_back({U_PRECOND, &Tune::f64_cb, {1, 2}});
+  else params.push_back({U_PRECOND, &Tune::lp_cb, {1, 2}});
+  if (P.ntp > 0 && allow_pers) params.push_back({U_PRECOND, &Tune::tgemm_pers, {0, 1}});
+  params.push_back({U_PRECOND, &Tune::fft_reg, {1, 0}});
+  params.push_back({U_PRECOND, &Tune::rows_elems, {256, 512, 1024, 2048, 4096}});
+  if (P.g.has0) params.push_back({U_PRECOND, &Tune::cols_lines, {1, 2, 4, 8, 16}});
+  params.push_back({U_AAT, &Tune::aat_tc, {0, 4, 8, 16, 32}});
   if (!allow_pers) P.tune.tgemm_pers = 0;
   int rc = MFG_OK;
-  float cur = 0.0f;
-  rc = time_precond(P, a, b, reps, trials, &cur);
+  float cur[2] = {0.0f, 0.0f};
+  launch_precond(P, P.r, P.z, false, nullptr, P.stream);  // a z for the A unit
+  for (int u = 0; u < 2 && !rc; ++u) rc = time_unit(P, u, a, b, reps, trials, &cur[u]);
   const int passes = effort >= 2 ? 2 : 1;
   for (int pass = 0; pass < passes && !rc; ++pass) {
     for (const Param& prm : params) {
@@ -170,9 +176,9 @@ int autotune(Plan& P, int effort, bool allow_pers) {
         if (v == keep) continue;
         P.tune.*(prm.field) = v;
         float ms;
-        if ((rc = time_precond(P, a, b, reps, trials, &ms))) break;
-        if (ms < 0.97f * cur) {  // switch only on a clear gain
-          cur = ms;
+        if ((rc = time_unit(P, prm.unit, a, b, reps, trials, &ms))) break;
+        if (ms < 0.97f * cur[prm.unit]) {  // switch only on a clear gain
+          cur[prm.unit] = ms;
           best_v = v;
         }
       }
