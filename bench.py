@@ -51,7 +51,7 @@ def algorithmic(kernel, inst, variant):
     (matrix-core bound: 2 N_t flops per element against 16 bytes)."""
     n = inst.n
     nb = 1 + 2 * inst.d  # primal blocks
-    flex = variant != "fp64"
+    flex = variant in ("mixed_fp16", "mixed_bf16")  # PCG form with that preconditioner
     if kernel.startswith("tgemm_f64"):
         return "mfma", 2.0 * inst.nt * inst.nt * inst.M, "fp64"
     for base in ("rows_fwd", "rows_inv", "rows_solve", "cols_solve"):

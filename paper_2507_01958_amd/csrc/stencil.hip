@@ -349,12 +349,14 @@ __device__ void backproj_body(const BackprojArgs& a, int bid, int nb) {
       for (int c = 0; c < g.ncomp; ++c) vout[(size_t)(c + 1) * n + p] = w[c];
     }
     const double m = prox_cell(mbar, w, g.ncomp, Vpot[rem], tau);
-    for (int c = 0; c <= g.ncomp; ++c) xi[(size_t)c * n + p] = x[c];
-    y[p] = m;
-    ybar[p] = m + theta * (m - yo[0]);
+    // streaming stores: the new state is read again only by the next step
+    for (int c = 0; c <= g.ncomp; ++c) __builtin_nontemporal_store(x[c], &xi[(size_t)c * n + p]);
+    __builtin_nontemporal_store(m, &y[p]);
+    __builtin_nontemporal_store(m + theta * (m - yo[0]), &ybar[p]);
     for (int c = 0; c < g.ncomp; ++c) {
-      y[(size_t)(c + 1) * n + p] = w[c];
-      ybar[(size_t)(c + 1) * n + p] = w[c] + theta * (w[c] - yo[1 + c]);
+      __builtin_nontemporal_store(w[c], &y[(size_t)(c + 1) * n + p]);
+      __builtin_nontemporal_store(w[c] + theta * (w[c] - yo[1 + c]),
+                                  &ybar[(size_t)(c + 1) * n + p]);
     }
     const double dm = m - yo[0];
     acc[0] += dm * dm;

@@ -31,10 +31,25 @@ def _short(name: str) -> str:
     return m.group(1).strip() if m else name
 
 
+def _targs(s: str):
+    """Template arguments of a short kernel name, as stripped strings."""
+    if "<" not in s:
+        return []
+    return [a.strip() for a in s[s.index("<") + 1:s.rindex(">")].split(",")]
+
+
+def _prec_sfx(s: str) -> str:
+    return "_f64" if "double" in _targs(s)[:1] else "_f32"
+
+
 def classify(seq):
     """Map an ordered list of raw kernel names to logical names."""
     shorts = [_short(n) for n in seq]
     out = []
+    is_rows = lambda x: x.startswith("k_rows") and not x.startswith("k_rows_batch") \
+        and not x.startswith("k_rows_reg_batch")
+    is_cols = lambda x: x.startswith(("k_cols_solve", "k_cols_reg")) \
+        and not x.startswith("k_cols_reg_batch")
     for i, s in enumerate(shorts):
         prev = shorts[i - 1] if i else ""
         nxt = shorts[i + 1] if i + 1 < len(shorts) else ""
@@ -42,9 +57,8 @@ def classify(seq):
             out.append("aat_fused" if s.endswith("true>") else "aat")
         elif s.startswith("k_rhs"):
             out.append("rhs" if "<true>" in s else "apply_C")
-        elif s.startswith(("k_tgemm64", "k_tgemm_lp", "k_tgemm_pers")):
-            args = s[s.index("<") + 1:-1].split(",")
-            args = [a.strip() for a in args]
+        elif s.startswith(("k_tgemm64", "k_tgemm_lp<", "k_tgemm_stream")):
+            args = _targs(s)
             mode = "f64" if s.startswith("k_tgemm64") else MODES.get(args[0], "f64")
             tx, ty = args[-2], args[-1]
             if tx == "double" and ty == "float":
@@ -52,20 +66,21 @@ def classify(seq):
             elif tx == "float" and ty == "double":
                 d = "inv"
             else:
-                d = "inv" if prev.startswith(("k_rows", "k_cols_solve")) else "fwd"
+                d = "inv" if (is_rows(prev) or is_cols(prev)) else "fwd"
             out.append(f"tgemm_{mode}_{d}")
-        elif s.startswith(("k_rows_batch", "k_cols_batch", "k_AAt_batch", "k_tgemm_lp_batch")):
+        elif s.startswith(("k_rows_batch", "k_rows_reg_batch", "k_cols_batch", "k_cols_reg_batch",
+                           "k_AAt_batch", "k_tgemm_lp_batch")):
             out.append(s[2:].split("<")[0])
-        elif s.startswith("k_rows"):
-            sfx = "_f64" if "<double>" in s else "_f32"
-            if nxt.startswith("k_cols_solve"):
+        elif is_rows(s):
+            sfx = _prec_sfx(s)
+            if is_cols(nxt):
                 out.append("rows_fwd" + sfx)
-            elif prev.startswith("k_cols_solve"):
+            elif is_cols(prev):
                 out.append("rows_inv" + sfx)
             else:
                 out.append("rows_solve" + sfx)
-        elif s.startswith("k_cols_solve"):
-            out.append("cols_solve" + ("_f64" if "<double>" in s else "_f32"))
+        elif is_cols(s):
+            out.append("cols_solve" + _prec_sfx(s))
         elif s.startswith("k_"):
             out.append(s[2:].split("<")[0])
         else:
