@@ -162,6 +162,9 @@ static void read_tune_env(Tune& t) {
       const int v = std::atoi(kv.c_str() + eq + 1);
       if (k == "f64_cb" && (v == 1 || v == 2)) t.f64_cb = v;
       else if (k == "lp_cb" && (v == 1 || v == 2)) t.lp_cb = v;
+      else if (k == "lp_waves" && (v == 4 || v == 8)) t.lp_waves = v;
+      else if (k == "lp_cb_i" && (v == 1 || v == 2)) t.lp_cb_i = v;
+      else if (k == "lp_waves_i" && (v == 4 || v == 8)) t.lp_waves_i = v;
       else if (k == "rows_elems" && v >= 64 && v <= 8192) t.rows_elems = v;
       else if (k == "cols_lines" && v >= 1 && v <= 16) t.cols_lines = v;
       else if (k == "tgemm_pers" && (v == 0 || v == 1)) t.tgemm_pers = v;

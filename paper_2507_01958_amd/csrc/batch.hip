@@ -394,7 +394,7 @@ int batch_create(Batch& B, const mfg_problem_t* pbs, const double* const* V,
     int rc = mfg_plan(&pbs[i], V[i], m0[i], stream, &h);
     if (rc) return rc;
     B.plans.push_back(h);
-    h->P.tune.tgemm_pers = 0;  // batched launches use the blocked time GEMM
+    batch_shape(h->P.tune);  // launch shapes the batched kernels support
   }
   int rc;
   void* p;

@@ -14,8 +14,10 @@
 // row stride S and line stride L; the pairing buffer (element k of a line at
 // k, line stride L2). They were chosen, by exhaustive count over the lanes of
 // each access, to be free of bank conflicts for 16-byte (float64 complex) and
-// 8-byte (float32 complex) accesses with 64 banks of 4 bytes (with 32 banks,
-// the line-fastest N = 256 layout has 2-way conflicts, the others none).
+// 8-byte (float32 complex) accesses served 128 bytes (32 banks of 4 bytes) at
+// a time, which is how gfx950 behaves for these accesses (the hardware's
+// SQ_LDS_BANK_CONFLICT counter reads zero on them and flagged an earlier
+// layout that was conflict-free only for 256 bytes at a time).
 #pragma once
 
 #include "mfg_internal.h"
@@ -113,10 +115,9 @@ struct Shape {
   static constexpr int N2 = N / 16;          // threads per line
   static constexpr int NT = sizeof(T) == 8 ? 128 : 256;  // threads per block
   static constexpr int LPB = NT / N2;        // complex lines per block
-  static constexpr int S = LF ? (N2 == 16 ? 17 : N2) : N2 + 1;
-  static constexpr int L = LF ? (N2 == 16 ? 274 : N + 1) : 16 * S + (N2 == 16 ? 0 : N2);
-  static constexpr int L2 =
-      LF ? (N2 == 16 ? 258 : N + 1) : N + ((N2 == 16 && sizeof(T) == 8) ? 0 : N2);
+  static constexpr int S = LF ? N2 : N2 + 1;
+  static constexpr int L = LF ? N + 1 : 16 * S + (N2 == 16 ? 0 : N2);
+  static constexpr int L2 = LF ? N + 1 : N + ((N2 == 16 && sizeof(T) == 8) ? 0 : N2);
   static constexpr int BUF = LPB * (L > L2 ? L : L2);  // complex elements of LDS
   __device__ static __forceinline__ int line(int tid) { return LF ? tid % LPB : tid / N2; }
   __device__ static __forceinline__ int pos(int tid) { return LF ? tid / LPB : tid % N2; }

@@ -180,7 +180,7 @@ struct LpTraits<GM_BF16> {
 
 // NTP: N_t padded to a multiple of 16 (<= 128). The block covers 4 waves x CB
 // blocks of 16 nodes and all N_t output rows.
-template <int MODE, int NTP, int CB, typename TX, typename TY>
+template <int MODE, int NTP, int CB, typename TX, typename TY, int WPB = 4>
 __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
   if (ga.done && *ga.done != 0.0) return;
   using VT = typename LpTraits<MODE>::VT;
@@ -196,10 +196,10 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
   constexpr int NKB = NTP / 16;     // output row blocks
   constexpr int PER = KSTEP / 4;    // operand values per lane per k-step (1 or 4)
   __shared__ __align__(16) VT Vs[NTP * NTP];  // Vs[k * NTP + t] = V[k][t]
-  __shared__ float smax[4];
+  __shared__ float smax[WPB];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int kq = lane >> 4;
-  const int col0 = (bid * 4 + wave) * CB * 16 + (lane & 15);
+  const int col0 = (bid * WPB + wave) * CB * 16 + (lane & 15);
   // operands: t = KSTEP*ks + PER*kq + j
   float xs[CB][NKS][PER];
   float amax = 0.0f;
@@ -222,7 +222,7 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
     constexpr int NV16 = NTP * NTP * (int)sizeof(VT) / 16;
     const uint4* src = reinterpret_cast<const uint4*>(Vg);
     uint4* dst = reinterpret_cast<uint4*>(Vs);
-    for (int i = threadIdx.x; i < NV16; i += 256) dst[VsLayout<NTP, VT>::chunk(i)] = src[i];
+    for (int i = threadIdx.x; i < NV16; i += WPB * 64) dst[VsLayout<NTP, VT>::chunk(i)] = src[i];
   }
   float scale = 1.0f, unscale = 1.0f;
   if (MODE == GM_F16) {
@@ -232,7 +232,9 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
   }
   __syncthreads();
   if (MODE == GM_F16) {
-    const float bm = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
+    float bm = smax[0];
+#pragma unroll
+    for (int w = 1; w < WPB; ++w) bm = fmaxf(bm, smax[w]);
     if (bm > 0.0f && __builtin_isfinite(bm)) {
       int e;
       frexpf(bm, &e);             // bm < 2^e
@@ -316,9 +318,9 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
   if (dotmode != DOT_NONE) reduce_store<2>(dots, rb, T_RZ, bid);
 }
 
-template <int MODE, int NTP, int CB, typename TX, typename TY>
-__global__ __launch_bounds__(256) void k_tgemm_lp(GemmArgs<TX, TY> a) {
-  tgemm_lp_body<MODE, NTP, CB, TX, TY>(a, blockIdx.x);
+template <int MODE, int NTP, int CB, typename TX, typename TY, int WPB>
+__global__ __launch_bounds__(WPB * 64) void k_tgemm_lp(GemmArgs<TX, TY> a) {
+  tgemm_lp_body<MODE, NTP, CB, TX, TY, WPB>(a, blockIdx.x);
 }
 
 template <int MODE, int NTP, int CB, typename TX, typename TY>
@@ -600,22 +602,31 @@ const void* lp_table(const Plan& P, int mode) {
          : (mode == GM_F16) ? (const void*)P.Vp16 : (const void*)P.Vpbf;
 }
 
-template <int MODE, int NTP, int CB, typename TX, typename TY>
+template <int MODE, int NTP, int CB, int WPB, typename TX, typename TY>
 int lp_launch_cb(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r, const double* q,
                  hipStream_t s) {
   const int M = P.g.M;
-  const int grid = (M + 64 * CB - 1) / (64 * CB);
+  const int grid = (M + 16 * WPB * CB - 1) / (16 * WPB * CB);
   const GemmArgs<TX, TY> a{lp_table(P, MODE), X, Y, P.g.nt, M, 0, dotmode, r, q, P.red,
                            P.pcg_done};
-  hipLaunchKernelGGL((k_tgemm_lp<MODE, NTP, CB, TX, TY>), dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_tgemm_lp<MODE, NTP, CB, TX, TY, WPB>), dim3(grid), dim3(WPB * 64), 0, s,
+                     a);
   return grid;
 }
 
+// Launch shape by direction: forward (float64 in) or inverse (float64 out).
 template <int MODE, int NTP, typename TX, typename TY>
 int lp_launch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r, const double* q,
               hipStream_t s) {
-  if (P.tune.lp_cb == 1) return lp_launch_cb<MODE, NTP, 1>(P, X, Y, dotmode, r, q, s);
-  return lp_launch_cb<MODE, NTP, 2>(P, X, Y, dotmode, r, q, s);
+  const bool fwd = std::is_same<TX, double>::value;
+  const int cb = fwd ? P.tune.lp_cb : P.tune.lp_cb_i;
+  const int waves = fwd ? P.tune.lp_waves : P.tune.lp_waves_i;
+  if (waves == 8) {
+    if (cb == 1) return lp_launch_cb<MODE, NTP, 1, 8>(P, X, Y, dotmode, r, q, s);
+    return lp_launch_cb<MODE, NTP, 2, 8>(P, X, Y, dotmode, r, q, s);
+  }
+  if (cb == 1) return lp_launch_cb<MODE, NTP, 1, 4>(P, X, Y, dotmode, r, q, s);
+  return lp_launch_cb<MODE, NTP, 2, 4>(P, X, Y, dotmode, r, q, s);
 }
 
 template <int MODE, typename TX, typename TY>

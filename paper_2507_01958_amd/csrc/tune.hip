@@ -12,10 +12,12 @@
 // and, when MFG_TUNE_CACHE names a file, read from and appended to it.
 #include <cstdio>
 #include <cstdlib>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "plan.h"
@@ -52,7 +54,7 @@ Key key_of(const Plan& P) {
 }
 
 // One cache line: "d n0 n1 nt bc precision l arch f64_cb lp_cb rows_elems cols_lines pers
-// fft_reg aat_tc".
+// fft_reg aat_tc lp_waves lp_cb_i lp_waves_i".
 void load_file_locked() {
   if (g_file_loaded) return;
   g_file_loaded = true;
@@ -63,9 +65,10 @@ void load_file_locked() {
   char arch[64];
   int d, n0, n1, nt, bc, prec, l;
   Tune t;
-  while (std::fscanf(f, "%d %d %d %d %d %d %d %63s %d %d %d %d %d %d %d", &d, &n0, &n1, &nt,
-                     &bc, &prec, &l, arch, &t.f64_cb, &t.lp_cb, &t.rows_elems, &t.cols_lines,
-                     &t.tgemm_pers, &t.fft_reg, &t.aat_tc) == 15)
+  while (std::fscanf(f, "%d %d %d %d %d %d %d %63s %d %d %d %d %d %d %d %d %d %d", &d, &n0, &n1,
+                     &nt, &bc, &prec, &l, arch, &t.f64_cb, &t.lp_cb, &t.rows_elems,
+                     &t.cols_lines, &t.tgemm_pers, &t.fft_reg, &t.aat_tc, &t.lp_waves,
+                     &t.lp_cb_i, &t.lp_waves_i) == 18)
     g_cache[Key{d, n0, n1, nt, bc, prec, l, arch}] = t;
   std::fclose(f);
 }
@@ -79,10 +82,11 @@ void store(const Plan& P, const Tune& t) {
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%d %d %d %d %d %d %d %s %d %d %d %d %d %d %d\n", std::get<0>(k),
+  std::fprintf(f, "%d %d %d %d %d %d %d %s %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k),
                std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k),
                std::get<6>(k), std::get<7>(k).c_str(), t.f64_cb, t.lp_cb, t.rows_elems,
-               t.cols_lines, t.tgemm_pers, t.fft_reg, t.aat_tc);
+               t.cols_lines, t.tgemm_pers, t.fft_reg, t.aat_tc, t.lp_waves, t.lp_cb_i,
+               t.lp_waves_i);
   std::fclose(f);
 }
 
@@ -117,6 +121,14 @@ int time_unit(Plan& P, int unit, hipEvent_t a, hipEvent_t b, int reps, int trial
 
 }  // namespace
 
+// Launch shapes the batched kernels support: the blocked time GEMM with
+// 4-wave blocks and one column-block count for both directions.
+void batch_shape(Tune& t) {
+  t.tgemm_pers = 0;
+  t.lp_waves = t.lp_waves_i = 4;
+  t.lp_cb_i = t.lp_cb;
+}
+
 bool tune_lookup(const Plan& P, Tune* out) {
   std::lock_guard<std::mutex> lk(g_mu);
   load_file_locked();
@@ -131,7 +143,7 @@ int autotune(Plan& P, int effort, bool allow_pers) {
   if (effort < 2) {
     Tune t;
     if (tune_lookup(P, &t)) {
-      if (!allow_pers) t.tgemm_pers = 0;
+      if (!allow_pers) batch_shape(t);
       t.flex = P.tune.flex;  // a choice of method, not a launch shape
       P.tune = t;
       return MFG_OK;
@@ -149,20 +161,40 @@ int autotune(Plan& P, int effort, bool allow_pers) {
   const long long work = P.g.n;
   const int reps = work >= (1LL << 22) ? 5 : (work >= (1LL << 18) ? 10 : 40);
   const int trials = 3;
+  // A parameter is a list of candidate settings, each setting one or more
+  // fields (joint choices where fields interact, e.g. column blocks x waves).
+  using Setting = std::vector<std::pair<int Tune::*, int>>;
   struct Param {
     int unit;
-    int Tune::*field;
-    std::vector<int> values;
+    std::vector<Setting> values;
+  };
+  auto single = [](int Tune::*f, std::initializer_list<int> vs) {
+    std::vector<Setting> out;
+    for (int v : vs) out.push_back(Setting{{f, v}});
+    return out;
+  };
+  auto joint = [](int Tune::*fa, int Tune::*fb, std::initializer_list<std::pair<int, int>> vs) {
+    std::vector<Setting> out;
+    for (auto v : vs) out.push_back(Setting{{fa, v.first}, {fb, v.second}});
+    return out;
   };
   std::vector<Param> params;
-  if (P.precision == MFG_FP64) params.push_back({U_PRECOND, &Tune::f64_cb, {1, 2}});
-  else params.push_back({U_PRECOND, &Tune::lp_cb, {1, 2}});
-  if (P.ntp > 0 && allow_pers) params.push_back({U_PRECOND, &Tune::tgemm_pers, {0, 1}});
-  params.push_back({U_PRECOND, &Tune::fft_reg, {1, 0}});
-  params.push_back({U_PRECOND, &Tune::rows_elems, {256, 512, 1024, 2048, 4096}});
-  if (P.g.has0) params.push_back({U_PRECOND, &Tune::cols_lines, {1, 2, 4, 8, 16}});
-  params.push_back({U_AAT, &Tune::aat_tc, {0, 4, 8, 16, 32}});
-  if (!allow_pers) P.tune.tgemm_pers = 0;
+  if (P.precision == MFG_FP64) {
+    params.push_back({U_PRECOND, single(&Tune::f64_cb, {1, 2})});
+  } else if (allow_pers) {
+    params.push_back({U_PRECOND, joint(&Tune::lp_cb, &Tune::lp_waves,
+                                       {{2, 4}, {1, 4}, {2, 8}, {1, 8}})});
+    params.push_back({U_PRECOND, joint(&Tune::lp_cb_i, &Tune::lp_waves_i,
+                                       {{2, 4}, {1, 4}, {2, 8}, {1, 8}})});
+  } else {  // batched GEMMs: 4-wave blocks, one column-block count for both directions
+    params.push_back({U_PRECOND, joint(&Tune::lp_cb, &Tune::lp_cb_i, {{2, 2}, {1, 1}})});
+  }
+  if (P.ntp > 0 && allow_pers) params.push_back({U_PRECOND, single(&Tune::tgemm_pers, {0, 1})});
+  params.push_back({U_PRECOND, single(&Tune::fft_reg, {1, 0})});
+  params.push_back({U_PRECOND, single(&Tune::rows_elems, {256, 512, 1024, 2048, 4096})});
+  if (P.g.has0) params.push_back({U_PRECOND, single(&Tune::cols_lines, {1, 2, 4, 8, 16})});
+  params.push_back({U_AAT, single(&Tune::aat_tc, {0, 4, 8, 16, 32})});
+  if (!allow_pers) batch_shape(P.tune);
   int rc = MFG_OK;
   float cur[2] = {0.0f, 0.0f};
   launch_precond(P, P.r, P.z, false, nullptr, P.stream);  // a z for the A unit
@@ -170,25 +202,30 @@ int autotune(Plan& P, int effort, bool allow_pers) {
   const int passes = effort >= 2 ? 2 : 1;
   for (int pass = 0; pass < passes && !rc; ++pass) {
     for (const Param& prm : params) {
-      const int keep = P.tune.*(prm.field);
-      int best_v = keep;
-      for (int v : prm.values) {
-        if (v == keep) continue;
-        P.tune.*(prm.field) = v;
+      const Tune keep = P.tune;
+      Tune best = keep;
+      for (const Setting& st : prm.values) {
+        Tune t = keep;
+        for (const auto& fv : st) t.*(fv.first) = fv.second;
+        bool same = true;
+        for (const auto& fv : st) same = same && (keep.*(fv.first) == fv.second);
+        if (same) continue;
+        P.tune = t;
         float ms;
         if ((rc = time_unit(P, prm.unit, a, b, reps, trials, &ms))) break;
-        if (ms < 0.97f * cur[prm.unit]) {  // switch only on a clear gain
+        if (ms < 0.985f * cur[prm.unit]) {  // switch only on a clear gain
           cur[prm.unit] = ms;
-          best_v = v;
+          best = t;
         }
       }
-      P.tune.*(prm.field) = best_v;
+      P.tune = best;
       if (rc) break;
     }
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (rc) return rc;
+  if (!allow_pers) batch_shape(P.tune);  // both GEMM directions share the tuned lp_cb
   store(P, P.tune);
   return MFG_OK;
 }
