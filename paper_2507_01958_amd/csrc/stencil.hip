@@ -147,9 +147,12 @@ __global__ __launch_bounds__(kThreads) void k_apply_CT(Geom g, const double* __r
 // by the block that owns the node; p_old and p_new are different buffers, so
 // halo reads never see a value updated by a neighbouring block.
 constexpr int kTJ = 64;
-template <bool HAS0>
+// BIG: 32-row tiles for 512-thread blocks (smaller halo share, barriers
+// amortised over twice the work).
+template <bool HAS0, bool BIG = false>
 struct Tile {
-  static constexpr int TI = HAS0 ? 16 : 1;   // tile rows (axis 0)
+  static constexpr int NT = BIG ? 512 : 256;  // threads per block
+  static constexpr int TI = HAS0 ? (BIG ? 32 : 16) : 1;   // tile rows (axis 0)
   static constexpr int HI = HAS0 ? 2 : 0;    // halo rows of the u slots
   static constexpr int GH = HAS0 ? 1 : 0;    // halo rows of g
   static constexpr int SI = TI + 2 * HI;
@@ -158,10 +161,10 @@ struct Tile {
   static constexpr int GJ = kTJ + 2;
 };
 
-template <bool HAS0, bool FUSE>
+template <bool HAS0, bool FUSE, bool BIG = false>
 __device__ void aat_body(const AatArgs& a, int bid, int nb) {
   if (a.done && *a.done != 0.0) return;
-  using C = Tile<HAS0>;
+  using C = Tile<HAS0, BIG>;
   const Geom g = a.g;
   const double* __restrict__ src = a.src;
   const double* __restrict__ pold = a.pold;
@@ -187,12 +190,12 @@ __device__ void aat_body(const AatArgs& a, int bid, int nb) {
   // (combine, publish p_new, store to LDS), so the loads of slice t+2 are in
   // flight while slice t is being computed.
   constexpr int NS = C::SI * C::SJ;
-  constexpr int NPER = (NS + kThreads - 1) / kThreads;
+  constexpr int NPER = (NS + C::NT - 1) / C::NT;
   double rz[NPER], rp[NPER];
   auto issue = [&](int t) {
 #pragma unroll
     for (int e = 0; e < NPER; ++e) {
-      const int idx = threadIdx.x + kThreads * e;
+      const int idx = threadIdx.x + C::NT * e;
       rz[e] = 0.0;
       rp[e] = 0.0;
       if (idx < NS && t >= 0 && t < g.nt) {
@@ -208,7 +211,7 @@ __device__ void aat_body(const AatArgs& a, int bid, int nb) {
   auto commit = [&](int t, double* dst) {
 #pragma unroll
     for (int e = 0; e < NPER; ++e) {
-      const int idx = threadIdx.x + kThreads * e;
+      const int idx = threadIdx.x + C::NT * e;
       if (idx < NS) {
         const double v = FUSE ? rz[e] + beta * rp[e] : rz[e];
         if (FUSE && t >= t_lo && t < t_hi) {
@@ -385,9 +388,9 @@ __global__ __launch_bounds__(kThreads) void k_rhs_batch(const RhsArgs* A, const 
   rhs_body<true>(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
 }
 
-template <bool HAS0, bool FUSE>
-__global__ __launch_bounds__(kThreads) void k_AAt_tile(AatArgs a) {
-  aat_body<HAS0, FUSE>(a, blockIdx.x, gridDim.x);
+template <bool HAS0, bool FUSE, bool BIG>
+__global__ __launch_bounds__((Tile<HAS0, BIG>::NT)) void k_AAt_tile(AatArgs a) {
+  aat_body<HAS0, FUSE, BIG>(a, blockIdx.x, gridDim.x);
 }
 
 template <bool HAS0>
@@ -417,26 +420,40 @@ int aat_chunk(const Geom& g, int ntile, int max_blocks, int want) {
   return (int)tc;
 }
 
-template <bool HAS0>
+template <bool HAS0, bool BIG = false>
 int aat_shape(const Plan& P, int* tc_out) {
   const Geom& g = P.g;
-  const int ntile = ((g.n0 + Tile<HAS0>::TI - 1) / Tile<HAS0>::TI) * ((g.n1 + kTJ - 1) / kTJ);
+  constexpr int TI = Tile<HAS0, BIG>::TI;
+  const int ntile = ((g.n0 + TI - 1) / TI) * ((g.n1 + kTJ - 1) / kTJ);
   const int tc = aat_chunk(g, ntile, P.red.max_blocks, P.tune.aat_tc);
   *tc_out = tc;
   return ntile * ((g.nt + tc - 1) / tc);
 }
 
-template <bool HAS0, bool FUSE>
-void aat_launch(const Plan& P, const double* src, const double* pold, double* pnew, double* q,
-                bool first, bool reduce, hipStream_t s) {
+template <bool HAS0, bool FUSE, bool BIG>
+void aat_launch_t(const Plan& P, const double* src, const double* pold, double* pnew, double* q,
+                  bool first, bool reduce, hipStream_t s) {
   int tc;
-  const int grid = aat_shape<HAS0>(P, &tc);
+  const int grid = aat_shape<HAS0, BIG>(P, &tc);
   const AatArgs a{P.g, src, pold, pnew, q, P.red, tc, first ? 1 : 0, reduce ? 1 : 0, P.pcg_done};
   {
     ProfScope ps(P, FUSE ? "aat_fused" : "aat", s);
-    hipLaunchKernelGGL((k_AAt_tile<HAS0, FUSE>), dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((k_AAt_tile<HAS0, FUSE, BIG>), dim3(grid), dim3(Tile<HAS0, BIG>::NT), 0, s,
+                       a);
   }
   if (reduce) launch_finish(P, T_PQ, grid, OP_PQ, s);
+}
+
+template <bool HAS0, bool FUSE>
+void aat_launch(const Plan& P, const double* src, const double* pold, double* pnew, double* q,
+                bool first, bool reduce, hipStream_t s) {
+  if constexpr (HAS0) {
+    if (P.tune.aat_big) {
+      aat_launch_t<HAS0, FUSE, true>(P, src, pold, pnew, q, first, reduce, s);
+      return;
+    }
+  }
+  aat_launch_t<HAS0, FUSE, false>(P, src, pold, pnew, q, first, reduce, s);
 }
 
 }  // namespace

@@ -54,7 +54,7 @@ Key key_of(const Plan& P) {
 }
 
 // One cache line: "d n0 n1 nt bc precision l arch f64_cb lp_cb rows_elems cols_lines pers
-// fft_reg aat_tc lp_waves lp_cb_i lp_waves_i".
+// fft_reg aat_tc lp_waves lp_cb_i lp_waves_i aat_big".
 void load_file_locked() {
   if (g_file_loaded) return;
   g_file_loaded = true;
@@ -65,10 +65,10 @@ void load_file_locked() {
   char arch[64];
   int d, n0, n1, nt, bc, prec, l;
   Tune t;
-  while (std::fscanf(f, "%d %d %d %d %d %d %d %63s %d %d %d %d %d %d %d %d %d %d", &d, &n0, &n1,
-                     &nt, &bc, &prec, &l, arch, &t.f64_cb, &t.lp_cb, &t.rows_elems,
+  while (std::fscanf(f, "%d %d %d %d %d %d %d %63s %d %d %d %d %d %d %d %d %d %d %d", &d, &n0,
+                     &n1, &nt, &bc, &prec, &l, arch, &t.f64_cb, &t.lp_cb, &t.rows_elems,
                      &t.cols_lines, &t.tgemm_pers, &t.fft_reg, &t.aat_tc, &t.lp_waves,
-                     &t.lp_cb_i, &t.lp_waves_i) == 18)
+                     &t.lp_cb_i, &t.lp_waves_i, &t.aat_big) == 19)
     g_cache[Key{d, n0, n1, nt, bc, prec, l, arch}] = t;
   std::fclose(f);
 }
@@ -82,11 +82,11 @@ void store(const Plan& P, const Tune& t) {
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%d %d %d %d %d %d %d %s %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k),
-               std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k),
-               std::get<6>(k), std::get<7>(k).c_str(), t.f64_cb, t.lp_cb, t.rows_elems,
-               t.cols_lines, t.tgemm_pers, t.fft_reg, t.aat_tc, t.lp_waves, t.lp_cb_i,
-               t.lp_waves_i);
+  std::fprintf(f, "%d %d %d %d %d %d %d %s %d %d %d %d %d %d %d %d %d %d %d\n",
+               std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
+               std::get<5>(k), std::get<6>(k), std::get<7>(k).c_str(), t.f64_cb, t.lp_cb,
+               t.rows_elems, t.cols_lines, t.tgemm_pers, t.fft_reg, t.aat_tc, t.lp_waves,
+               t.lp_cb_i, t.lp_waves_i, t.aat_big);
   std::fclose(f);
 }
 
@@ -122,9 +122,11 @@ int time_unit(Plan& P, int unit, hipEvent_t a, hipEvent_t b, int reps, int trial
 }  // namespace
 
 // Launch shapes the batched kernels support: the blocked time GEMM with
-// 4-wave blocks and one column-block count for both directions.
+// 4-wave blocks and one column-block count for both directions, 256-thread
+// A-kernel blocks.
 void batch_shape(Tune& t) {
   t.tgemm_pers = 0;
+  t.aat_big = 0;
   t.lp_waves = t.lp_waves_i = 4;
   t.lp_cb_i = t.lp_cb;
 }
@@ -193,7 +195,13 @@ int autotune(Plan& P, int effort, bool allow_pers) {
   params.push_back({U_PRECOND, single(&Tune::fft_reg, {1, 0})});
   params.push_back({U_PRECOND, single(&Tune::rows_elems, {256, 512, 1024, 2048, 4096})});
   if (P.g.has0) params.push_back({U_PRECOND, single(&Tune::cols_lines, {1, 2, 4, 8, 16})});
-  params.push_back({U_AAT, single(&Tune::aat_tc, {0, 4, 8, 16, 32})});
+  if (P.g.has0 && allow_pers) {
+    params.push_back({U_AAT, joint(&Tune::aat_big, &Tune::aat_tc,
+                                   {{0, 0}, {0, 8}, {0, 16}, {0, 32}, {1, 0}, {1, 8}, {1, 16},
+                                    {1, 32}})});
+  } else {
+    params.push_back({U_AAT, single(&Tune::aat_tc, {0, 4, 8, 16, 32})});
+  }
   if (!allow_pers) batch_shape(P.tune);
   int rc = MFG_OK;
   float cur[2] = {0.0f, 0.0f};

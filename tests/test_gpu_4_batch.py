@@ -135,7 +135,7 @@ def test_autotune_keeps_results_and_caches(tmp_path, monkeypatch):
         P0.close()
     lines = cache.read_text().split("\n")
     rows = [ln.split() for ln in lines if ln.strip()]
-    assert len(rows) == 2 and all(len(x) == 18 for x in rows)
+    assert len(rows) == 2 and all(len(x) == 19 for x in rows)
     assert rows[0][:7] == ["2", "48", "36", "24", "1", "0", "1"] and rows[0][7].startswith("gfx")
     assert rows[1][5] == "1"
 
