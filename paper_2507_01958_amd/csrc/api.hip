@@ -170,7 +170,7 @@ static void read_tune_env(Tune& t) {
       else if (k == "tgemm_pers" && (v == 0 || v == 1)) t.tgemm_pers = v;
       else if (k == "fft_reg" && (v == 0 || v == 1)) t.fft_reg = v;
       else if (k == "aat_tc" && v >= 0 && v <= 64) t.aat_tc = v;
-      else if (k == "aat_big" && (v == 0 || v == 1)) t.aat_big = v;
+      else if (k == "aat_big" && v >= 0 && v <= 2) t.aat_big = v;
       else if (k == "flex" && (v >= -1 && v <= 1)) t.flex = v;
     }
     pos = end + 1;

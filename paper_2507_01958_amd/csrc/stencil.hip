@@ -147,12 +147,12 @@ __global__ __launch_bounds__(kThreads) void k_apply_CT(Geom g, const double* __r
 // by the block that owns the node; p_old and p_new are different buffers, so
 // halo reads never see a value updated by a neighbouring block.
 constexpr int kTJ = 64;
-// BIG: 32-row tiles for 512-thread blocks (smaller halo share, barriers
-// amortised over twice the work).
-template <bool HAS0, bool BIG = false>
+// BIG = 0, 1, 2: 16-, 32- or 64-row tiles for 256-, 512- or 1024-thread blocks
+// (larger tiles: smaller halo share, barriers amortised over more work).
+template <bool HAS0, int BIG = 0>
 struct Tile {
-  static constexpr int NT = BIG ? 512 : 256;  // threads per block
-  static constexpr int TI = HAS0 ? (BIG ? 32 : 16) : 1;   // tile rows (axis 0)
+  static constexpr int NT = 256 << BIG;  // threads per block
+  static constexpr int TI = HAS0 ? (16 << BIG) : 1;   // tile rows (axis 0)
   static constexpr int HI = HAS0 ? 2 : 0;    // halo rows of the u slots
   static constexpr int GH = HAS0 ? 1 : 0;    // halo rows of g
   static constexpr int SI = TI + 2 * HI;
@@ -161,7 +161,7 @@ struct Tile {
   static constexpr int GJ = kTJ + 2;
 };
 
-template <bool HAS0, bool FUSE, bool BIG = false>
+template <bool HAS0, bool FUSE, int BIG = 0>
 __device__ void aat_body(const AatArgs& a, int bid, int nb) {
   if (a.done && *a.done != 0.0) return;
   using C = Tile<HAS0, BIG>;
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(kThreads) void k_rhs_batch(const RhsArgs* A, const 
   rhs_body<true>(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
 }
 
-template <bool HAS0, bool FUSE, bool BIG>
+template <bool HAS0, bool FUSE, int BIG>
 __global__ __launch_bounds__((Tile<HAS0, BIG>::NT)) void k_AAt_tile(AatArgs a) {
   aat_body<HAS0, FUSE, BIG>(a, blockIdx.x, gridDim.x);
 }
@@ -420,7 +420,7 @@ int aat_chunk(const Geom& g, int ntile, int max_blocks, int want) {
   return (int)tc;
 }
 
-template <bool HAS0, bool BIG = false>
+template <bool HAS0, int BIG = 0>
 int aat_shape(const Plan& P, int* tc_out) {
   const Geom& g = P.g;
   constexpr int TI = Tile<HAS0, BIG>::TI;
@@ -430,7 +430,7 @@ int aat_shape(const Plan& P, int* tc_out) {
   return ntile * ((g.nt + tc - 1) / tc);
 }
 
-template <bool HAS0, bool FUSE, bool BIG>
+template <bool HAS0, bool FUSE, int BIG>
 void aat_launch_t(const Plan& P, const double* src, const double* pold, double* pnew, double* q,
                   bool first, bool reduce, hipStream_t s) {
   int tc;
@@ -448,12 +448,16 @@ template <bool HAS0, bool FUSE>
 void aat_launch(const Plan& P, const double* src, const double* pold, double* pnew, double* q,
                 bool first, bool reduce, hipStream_t s) {
   if constexpr (HAS0) {
-    if (P.tune.aat_big) {
-      aat_launch_t<HAS0, FUSE, true>(P, src, pold, pnew, q, first, reduce, s);
+    if (P.tune.aat_big == 1) {
+      aat_launch_t<HAS0, FUSE, 1>(P, src, pold, pnew, q, first, reduce, s);
+      return;
+    }
+    if (P.tune.aat_big == 2) {
+      aat_launch_t<HAS0, FUSE, 2>(P, src, pold, pnew, q, first, reduce, s);
       return;
     }
   }
-  aat_launch_t<HAS0, FUSE, false>(P, src, pold, pnew, q, first, reduce, s);
+  aat_launch_t<HAS0, FUSE, 0>(P, src, pold, pnew, q, first, reduce, s);
 }
 
 }  // namespace

@@ -198,7 +198,7 @@ int autotune(Plan& P, int effort, bool allow_pers) {
   if (P.g.has0 && allow_pers) {
     params.push_back({U_AAT, joint(&Tune::aat_big, &Tune::aat_tc,
                                    {{0, 0}, {0, 8}, {0, 16}, {0, 32}, {1, 0}, {1, 8}, {1, 16},
-                                    {1, 32}})});
+                                    {1, 32}, {2, 0}, {2, 4}, {2, 8}, {2, 16}})});
   } else {
     params.push_back({U_AAT, single(&Tune::aat_tc, {0, 4, 8, 16, 32})});
   }

@@ -155,11 +155,12 @@ def test_pcg_true_residual(case):
     assert np.abs(got - x_ref).max() <= 1e-9 * np.abs(x_ref).max()
 
 
-# The A kernel's 32-row tiles (512-thread blocks, MFG_TUNE=aat_big=1): same
+# The A kernel's 32- and 64-row tiles (512- and 1024-thread blocks,
+# MFG_TUNE=aat_big=1, 2): same
 # per-node arithmetic, so the product meets the same bound, and PCG (which
 # runs the fused form) takes the same iterations to the same solution up to the
-# summation order of p.q. Ragged cases: 72 rows (2 tiles + 8), 9 rows (one
-# partial tile), several time chunks.
+# summation order of p.q. Ragged cases: 72 rows (2 or 1 tiles + 8), 9 rows
+# (one partial tile), several time chunks.
 BIG_CASES = CASES[3:] + [(2, 72, 96, 5, "neumann", 0.05), (2, 9, 64, 3, "periodic", 0.2)]
 
 
@@ -173,7 +174,7 @@ def test_AAt_big_tiles(case, tc, monkeypatch):
     u = np.random.default_rng(3).standard_normal(g.n)
     b = np.random.default_rng(4).standard_normal(g.n)
     res = {}
-    for big in [0, 1]:
+    for big in [0, 1, 2]:
         monkeypatch.setenv("MFG_TUNE", f"aat_big={big},aat_tc={tc}")
         with plan_of(inst) as P:
             q = empty(g.n)
@@ -182,10 +183,11 @@ def test_AAt_big_tiles(case, tc, monkeypatch):
             its, rel, _ = mfg.mfg_pcg(P, dev(b), x, 1e-12, 200)
             res[big] = (host(q), host(x), its)
     scale = ops.abs_AAt_bound(g, S, u)
-    assert np.all(np.abs(res[1][0] - ops.apply_AAt(g, S, u)) <= 1e-12 * scale + 1e-300)
-    assert np.array_equal(res[1][0], res[0][0])
-    assert res[1][2] == res[0][2]
-    assert np.abs(res[1][1] - res[0][1]).max() <= 1e-11 * np.abs(res[0][1]).max()
+    for big in [1, 2]:
+        assert np.all(np.abs(res[big][0] - ops.apply_AAt(g, S, u)) <= 1e-12 * scale + 1e-300)
+        assert np.array_equal(res[big][0], res[0][0])
+        assert res[big][2] == res[0][2]
+        assert np.abs(res[big][1] - res[0][1]).max() <= 1e-11 * np.abs(res[0][1]).max()
 
 
 # Mixed precision: the preconditioner is approximate; its normwise error
