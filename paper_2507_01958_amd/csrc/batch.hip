@@ -78,8 +78,7 @@ struct Batch {
   std::vector<ColsGroup> cols;
   Phase<RhsArgs> rhs;
   Phase<BackprojArgs> bp;
-  FinishArgs *f_bb = nullptr, *f_pq = nullptr, *f_rr = nullptr, *f_rz0 = nullptr,
-             *f_rz = nullptr, *f_dm = nullptr;
+  FinishArgs *f_bb = nullptr, *f_rr = nullptr, *f_dm = nullptr;
   std::vector<const double*> bound;  // state vectors the rhs/bp phases were built for
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -153,7 +152,7 @@ int build_pcg_phases(Batch& B) {
   std::vector<UpdArgs> uo, ue;
   std::vector<AatArgs> af, ao, ae;
   std::vector<int> b_init, b_upd, b_aat;
-  std::vector<FinishArgs> fbb, fpq, frr, frz0, frz;
+  std::vector<FinishArgs> fbb, frr;
   // spatial launches grouped by size class
   std::vector<int> rcls(n), ccls(n);
   std::vector<RowsArgs<float>> rf(n), ri(n);
@@ -180,22 +179,16 @@ int build_pcg_phases(Batch& B) {
     rcls[i] = batch_rows_args(P, tmp, 0, done, &rf[i], &b_rows[i], &rshm[i]);
     batch_rows_args(P, tmp, 1, done, &ri[i], &b_rows[i], &rshm[i]);
     ccls[i] = batch_cols_args(P, tmp, done, &cl[i], &b_cols[i], &cshm[i]);
+    uo.back().npq = ue.back().npq = g;
     FinishArgs f = finish_args(P, T_BB, pcg_init_grid(P), OP_BB);
     fbb.push_back(f);
-    f = finish_args(P, T_PQ, g, OP_PQ);
-    f.done = done;
-    fpq.push_back(f);
     f = finish_args(P, T_RR, update_grid(P), OP_RR);
     f.done = done;
     frr.push_back(f);
   }
   int rc;
-  if ((rc = upload_phase(B, init, b_init, B.init)) || (rc = upload_phase(B, uo, b_upd, B.upd_odd)) ||
-      (rc = upload_phase(B, ue, b_upd, B.upd_even)) ||
-      (rc = upload_phase(B, af, b_aat, B.aat_first)) ||
-      (rc = upload_phase(B, ao, b_aat, B.aat_odd)) || (rc = upload_phase(B, ae, b_aat, B.aat_even)) ||
-      (rc = upload_finish(B, fbb, &B.f_bb)) ||
-      (rc = upload_finish(B, fpq, &B.f_pq)) || (rc = upload_finish(B, frr, &B.f_rr)))
+  if ((rc = upload_phase(B, init, b_init, B.init)) || (rc = upload_finish(B, fbb, &B.f_bb)) ||
+      (rc = upload_finish(B, frr, &B.f_rr)))
     return rc;
   {
     std::vector<int> classes(rcls);
@@ -270,15 +263,15 @@ int build_pcg_phases(Batch& B) {
         (rc = upload_phase(B, i1, blocks, G.inv_iter)))
       return rc;
   }
+  // the update and the A kernel sum the inverse GEMM's r.z partials themselves
   for (int i = 0; i < n; ++i) {
-    Plan& P = plan_of(B, i);
-    FinishArgs f = finish_args(P, T_RZ, gemm_grid[i], OP_RZ_INIT);
-    f.done = done_of(B, i);
-    frz0.push_back(f);
-    f.op = pcg_flexible(P) ? OP_RZ_FLEX : OP_RZ_STD;
-    frz.push_back(f);
+    uo[i].nrz = ue[i].nrz = gemm_grid[i];
+    af[i].nrz = ao[i].nrz = ae[i].nrz = gemm_grid[i];
   }
-  if ((rc = upload_finish(B, frz0, &B.f_rz0)) || (rc = upload_finish(B, frz, &B.f_rz))) return rc;
+  if ((rc = upload_phase(B, uo, b_upd, B.upd_odd)) || (rc = upload_phase(B, ue, b_upd, B.upd_even)) ||
+      (rc = upload_phase(B, af, b_aat, B.aat_first)) ||
+      (rc = upload_phase(B, ao, b_aat, B.aat_odd)) || (rc = upload_phase(B, ae, b_aat, B.aat_even)))
+    return rc;
   return MFG_OK;
 }
 
@@ -323,14 +316,12 @@ void precond_phase(Batch& B, bool init, hipStream_t s) {
     launch_gemm_batch<float, double>(B.mode, G.ntp, G.cb, ph.args, ph.off, ph.ninst, ph.total,
                                      s);
   }
-  launch_finish_batch(init ? B.f_rz0 : B.f_rz, B.count, s);
 }
 
 // PCG iteration k >= 1 for every instance not yet converged.
 void pcg_iteration(Batch& B, int k, hipStream_t s) {
   const auto& aat = (k == 1) ? B.aat_first : ((k & 1) ? B.aat_odd : B.aat_even);
   launch_aat_batch(true, aat.args, aat.off, B.count, aat.total, s);
-  launch_finish_batch(B.f_pq, B.count, s);
   const auto& upd = (k & 1) ? B.upd_odd : B.upd_even;
   launch_update_batch(upd.args, upd.off, B.count, upd.total, s);
   launch_finish_batch(B.f_rr, B.count, s);

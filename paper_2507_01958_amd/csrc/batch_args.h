@@ -28,6 +28,8 @@ struct InitArgs {
   RedBuf rb;
 };
 
+// npq, nrz: partial counts of the p.q site (the A kernel's grid) and of the
+// r.z site (the inverse time GEMM's grid), summed by each block.
 struct UpdArgs {
   long long n;
   double* x;
@@ -36,6 +38,7 @@ struct UpdArgs {
   const double* q;
   RedBuf rb;
   const double* done;
+  int npq, nrz;
 };
 
 struct FinishArgs {
@@ -44,6 +47,8 @@ struct FinishArgs {
   const double* done;
 };
 
+// nrz > 0 (PCG direction form): partial count of the r.z site, from which each
+// block forms beta (flex: the flexible formula).
 struct AatArgs {
   Geom g;
   const double* src;   // u, or z when forming p = z + beta p_old
@@ -53,6 +58,7 @@ struct AatArgs {
   RedBuf rb;
   int tc, first, reduce;
   const double* done;
+  int nrz, flex;
 };
 
 // Step sizes either by value or from device memory (pointer non-null).

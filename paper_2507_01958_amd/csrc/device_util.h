@@ -71,6 +71,39 @@ __device__ __forceinline__ void reduce_store(double (&v)[NV], const RedBuf& rb, 
 
 __device__ __forceinline__ bool finite_d(double x) { return __builtin_isfinite(x); }
 
+// The sums of slots 0..NV-1 of a site's first n partials, formed inside the
+// kernel that consumes them (in place of a one-block finisher launch between
+// producer and consumer). Wave 0 adds entries lane, lane + 64, ... in order
+// and combines the 64 lane sums by a butterfly, so the result depends only on
+// n: every block, whatever its size, gets the same bits. Broadcast to the
+// block through LDS; every thread of the block must call it.
+template <int NV>
+__device__ __forceinline__ void fold_partials(const RedBuf& rb, int site, int n,
+                                              double (&out)[NV]) {
+  __shared__ double sh[NV];
+  if (threadIdx.x < 64) {
+    const double* part = rb.partials + (size_t)site * kSlotsPerSite * rb.max_blocks;
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+#pragma unroll 4
+    for (int b = threadIdx.x; b < n; b += 64) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) v[k] += part[(size_t)k * rb.max_blocks + b];
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) sh[k] = v[k];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) out[k] = sh[k];
+  __syncthreads();
+}
+
 // XCD-aware block order: blocks b and b+8 run on the same XCD, so map them to
 // neighbouring logical tiles (shared cache lines and halos stay in one L2).
 __device__ __forceinline__ int xcd_remap(int b, int nb) {

@@ -54,6 +54,9 @@ struct Plan {
   // the solve has converged (set only while mfg_pcg / a CP step iterates).
   const double* pcg_done = nullptr;
   int last_pcg_its = 0;  // iterations of the previous solve (launch chunking)
+  // Grids of the last launches that stored p.q and r.z partials: the update
+  // and the A kernel sum that many partials themselves.
+  mutable int pq_blocks = 0, rz_blocks = 0;
   Geom g{};
   int precision = MFG_FP64;
   int l = 1;

@@ -183,7 +183,27 @@ __device__ void aat_body(const AatArgs& a, int bid, int nb) {
   (void)tiles0;
   const int t_lo = chunk * tc;
   const int t_hi = (t_lo + tc < g.nt) ? t_lo + tc : g.nt;
-  const double beta = (FUSE && !first) ? rb.scal[S_BETA] : 0.0;
+  // PCG direction form: beta from the r.z (z.q) partials of the last
+  // preconditioner application; a breakdown there (r.z not positive or not
+  // finite) ends the solve.
+  double beta = 0.0;
+  if (FUSE && a.nrz > 0) {
+    double f[2];
+    fold_partials<2>(rb, T_RZ, a.nrz, f);
+    const int bad = (!finite_d(f[0]) || !finite_d(f[1])) ? 2 : (!(f[0] > 0.0) ? 1 : 0);
+    if (bad) {
+      if (bid == 0 && threadIdx.x == 0) {
+        rb.scal[S_BAD] = (double)bad;
+        rb.scal[S_DONE] = 1.0;
+      }
+      return;
+    }
+    if (!first) {
+      const double rho = rb.scal[S_RHO];
+      beta = a.flex ? -rb.scal[S_ALPHA] * f[1] / rho : f[0] / rho;
+    }
+    if (bid == 0 && threadIdx.x == 0) rb.scal[S_BETA] = beta;
+  }
   const double c1 = 2.0 * g.nu * g.idt + 2.0, c2 = g.nu * g.idt, nu2 = g.nu * g.nu;
 
   // Slot loads are split into issue (global loads into registers) and commit
@@ -435,13 +455,17 @@ void aat_launch_t(const Plan& P, const double* src, const double* pold, double* 
                   bool first, bool reduce, hipStream_t s) {
   int tc;
   const int grid = aat_shape<HAS0, BIG>(P, &tc);
-  const AatArgs a{P.g, src, pold, pnew, q, P.red, tc, first ? 1 : 0, reduce ? 1 : 0, P.pcg_done};
+  // inside a PCG solve, the direction form takes beta from the r.z partials
+  const int nrz = (FUSE && P.pcg_done) ? P.rz_blocks : 0;
+  const AatArgs a{P.g,    src, pold, pnew, q, P.red, tc, first ? 1 : 0, reduce ? 1 : 0,
+                  P.pcg_done, nrz, pcg_flexible(P) ? 1 : 0};
   {
     ProfScope ps(P, FUSE ? "aat_fused" : "aat", s);
     hipLaunchKernelGGL((k_AAt_tile<HAS0, FUSE, BIG>), dim3(grid), dim3(Tile<HAS0, BIG>::NT), 0, s,
                        a);
   }
-  if (reduce) launch_finish(P, T_PQ, grid, OP_PQ, s);
+  // the p.q partials are summed by the update that consumes them
+  if (reduce) P.pq_blocks = grid;
 }
 
 template <bool HAS0, bool FUSE>
@@ -530,7 +554,9 @@ AatArgs aat_args(const Plan& P, const double* z, const double* pold, double* pne
                  bool first, const double* done, int* grid) {
   int tc;
   *grid = P.g.has0 ? aat_shape<true>(P, &tc) : aat_shape<false>(P, &tc);
-  return AatArgs{P.g, z, pold, pnew, q, P.red, tc, first ? 1 : 0, 1, done};
+  // nrz is filled in once the inverse time GEMM's grid is known
+  return AatArgs{P.g, z, pold, pnew, q, P.red, tc, first ? 1 : 0, 1, done, 0,
+                 pcg_flexible(P) ? 1 : 0};
 }
 
 void launch_aat_batch(bool has0, const AatArgs* A, const int* off, int ninst, int total,

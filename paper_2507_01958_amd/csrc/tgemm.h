@@ -2,7 +2,7 @@
 //   Y[k][s] = sum_t V[k][t] X[t][s],  k, t < N_t,  s < M (all spatial nodes).
 // V (DCT-VIII or DST-I) is symmetric and orthogonal, so the same kernel applies
 // V and V^{-1} = V. Optional epilogue: per-block partials of r.Y and q.Y for
-// the PCG scalars (reduced by the finisher kernel).
+// the PCG scalars (summed by the kernels that consume them).
 #pragma once
 
 #include "device_util.h"
@@ -11,10 +11,6 @@
 namespace mfg {
 
 enum DotMode { DOT_NONE = 0, DOT_INIT = 1, DOT_STD = 2, DOT_FLEX = 3 };
-
-inline int finish_op(int dotmode) {
-  return dotmode == DOT_INIT ? OP_RZ_INIT : (dotmode == DOT_STD ? OP_RZ_STD : OP_RZ_FLEX);
-}
 
 // Precision of the matrix-core products.
 enum GemmMode { GM_F64 = 0, GM_F32 = 1, GM_F16 = 2, GM_BF16 = 3 };

@@ -692,7 +692,8 @@ void tgemm(const Plan& P, int mode, const TX* X, TY* Y, int dotmode, const doubl
     ProfScope ps(P, name, s);
     grid = tgemm_launch(P, mode, X, Y, dotmode, r, q, s);
   }
-  if (dotmode != DOT_NONE) launch_finish(P, T_RZ, grid, finish_op(dotmode), s);
+  // the r.z (and z.q) partials are summed by the kernels that consume them
+  if (dotmode != DOT_NONE) P.rz_blocks = grid;
 }
 
 template void tgemm<double, double>(const Plan&, int, const double*, double*, int,

@@ -37,11 +37,24 @@ __device__ void pcg_init_body(const InitArgs& a, int bid, int nb) {
   reduce_store<1>(acc, a.rb, T_BB, bid);
 }
 
-// x += alpha p; r -= alpha q; partial r.r. Skipped once the instance has
-// converged (batched path only: a.done is null otherwise).
+// alpha = r.z / p.q from the partials of both sites (breakdown, p.q not
+// positive or not finite: alpha = 0 and S_BAD, which ends the solve at the next
+// r.r check); x += alpha p; r -= alpha q; partial r.r. Block 0 records p.q,
+// alpha and rho = r.z for the next direction. Skipped once the solve is done.
 __device__ void update_body(const UpdArgs& a, int bid, int nb) {
   if (a.done && *a.done != 0.0) return;
-  const double alpha = a.rb.scal[S_ALPHA];
+  double pq[1], rz[1];
+  fold_partials<1>(a.rb, T_PQ, a.npq, pq);
+  fold_partials<1>(a.rb, T_RZ, a.nrz, rz);
+  const int bad = !finite_d(pq[0]) ? 2 : (!(pq[0] > 0.0) ? 1 : 0);
+  const double alpha = bad ? 0.0 : rz[0] / pq[0];
+  if (bid == 0 && threadIdx.x == 0) {
+    double* S = a.rb.scal;
+    S[S_PQ] = pq[0];
+    S[S_ALPHA] = alpha;
+    S[S_RHO] = rz[0];
+    if (bad) S[S_BAD] = (double)bad;
+  }
   double acc[1] = {0.0};
   for (long long i = (long long)bid * blockDim.x + threadIdx.x; i < a.n;
        i += (long long)nb * blockDim.x) {
@@ -75,40 +88,11 @@ __device__ void finish_body(const FinishArgs& f) {
       S[S_BAD] = finite_d(a) ? 0.0 : 2.0;
       S[S_DONE] = (a == 0.0) ? 1.0 : 0.0;
       break;
-    case OP_PQ:
-      S[S_PQ] = a;
-      if (!finite_d(a)) {
-        S[S_BAD] = 2.0;
-        S[S_ALPHA] = 0.0;
-      } else if (!(a > 0.0)) {
-        S[S_BAD] = 1.0;
-        S[S_ALPHA] = 0.0;
-      } else {
-        S[S_ALPHA] = S[S_RHO] / a;
-      }
-      break;
     case OP_RR:
       S[S_RR] = a;
       S[S_ITS] += 1.0;
       if (!finite_d(a)) S[S_BAD] = 2.0;
       if (a <= S[S_TOL2] * S[S_BB] || S[S_BAD] != 0.0) S[S_DONE] = 1.0;
-      break;
-    case OP_RZ_INIT:
-    case OP_RZ_STD:
-    case OP_RZ_FLEX:
-      if (!finite_d(a) || !finite_d(c)) {
-        S[S_BAD] = 2.0;
-      } else if (!(a > 0.0)) {
-        S[S_BAD] = 1.0;
-      } else if (f.op == OP_RZ_INIT) {
-        S[S_RHO] = a;
-        S[S_BETA] = 0.0;
-      } else {
-        const double rho = S[S_RHO];
-        S[S_BETA] = (f.op == OP_RZ_FLEX) ? -S[S_ALPHA] * c / rho : a / rho;
-        S[S_RHO] = a;
-      }
-      if (S[S_BAD] != 0.0) S[S_DONE] = 1.0;
       break;
     case OP_DM:
       S[S_DM] = a;
@@ -217,7 +201,7 @@ void launch_pcg_init(const Plan& P, const double* b, double* x, double* r, doubl
 }
 
 UpdArgs update_args(const Plan& P, double* x, double* r, const double* p, const double* q) {
-  return UpdArgs{P.g.n, x, r, p, q, P.red, P.pcg_done};
+  return UpdArgs{P.g.n, x, r, p, q, P.red, P.pcg_done, P.pq_blocks, P.rz_blocks};
 }
 
 int update_grid(const Plan& P) { return grid_for(P.g.n); }
