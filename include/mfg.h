@@ -176,6 +176,11 @@ int mfg_cp_init(mfg_plan_t plan, mfg_state_t* st);
  *   ybar <- y' + theta (y' - y);  tau <- theta tau;  sigma <- sigma / theta
  * with each A-solve done by PCG to pcg_rtol (at most pcg_maxit iterations,
  * zero initial guess). The state is updated in place. stats may be NULL.
+ * Between the iterations of one call, xi and ybar are kept only through
+ * z = xi + sigma ybar in plan workspace (the right-hand side needs nothing
+ * else); the last iteration writes them back, so the state after the call is
+ * bitwise that of n_iter single-iteration calls. If the call fails with an
+ * error other than MFG_ERR_NOT_CONVERGED, the state's vectors are unspecified.
  * Returns MFG_ERR_NOT_CONVERGED (after finishing all iterations) if some PCG
  * solve hit pcg_maxit. */
 int mfg_cp_solve(mfg_plan_t plan, mfg_state_t* st, int n_iter, double pcg_rtol,

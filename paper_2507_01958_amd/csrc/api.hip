@@ -321,7 +321,7 @@ static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const d
   if ((rc = dalloc(P, &P.r, n)) || (rc = dalloc(P, &P.z, n)) || (rc = dalloc(P, &P.p, n)) ||
       (rc = dalloc(P, &P.p2, n)) ||
       (rc = dalloc(P, &P.q, n)) || (rc = dalloc(P, &P.tmp, n)) || (rc = dalloc(P, &P.b, n)) ||
-      (rc = dalloc(P, &P.u, n)))
+      (rc = dalloc(P, &P.u, n)) || (rc = dalloc(P, &P.zn, (size_t)n * (1 + g.ncomp))))
     return rc;
   P.red.max_blocks = 32768;
   {
@@ -464,15 +464,21 @@ static int run_pcg(Plan& P, const double* b, double* x, double rtol, int maxit, 
 }
 
 // One Chambolle-Pock iteration (eq. pasosChamPock, Section 5 schedule) on the
-// state; vout (optional) receives the prox input v = y - tau xi'.
+// state; vout (optional) receives the prox input v = y - tau xi'. Inside a
+// multi-step call the right-hand side only needs z = xi + sigma ybar: z_in, the
+// previous step left it in P.zn (st->xi, st->ybar are stale); z_out, store it
+// there for the next step instead of xi' and ybar'. The first step of a call
+// reads the state and the last one writes it back, so the caller sees the
+// same state either way, and 10 n-vectors of traffic per step are saved.
 static int cp_step(Plan& P, mfg_state_t* st, double rtol, int maxit, int* its, double* rel,
-                   double* vout) {
+                   double* vout, bool z_in = false, bool z_out = false) {
   hipStream_t s = P.stream;
-  launch_rhs(P, st->xi, st->ybar, st->sigma, P.m0, P.b, s);
+  launch_rhs(P, st->xi, st->ybar, st->sigma, P.m0, P.b, s, z_in ? P.zn : nullptr);
   int rc = run_pcg(P, P.b, P.u, rtol, maxit, its, rel, nullptr);
   if (rc && rc != MFG_ERR_NOT_CONVERGED) return rc;
   const double theta = 1.0 / std::sqrt(1.0 + 2.0 * P.gamma * st->tau);
-  launch_backproj_prox(P, P.u, st->xi, st->y, st->ybar, st->tau, theta, s, vout);
+  launch_backproj_prox(P, P.u, st->xi, st->y, st->ybar, st->tau, theta, s, vout,
+                       z_out ? P.zn : nullptr, st->sigma);
   HIP_TRY(hipGetLastError());
   st->tau *= theta;
   st->sigma /= theta;
@@ -683,7 +689,8 @@ int mfg_cp_solve(mfg_plan_t plan, mfg_state_t* st, int n_iter, double pcg_rtol, 
   for (int it = 0; it < n_iter; ++it) {
     int its = 0;
     double rel = 0.0;
-    int rc = mfg::cp_step(P, st, pcg_rtol, pcg_maxit, &its, &rel, nullptr);
+    int rc = mfg::cp_step(P, st, pcg_rtol, pcg_maxit, &its, &rel, nullptr, it > 0,
+                          it + 1 < n_iter);
     if (rc == MFG_ERR_NOT_CONVERGED) final_rc = rc;
     else if (rc) return rc;
     if (stats) {

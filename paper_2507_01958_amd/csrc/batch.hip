@@ -77,7 +77,9 @@ struct Batch {
   std::vector<SpatialGroup> rows;
   std::vector<ColsGroup> cols;
   Phase<RhsArgs> rhs;
-  Phase<BackprojArgs> bp;
+  // back-projection of the last step of a call (writes xi', ybar') and of the
+  // other steps (hands z = xi' + sigma' ybar' to the next right-hand side)
+  Phase<BackprojArgs> bp, bp_mid;
   FinishArgs *f_bb = nullptr, *f_rr = nullptr, *f_dm = nullptr;
   std::vector<const double*> bound;  // state vectors the rhs/bp phases were built for
   hipGraph_t graph = nullptr;
@@ -278,21 +280,28 @@ int build_pcg_phases(Batch& B) {
 // Right-hand side and back-projection phases bound to the states' vectors.
 int build_state_phases(Batch& B, mfg_state_t* st) {
   std::vector<RhsArgs> rh;
-  std::vector<BackprojArgs> bp;
+  std::vector<BackprojArgs> bp, bpm;
   std::vector<int> b_rhs, b_bp;
   std::vector<FinishArgs> fdm;
   for (int i = 0; i < B.count; ++i) {
     Plan& P = plan_of(B, i);
     const double* S = B.scal_all + (size_t)i * S_COUNT;
-    rh.push_back(rhs_args(P, st[i].xi, st[i].ybar, 0.0, S + S_SIGMA, P.b));
+    double* Sw = B.scal_all + (size_t)i * S_COUNT;
+    rh.push_back(rhs_args(P, st[i].xi, st[i].ybar, 0.0, S + S_SIGMA, P.b, P.zn, S + S_ZMODE));
     b_rhs.push_back(rhs_grid(P));
-    bp.push_back(backproj_args(P, P.u, st[i].xi, st[i].y, st[i].ybar, 0.0, 0.0, S + S_TAU,
-                               S + S_THETA, nullptr));
+    BackprojArgs a = backproj_args(P, P.u, st[i].xi, st[i].y, st[i].ybar, 0.0, 0.0, S + S_TAU,
+                                   S + S_THETA, nullptr);
+    a.zflag = Sw + S_ZMODE;
+    bp.push_back(a);
+    a.zout = P.zn;
+    a.sigma_dev = S + S_SIGMA;
+    bpm.push_back(a);
     b_bp.push_back(backproj_grid(P));
     fdm.push_back(finish_args(P, T_DM, backproj_grid(P), OP_DM));
   }
   int rc;
   if ((rc = upload_phase(B, rh, b_rhs, B.rhs)) || (rc = upload_phase(B, bp, b_bp, B.bp)) ||
+      (rc = upload_phase(B, bpm, b_bp, B.bp_mid)) ||
       (rc = upload_finish(B, fdm, &B.f_dm)))
     return rc;
   return MFG_OK;
@@ -488,6 +497,9 @@ int batch_cp_solve(Batch& B, mfg_state_t* st, int n_iter, double rtol, int maxit
   (void)hipStreamWaitEvent(s, B.ev_in, 0);
   hipLaunchKernelGGL(k_batch_set, dim3((n + 63) / 64), dim3(64), 0, s, B.scal_all, S_COUNT, n,
                      (int)S_CPIT, 0.0);
+  // the first step of the call reads the states' xi and ybar
+  hipLaunchKernelGGL(k_batch_set, dim3((n + 63) / 64), dim3(64), 0, s, B.scal_all, S_COUNT, n,
+                     (int)S_ZMODE, 0.0);
   int final_rc = MFG_OK;
   for (int it = 0; it < n_iter; ++it) {
     int K = std::min(B.graph_k > 0 ? B.graph_k : 8, maxit);
@@ -533,7 +545,8 @@ int batch_cp_solve(Batch& B, mfg_state_t* st, int n_iter, double rtol, int maxit
       if (pcg_iters) pcg_iters[(size_t)it * n + i] = its;
     }
     if (!B.exec && B.graph_k == 0) B.graph_k = std::min(std::max(maxits + 1, 2), maxit);
-    launch_backproj_batch(B.bp.args, B.bp.off, n, B.bp.total, s);
+    const auto& bp = (it + 1 < n_iter) ? B.bp_mid : B.bp;
+    launch_backproj_batch(bp.args, bp.off, n, bp.total, s);
     launch_finish_batch(B.f_dm, n, s);
   }
   (void)hipEventRecord(B.ev_out, s);

@@ -62,6 +62,9 @@ struct AatArgs {
 };
 
 // Step sizes either by value or from device memory (pointer non-null).
+// zin (optional): z = xi + sigma ybar as written by the previous step's
+// back-projection, read in place of xi and ybar; with zmode_dev set (batched
+// runs) only while *zmode_dev != 0.
 struct RhsArgs {
   Geom g;
   const double* xi;
@@ -70,6 +73,8 @@ struct RhsArgs {
   const double* sigma_dev;
   const double* m0;
   double* b;
+  const double* zin;
+  const double* zmode_dev;
 };
 
 struct BackprojArgs {
@@ -84,6 +89,14 @@ struct BackprojArgs {
   const double* theta_dev;
   RedBuf rb;
   double* vout;
+  // zout (optional): in place of xi' and ybar', store z = xi' + sigma' ybar'
+  // with sigma' = sigma / theta, the input of the next step's right-hand side
+  // (sigma by value or from sigma_dev); zflag (batched runs): set to 1 when z
+  // is stored, 0 when xi' and ybar' are.
+  double* zout;
+  double sigma;
+  const double* sigma_dev;
+  double* zflag;
 };
 
 template <typename T>
@@ -140,7 +153,8 @@ UpdArgs update_args(const Plan& P, double* x, double* r, const double* p, const 
 int update_grid(const Plan& P);
 FinishArgs finish_args(const Plan& P, int site, int nblocks, int op);
 RhsArgs rhs_args(const Plan& P, const double* xi, const double* ybar, double sigma,
-                 const double* sigma_dev, double* b);
+                 const double* sigma_dev, double* b, const double* zin = nullptr,
+                 const double* zmode_dev = nullptr);
 int rhs_grid(const Plan& P);
 BackprojArgs backproj_args(const Plan& P, const double* u, double* xi, double* y, double* ybar,
                            double tau, double theta, const double* tau_dev,

@@ -61,6 +61,7 @@ enum ScalarSlot {
   S_TAU = 15,
   S_THETA = 16,
   S_CPIT = 17,  // CP iterations done (graph-driven runs)
+  S_ZMODE = 18, // 1 while the right-hand side's input z is in the plan's buffer
   S_COUNT = 24
 };
 
@@ -95,17 +96,20 @@ struct Plan;
 
 // ---- launchers (each defined in its .hip file) ----
 // stencil.hip
+// zin (optional): z = xi + sigma ybar stored by the previous back-projection
 void launch_rhs(const Plan& P, const double* xi, const double* ybar, double sigma,
-                const double* m0, double* b, hipStream_t s);
+                const double* m0, double* b, hipStream_t s, const double* zin = nullptr);
 void launch_apply_C(const Plan& P, const double* y, double* b, hipStream_t s);
 void launch_apply_CT(const Plan& P, const double* u, double* y, hipStream_t s);
 void launch_AAt(const Plan& P, const double* u, double* q, bool reduce_pq, hipStream_t s);
 void launch_pdir_AAt(const Plan& P, const double* z, const double* pold, double* pnew, double* q,
                      bool first, hipStream_t s);
 void launch_prox(const Plan& P, const double* v, double tau, double* y, hipStream_t s);
-// vout (optional): stores v = y - tau xi' (the prox input) for the reverse sweep
+// vout (optional): stores v = y - tau xi' (the prox input) for the reverse sweep;
+// zout (optional): stores z = xi' + (sigma / theta) ybar' in place of xi', ybar'
 void launch_backproj_prox(const Plan& P, const double* u, double* xi, double* y, double* ybar,
-                          double tau, double theta, hipStream_t s, double* vout = nullptr);
+                          double tau, double theta, hipStream_t s, double* vout = nullptr,
+                          double* zout = nullptr, double sigma = 0.0);
 // vec.hip
 void launch_pcg_init(const Plan& P, const double* b, double* x, double* r, double rtol,
                      hipStream_t s);

@@ -90,7 +90,9 @@ struct Plan {
   double *r = nullptr, *z = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr;
   double *tmp = nullptr;  // preconditioner intermediate (float64 or float32 view)
   double *b = nullptr, *u = nullptr;
-  double *xi_tmp = nullptr;
+  // z = xi + sigma ybar handed from one CP step's back-projection to the next
+  // step's right-hand side inside one multi-step call ((1 + 2d) n values)
+  double *zn = nullptr;
   RedBuf red{};
   double* host_scal = nullptr;  // pinned mirror of red.scal
 

@@ -54,11 +54,11 @@ __device__ __forceinline__ double D2w(F f, int i, int n, int neumann) {
 }
 
 // b = Cr (xi + sigma ybar) - sigma [t==0] m0/dt. With ybar == nullptr this is
-// b = Cr xi (apply_C).
-template <bool HASBAR>
-__device__ void rhs_body(const RhsArgs& a, int bid, int nb) {
+// b = Cr xi (apply_C). ZM: z = xi + sigma ybar read ready-made from zin.
+template <bool HASBAR, bool ZM>
+__device__ void rhs_cells(const RhsArgs& a, int bid, int nb) {
   const Geom g = a.g;
-  const double* __restrict__ xi = a.xi;
+  const double* __restrict__ xi = ZM ? a.zin : a.xi;
   const double* __restrict__ ybar = a.ybar;
   const double* __restrict__ m0 = a.m0;
   double* __restrict__ b = a.b;
@@ -71,7 +71,8 @@ __device__ void rhs_body(const RhsArgs& a, int bid, int nb) {
     const int i0 = rem / g.n1, i1 = rem - i0 * g.n1;
     auto z = [&](int c, size_t idx) -> double {
       const size_t k = (size_t)c * n + idx;
-      return HASBAR ? xi[k] + sigma * ybar[k] : xi[k];
+      // one rounding (fma), as where z is formed by the back-projection
+      return (HASBAR && !ZM) ? __builtin_fma(sigma, ybar[k], xi[k]) : xi[k];
     };
     // m-part: L z_t - [t>=1] z_{t-1}/dt
     const double zc = z(0, at(g, t, i0, i1));
@@ -97,6 +98,14 @@ __device__ void rhs_body(const RhsArgs& a, int bid, int nb) {
     if (HASBAR && t == 0) r -= sigma * m0[rem] * g.idt;
     b[p] = r;
   }
+}
+
+template <bool HASBAR>
+__device__ void rhs_body(const RhsArgs& a, int bid, int nb) {
+  if (HASBAR && a.zin && (!a.zmode_dev || *a.zmode_dev != 0.0))
+    rhs_cells<HASBAR, true>(a, bid, nb);
+  else
+    rhs_cells<HASBAR, false>(a, bid, nb);
 }
 
 // Components of Cr^T u at one cell: out[0] = m-part, out[1+c] = B_c^T u_t.
@@ -355,6 +364,9 @@ __device__ void backproj_body(const BackprojArgs& a, int bid, int nb) {
   double* __restrict__ vout = a.vout;
   const double tau = a.tau_dev ? *a.tau_dev : a.tau;
   const double theta = a.theta_dev ? *a.theta_dev : a.theta;
+  double* __restrict__ zout = a.zout;
+  const double sig_next = zout ? (a.sigma_dev ? *a.sigma_dev : a.sigma) / theta : 0.0;
+  if (a.zflag && bid == 0 && threadIdx.x == 0) *a.zflag = zout ? 1.0 : 0.0;
   const long long n = g.n;
   double acc[1] = {0.0};
   for (long long p = (long long)bid * blockDim.x + threadIdx.x; p < n;
@@ -373,13 +385,24 @@ __device__ void backproj_body(const BackprojArgs& a, int bid, int nb) {
     }
     const double m = prox_cell(mbar, w, g.ncomp, Vpot[rem], tau);
     // streaming stores: the new state is read again only by the next step
-    for (int c = 0; c <= g.ncomp; ++c) __builtin_nontemporal_store(x[c], &xi[(size_t)c * n + p]);
+    const double mb = m + theta * (m - yo[0]);
     __builtin_nontemporal_store(m, &y[p]);
-    __builtin_nontemporal_store(m + theta * (m - yo[0]), &ybar[p]);
-    for (int c = 0; c < g.ncomp; ++c) {
-      __builtin_nontemporal_store(w[c], &y[(size_t)(c + 1) * n + p]);
-      __builtin_nontemporal_store(w[c] + theta * (w[c] - yo[1 + c]),
-                                  &ybar[(size_t)(c + 1) * n + p]);
+    for (int c = 0; c < g.ncomp; ++c) __builtin_nontemporal_store(w[c], &y[(size_t)(c + 1) * n + p]);
+    if (zout) {
+      // one rounding (fma), as where the right-hand side forms z from xi, ybar
+      __builtin_nontemporal_store(__builtin_fma(sig_next, mb, x[0]), &zout[p]);
+      for (int c = 0; c < g.ncomp; ++c) {
+        const double wb = w[c] + theta * (w[c] - yo[1 + c]);
+        __builtin_nontemporal_store(__builtin_fma(sig_next, wb, x[1 + c]),
+                                    &zout[(size_t)(c + 1) * n + p]);
+      }
+    } else {
+      for (int c = 0; c <= g.ncomp; ++c)
+        __builtin_nontemporal_store(x[c], &xi[(size_t)c * n + p]);
+      __builtin_nontemporal_store(mb, &ybar[p]);
+      for (int c = 0; c < g.ncomp; ++c)
+        __builtin_nontemporal_store(w[c] + theta * (w[c] - yo[1 + c]),
+                                    &ybar[(size_t)(c + 1) * n + p]);
     }
     const double dm = m - yo[0];
     acc[0] += dm * dm;
@@ -487,23 +510,24 @@ void aat_launch(const Plan& P, const double* src, const double* pold, double* pn
 }  // namespace
 
 RhsArgs rhs_args(const Plan& P, const double* xi, const double* ybar, double sigma,
-                 const double* sigma_dev, double* b) {
-  return RhsArgs{P.g, xi, ybar, sigma, sigma_dev, P.m0, b};
+                 const double* sigma_dev, double* b, const double* zin,
+                 const double* zmode_dev) {
+  return RhsArgs{P.g, xi, ybar, sigma, sigma_dev, P.m0, b, zin, zmode_dev};
 }
 
 int rhs_grid(const Plan& P) { return grid_for(P.g.n, 1 << 20); }
 
 void launch_rhs(const Plan& P, const double* xi, const double* ybar, double sigma,
-                const double* m0, double* b, hipStream_t s) {
+                const double* m0, double* b, hipStream_t s, const double* zin) {
   ProfScope ps(P, "rhs", s);
-  RhsArgs a = rhs_args(P, xi, ybar, sigma, nullptr, b);
+  RhsArgs a = rhs_args(P, xi, ybar, sigma, nullptr, b, zin);
   a.m0 = m0;
   hipLaunchKernelGGL(k_rhs<true>, dim3(rhs_grid(P)), dim3(kThreads), 0, s, a);
 }
 
 void launch_apply_C(const Plan& P, const double* y, double* b, hipStream_t s) {
   ProfScope ps(P, "apply_C", s);
-  const RhsArgs a{P.g, y, nullptr, 0.0, nullptr, nullptr, b};
+  const RhsArgs a{P.g, y, nullptr, 0.0, nullptr, nullptr, b, nullptr, nullptr};
   hipLaunchKernelGGL(k_rhs<false>, dim3(rhs_grid(P)), dim3(kThreads), 0, s, a);
 }
 
@@ -533,18 +557,22 @@ void launch_prox(const Plan& P, const double* v, double tau, double* y, hipStrea
 BackprojArgs backproj_args(const Plan& P, const double* u, double* xi, double* y, double* ybar,
                            double tau, double theta, const double* tau_dev,
                            const double* theta_dev, double* vout) {
-  return BackprojArgs{P.g, u, xi, y, ybar, P.V, tau, theta, tau_dev, theta_dev, P.red, vout};
+  return BackprojArgs{P.g,      u,         xi,   y,       ybar,    P.V,     tau,    theta,
+                      tau_dev,  theta_dev, P.red, vout, nullptr, 0.0, nullptr, nullptr};
 }
 
 int backproj_grid(const Plan& P) { return grid_for(P.g.n, P.red.max_blocks); }
 
 void launch_backproj_prox(const Plan& P, const double* u, double* xi, double* y, double* ybar,
-                          double tau, double theta, hipStream_t s, double* vout) {
+                          double tau, double theta, hipStream_t s, double* vout, double* zout,
+                          double sigma) {
   const int grid = backproj_grid(P);
   {
     ProfScope ps(P, "backproj_prox", s);
-    hipLaunchKernelGGL(k_backproj_prox, dim3(grid), dim3(kThreads), 0, s,
-                       backproj_args(P, u, xi, y, ybar, tau, theta, nullptr, nullptr, vout));
+    BackprojArgs a = backproj_args(P, u, xi, y, ybar, tau, theta, nullptr, nullptr, vout);
+    a.zout = zout;
+    a.sigma = sigma;
+    hipLaunchKernelGGL(k_backproj_prox, dim3(grid), dim3(kThreads), 0, s, a);
   }
   launch_finish(P, T_DM, grid, OP_DM, s);
 }

@@ -94,3 +94,26 @@ def test_resume_is_bitwise():
         assert np.array_equal(host(x), host(y))
     assert a.tau == c.tau and a.sigma == c.sigma and a.iter == c.iter == 20
     P.close()
+
+
+@pytest.mark.parametrize("bc", ["periodic", "neumann"])
+def test_multistep_call_equals_single_steps(bc):
+    """Inside one multi-step call, each step hands z = xi + sigma ybar to the
+    next step's right-hand side instead of storing xi and ybar; the state the
+    call returns is bitwise the one of as many single-step calls."""
+    inst = wl.small_instance(10, 2, 24, 18, 9, bc, 0.02)
+    say(f"cp multistep {bc}")
+    P = plan_of(inst)
+    a = mfg.CPState(P)
+    mfg.mfg_cp_init(P, a)
+    its_a = mfg.mfg_cp_solve(P, a, 7, 1e-10, 500)["pcg_iters"]
+    b = mfg.CPState(P)
+    mfg.mfg_cp_init(P, b)
+    its_b = []
+    for _ in range(7):
+        its_b += mfg.mfg_cp_solve(P, b, 1, 1e-10, 500)["pcg_iters"]
+    assert list(its_a) == list(its_b)
+    for x, y in [(a.xi, b.xi), (a.y, b.y), (a.ybar, b.ybar)]:
+        assert np.array_equal(host(x), host(y))
+    assert a.tau == b.tau and a.sigma == b.sigma and a.iter == b.iter == 7
+    P.close()
