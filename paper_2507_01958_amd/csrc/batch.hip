@@ -52,7 +52,7 @@ struct ColsGroup {
 
 struct GemmGroup {
   int ntp = 0, cb = 2;
-  Phase<GemmArgs<double, float>> fwd;
+  Phase<GemmArgs<double, float>> fwd_init, fwd;  // fwd: with the r.r stopping test
   Phase<GemmArgs<float, double>> inv_init, inv_iter;
 };
 
@@ -80,7 +80,7 @@ struct Batch {
   // back-projection of the last step of a call (writes xi', ybar') and of the
   // other steps (hands z = xi' + sigma' ybar' to the next right-hand side)
   Phase<BackprojArgs> bp, bp_mid;
-  FinishArgs *f_bb = nullptr, *f_rr = nullptr, *f_dm = nullptr;
+  FinishArgs *f_bb = nullptr, *f_dm = nullptr;
   std::vector<const double*> bound;  // state vectors the rhs/bp phases were built for
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -154,7 +154,7 @@ int build_pcg_phases(Batch& B) {
   std::vector<UpdArgs> uo, ue;
   std::vector<AatArgs> af, ao, ae;
   std::vector<int> b_init, b_upd, b_aat;
-  std::vector<FinishArgs> fbb, frr;
+  std::vector<FinishArgs> fbb;
   // spatial launches grouped by size class
   std::vector<int> rcls(n), ccls(n);
   std::vector<RowsArgs<float>> rf(n), ri(n);
@@ -182,15 +182,10 @@ int build_pcg_phases(Batch& B) {
     batch_rows_args(P, tmp, 1, done, &ri[i], &b_rows[i], &rshm[i]);
     ccls[i] = batch_cols_args(P, tmp, done, &cl[i], &b_cols[i], &cshm[i]);
     uo.back().npq = ue.back().npq = g;
-    FinishArgs f = finish_args(P, T_BB, pcg_init_grid(P), OP_BB);
-    fbb.push_back(f);
-    f = finish_args(P, T_RR, update_grid(P), OP_RR);
-    f.done = done;
-    frr.push_back(f);
+    fbb.push_back(finish_args(P, T_BB, pcg_init_grid(P), OP_BB));
   }
   int rc;
-  if ((rc = upload_phase(B, init, b_init, B.init)) || (rc = upload_finish(B, fbb, &B.f_bb)) ||
-      (rc = upload_finish(B, frr, &B.f_rr)))
+  if ((rc = upload_phase(B, init, b_init, B.init)) || (rc = upload_finish(B, fbb, &B.f_bb)))
     return rc;
   {
     std::vector<int> classes(rcls);
@@ -243,7 +238,7 @@ int build_pcg_phases(Batch& B) {
     GemmGroup& G = B.groups[gi];
     G.ntp = classes[gi].first;
     G.cb = classes[gi].second;
-    std::vector<GemmArgs<double, float>> fw;
+    std::vector<GemmArgs<double, float>> fw0, fw;
     std::vector<GemmArgs<float, double>> i0, i1;
     std::vector<int> blocks;
     for (int i = 0; i < n; ++i) {
@@ -251,8 +246,10 @@ int build_pcg_phases(Batch& B) {
       if (P.ntp != G.ntp || (P.tune.lp_cb == 1 ? 1 : 2) != G.cb) continue;
       float* tmp = reinterpret_cast<float*>(P.tmp);
       int blk;
-      fw.push_back(batch_gemm_args<double, float>(P, B.mode, P.r, tmp, DOT_NONE, nullptr, nullptr,
-                                                  done_of(B, i), &blk));
+      fw0.push_back(batch_gemm_args<double, float>(P, B.mode, P.r, tmp, DOT_NONE, nullptr,
+                                                   nullptr, done_of(B, i), &blk));
+      fw.push_back(fw0.back());
+      fw.back().nrr = update_grid(P);
       i0.push_back(batch_gemm_args<float, double>(P, B.mode, tmp, P.z, DOT_INIT, P.r, nullptr,
                                                   done_of(B, i), &blk));
       i1.push_back(batch_gemm_args<float, double>(P, B.mode, tmp, P.z,
@@ -261,7 +258,8 @@ int build_pcg_phases(Batch& B) {
       blocks.push_back(blk);
       gemm_grid[i] = blk;
     }
-    if ((rc = upload_phase(B, fw, blocks, G.fwd)) || (rc = upload_phase(B, i0, blocks, G.inv_init)) ||
+    if ((rc = upload_phase(B, fw0, blocks, G.fwd_init)) || (rc = upload_phase(B, fw, blocks, G.fwd)) ||
+        (rc = upload_phase(B, i0, blocks, G.inv_init)) ||
         (rc = upload_phase(B, i1, blocks, G.inv_iter)))
       return rc;
   }
@@ -308,9 +306,11 @@ int build_state_phases(Batch& B, mfg_state_t* st) {
 }
 
 void precond_phase(Batch& B, bool init, hipStream_t s) {
-  for (auto& G : B.groups)
-    launch_gemm_batch<double, float>(B.mode, G.ntp, G.cb, G.fwd.args, G.fwd.off, G.fwd.ninst,
-                                     G.fwd.total, s);
+  for (auto& G : B.groups) {
+    const auto& ph = init ? G.fwd_init : G.fwd;
+    launch_gemm_batch<double, float>(B.mode, G.ntp, G.cb, ph.args, ph.off, ph.ninst, ph.total,
+                                     s);
+  }
   for (const auto& G : B.rows)
     launch_rows_batch_f32(G.cls, G.rows_fwd.args, G.rows_fwd.off, G.rows_fwd.ninst,
                           G.rows_fwd.total, G.rows_fwd.shm, s);
@@ -333,7 +333,6 @@ void pcg_iteration(Batch& B, int k, hipStream_t s) {
   launch_aat_batch(true, aat.args, aat.off, B.count, aat.total, s);
   const auto& upd = (k & 1) ? B.upd_odd : B.upd_even;
   launch_update_batch(upd.args, upd.off, B.count, upd.total, s);
-  launch_finish_batch(B.f_rr, B.count, s);
   precond_phase(B, false, s);
 }
 

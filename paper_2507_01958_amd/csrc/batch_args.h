@@ -132,6 +132,7 @@ struct GemmArgs {
   const double* qvec;
   RedBuf rb;
   const double* done;
+  int nrr;  // > 0: first take the PCG r.r check over that many partials
 };
 
 // Instance that owns block b of a batched launch (off[0] = 0 <= b < off[ninst]).

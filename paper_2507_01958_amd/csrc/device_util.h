@@ -104,6 +104,28 @@ __device__ __forceinline__ void fold_partials(const RedBuf& rb, int site, int n,
   __syncthreads();
 }
 
+// The PCG stopping test on r.r, taken by the kernel that next reads r (the
+// preconditioner's first pass) instead of a finisher launch. Every block sums
+// the n partials (same bits everywhere); block 0 records r.r, counts the
+// iteration and sets S_DONE on convergence (r.r <= tol^2 b.b), a non-finite
+// r.r or an earlier breakdown. Returns true when the solve is over. Every
+// thread of the block must call it.
+__device__ __forceinline__ bool rr_check(const RedBuf& rb, int n, int bid) {
+  double rr[1];
+  fold_partials<1>(rb, T_RR, n, rr);
+  const double* S = rb.scal;
+  const bool bad = !finite_d(rr[0]);
+  const bool done = bad || S[S_BAD] != 0.0 || rr[0] <= S[S_TOL2] * S[S_BB];
+  if (bid == 0 && threadIdx.x == 0) {
+    double* Sw = rb.scal;
+    Sw[S_RR] = rr[0];
+    Sw[S_ITS] += 1.0;
+    if (bad) Sw[S_BAD] = 2.0;
+    if (done) Sw[S_DONE] = 1.0;
+  }
+  return done;
+}
+
 // XCD-aware block order: blocks b and b+8 run on the same XCD, so map them to
 // neighbouring logical tiles (shared cache lines and halos stay in one L2).
 __device__ __forceinline__ int xcd_remap(int b, int nb) {

@@ -68,10 +68,10 @@ enum ScalarSlot {
 enum ReduceSite { T_BB = 0, T_PQ = 1, T_RR = 2, T_RZ = 3, T_DM = 4, T_AUX = 5, T_COUNT = 8 };
 
 // What the finisher does with the summed partials of a site.
-// (p.q and r.z are summed by their consumers, the update and the A kernel.)
+// (p.q, r.z and r.r are summed by their consumers: the update, the A kernel
+// and the preconditioner's forward time transform.)
 enum FinishOp {
   OP_BB = 0,        // b.b -> S_BB, S_RR; S_DONE if zero; S_BAD if non-finite
-  OP_RR = 2,        // r.r -> S_RR; S_DONE if r.r <= S_TOL2 * S_BB
   OP_DM = 6,        // -> S_DM
   OP_AUX = 7        // -> S_AUX0, S_AUX1
 };

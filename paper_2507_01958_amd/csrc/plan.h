@@ -57,6 +57,9 @@ struct Plan {
   // Grids of the last launches that stored p.q and r.z partials: the update
   // and the A kernel sum that many partials themselves.
   mutable int pq_blocks = 0, rz_blocks = 0;
+  // r.r partials of the last update (rr_blocks), and the count the next time
+  // GEMM launch folds its stopping test over (rr_gate; 0: none)
+  mutable int rr_blocks = 0, rr_gate = 0;
   Geom g{};
   int precision = MFG_FP64;
   int l = 1;

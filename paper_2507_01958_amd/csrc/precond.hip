@@ -809,9 +809,13 @@ void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
   int dotmode = DOT_NONE;
   if (fused_dots)
     dotmode = (q == nullptr) ? DOT_INIT : (pcg_flexible(P) ? DOT_FLEX : DOT_STD);
+  // inside the PCG loop the forward transform takes the r.r stopping test
+  // over the update's partials (no finisher launch between them)
+  P.rr_gate = (fused_dots && q != nullptr && P.pcg_done) ? P.rr_blocks : 0;
   if (P.precision == MFG_FP64) {
     double* tmp = P.tmp;
     tgemm<double, double>(P, GM_F64, r, tmp, DOT_NONE, nullptr, nullptr, s, "tgemm_f64_fwd");
+    P.rr_gate = 0;
     spatial_solves<double>(P, tmp, s);
     tgemm<double, double>(P, GM_F64, tmp, z, dotmode, r, q, s, "tgemm_f64_inv");
     return;
@@ -826,6 +830,7 @@ void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
   static const char* inv_names[4] = {"tgemm_f64_inv", "tgemm_f32_inv", "tgemm_f16_inv",
                                      "tgemm_bf16_inv"};
   tgemm<double, float>(P, mode, r, tmp, DOT_NONE, nullptr, nullptr, s, fwd_names[mode]);
+  P.rr_gate = 0;
   spatial_solves<float>(P, tmp, s);
   tgemm<float, double>(P, mode, tmp, z, dotmode, r, q, s, inv_names[mode]);
 }

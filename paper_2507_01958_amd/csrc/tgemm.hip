@@ -22,6 +22,14 @@ namespace mfg {
 
 namespace {
 
+// Whether a GEMM block has nothing to do: the solve is over, or the r.r check
+// folded into the forward transform (nrr > 0) ends it now.
+template <typename TX, typename TY>
+__device__ __forceinline__ bool gemm_skip(const GemmArgs<TX, TY>& ga, int bid) {
+  if (ga.done && *ga.done != 0.0) return true;
+  return ga.nrr > 0 && rr_check(ga.rb, ga.nrr, bid);
+}
+
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef _Float16 v4h __attribute__((ext_vector_type(4)));
@@ -29,7 +37,7 @@ typedef short v4s __attribute__((ext_vector_type(4)));
 
 template <int KB, int CB, typename TX, typename TY>
 __device__ void tgemm64_body(const GemmArgs<TX, TY>& ga, int bid) {
-  if (ga.done && *ga.done != 0.0) return;
+  if (gemm_skip(ga, bid)) return;
   const double* __restrict__ Vt = static_cast<const double*>(ga.V);
   const TX* __restrict__ X = ga.X;
   TY* __restrict__ Y = ga.Y;
@@ -182,7 +190,7 @@ struct LpTraits<GM_BF16> {
 // blocks of 16 nodes and all N_t output rows.
 template <int MODE, int NTP, int CB, typename TX, typename TY, int WPB = 4>
 __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
-  if (ga.done && *ga.done != 0.0) return;
+  if (gemm_skip(ga, bid)) return;
   using VT = typename LpTraits<MODE>::VT;
   const VT* __restrict__ Vg = static_cast<const VT*>(ga.V);
   const TX* __restrict__ X = ga.X;
@@ -525,7 +533,7 @@ __device__ __forceinline__ void stream_tile(const TX (&x)[NXA],
 
 template <int MODE, int NTP, int WAVES, typename TX, typename TY>
 __global__ __launch_bounds__(WAVES * 64) void k_tgemm_stream(GemmArgs<TX, TY> ga) {
-  if (ga.done && *ga.done != 0.0) return;
+  if (gemm_skip(ga, (int)blockIdx.x)) return;
   using VT = typename StreamTraits<MODE>::VT;
   using Sh = StreamShape<MODE, NTP>;
   constexpr int NT = WAVES * 64;
@@ -576,7 +584,7 @@ int stream_launch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* 
   const void* V = (MODE == GM_F64) ? (const void*)P.Vp64
                   : (MODE == GM_F32) ? (const void*)P.Vp32
                   : (MODE == GM_F16) ? (const void*)P.Vp16 : (const void*)P.Vpbf;
-  const GemmArgs<TX, TY> a{V, X, Y, P.g.nt, M, 0, dotmode, r, q, P.red, P.pcg_done};
+  const GemmArgs<TX, TY> a{V, X, Y, P.g.nt, M, 0, dotmode, r, q, P.red, P.pcg_done, P.rr_gate};
   hipLaunchKernelGGL((k_tgemm_stream<MODE, NTP, WAVES, TX, TY>), dim3(grid), dim3(WAVES * 64), 0,
                      s, a);
   return grid;
@@ -608,7 +616,7 @@ int lp_launch_cb(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r
   const int M = P.g.M;
   const int grid = (M + 16 * WPB * CB - 1) / (16 * WPB * CB);
   const GemmArgs<TX, TY> a{lp_table(P, MODE), X, Y, P.g.nt, M, 0, dotmode, r, q, P.red,
-                           P.pcg_done};
+                           P.pcg_done, P.rr_gate};
   hipLaunchKernelGGL((k_tgemm_lp<MODE, NTP, CB, TX, TY, WPB>), dim3(grid), dim3(WPB * 64), 0, s,
                      a);
   return grid;
@@ -651,7 +659,8 @@ int f64_launch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r, 
   const int ncolblk = (M + 64 * CB - 1) / (64 * CB);
   const int nkc = (nt + KB * 16 - 1) / (KB * 16);
   const int grid = ncolblk * nkc;
-  const GemmArgs<TX, TY> a{P.Vt64, X, Y, nt, M, ncolblk, dotmode, r, q, P.red, P.pcg_done};
+  const GemmArgs<TX, TY> a{P.Vt64, X, Y, nt, M, ncolblk, dotmode, r, q, P.red, P.pcg_done,
+                           P.rr_gate};
   hipLaunchKernelGGL((k_tgemm64<KB, CB, TX, TY>), dim3(grid), dim3(256), 0, s, a);
   return grid;
 }
@@ -710,7 +719,8 @@ GemmArgs<TX, TY> batch_gemm_args(const Plan& P, int mode, const TX* X, TY* Y, in
                                  int* blocks) {
   const int cb = P.tune.lp_cb == 1 ? 1 : 2;
   *blocks = (P.g.M + 64 * cb - 1) / (64 * cb);
-  return GemmArgs<TX, TY>{lp_table(P, mode), X, Y, P.g.nt, P.g.M, 0, dotmode, r, q, P.red, done};
+  return GemmArgs<TX, TY>{lp_table(P, mode), X, Y, P.g.nt, P.g.M, 0, dotmode, r, q, P.red, done,
+                          0};
 }
 
 template <int MODE, int CB, typename TX, typename TY>

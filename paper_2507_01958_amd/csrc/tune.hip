@@ -91,7 +91,7 @@ void store(const Plan& P, const Tune& t) {
 }
 
 // Timed units: the preconditioner as PCG applies it (with its fused dot
-// products and finisher), and the fused A apply (PCG direction update
+// products), and the fused A apply (PCG direction update
 // p = z + beta p_old with q = A p), each tuned on its own launch shapes.
 enum Unit { U_PRECOND = 0, U_AAT = 1 };
 

@@ -88,12 +88,6 @@ __device__ void finish_body(const FinishArgs& f) {
       S[S_BAD] = finite_d(a) ? 0.0 : 2.0;
       S[S_DONE] = (a == 0.0) ? 1.0 : 0.0;
       break;
-    case OP_RR:
-      S[S_RR] = a;
-      S[S_ITS] += 1.0;
-      if (!finite_d(a)) S[S_BAD] = 2.0;
-      if (a <= S[S_TOL2] * S[S_BB] || S[S_BAD] != 0.0) S[S_DONE] = 1.0;
-      break;
     case OP_DM:
       S[S_DM] = a;
       break;
@@ -213,7 +207,9 @@ void launch_update(const Plan& P, double* x, double* r, const double* p, const d
     ProfScope ps(P, "update", s);
     hipLaunchKernelGGL(k_update, dim3(grid), dim3(kThreads), 0, s, update_args(P, x, r, p, q));
   }
-  launch_finish(P, T_RR, grid, OP_RR, s);
+  // the r.r partials are summed by the stopping test of the next
+  // preconditioner application (its forward time transform)
+  P.rr_blocks = grid;
 }
 
 void launch_residual(const Plan& P, const double* b, const double* Ax, hipStream_t s) {
