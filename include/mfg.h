@@ -77,7 +77,8 @@ typedef struct {
   int n[2];          /* N_x, N_y: nodes per axis (interior nodes if Neumann);
                         n[1] is ignored when d = 1. Each must be >= 4 and of
                         the form 2^a 3^b (spatial transform sizes). */
-  int nt;            /* N_t >= 2 time steps; any value */
+  int nt;            /* N_t time steps, 2 <= N_t <= 4096; N_t times the
+                        spatial node count must be below 2^31 */
   double T;          /* horizon T > 0; dt = T / N_t */
   double lo[2], hi[2]; /* domain [a,b] x [c,d]: periodic dx = (b-a)/N_x,
                           Neumann dx = (b-a)/(N_x+1) (Section 2) */
@@ -95,7 +96,7 @@ typedef struct mfg_plan_s* mfg_plan_t;
 
 /* Build a plan: validate the problem, compute the grid constants and the
  * eigenvalue / transform tables (eqs. eigs, lambda1, lambda2) and allocate the
- * plan's workspace (about 7 n-vectors). V (the potential of the coupling
+ * plan's workspace (about 8 n-vectors plus one primal vector). V (the potential of the coupling
  * f(x, m) = m + V(x), M values) and m0 (initial density, M values, >= 0 and
  * finite) are device pointers; the plan copies them. stream may be 0 (the
  * null stream). The coupling is f = m + V and the terminal cost g = 0. */

@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_prox(Geom g, double* __restric
   const long long n = g.n;
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
        p += (long long)gridDim.x * blockDim.x) {
-    const int rem = (int)(p % g.M);
+    const int rem = (int)((unsigned)p % (unsigned)g.M);  // n < 2^31
     double wb[4], wt[4], gyn[5], gv[5];
     for (int c = 0; c < g.ncomp; ++c) wb[c] = wt[c] = v[(size_t)(c + 1) * n + p];
     double a;

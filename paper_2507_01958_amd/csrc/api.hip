@@ -189,6 +189,12 @@ static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const d
       return fail(MFG_ERR_INVALID_ARG, "domain needs hi > lo");
   }
   if (pb->nt < 2 || pb->nt > kMaxNt) return fail(MFG_ERR_INVALID_ARG, "nt must be in [2, 4096]");
+  {
+    // the kernels index cells of an n-vector with 32-bit arithmetic
+    const long long ncell = (long long)pb->nt * pb->n[0] * (pb->d == 2 ? pb->n[1] : 1);
+    if (ncell >= (1LL << 31))
+      return fail(MFG_ERR_UNSUPPORTED, "grid too large: N_t times the spatial nodes must be below 2^31");
+  }
   if (!(pb->T > 0.0) || !std::isfinite(pb->T)) return fail(MFG_ERR_INVALID_ARG, "T must be > 0");
   if (pb->bc != MFG_BC_PERIODIC && pb->bc != MFG_BC_NEUMANN)
     return fail(MFG_ERR_INVALID_ARG, "bc must be periodic or neumann");

@@ -23,6 +23,13 @@ __device__ __forceinline__ int nbr(int p, int n, int neumann) {
   return p < 0 ? p + n : p;
 }
 
+// nbr for a direct neighbour of a node, p in [-1, n] (no division).
+__device__ __forceinline__ int nbr1(int p, int n, int neumann) {
+  if (p < 0) return neumann ? 0 : n - 1;
+  if (p >= n) return neumann ? n - 1 : 0;
+  return p;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -24,7 +24,7 @@ struct Tune {
   int tgemm_pers = 0;     // persistent time GEMM (whole V in LDS) when N_t <= 128
   int fft_reg = 1;        // register-resident FFTs for axis lengths 64, 128, 256
   int aat_tc = 0;         // A kernel: time slices per block (0: chosen from the grid)
-  int aat_big = 0;        // A kernel (d = 2): 16 << aat_big tile rows, 256 << aat_big threads
+  int aat_big = 1;        // A kernel (d = 2): 16 << aat_big tile rows, 256 << aat_big threads
   // PCG update with the mixed-precision preconditioner: 1 flexible
   // (Polak-Ribiere), 0 standard, -1 by precision (standard for float32, whose
   // preconditioner is symmetric to float32 rounding; flexible for float16 and

@@ -29,33 +29,50 @@ __device__ __forceinline__ size_t at(const Geom& g, int t, int i0, int i1) {
   return (size_t)t * g.M + (size_t)i0 * g.n1 + i1;
 }
 
+// The per-cell stencils below are specialised on the axis count (HAS0: d = 2)
+// and the boundary type (NEU: Neumann) so the cell loops carry no branches on
+// them; *_dispatch picks the specialisation once per block.
+
 // (K v)(i0, i1) in slice t of v.
+template <bool HAS0, bool NEU>
 __device__ __forceinline__ double Kop(const double* __restrict__ v, const Geom& g, int t, int i0,
                                       int i1) {
   const double c = v[at(g, t, i0, i1)];
-  double r = (2.0 * c - v[at(g, t, i0, nbr(i1 + 1, g.n1, g.neumann))] -
-              v[at(g, t, i0, nbr(i1 - 1, g.n1, g.neumann))]) * g.ih1sq;
-  if (g.has0)
-    r += (2.0 * c - v[at(g, t, nbr(i0 + 1, g.n0, g.neumann), i1)] -
-          v[at(g, t, nbr(i0 - 1, g.n0, g.neumann), i1)]) * g.ih0sq;
+  double r = (2.0 * c - v[at(g, t, i0, nbr1(i1 + 1, g.n1, NEU))] -
+              v[at(g, t, i0, nbr1(i1 - 1, g.n1, NEU))]) * g.ih1sq;
+  if (HAS0)
+    r += (2.0 * c - v[at(g, t, nbr1(i0 + 1, g.n0, NEU), i1)] -
+          v[at(g, t, nbr1(i0 - 1, g.n0, NEU), i1)]) * g.ih0sq;
   return r;
 }
 
 // (D^1 w)_i and (D^2 w)_i along one axis for the value accessor f(index).
-template <class F>
-__device__ __forceinline__ double D1w(F f, int i, int n, int neumann) {
-  if (!neumann) return f(i) - f(nbr(i - 1, n, 0));
+template <bool NEU, class F>
+__device__ __forceinline__ double D1w(F f, int i, int n) {
+  if (!NEU) return f(i) - f(i == 0 ? n - 1 : i - 1);
   return (i <= n - 2 ? f(i) : 0.0) - (i >= 1 ? f(i - 1) : 0.0);
 }
-template <class F>
-__device__ __forceinline__ double D2w(F f, int i, int n, int neumann) {
-  if (!neumann) return f(nbr(i + 1, n, 0)) - f(i);
+template <bool NEU, class F>
+__device__ __forceinline__ double D2w(F f, int i, int n) {
+  if (!NEU) return f(i + 1 == n ? 0 : i + 1) - f(i);
   return (i <= n - 2 ? f(i + 1) : 0.0) - (i >= 1 ? f(i) : 0.0);
+}
+
+// Calls F<HAS0, NEU>::run(args...) for the geometry's axis count and boundary.
+template <template <bool, bool> class F, class... A>
+__device__ __forceinline__ void geom_dispatch(const Geom& g, A&&... args) {
+  if (g.has0) {
+    if (g.neumann) F<true, true>::run(args...);
+    else F<true, false>::run(args...);
+  } else {
+    if (g.neumann) F<false, true>::run(args...);
+    else F<false, false>::run(args...);
+  }
 }
 
 // b = Cr (xi + sigma ybar) - sigma [t==0] m0/dt. With ybar == nullptr this is
 // b = Cr xi (apply_C). ZM: z = xi + sigma ybar read ready-made from zin.
-template <bool HASBAR, bool ZM>
+template <bool HASBAR, bool ZM, bool HAS0, bool NEU>
 __device__ void rhs_cells(const RhsArgs& a, int bid, int nb) {
   const Geom g = a.g;
   const double* __restrict__ xi = ZM ? a.zin : a.xi;
@@ -66,9 +83,11 @@ __device__ void rhs_cells(const RhsArgs& a, int bid, int nb) {
   const long long n = g.n;
   for (long long p = (long long)bid * blockDim.x + threadIdx.x; p < n;
        p += (long long)nb * blockDim.x) {
-    const int t = (int)(p / g.M);
-    const int rem = (int)(p - (long long)t * g.M);
-    const int i0 = rem / g.n1, i1 = rem - i0 * g.n1;
+    // n < 2^31 (checked by the plan): 32-bit index arithmetic
+    const unsigned pu = (unsigned)p;
+    const int t = (int)(pu / (unsigned)g.M);
+    const int rem = (int)(pu - (unsigned)t * (unsigned)g.M);
+    const int i0 = (int)((unsigned)rem / (unsigned)g.n1), i1 = rem - i0 * g.n1;
     auto z = [&](int c, size_t idx) -> double {
       const size_t k = (size_t)c * n + idx;
       // one rounding (fma), as where z is formed by the back-projection
@@ -76,71 +95,95 @@ __device__ void rhs_cells(const RhsArgs& a, int bid, int nb) {
     };
     // m-part: L z_t - [t>=1] z_{t-1}/dt
     const double zc = z(0, at(g, t, i0, i1));
-    double Kz = (2.0 * zc - z(0, at(g, t, i0, nbr(i1 + 1, g.n1, g.neumann))) -
-                 z(0, at(g, t, i0, nbr(i1 - 1, g.n1, g.neumann)))) * g.ih1sq;
-    if (g.has0)
-      Kz += (2.0 * zc - z(0, at(g, t, nbr(i0 + 1, g.n0, g.neumann), i1)) -
-             z(0, at(g, t, nbr(i0 - 1, g.n0, g.neumann), i1))) * g.ih0sq;
+    double Kz = (2.0 * zc - z(0, at(g, t, i0, nbr1(i1 + 1, g.n1, NEU))) -
+                 z(0, at(g, t, i0, nbr1(i1 - 1, g.n1, NEU)))) * g.ih1sq;
+    if (HAS0)
+      Kz += (2.0 * zc - z(0, at(g, t, nbr1(i0 + 1, g.n0, NEU), i1)) -
+             z(0, at(g, t, nbr1(i0 - 1, g.n0, NEU), i1))) * g.ih0sq;
     double r = g.nu * Kz + zc * g.idt;
     if (t >= 1) r -= z(0, at(g, t - 1, i0, i1)) * g.idt;
     // flux part: sum_c B_c w^(c)_t
     {
-      const int ce = 1 + g.cb1, co = 2 + g.cb1;
+      constexpr int ce = HAS0 ? 3 : 1, co = HAS0 ? 4 : 2;
       auto fe = [&](int j) { return z(ce, at(g, t, i0, j)); };
       auto fo = [&](int j) { return z(co, at(g, t, i0, j)); };
-      r += (D1w(fe, i1, g.n1, g.neumann) + D2w(fo, i1, g.n1, g.neumann)) * g.ih1;
+      r += (D1w<NEU>(fe, i1, g.n1) + D2w<NEU>(fo, i1, g.n1)) * g.ih1;
     }
-    if (g.has0) {
+    if (HAS0) {
       auto fe = [&](int i) { return z(1, at(g, t, i, i1)); };
       auto fo = [&](int i) { return z(2, at(g, t, i, i1)); };
-      r += (D1w(fe, i0, g.n0, g.neumann) + D2w(fo, i0, g.n0, g.neumann)) * g.ih0;
+      r += (D1w<NEU>(fe, i0, g.n0) + D2w<NEU>(fo, i0, g.n0)) * g.ih0;
     }
     if (HASBAR && t == 0) r -= sigma * m0[rem] * g.idt;
     b[p] = r;
   }
 }
 
+template <bool HASBAR, bool ZM>
+struct RhsCells {
+  template <bool HAS0, bool NEU>
+  struct F {
+    __device__ static void run(const RhsArgs& a, int bid, int nb) {
+      rhs_cells<HASBAR, ZM, HAS0, NEU>(a, bid, nb);
+    }
+  };
+};
+
 template <bool HASBAR>
 __device__ void rhs_body(const RhsArgs& a, int bid, int nb) {
   if (HASBAR && a.zin && (!a.zmode_dev || *a.zmode_dev != 0.0))
-    rhs_cells<HASBAR, true>(a, bid, nb);
+    geom_dispatch<RhsCells<HASBAR, true>::template F>(a.g, a, bid, nb);
   else
-    rhs_cells<HASBAR, false>(a, bid, nb);
+    geom_dispatch<RhsCells<HASBAR, false>::template F>(a.g, a, bid, nb);
 }
 
 // Components of Cr^T u at one cell: out[0] = m-part, out[1+c] = B_c^T u_t.
+template <bool HAS0, bool NEU>
 __device__ __forceinline__ void CT_cell(const Geom& g, const double* __restrict__ u, int t, int i0,
                                         int i1, double* out) {
   const double uc = u[at(g, t, i0, i1)];
-  double m = g.nu * Kop(u, g, t, i0, i1) + uc * g.idt;
+  double m = g.nu * Kop<HAS0, NEU>(u, g, t, i0, i1) + uc * g.idt;
   if (t <= g.nt - 2) m -= u[at(g, t + 1, i0, i1)] * g.idt;
   out[0] = m;
   {
-    const double up = u[at(g, t, i0, nbr(i1 + 1, g.n1, g.neumann))];
-    const double um = u[at(g, t, i0, nbr(i1 - 1, g.n1, g.neumann))];
-    out[1 + g.cb1] = (uc - up) * g.ih1;
-    out[2 + g.cb1] = (um - uc) * g.ih1;
+    constexpr int cb1 = HAS0 ? 2 : 0;
+    const double up = u[at(g, t, i0, nbr1(i1 + 1, g.n1, NEU))];
+    const double um = u[at(g, t, i0, nbr1(i1 - 1, g.n1, NEU))];
+    out[1 + cb1] = (uc - up) * g.ih1;
+    out[2 + cb1] = (um - uc) * g.ih1;
   }
-  if (g.has0) {
-    const double up = u[at(g, t, nbr(i0 + 1, g.n0, g.neumann), i1)];
-    const double um = u[at(g, t, nbr(i0 - 1, g.n0, g.neumann), i1)];
+  if (HAS0) {
+    const double up = u[at(g, t, nbr1(i0 + 1, g.n0, NEU), i1)];
+    const double um = u[at(g, t, nbr1(i0 - 1, g.n0, NEU), i1)];
     out[1] = (uc - up) * g.ih0;
     out[2] = (um - uc) * g.ih0;
   }
 }
 
+template <bool HAS0, bool NEU>
+struct ApplyCT {
+  __device__ static void run(const Geom& g, const double* __restrict__ u,
+                             double* __restrict__ y) {
+    constexpr int NC = HAS0 ? 4 : 2;
+    const long long n = g.n;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (long long)gridDim.x * blockDim.x) {
+      // n < 2^31 (checked by the plan): 32-bit index arithmetic
+      const unsigned pu = (unsigned)p;
+      const int t = (int)(pu / (unsigned)g.M);
+      const int rem = (int)(pu - (unsigned)t * (unsigned)g.M);
+      const int i0 = (int)((unsigned)rem / (unsigned)g.n1), i1 = rem - i0 * g.n1;
+      double out[5];
+      CT_cell<HAS0, NEU>(g, u, t, i0, i1, out);
+#pragma unroll
+      for (int c = 0; c <= NC; ++c) y[(size_t)c * n + p] = out[c];
+    }
+  }
+};
+
 __global__ __launch_bounds__(kThreads) void k_apply_CT(Geom g, const double* __restrict__ u,
                                                        double* __restrict__ y) {
-  const long long n = g.n;
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-       p += (long long)gridDim.x * blockDim.x) {
-    const int t = (int)(p / g.M);
-    const int rem = (int)(p - (long long)t * g.M);
-    const int i0 = rem / g.n1, i1 = rem - i0 * g.n1;
-    double out[5];
-    CT_cell(g, u, t, i0, i1, out);
-    for (int c = 0; c <= g.ncomp; ++c) y[(size_t)c * n + p] = out[c];
-  }
+  geom_dispatch<ApplyCT>(g, g, u, y);
 }
 
 // (A u)_t = K g_t + ((1 + [t>=1]) u_t - s_t)/dt^2 with
@@ -308,17 +351,20 @@ __device__ void aat_body(const AatArgs& a, int bid, int nb) {
 // root of h'(m) = -a/(2(m+tau)^2) + (1 + 1/tau) m + V - mbar/tau by Newton from
 // max(0, (mbar - tau V)/(1 + tau)) while the iterate still increases (<= 64);
 // w = m/(m + tau) w~.
-__device__ __forceinline__ double prox_cell(double mbar, double* w, int ncomp, double V,
-                                            double tau) {
+// NC: flux components (2d).
+template <int NC>
+__device__ __forceinline__ double prox_cell(double mbar, double* w, double V, double tau) {
   double a = 0.0;
-  for (int c = 0; c < ncomp; ++c) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
     double v = w[c];
     v = (c & 1) ? fmin(v, 0.0) : fmax(v, 0.0);
     w[c] = v;
     a += v * v;
   }
   if (2.0 * tau * tau * V - 2.0 * tau * mbar - a >= 0.0) {
-    for (int c = 0; c < ncomp; ++c) w[c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) w[c] = 0.0;
     return 0.0;
   }
   double m = fmax(0.0, (mbar - tau * V) / (1.0 + tau));
@@ -332,7 +378,8 @@ __device__ __forceinline__ double prox_cell(double mbar, double* w, int ncomp, d
     m = mn;
   }
   const double f = m / (m + tau);
-  for (int c = 0; c < ncomp; ++c) w[c] *= f;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) w[c] *= f;
   return m;
 }
 
@@ -342,10 +389,11 @@ __global__ __launch_bounds__(kThreads) void k_prox(Geom g, const double* __restr
   const long long n = g.n;
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
        p += (long long)gridDim.x * blockDim.x) {
-    const int rem = (int)(p % g.M);
+    const int rem = (int)((unsigned)p % (unsigned)g.M);  // n < 2^31
     double w[4];
     for (int c = 0; c < g.ncomp; ++c) w[c] = v[(size_t)(c + 1) * n + p];
-    const double m = prox_cell(v[p], w, g.ncomp, Vpot[rem], tau);
+    const double m = g.has0 ? prox_cell<4>(v[p], w, Vpot[rem], tau)
+                            : prox_cell<2>(v[p], w, Vpot[rem], tau);
     y[p] = m;
     for (int c = 0; c < g.ncomp; ++c) y[(size_t)(c + 1) * n + p] = w[c];
   }
@@ -354,59 +402,76 @@ __global__ __launch_bounds__(kThreads) void k_prox(Geom g, const double* __restr
 // One CP iteration after the projection solve:
 //   xi' = Cr^T u;  y' = prox_{tau phi}(y - tau xi');  ybar = y' + theta (y' - y);
 // partial ||m' - m||^2 reduced into the device scalar S_DM.
+template <bool HAS0, bool NEU>
+struct BackprojCells {
+  __device__ static void run(const BackprojArgs& a, int bid, int nb, double tau, double theta,
+                             double sig_next, double& acc) {
+    constexpr int NC = HAS0 ? 4 : 2;
+    const Geom& g = a.g;
+    const double* __restrict__ u = a.u;
+    double* __restrict__ xi = a.xi;
+    double* __restrict__ y = a.y;
+    double* __restrict__ ybar = a.ybar;
+    const double* __restrict__ Vpot = a.V;
+    double* __restrict__ vout = a.vout;
+    double* __restrict__ zout = a.zout;
+    const long long n = g.n;
+    for (long long p = (long long)bid * blockDim.x + threadIdx.x; p < n;
+         p += (long long)nb * blockDim.x) {
+      // n < 2^31 (checked by the plan): 32-bit index arithmetic
+      const unsigned pu = (unsigned)p;
+      const int t = (int)(pu / (unsigned)g.M);
+      const int rem = (int)(pu - (unsigned)t * (unsigned)g.M);
+      const int i0 = (int)((unsigned)rem / (unsigned)g.n1), i1 = rem - i0 * g.n1;
+      double x[5], yo[5], w[4];
+      CT_cell<HAS0, NEU>(g, u, t, i0, i1, x);
+#pragma unroll
+      for (int c = 0; c <= NC; ++c) yo[c] = y[(size_t)c * n + p];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) w[c] = yo[1 + c] - tau * x[1 + c];
+      const double mbar = yo[0] - tau * x[0];
+      if (vout) {
+        vout[p] = mbar;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) vout[(size_t)(c + 1) * n + p] = w[c];
+      }
+      const double m = prox_cell<NC>(mbar, w, Vpot[rem], tau);
+      // streaming stores: the new state is read again only by the next step
+      const double mb = m + theta * (m - yo[0]);
+      __builtin_nontemporal_store(m, &y[p]);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) __builtin_nontemporal_store(w[c], &y[(size_t)(c + 1) * n + p]);
+      if (zout) {
+        // one rounding (fma), as where the right-hand side forms z from xi, ybar
+        __builtin_nontemporal_store(__builtin_fma(sig_next, mb, x[0]), &zout[p]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const double wb = w[c] + theta * (w[c] - yo[1 + c]);
+          __builtin_nontemporal_store(__builtin_fma(sig_next, wb, x[1 + c]),
+                                      &zout[(size_t)(c + 1) * n + p]);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c <= NC; ++c) __builtin_nontemporal_store(x[c], &xi[(size_t)c * n + p]);
+        __builtin_nontemporal_store(mb, &ybar[p]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          __builtin_nontemporal_store(w[c] + theta * (w[c] - yo[1 + c]),
+                                      &ybar[(size_t)(c + 1) * n + p]);
+      }
+      const double dm = m - yo[0];
+      acc += dm * dm;
+    }
+  }
+};
+
 __device__ void backproj_body(const BackprojArgs& a, int bid, int nb) {
-  const Geom g = a.g;
-  const double* __restrict__ u = a.u;
-  double* __restrict__ xi = a.xi;
-  double* __restrict__ y = a.y;
-  double* __restrict__ ybar = a.ybar;
-  const double* __restrict__ Vpot = a.V;
-  double* __restrict__ vout = a.vout;
   const double tau = a.tau_dev ? *a.tau_dev : a.tau;
   const double theta = a.theta_dev ? *a.theta_dev : a.theta;
-  double* __restrict__ zout = a.zout;
-  const double sig_next = zout ? (a.sigma_dev ? *a.sigma_dev : a.sigma) / theta : 0.0;
-  if (a.zflag && bid == 0 && threadIdx.x == 0) *a.zflag = zout ? 1.0 : 0.0;
-  const long long n = g.n;
+  const double sig_next = a.zout ? (a.sigma_dev ? *a.sigma_dev : a.sigma) / theta : 0.0;
+  if (a.zflag && bid == 0 && threadIdx.x == 0) *a.zflag = a.zout ? 1.0 : 0.0;
   double acc[1] = {0.0};
-  for (long long p = (long long)bid * blockDim.x + threadIdx.x; p < n;
-       p += (long long)nb * blockDim.x) {
-    const int t = (int)(p / g.M);
-    const int rem = (int)(p - (long long)t * g.M);
-    const int i0 = rem / g.n1, i1 = rem - i0 * g.n1;
-    double x[5], yo[5], w[4];
-    CT_cell(g, u, t, i0, i1, x);
-    for (int c = 0; c <= g.ncomp; ++c) yo[c] = y[(size_t)c * n + p];
-    for (int c = 0; c < g.ncomp; ++c) w[c] = yo[1 + c] - tau * x[1 + c];
-    const double mbar = yo[0] - tau * x[0];
-    if (vout) {
-      vout[p] = mbar;
-      for (int c = 0; c < g.ncomp; ++c) vout[(size_t)(c + 1) * n + p] = w[c];
-    }
-    const double m = prox_cell(mbar, w, g.ncomp, Vpot[rem], tau);
-    // streaming stores: the new state is read again only by the next step
-    const double mb = m + theta * (m - yo[0]);
-    __builtin_nontemporal_store(m, &y[p]);
-    for (int c = 0; c < g.ncomp; ++c) __builtin_nontemporal_store(w[c], &y[(size_t)(c + 1) * n + p]);
-    if (zout) {
-      // one rounding (fma), as where the right-hand side forms z from xi, ybar
-      __builtin_nontemporal_store(__builtin_fma(sig_next, mb, x[0]), &zout[p]);
-      for (int c = 0; c < g.ncomp; ++c) {
-        const double wb = w[c] + theta * (w[c] - yo[1 + c]);
-        __builtin_nontemporal_store(__builtin_fma(sig_next, wb, x[1 + c]),
-                                    &zout[(size_t)(c + 1) * n + p]);
-      }
-    } else {
-      for (int c = 0; c <= g.ncomp; ++c)
-        __builtin_nontemporal_store(x[c], &xi[(size_t)c * n + p]);
-      __builtin_nontemporal_store(mb, &ybar[p]);
-      for (int c = 0; c < g.ncomp; ++c)
-        __builtin_nontemporal_store(w[c] + theta * (w[c] - yo[1 + c]),
-                                    &ybar[(size_t)(c + 1) * n + p]);
-    }
-    const double dm = m - yo[0];
-    acc[0] += dm * dm;
-  }
+  geom_dispatch<BackprojCells>(a.g, a, bid, nb, tau, theta, sig_next, acc[0]);
   reduce_store<1>(acc, a.rb, T_DM, bid);
 }
 
@@ -417,7 +482,8 @@ __global__ __launch_bounds__(kThreads) void k_backproj_prox(BackprojArgs a) {
 __global__ __launch_bounds__(kThreads) void k_backproj_prox_batch(const BackprojArgs* A,
                                                                   const int* off, int ninst) {
   const int i = batch_instance(off, ninst, blockIdx.x);
-  backproj_body(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
+  const BackprojArgs a = A[i];
+  backproj_body(a, blockIdx.x - off[i], off[i + 1] - off[i]);
 }
 
 template <bool HASBAR>
@@ -428,7 +494,8 @@ __global__ __launch_bounds__(kThreads) void k_rhs(RhsArgs a) {
 __global__ __launch_bounds__(kThreads) void k_rhs_batch(const RhsArgs* A, const int* off,
                                                         int ninst) {
   const int i = batch_instance(off, ninst, blockIdx.x);
-  rhs_body<true>(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
+  const RhsArgs a = A[i];  // one copy of the instance's arguments for every specialisation
+  rhs_body<true>(a, blockIdx.x - off[i], off[i + 1] - off[i]);
 }
 
 template <bool HAS0, bool FUSE, int BIG>
@@ -436,11 +503,16 @@ __global__ __launch_bounds__((Tile<HAS0, BIG>::NT)) void k_AAt_tile(AatArgs a) {
   aat_body<HAS0, FUSE, BIG>(a, blockIdx.x, gridDim.x);
 }
 
+// Batched launches use the default tile (32 rows for d = 2): one block size
+// for every instance.
+constexpr int kBatchBig = 1;
+static_assert(kBatchBig == Tune{}.aat_big, "batched and single-plan default A tiles differ");
+
 template <bool HAS0>
-__global__ __launch_bounds__(kThreads) void k_AAt_batch(const AatArgs* A, const int* off,
-                                                        int ninst) {
+__global__ __launch_bounds__((Tile<HAS0, HAS0 ? kBatchBig : 0>::NT)) void k_AAt_batch(
+    const AatArgs* A, const int* off, int ninst) {
   const int i = batch_instance(off, ninst, blockIdx.x);
-  aat_body<HAS0, true>(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
+  aat_body<HAS0, true, HAS0 ? kBatchBig : 0>(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
 }
 
 // One thread per node up to `cap` blocks (grid-stride beyond that).
@@ -581,7 +653,7 @@ void launch_backproj_prox(const Plan& P, const double* u, double* xi, double* y,
 AatArgs aat_args(const Plan& P, const double* z, const double* pold, double* pnew, double* q,
                  bool first, const double* done, int* grid) {
   int tc;
-  *grid = P.g.has0 ? aat_shape<true>(P, &tc) : aat_shape<false>(P, &tc);
+  *grid = P.g.has0 ? aat_shape<true, kBatchBig>(P, &tc) : aat_shape<false>(P, &tc);
   // nrz is filled in once the inverse time GEMM's grid is known
   return AatArgs{P.g, z, pold, pnew, q, P.red, tc, first ? 1 : 0, 1, done, 0,
                  pcg_flexible(P) ? 1 : 0};
@@ -590,9 +662,11 @@ AatArgs aat_args(const Plan& P, const double* z, const double* pold, double* pne
 void launch_aat_batch(bool has0, const AatArgs* A, const int* off, int ninst, int total,
                       hipStream_t s) {
   if (has0)
-    hipLaunchKernelGGL(k_AAt_batch<true>, dim3(total), dim3(kThreads), 0, s, A, off, ninst);
+    hipLaunchKernelGGL(k_AAt_batch<true>, dim3(total), dim3(Tile<true, kBatchBig>::NT), 0, s, A,
+                       off, ninst);
   else
-    hipLaunchKernelGGL(k_AAt_batch<false>, dim3(total), dim3(kThreads), 0, s, A, off, ninst);
+    hipLaunchKernelGGL(k_AAt_batch<false>, dim3(total), dim3(Tile<false, 0>::NT), 0, s, A, off,
+                       ninst);
 }
 
 void launch_rhs_batch(const RhsArgs* A, const int* off, int ninst, int total, hipStream_t s) {

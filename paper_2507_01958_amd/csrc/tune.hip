@@ -122,11 +122,11 @@ int time_unit(Plan& P, int unit, hipEvent_t a, hipEvent_t b, int reps, int trial
 }  // namespace
 
 // Launch shapes the batched kernels support: the blocked time GEMM with
-// 4-wave blocks and one column-block count for both directions, 256-thread
-// A-kernel blocks.
+// 4-wave blocks and one column-block count for both directions, the default
+// A-kernel tile.
 void batch_shape(Tune& t) {
   t.tgemm_pers = 0;
-  t.aat_big = 0;
+  t.aat_big = Tune{}.aat_big;
   t.lp_waves = t.lp_waves_i = 4;
   t.lp_cb_i = t.lp_cb;
 }

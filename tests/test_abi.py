@@ -51,6 +51,10 @@ def test_version_and_error_without_gpu():
     assert lib.mfg_plan(ctypes.byref(pb), None, None, None, ctypes.byref(h)) == 2
     pb = mfg.make_problem(2, 8, 8, 4, "periodic", 0.1, 5e-4, qprime=3.0)
     assert lib.mfg_plan(ctypes.byref(pb), None, None, None, ctypes.byref(h)) == 2
+    # cells of an n-vector are indexed with 32-bit arithmetic: n < 2^31
+    pb = mfg.make_problem(2, 1024, 1024, 2048, "periodic", 0.1, 5e-4)
+    assert lib.mfg_plan(ctypes.byref(pb), None, None, None, ctypes.byref(h)) == 2
+    assert b"grid too large" in lib.mfg_last_error()
     pb = mfg.make_problem(2, 8, 8, 4, "periodic", -1.0, 5e-4)
     assert lib.mfg_plan(ctypes.byref(pb), None, None, None, ctypes.byref(h)) == 1
     pb = mfg.make_problem(2, 8, 8, 4, "periodic", 0.1, 5e-4, l=3)
