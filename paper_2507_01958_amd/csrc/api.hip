@@ -414,7 +414,7 @@ static int read_scalars(Plan& P) {
 
 // PCG from x = 0 (flexible form where pcg_flexible says so). Iterations are
 // launched in chunks without a host round trip: every kernel of an iteration
-// tests the device `done` flag (set by the r.r finisher on convergence,
+// tests the device `done` flag (set by the r.r stopping test on convergence,
 // breakdown or a non-finite value) and returns at once when it is set, so
 // launching past convergence only costs launch latency. The first chunk is as
 // long as the previous solve on this plan; later ones are single iterations.
@@ -691,24 +691,41 @@ int mfg_cp_solve(mfg_plan_t plan, mfg_state_t* st, int n_iter, double pcg_rtol, 
     return fail(MFG_ERR_INVALID_ARG, "bad iteration arguments");
   if (!(st->sigma > 0.0) || !(st->tau > 0.0)) return fail(MFG_ERR_INVALID_ARG, "bad step sizes");
   mfg::Plan& P = plan->P;
-  int final_rc = MFG_OK;
+  // ||m' - m||^2 of each step is copied to pinned host memory in stream order
+  // (no host wait between steps) and read once at the end
+  double* dm_host = nullptr;
+  if (stats && stats->dm && n_iter > 0 &&
+      hipHostMalloc(reinterpret_cast<void**>(&dm_host), (size_t)n_iter * sizeof(double)) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MFG_ERR_OOM, "pinned statistics buffer");
+  }
+  int final_rc = MFG_OK, rc = MFG_OK;
   for (int it = 0; it < n_iter; ++it) {
     int its = 0;
     double rel = 0.0;
-    int rc = mfg::cp_step(P, st, pcg_rtol, pcg_maxit, &its, &rel, nullptr, it > 0,
-                          it + 1 < n_iter);
+    rc = mfg::cp_step(P, st, pcg_rtol, pcg_maxit, &its, &rel, nullptr, it > 0, it + 1 < n_iter);
     if (rc == MFG_ERR_NOT_CONVERGED) final_rc = rc;
-    else if (rc) return rc;
+    else if (rc) break;
+    rc = MFG_OK;
     if (stats) {
       if (stats->pcg_iters) stats->pcg_iters[it] = its;
       if (stats->pcg_relres) stats->pcg_relres[it] = rel;
-      if (stats->dm) {
-        int r2 = mfg::read_scalars(P);
-        if (r2) return r2;
-        stats->dm[it] = std::sqrt(P.host_scal[mfg::S_DM]);
+      if (dm_host && hipMemcpyAsync(dm_host + it, P.red.scal + mfg::S_DM, sizeof(double),
+                                    hipMemcpyDeviceToHost, P.stream) != hipSuccess) {
+        rc = fail(MFG_ERR_HIP, "statistics copy failed");
+        break;
       }
     }
   }
+  if (dm_host) {
+    if (hipStreamSynchronize(P.stream) != hipSuccess && !rc)
+      rc = fail(MFG_ERR_HIP, "stream synchronisation failed");
+    if (!rc)
+      for (int it = 0; it < n_iter; ++it) stats->dm[it] = std::sqrt(dm_host[it]);
+    (void)hipHostFree(dm_host);
+  }
+  if (rc) return rc;
   if (final_rc) return fail(final_rc, "some PCG solve reached maxit");
   return MFG_OK;
 }

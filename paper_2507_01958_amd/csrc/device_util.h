@@ -23,6 +23,16 @@ __device__ __forceinline__ int nbr(int p, int n, int neumann) {
   return p < 0 ? p + n : p;
 }
 
+// nbr for a tile row or column p >= -2 whose value is needed only when
+// p <= n + 1 (two-node halo of a tile that may run past the end of the axis):
+// exact there, some valid index beyond (no division). Needs n >= 2.
+__device__ __forceinline__ int nbr_tile(int p, int n, int neumann) {
+  if (p < 0) return neumann ? -1 - p : p + n;
+  if (p < n) return p;
+  if (p >= n + 2) return 0;
+  return neumann ? 2 * n - 1 - p : p - n;
+}
+
 // nbr for a direct neighbour of a node, p in [-1, n] (no division).
 __device__ __forceinline__ int nbr1(int p, int n, int neumann) {
   if (p < 0) return neumann ? 0 : n - 1;

@@ -272,8 +272,8 @@ __device__ void aat_body(const AatArgs& a, int bid, int nb) {
       rp[e] = 0.0;
       if (idx < NS && t >= 0 && t < g.nt) {
         const int ii = idx / C::SJ - C::HI, jj = idx % C::SJ - 2;
-        const int gi = HAS0 ? nbr(i0 + ii, g.n0, g.neumann) : 0;
-        const int gj = nbr(j0 + jj, g.n1, g.neumann);
+        const int gi = HAS0 ? nbr_tile(i0 + ii, g.n0, g.neumann) : 0;
+        const int gj = nbr_tile(j0 + jj, g.n1, g.neumann);
         const size_t o = (size_t)t * g.M + (size_t)gi * g.n1 + gj;
         rz[e] = src[o];
         if (FUSE && !first) rp[e] = pold[o];
