@@ -418,11 +418,13 @@ static int read_scalars(Plan& P) {
 // breakdown or a non-finite value) and returns at once when it is set, so
 // launching past convergence only costs launch latency. The first chunk is as
 // long as the previous solve on this plan; later ones are single iterations.
+// r_ready: the start (r = b, b.b, status reset) was already done by the
+// kernel that formed b (b is then not needed).
 static int run_pcg(Plan& P, const double* b, double* x, double rtol, int maxit, int* iters_out,
-                   double* relres_rec, double* relres_true) {
+                   double* relres_rec, double* relres_true, bool r_ready = false) {
   hipStream_t s = P.stream;
   P.pcg_done = P.red.scal + S_DONE;
-  launch_pcg_init(P, b, x, P.r, rtol, s);
+  if (!r_ready) launch_pcg_init(P, b, P.r, rtol, s);
   launch_precond(P, P.r, P.z, true, nullptr, s);
   double* pold = P.p2;
   double* pnew = P.p;
@@ -433,7 +435,7 @@ static int run_pcg(Plan& P, const double* b, double* x, double rtol, int maxit, 
     for (int j = 0; j < todo; ++j) {
       ++k;
       launch_pdir_AAt(P, P.z, pold, pnew, P.q, k == 1, s);
-      launch_update_precond(P, x, P.r, pnew, P.q, P.z, s);
+      launch_update_precond(P, x, P.r, pnew, P.q, P.z, k == 1, s);
       std::swap(pold, pnew);
     }
     const hipError_t le = hipGetLastError();
@@ -455,6 +457,8 @@ static int run_pcg(Plan& P, const double* b, double* x, double rtol, int maxit, 
   const bool conv = P.host_scal[S_DONE] != 0.0;
   const int its = (int)P.host_scal[S_ITS];
   const double bb = P.host_scal[S_BB];
+  // b = 0: done before the first update, which would have written x
+  if (conv && its == 0) launch_fill(x, P.g.n, 0.0, s);
   P.last_pcg_its = its;
   if (iters_out) *iters_out = its;
   if (relres_rec) *relres_rec = (bb > 0.0) ? std::sqrt(P.host_scal[S_RR] / bb) : 0.0;
@@ -479,8 +483,9 @@ static int run_pcg(Plan& P, const double* b, double* x, double rtol, int maxit, 
 static int cp_step(Plan& P, mfg_state_t* st, double rtol, int maxit, int* its, double* rel,
                    double* vout, bool z_in = false, bool z_out = false) {
   hipStream_t s = P.stream;
-  launch_rhs(P, st->xi, st->ybar, st->sigma, P.m0, P.b, s, z_in ? P.zn : nullptr);
-  int rc = run_pcg(P, P.b, P.u, rtol, maxit, its, rel, nullptr);
+  // the right-hand side goes straight into the PCG residual and starts the solve
+  launch_rhs(P, st->xi, st->ybar, st->sigma, P.m0, P.r, s, z_in ? P.zn : nullptr, rtol);
+  int rc = run_pcg(P, nullptr, P.u, rtol, maxit, its, rel, nullptr, true);
   if (rc && rc != MFG_ERR_NOT_CONVERGED) return rc;
   const double theta = 1.0 / std::sqrt(1.0 + 2.0 * P.gamma * st->tau);
   launch_backproj_prox(P, P.u, st->xi, st->y, st->ybar, st->tau, theta, s, vout,

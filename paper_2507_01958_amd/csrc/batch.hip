@@ -71,8 +71,7 @@ struct Batch {
   double* sched = nullptr;
   int sched_cap = 0;
   std::vector<GemmGroup> groups;
-  Phase<InitArgs> init;
-  Phase<UpdArgs> upd_odd, upd_even;
+  Phase<UpdArgs> upd_first, upd_odd, upd_even;
   Phase<AatArgs> aat_first, aat_odd, aat_even;
   std::vector<SpatialGroup> rows;
   std::vector<ColsGroup> cols;
@@ -150,10 +149,9 @@ const double* done_of(Batch& B, int i) { return B.scal_all + (size_t)i * S_COUNT
 // Build the argument arrays of the PCG phases (state independent).
 int build_pcg_phases(Batch& B) {
   const int n = B.count;
-  std::vector<InitArgs> init;
-  std::vector<UpdArgs> uo, ue;
+  std::vector<UpdArgs> u0, uo, ue;
   std::vector<AatArgs> af, ao, ae;
-  std::vector<int> b_init, b_upd, b_aat;
+  std::vector<int> b_upd, b_aat;
   std::vector<FinishArgs> fbb;
   // spatial launches grouped by size class
   std::vector<int> rcls(n), ccls(n);
@@ -165,13 +163,13 @@ int build_pcg_phases(Batch& B) {
     Plan& P = plan_of(B, i);
     const double* done = done_of(B, i);
     float* tmp = reinterpret_cast<float*>(P.tmp);
-    init.push_back(pcg_init_args(P, P.b, P.u, P.r));
-    b_init.push_back(pcg_init_grid(P));
-    UpdArgs u1 = update_args(P, P.u, P.r, P.p, P.q);   // odd k: p_new = p
-    UpdArgs u2 = update_args(P, P.u, P.r, P.p2, P.q);  // even k: p_new = p2
+    UpdArgs u1 = update_args(P, P.u, P.r, P.p, P.q, false);   // odd k: p_new = p
+    UpdArgs u2 = update_args(P, P.u, P.r, P.p2, P.q, false);  // even k: p_new = p2
     u1.done = u2.done = done;
     uo.push_back(u1);
     ue.push_back(u2);
+    u1.first = 1;  // k = 1: x = alpha p
+    u0.push_back(u1);
     b_upd.push_back(update_grid(P));
     int g;
     af.push_back(aat_args(P, P.z, P.p2, P.p, P.q, true, done, &g));
@@ -181,12 +179,12 @@ int build_pcg_phases(Batch& B) {
     rcls[i] = batch_rows_args(P, tmp, 0, done, &rf[i], &b_rows[i], &rshm[i]);
     batch_rows_args(P, tmp, 1, done, &ri[i], &b_rows[i], &rshm[i]);
     ccls[i] = batch_cols_args(P, tmp, done, &cl[i], &b_cols[i], &cshm[i]);
-    uo.back().npq = ue.back().npq = g;
-    fbb.push_back(finish_args(P, T_BB, pcg_init_grid(P), OP_BB));
+    u0.back().npq = uo.back().npq = ue.back().npq = g;
+    // b.b partials come from the right-hand side kernel, which starts the solve
+    fbb.push_back(finish_args(P, T_BB, rhs_grid(P), OP_BB));
   }
   int rc;
-  if ((rc = upload_phase(B, init, b_init, B.init)) || (rc = upload_finish(B, fbb, &B.f_bb)))
-    return rc;
+  if ((rc = upload_finish(B, fbb, &B.f_bb))) return rc;
   {
     std::vector<int> classes(rcls);
     std::sort(classes.begin(), classes.end());
@@ -265,10 +263,11 @@ int build_pcg_phases(Batch& B) {
   }
   // the update and the A kernel sum the inverse GEMM's r.z partials themselves
   for (int i = 0; i < n; ++i) {
-    uo[i].nrz = ue[i].nrz = gemm_grid[i];
+    u0[i].nrz = uo[i].nrz = ue[i].nrz = gemm_grid[i];
     af[i].nrz = ao[i].nrz = ae[i].nrz = gemm_grid[i];
   }
-  if ((rc = upload_phase(B, uo, b_upd, B.upd_odd)) || (rc = upload_phase(B, ue, b_upd, B.upd_even)) ||
+  if ((rc = upload_phase(B, u0, b_upd, B.upd_first)) ||
+      (rc = upload_phase(B, uo, b_upd, B.upd_odd)) || (rc = upload_phase(B, ue, b_upd, B.upd_even)) ||
       (rc = upload_phase(B, af, b_aat, B.aat_first)) ||
       (rc = upload_phase(B, ao, b_aat, B.aat_odd)) || (rc = upload_phase(B, ae, b_aat, B.aat_even)))
     return rc;
@@ -285,7 +284,11 @@ int build_state_phases(Batch& B, mfg_state_t* st) {
     Plan& P = plan_of(B, i);
     const double* S = B.scal_all + (size_t)i * S_COUNT;
     double* Sw = B.scal_all + (size_t)i * S_COUNT;
-    rh.push_back(rhs_args(P, st[i].xi, st[i].ybar, 0.0, S + S_SIGMA, P.b, P.zn, S + S_ZMODE));
+    // the right-hand side goes straight into the PCG residual and starts the solve
+    RhsArgs ra = rhs_args(P, st[i].xi, st[i].ybar, 0.0, S + S_SIGMA, P.r, P.zn, S + S_ZMODE);
+    ra.init = 1;
+    ra.tol2_dev = B.tol2 + i;
+    rh.push_back(ra);
     b_rhs.push_back(rhs_grid(P));
     BackprojArgs a = backproj_args(P, P.u, st[i].xi, st[i].y, st[i].ybar, 0.0, 0.0, S + S_TAU,
                                    S + S_THETA, nullptr);
@@ -331,7 +334,7 @@ void precond_phase(Batch& B, bool init, hipStream_t s) {
 void pcg_iteration(Batch& B, int k, hipStream_t s) {
   const auto& aat = (k == 1) ? B.aat_first : ((k & 1) ? B.aat_odd : B.aat_even);
   launch_aat_batch(true, aat.args, aat.off, B.count, aat.total, s);
-  const auto& upd = (k & 1) ? B.upd_odd : B.upd_even;
+  const auto& upd = (k == 1) ? B.upd_first : ((k & 1) ? B.upd_odd : B.upd_even);
   launch_update_batch(upd.args, upd.off, B.count, upd.total, s);
   precond_phase(B, false, s);
 }
@@ -340,9 +343,7 @@ void pcg_iteration(Batch& B, int k, hipStream_t s) {
 // right-hand side, PCG initialisation and K iterations.
 void step_head(Batch& B, int K, int maxit_sched, hipStream_t s) {
   launch_cp_advance_batch(B.scal_all, S_COUNT, B.count, B.sched, maxit_sched, s);
-  launch_rhs_batch(B.rhs.args, B.rhs.off, B.count, B.rhs.total, s);
-  launch_set_scalars_batch(B.scal_all, S_COUNT, B.count, B.tol2, s);
-  launch_pcg_init_batch(B.init.args, B.init.off, B.count, B.init.total, s);
+  launch_rhs_batch(B.rhs.args, B.rhs.off, B.count, B.rhs.total, s);  // also starts the PCG
   launch_finish_batch(B.f_bb, B.count, s);
   precond_phase(B, true, s);
   for (int k = 1; k <= K; ++k) pcg_iteration(B, k, s);
@@ -542,6 +543,8 @@ int batch_cp_solve(Batch& B, mfg_state_t* st, int n_iter, double rtol, int maxit
       maxits = std::max(maxits, its);
       if (S[S_DONE] == 0.0) final_rc = MFG_ERR_NOT_CONVERGED;
       if (pcg_iters) pcg_iters[(size_t)it * n + i] = its;
+      // b = 0: done before the first update, which would have written u
+      if (S[S_DONE] != 0.0 && its == 0) launch_fill(plan_of(B, i).u, plan_of(B, i).g.n, 0.0, s);
     }
     if (!B.exec && B.graph_k == 0) B.graph_k = std::min(std::max(maxits + 1, 2), maxit);
     const auto& bp = (it + 1 < n_iter) ? B.bp_mid : B.bp;

@@ -23,7 +23,6 @@ struct SolveCtx {
 struct InitArgs {
   long long n;
   const double* b;
-  double* x;
   double* r;
   RedBuf rb;
 };
@@ -39,6 +38,7 @@ struct UpdArgs {
   RedBuf rb;
   const double* done;
   int npq, nrz;
+  int first;  // first iteration: x = alpha p (x is not read; the solve starts at 0)
 };
 
 struct FinishArgs {
@@ -65,6 +65,9 @@ struct AatArgs {
 // zin (optional): z = xi + sigma ybar as written by the previous step's
 // back-projection, read in place of xi and ybar; with zmode_dev set (batched
 // runs) only while *zmode_dev != 0.
+// init (PCG start fused into the right-hand side): b is the PCG residual r
+// (the solve starts at x = 0), block partials of b.b go to the T_BB site and
+// block 0 resets the PCG status with tol2 = rtol^2 (by value or from tol2_dev).
 struct RhsArgs {
   Geom g;
   const double* xi;
@@ -75,6 +78,10 @@ struct RhsArgs {
   double* b;
   const double* zin;
   const double* zmode_dev;
+  int init;
+  RedBuf rb;
+  double tol2;
+  const double* tol2_dev;
 };
 
 struct BackprojArgs {
@@ -148,9 +155,10 @@ __device__ __forceinline__ int batch_instance(const int* off, int ninst, int b) 
 
 // ---- host-side builders and batched launchers (defined next to each kernel) ----
 struct Plan;
-InitArgs pcg_init_args(const Plan& P, const double* b, double* x, double* r);
+InitArgs pcg_init_args(const Plan& P, const double* b, double* r);
 int pcg_init_grid(const Plan& P);
-UpdArgs update_args(const Plan& P, double* x, double* r, const double* p, const double* q);
+UpdArgs update_args(const Plan& P, double* x, double* r, const double* p, const double* q,
+                    bool first);
 int update_grid(const Plan& P);
 FinishArgs finish_args(const Plan& P, int site, int nblocks, int op);
 RhsArgs rhs_args(const Plan& P, const double* xi, const double* ybar, double sigma,
@@ -173,12 +181,8 @@ GemmArgs<TX, TY> batch_gemm_args(const Plan& P, int mode, const TX* X, TY* Y, in
                                  const double* r, const double* q, const double* done,
                                  int* blocks);
 
-void launch_pcg_init_batch(const InitArgs* A, const int* off, int ninst, int total,
-                           hipStream_t s);
 void launch_update_batch(const UpdArgs* A, const int* off, int ninst, int total, hipStream_t s);
 void launch_finish_batch(const FinishArgs* F, int ninst, hipStream_t s);
-void launch_set_scalars_batch(double* scal, int stride, int ninst, const double* tol2,
-                              hipStream_t s);
 void launch_cp_advance_batch(double* scal, int stride, int ninst, const double* sched, int maxit,
                              hipStream_t s);
 void launch_aat_batch(bool has0, const AatArgs* A, const int* off, int ninst, int total,

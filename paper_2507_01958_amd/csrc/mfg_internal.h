@@ -96,9 +96,12 @@ struct Plan;
 
 // ---- launchers (each defined in its .hip file) ----
 // stencil.hip
-// zin (optional): z = xi + sigma ybar stored by the previous back-projection
+// zin (optional): z = xi + sigma ybar stored by the previous back-projection;
+// init_rtol >= 0: b is the PCG residual of x = 0 and the kernel also does the
+// PCG start (b.b, status reset with tolerance init_rtol)
 void launch_rhs(const Plan& P, const double* xi, const double* ybar, double sigma,
-                const double* m0, double* b, hipStream_t s, const double* zin = nullptr);
+                const double* m0, double* b, hipStream_t s, const double* zin = nullptr,
+                double init_rtol = -1.0);
 void launch_apply_C(const Plan& P, const double* y, double* b, hipStream_t s);
 void launch_apply_CT(const Plan& P, const double* u, double* y, hipStream_t s);
 void launch_AAt(const Plan& P, const double* u, double* q, bool reduce_pq, hipStream_t s);
@@ -111,10 +114,11 @@ void launch_backproj_prox(const Plan& P, const double* u, double* xi, double* y,
                           double tau, double theta, hipStream_t s, double* vout = nullptr,
                           double* zout = nullptr, double sigma = 0.0);
 // vec.hip
-void launch_pcg_init(const Plan& P, const double* b, double* x, double* r, double rtol,
-                     hipStream_t s);
+// r = b, b.b, PCG status reset (the solve starts at x = 0: the first update
+// writes x)
+void launch_pcg_init(const Plan& P, const double* b, double* r, double rtol, hipStream_t s);
 void launch_update(const Plan& P, double* x, double* r, const double* p, const double* q,
-                   hipStream_t s);
+                   bool first, hipStream_t s);
 void launch_residual(const Plan& P, const double* b, const double* Ax, hipStream_t s);
 void launch_finish(const Plan& P, int site, int nblocks, int op, hipStream_t s);
 void launch_fill(double* x, long long n, double v, hipStream_t s);
@@ -127,7 +131,7 @@ void launch_sum_slices(const Plan& P, const double* in, const double* in2, doubl
 void launch_axpby(long long n, double a, const double* x, double b, double* y, hipStream_t s);
 // precond.hip
 void launch_update_precond(const Plan& P, double* x, double* r, const double* p,
-                           const double* q, double* z, hipStream_t s);
+                           const double* q, double* z, bool first, hipStream_t s);
 void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
                     const double* q, hipStream_t s);
 

@@ -836,10 +836,11 @@ void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
 }
 
 // One PCG iteration's update and preconditioning: x += alpha p, r -= alpha q
-// (r.r finisher), then z = P^{-1} r with the fused r.z (and z.q) partials.
+// (r.r partials), then z = P^{-1} r (r.r stopping test first) with the fused
+// r.z (and z.q) partials.
 void launch_update_precond(const Plan& P, double* x, double* r, const double* p,
-                           const double* q, double* z, hipStream_t s) {
-  launch_update(P, x, r, p, q, s);
+                           const double* q, double* z, bool first, hipStream_t s) {
+  launch_update(P, x, r, p, q, first, s);
   launch_precond(P, r, z, true, q, s);
 }
 

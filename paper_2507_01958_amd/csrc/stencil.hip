@@ -73,7 +73,7 @@ __device__ __forceinline__ void geom_dispatch(const Geom& g, A&&... args) {
 // b = Cr (xi + sigma ybar) - sigma [t==0] m0/dt. With ybar == nullptr this is
 // b = Cr xi (apply_C). ZM: z = xi + sigma ybar read ready-made from zin.
 template <bool HASBAR, bool ZM, bool HAS0, bool NEU>
-__device__ void rhs_cells(const RhsArgs& a, int bid, int nb) {
+__device__ void rhs_cells(const RhsArgs& a, int bid, int nb, double& acc) {
   const Geom g = a.g;
   const double* __restrict__ xi = ZM ? a.zin : a.xi;
   const double* __restrict__ ybar = a.ybar;
@@ -116,6 +116,7 @@ __device__ void rhs_cells(const RhsArgs& a, int bid, int nb) {
     }
     if (HASBAR && t == 0) r -= sigma * m0[rem] * g.idt;
     b[p] = r;
+    if (HASBAR) acc += r * r;
   }
 }
 
@@ -123,18 +124,31 @@ template <bool HASBAR, bool ZM>
 struct RhsCells {
   template <bool HAS0, bool NEU>
   struct F {
-    __device__ static void run(const RhsArgs& a, int bid, int nb) {
-      rhs_cells<HASBAR, ZM, HAS0, NEU>(a, bid, nb);
+    __device__ static void run(const RhsArgs& a, int bid, int nb, double& acc) {
+      rhs_cells<HASBAR, ZM, HAS0, NEU>(a, bid, nb, acc);
     }
   };
 };
 
 template <bool HASBAR>
 __device__ void rhs_body(const RhsArgs& a, int bid, int nb) {
+  double acc[1] = {0.0};
   if (HASBAR && a.zin && (!a.zmode_dev || *a.zmode_dev != 0.0))
-    geom_dispatch<RhsCells<HASBAR, true>::template F>(a.g, a, bid, nb);
+    geom_dispatch<RhsCells<HASBAR, true>::template F>(a.g, a, bid, nb, acc[0]);
   else
-    geom_dispatch<RhsCells<HASBAR, false>::template F>(a.g, a, bid, nb);
+    geom_dispatch<RhsCells<HASBAR, false>::template F>(a.g, a, bid, nb, acc[0]);
+  if (HASBAR && a.init) {
+    // PCG start: x = 0 (written by the first update), r = b, b.b partials,
+    // status reset
+    if (bid == 0 && threadIdx.x == 0) {
+      double* S = a.rb.scal;
+      S[S_TOL2] = a.tol2_dev ? *a.tol2_dev : a.tol2;
+      S[S_BAD] = 0.0;
+      S[S_DONE] = 0.0;
+      S[S_ITS] = 0.0;
+    }
+    reduce_store<1>(acc, a.rb, T_BB, bid);
+  }
 }
 
 // Components of Cr^T u at one cell: out[0] = m-part, out[1+c] = B_c^T u_t.
@@ -584,22 +598,30 @@ void aat_launch(const Plan& P, const double* src, const double* pold, double* pn
 RhsArgs rhs_args(const Plan& P, const double* xi, const double* ybar, double sigma,
                  const double* sigma_dev, double* b, const double* zin,
                  const double* zmode_dev) {
-  return RhsArgs{P.g, xi, ybar, sigma, sigma_dev, P.m0, b, zin, zmode_dev};
+  return RhsArgs{P.g, xi, ybar, sigma, sigma_dev, P.m0, b, zin, zmode_dev, 0, P.red, 0.0, nullptr};
 }
 
-int rhs_grid(const Plan& P) { return grid_for(P.g.n, 1 << 20); }
+// (capped so that the b.b partials of a PCG start stay few)
+int rhs_grid(const Plan& P) { return grid_for(P.g.n, 4096); }
 
 void launch_rhs(const Plan& P, const double* xi, const double* ybar, double sigma,
-                const double* m0, double* b, hipStream_t s, const double* zin) {
-  ProfScope ps(P, "rhs", s);
+                const double* m0, double* b, hipStream_t s, const double* zin, double init_rtol) {
   RhsArgs a = rhs_args(P, xi, ybar, sigma, nullptr, b, zin);
   a.m0 = m0;
-  hipLaunchKernelGGL(k_rhs<true>, dim3(rhs_grid(P)), dim3(kThreads), 0, s, a);
+  a.init = init_rtol >= 0.0 ? 1 : 0;
+  a.tol2 = init_rtol * init_rtol;
+  const int grid = rhs_grid(P);
+  {
+    ProfScope ps(P, "rhs", s);
+    hipLaunchKernelGGL(k_rhs<true>, dim3(grid), dim3(kThreads), 0, s, a);
+  }
+  if (a.init) launch_finish(P, T_BB, grid, OP_BB, s);
 }
 
 void launch_apply_C(const Plan& P, const double* y, double* b, hipStream_t s) {
   ProfScope ps(P, "apply_C", s);
-  const RhsArgs a{P.g, y, nullptr, 0.0, nullptr, nullptr, b, nullptr, nullptr};
+  const RhsArgs a{P.g, y, nullptr, 0.0, nullptr, nullptr, b, nullptr, nullptr, 0, P.red, 0.0,
+                  nullptr};
   hipLaunchKernelGGL(k_rhs<false>, dim3(rhs_grid(P)), dim3(kThreads), 0, s, a);
 }
 

@@ -24,13 +24,12 @@ int grid_for(long long n) {
 
 }  // namespace
 
-// x = 0, r = b; partial b.b.
+// r = b (the residual of x = 0, which the first update writes); partial b.b.
 __device__ void pcg_init_body(const InitArgs& a, int bid, int nb) {
   double acc[1] = {0.0};
   for (long long i = (long long)bid * blockDim.x + threadIdx.x; i < a.n;
        i += (long long)nb * blockDim.x) {
     const double v = a.b[i];
-    a.x[i] = 0.0;
     a.r[i] = v;
     acc[0] += v * v;
   }
@@ -58,7 +57,8 @@ __device__ void update_body(const UpdArgs& a, int bid, int nb) {
   double acc[1] = {0.0};
   for (long long i = (long long)bid * blockDim.x + threadIdx.x; i < a.n;
        i += (long long)nb * blockDim.x) {
-    a.x[i] += alpha * a.p[i];
+    if (a.first) a.x[i] = alpha * a.p[i];
+    else a.x[i] += alpha * a.p[i];
     const double ri = a.r[i] - alpha * a.q[i];
     a.r[i] = ri;
     acc[0] += ri * ri;
@@ -173,8 +173,8 @@ void launch_finish(const Plan& P, int site, int nblocks, int op, hipStream_t s) 
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, finish_args(P, site, nblocks, op));
 }
 
-InitArgs pcg_init_args(const Plan& P, const double* b, double* x, double* r) {
-  return InitArgs{P.g.n, b, x, r, P.red};
+InitArgs pcg_init_args(const Plan& P, const double* b, double* r) {
+  return InitArgs{P.g.n, b, r, P.red};
 }
 
 int pcg_init_grid(const Plan& P) { return grid_for(P.g.n); }
@@ -183,29 +183,30 @@ void launch_set_scalars(const Plan& P, double rtol, hipStream_t s) {
   hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, P.red.scal, rtol * rtol);
 }
 
-void launch_pcg_init(const Plan& P, const double* b, double* x, double* r, double rtol,
-                     hipStream_t s) {
+void launch_pcg_init(const Plan& P, const double* b, double* r, double rtol, hipStream_t s) {
   launch_set_scalars(P, rtol, s);
   const int grid = pcg_init_grid(P);
   {
     ProfScope ps(P, "pcg_init", s);
-    hipLaunchKernelGGL(k_pcg_init, dim3(grid), dim3(kThreads), 0, s, pcg_init_args(P, b, x, r));
+    hipLaunchKernelGGL(k_pcg_init, dim3(grid), dim3(kThreads), 0, s, pcg_init_args(P, b, r));
   }
   launch_finish(P, T_BB, grid, OP_BB, s);
 }
 
-UpdArgs update_args(const Plan& P, double* x, double* r, const double* p, const double* q) {
-  return UpdArgs{P.g.n, x, r, p, q, P.red, P.pcg_done, P.pq_blocks, P.rz_blocks};
+UpdArgs update_args(const Plan& P, double* x, double* r, const double* p, const double* q,
+                    bool first) {
+  return UpdArgs{P.g.n, x, r, p, q, P.red, P.pcg_done, P.pq_blocks, P.rz_blocks, first ? 1 : 0};
 }
 
 int update_grid(const Plan& P) { return grid_for(P.g.n); }
 
 void launch_update(const Plan& P, double* x, double* r, const double* p, const double* q,
-                   hipStream_t s) {
+                   bool first, hipStream_t s) {
   const int grid = update_grid(P);
   {
     ProfScope ps(P, "update", s);
-    hipLaunchKernelGGL(k_update, dim3(grid), dim3(kThreads), 0, s, update_args(P, x, r, p, q));
+    hipLaunchKernelGGL(k_update, dim3(grid), dim3(kThreads), 0, s,
+                       update_args(P, x, r, p, q, first));
   }
   // the r.r partials are summed by the stopping test of the next
   // preconditioner application (its forward time transform)
@@ -234,12 +235,6 @@ void launch_cp_init(const Plan& P, double* xi, double* y, double* ybar, hipStrea
 // ---- batched launches (args / offsets are device arrays, see batch_args.h) ----
 namespace {
 
-__global__ __launch_bounds__(kThreads) void k_pcg_init_batch(const InitArgs* A, const int* off,
-                                                             int ninst) {
-  const int i = batch_instance(off, ninst, blockIdx.x);
-  pcg_init_body(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
-}
-
 __global__ __launch_bounds__(kThreads) void k_update_batch(const UpdArgs* A, const int* off,
                                                            int ninst) {
   const int i = batch_instance(off, ninst, blockIdx.x);
@@ -249,18 +244,6 @@ __global__ __launch_bounds__(kThreads) void k_update_batch(const UpdArgs* A, con
 // one block per instance
 __global__ __launch_bounds__(256) void k_finish_batch(const FinishArgs* F) {
   finish_body(F[blockIdx.x]);
-}
-
-// Per instance i (scalar block at scal + i * stride): reset the PCG status.
-__global__ __launch_bounds__(64) void k_set_scalars_batch(double* scal, int stride, int ninst,
-                                                          const double* tol2) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ninst) return;
-  double* S = scal + (size_t)i * stride;
-  S[S_TOL2] = tol2[i];
-  S[S_BAD] = 0.0;
-  S[S_DONE] = 0.0;
-  S[S_ITS] = 0.0;
 }
 
 // Per instance: load the step sizes of CP iteration S_CPIT from the schedule
@@ -281,23 +264,12 @@ __global__ __launch_bounds__(64) void k_cp_advance_batch(double* scal, int strid
 
 }  // namespace
 
-void launch_pcg_init_batch(const InitArgs* A, const int* off, int ninst, int total,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_init_batch, dim3(total), dim3(kThreads), 0, s, A, off, ninst);
-}
-
 void launch_update_batch(const UpdArgs* A, const int* off, int ninst, int total, hipStream_t s) {
   hipLaunchKernelGGL(k_update_batch, dim3(total), dim3(kThreads), 0, s, A, off, ninst);
 }
 
 void launch_finish_batch(const FinishArgs* F, int ninst, hipStream_t s) {
   hipLaunchKernelGGL(k_finish_batch, dim3(ninst), dim3(256), 0, s, F);
-}
-
-void launch_set_scalars_batch(double* scal, int stride, int ninst, const double* tol2,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_set_scalars_batch, dim3((ninst + 63) / 64), dim3(64), 0, s, scal, stride,
-                     ninst, tol2);
 }
 
 void launch_cp_advance_batch(double* scal, int stride, int ninst, const double* sched, int maxit,
