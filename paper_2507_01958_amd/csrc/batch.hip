@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "batch_args.h"
@@ -51,7 +52,7 @@ struct ColsGroup {
 };
 
 struct GemmGroup {
-  int ntp = 0, cb = 2;
+  int ntp = 0, cb = 2, waves = 4;
   Phase<GemmArgs<double, float>> fwd_init, fwd;  // fwd: with the r.r stopping test
   Phase<GemmArgs<float, double>> inv_init, inv_iter;
 };
@@ -224,24 +225,26 @@ int build_pcg_phases(Batch& B) {
       if ((rc = upload_phase(B, f, blocks, B.cols[c].cols, shm))) return rc;
     }
   }
-  // time GEMMs: one launch per (N_t padding class, column blocks per wave)
-  std::vector<std::pair<int, int>> classes;
-  for (int i = 0; i < n; ++i)
-    classes.emplace_back(plan_of(B, i).ntp, plan_of(B, i).tune.lp_cb == 1 ? 1 : 2);
+  // time GEMMs: one launch per (N_t padding class, column blocks per wave, waves)
+  auto shape_of = [&](int i) {
+    const Tune& t = plan_of(B, i).tune;
+    return std::make_tuple(plan_of(B, i).ntp, t.lp_cb == 1 ? 1 : 2, t.lp_waves == 8 ? 8 : 4);
+  };
+  std::vector<std::tuple<int, int, int>> classes;
+  for (int i = 0; i < n; ++i) classes.push_back(shape_of(i));
   std::sort(classes.begin(), classes.end());
   classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
   B.groups.assign(classes.size(), GemmGroup{});
   std::vector<int> gemm_grid(n, 0);
   for (size_t gi = 0; gi < classes.size(); ++gi) {
     GemmGroup& G = B.groups[gi];
-    G.ntp = classes[gi].first;
-    G.cb = classes[gi].second;
+    std::tie(G.ntp, G.cb, G.waves) = classes[gi];
     std::vector<GemmArgs<double, float>> fw0, fw;
     std::vector<GemmArgs<float, double>> i0, i1;
     std::vector<int> blocks;
     for (int i = 0; i < n; ++i) {
       Plan& P = plan_of(B, i);
-      if (P.ntp != G.ntp || (P.tune.lp_cb == 1 ? 1 : 2) != G.cb) continue;
+      if (shape_of(i) != classes[gi]) continue;
       float* tmp = reinterpret_cast<float*>(P.tmp);
       int blk;
       fw0.push_back(batch_gemm_args<double, float>(P, B.mode, P.r, tmp, DOT_NONE, nullptr,
@@ -311,8 +314,8 @@ int build_state_phases(Batch& B, mfg_state_t* st) {
 void precond_phase(Batch& B, bool init, hipStream_t s) {
   for (auto& G : B.groups) {
     const auto& ph = init ? G.fwd_init : G.fwd;
-    launch_gemm_batch<double, float>(B.mode, G.ntp, G.cb, ph.args, ph.off, ph.ninst, ph.total,
-                                     s);
+    launch_gemm_batch<double, float>(B.mode, G.ntp, G.cb, G.waves, ph.args, ph.off, ph.ninst,
+                                     ph.total, s);
   }
   for (const auto& G : B.rows)
     launch_rows_batch_f32(G.cls, G.rows_fwd.args, G.rows_fwd.off, G.rows_fwd.ninst,
@@ -325,8 +328,8 @@ void precond_phase(Batch& B, bool init, hipStream_t s) {
                           G.rows_inv.total, G.rows_inv.shm, s);
   for (auto& G : B.groups) {
     const auto& ph = init ? G.inv_init : G.inv_iter;
-    launch_gemm_batch<float, double>(B.mode, G.ntp, G.cb, ph.args, ph.off, ph.ninst, ph.total,
-                                     s);
+    launch_gemm_batch<float, double>(B.mode, G.ntp, G.cb, G.waves, ph.args, ph.off, ph.ninst,
+                                     ph.total, s);
   }
 }
 

@@ -195,7 +195,7 @@ void launch_rows_batch_f32(int cls, const void* A, const int* off, int ninst, in
 void launch_cols_batch_f32(int cls, const void* A, const int* off, int ninst, int total,
                            size_t shm, hipStream_t s);
 template <typename TX, typename TY>
-void launch_gemm_batch(int mode, int ntp, int cb, const GemmArgs<TX, TY>* A, const int* off,
-                       int ninst, int total, hipStream_t s);
+void launch_gemm_batch(int mode, int ntp, int cb, int waves, const GemmArgs<TX, TY>* A,
+                       const int* off, int ninst, int total, hipStream_t s);
 
 }  // namespace mfg

@@ -15,10 +15,10 @@ namespace mfg {
 // autotuner or the MFG_TUNE environment variable, "key=value,...").
 struct Tune {
   int f64_cb = 1;    // time GEMM (float64): 16-node column blocks per wave
-  int lp_cb = 2;     // time GEMM (low precision): column blocks per wave, forward
-  int lp_waves = 4;  // time GEMM (low precision): waves per block (4 or 8), forward
-  int lp_cb_i = 2;     // ... the same two for the inverse transform
-  int lp_waves_i = 4;
+  int lp_cb = 1;     // time GEMM (low precision): column blocks per wave, forward
+  int lp_waves = 8;  // time GEMM (low precision): waves per block (4 or 8), forward
+  int lp_cb_i = 1;     // ... the same two for the inverse transform
+  int lp_waves_i = 8;
   int rows_elems = 1024;  // row transforms: complex elements per block
   int cols_lines = 4;     // column solves: complex lines (column pairs) per block
   int tgemm_pers = 0;     // persistent time GEMM (whole V in LDS) when N_t <= 128

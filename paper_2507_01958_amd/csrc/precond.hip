@@ -390,8 +390,8 @@ __device__ void rows_fwd_reg(const RowsArgs<T>& a, int bid, C2<T>* lds) {
   for (int n1 = 0; n1 < 16; ++n1) {
     const int n = p + Sh::N2 * n1;
     const int src = dct ? dct_perm(n, N) : n;
-    v[n1].x = hasa ? data[(size_t)ra * N + src] : (T)0;
-    v[n1].y = hasb ? data[(size_t)rb * N + src] : (T)0;
+    v[n1].x = hasa ? data[(unsigned)ra * N + src] : (T)0;  // n < 2^31
+    v[n1].y = hasb ? data[(unsigned)rb * N + src] : (T)0;
   }
   fftr::fft4<T, N, -1>(v, lds + l * Sh::L, p, tw);
   __syncthreads();
@@ -415,8 +415,8 @@ __device__ void rows_fwd_reg(const RowsArgs<T>& a, int bid, C2<T>* lds) {
       oa = (T)0.5 * (c * (pp + r) + sn * (q - s));
       ob = (T)0.5 * (c * (q + s) + sn * (r - pp));
     }
-    if (hasa) data[(size_t)ra * N + k] = oa;
-    if (hasb) data[(size_t)rb * N + k] = ob;
+    if (hasa) data[(unsigned)ra * N + k] = oa;
+    if (hasb) data[(unsigned)rb * N + k] = ob;
   }
 }
 
@@ -440,10 +440,10 @@ __device__ void rows_inv_reg(const RowsArgs<T>& a, int bid, C2<T>* lds) {
   for (int m = 0; m < 16; ++m) {
     const int k = p + Sh::N2 * m;
     const int kr = k ? N - k : 0;
-    const T ca = hasa ? data[(size_t)ra * N + k] : (T)0;
-    const T cb = hasb ? data[(size_t)rb * N + k] : (T)0;
-    T ra_ = hasa ? data[(size_t)ra * N + kr] : (T)0;
-    T rb_ = hasb ? data[(size_t)rb * N + kr] : (T)0;
+    const T ca = hasa ? data[(unsigned)ra * N + k] : (T)0;  // n < 2^31
+    const T cb = hasb ? data[(unsigned)rb * N + k] : (T)0;
+    T ra_ = hasa ? data[(unsigned)ra * N + kr] : (T)0;
+    T rb_ = hasb ? data[(unsigned)rb * N + kr] : (T)0;
     if (!dct) {
       const T fa_re = (T)0.5 * (ca + ra_), fa_im = (T)0.5 * (ra_ - ca);
       const T fb_re = (T)0.5 * (cb + rb_), fb_im = (T)0.5 * (rb_ - cb);
@@ -463,8 +463,8 @@ __device__ void rows_inv_reg(const RowsArgs<T>& a, int bid, C2<T>* lds) {
   for (int m = 0; m < 16; ++m) {
     const int n = p + Sh::N2 * m;
     const int dst = dct ? dct_perm(n, N) : n;
-    if (hasa) data[(size_t)ra * N + dst] = v[m].x;
-    if (hasb) data[(size_t)rb * N + dst] = v[m].y;
+    if (hasa) data[(unsigned)ra * N + dst] = v[m].x;
+    if (hasb) data[(unsigned)rb * N + dst] = v[m].y;
   }
 }
 
@@ -524,15 +524,21 @@ __device__ void cols_reg(const ColsArgs<T>& a, int bid, int nb, C2<T>* lds) {
   T* __restrict__ slice = a.data + (size_t)t * g.M;
   const T* __restrict__ tw = tw_table<T>(a.ax);
   C2<T> v[16];
+  // 32-bit offsets within the slice (M < 2^31); the column-pair test is
+  // uniform, so each form is one straight run of loads
+  if (pair_ld) {
 #pragma unroll
-  for (int n1 = 0; n1 < 16; ++n1) {
-    const int n = p + Sh::N2 * n1;
-    const int i = dct ? dct_perm(n, N) : n;
-    const size_t o = (size_t)i * g.n1 + ja;
-    if (pair_ld) {
+    for (int n1 = 0; n1 < 16; ++n1) {
+      const int n = p + Sh::N2 * n1;
+      const unsigned o = (unsigned)(dct ? dct_perm(n, N) : n) * (unsigned)g.n1 + (unsigned)ja;
       const V2<T> w = *reinterpret_cast<const V2<T>*>(slice + o);
       v[n1] = C2<T>{w.x, w.y};
-    } else {
+    }
+  } else {
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) {
+      const int n = p + Sh::N2 * n1;
+      const unsigned o = (unsigned)(dct ? dct_perm(n, N) : n) * (unsigned)g.n1 + (unsigned)ja;
       v[n1].x = hasa ? slice[o] : (T)0;
       v[n1].y = hasb ? slice[o + 1] : (T)0;
     }
@@ -579,14 +585,18 @@ __device__ void cols_reg(const ColsArgs<T>& a, int bid, int nb, C2<T>* lds) {
   }
   __syncthreads();
   fftr::fft4<T, N, +1, true>(v, lds + l * Sh::L, p, tw);
+  if (pair_ld) {
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int n = p + Sh::N2 * m;
-    const int i = dct ? dct_perm(n, N) : n;
-    const size_t o = (size_t)i * g.n1 + ja;
-    if (pair_ld) {
+    for (int m = 0; m < 16; ++m) {
+      const int n = p + Sh::N2 * m;
+      const unsigned o = (unsigned)(dct ? dct_perm(n, N) : n) * (unsigned)g.n1 + (unsigned)ja;
       *reinterpret_cast<V2<T>*>(slice + o) = V2<T>{v[m].x, v[m].y};
-    } else {
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int n = p + Sh::N2 * m;
+      const unsigned o = (unsigned)(dct ? dct_perm(n, N) : n) * (unsigned)g.n1 + (unsigned)ja;
       if (hasa) slice[o] = v[m].x;
       if (hasb) slice[o + 1] = v[m].y;
     }
@@ -643,7 +653,8 @@ template <typename T, int N>
 __global__ __launch_bounds__(256) void k_rows_reg_batch(const RowsArgs<T>* A, const int* off,
                                                         int ninst) {
   const int i = batch_instance(off, ninst, blockIdx.x);
-  rows_reg<T, N>(A[i], blockIdx.x - off[i]);
+  const RowsArgs<T> a = A[i];
+  rows_reg<T, N>(a, blockIdx.x - off[i]);
 }
 
 template <typename T, int N>
@@ -655,7 +666,8 @@ template <typename T, int N>
 __global__ __launch_bounds__(256) void k_cols_reg_batch(const ColsArgs<T>* A, const int* off,
                                                         int ninst) {
   const int i = batch_instance(off, ninst, blockIdx.x);
-  cols_reg_entry<T, N>(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
+  const ColsArgs<T> a = A[i];
+  cols_reg_entry<T, N>(a, blockIdx.x - off[i], off[i + 1] - off[i]);
 }
 
 // Launch the row / column kernels of size class cls (0: LDS Stockham path,

@@ -331,11 +331,11 @@ __global__ __launch_bounds__(WPB * 64) void k_tgemm_lp(GemmArgs<TX, TY> a) {
   tgemm_lp_body<MODE, NTP, CB, TX, TY, WPB>(a, blockIdx.x);
 }
 
-template <int MODE, int NTP, int CB, typename TX, typename TY>
-__global__ __launch_bounds__(256) void k_tgemm_lp_batch(const GemmArgs<TX, TY>* A, const int* off,
-                                                        int ninst) {
+template <int MODE, int NTP, int CB, typename TX, typename TY, int WPB>
+__global__ __launch_bounds__(WPB * 64) void k_tgemm_lp_batch(const GemmArgs<TX, TY>* A,
+                                                             const int* off, int ninst) {
   const int i = batch_instance(off, ninst, blockIdx.x);
-  tgemm_lp_body<MODE, NTP, CB, TX, TY>(A[i], blockIdx.x - off[i]);
+  tgemm_lp_body<MODE, NTP, CB, TX, TY, WPB>(A[i], blockIdx.x - off[i]);
 }
 
 // Streaming persistent form for N_t <= 128 (NTP = N_t rounded up to 16):
@@ -717,19 +717,21 @@ template <typename TX, typename TY>
 GemmArgs<TX, TY> batch_gemm_args(const Plan& P, int mode, const TX* X, TY* Y, int dotmode,
                                  const double* r, const double* q, const double* done,
                                  int* blocks) {
+  // batched plans use one shape for both directions (the forward one)
   const int cb = P.tune.lp_cb == 1 ? 1 : 2;
-  *blocks = (P.g.M + 64 * cb - 1) / (64 * cb);
+  const int cols = 16 * (P.tune.lp_waves == 8 ? 8 : 4) * cb;
+  *blocks = (P.g.M + cols - 1) / cols;
   return GemmArgs<TX, TY>{lp_table(P, mode), X, Y, P.g.nt, P.g.M, 0, dotmode, r, q, P.red, done,
                           0};
 }
 
-template <int MODE, int CB, typename TX, typename TY>
+template <int MODE, int CB, int WPB, typename TX, typename TY>
 void lp_batch_dispatch(int ntp, const GemmArgs<TX, TY>* A, const int* off, int ninst, int total,
                        hipStream_t s) {
-#define MFG_LPB(NTPV)                                                                        \
-  case NTPV:                                                                                 \
-    hipLaunchKernelGGL((k_tgemm_lp_batch<MODE, NTPV, CB, TX, TY>), dim3(total), dim3(256), 0, \
-                       s, A, off, ninst);                                                    \
+#define MFG_LPB(NTPV)                                                                     \
+  case NTPV:                                                                              \
+    hipLaunchKernelGGL((k_tgemm_lp_batch<MODE, NTPV, CB, TX, TY, WPB>), dim3(total),     \
+                       dim3(WPB * 64), 0, s, A, off, ninst);                              \
     break;
   switch (ntp) {
     MFG_LPB(16)
@@ -740,25 +742,30 @@ void lp_batch_dispatch(int ntp, const GemmArgs<TX, TY>* A, const int* off, int n
     MFG_LPB(96)
     MFG_LPB(112)
     default:
-      hipLaunchKernelGGL((k_tgemm_lp_batch<MODE, 128, CB, TX, TY>), dim3(total), dim3(256), 0, s,
-                         A, off, ninst);
+      hipLaunchKernelGGL((k_tgemm_lp_batch<MODE, 128, CB, TX, TY, WPB>), dim3(total),
+                         dim3(WPB * 64), 0, s, A, off, ninst);
   }
 #undef MFG_LPB
 }
 
 template <int MODE, typename TX, typename TY>
-void lp_batch_cb(int ntp, int cb, const GemmArgs<TX, TY>* A, const int* off, int ninst, int total,
-                 hipStream_t s) {
-  if (cb == 1) lp_batch_dispatch<MODE, 1>(ntp, A, off, ninst, total, s);
-  else lp_batch_dispatch<MODE, 2>(ntp, A, off, ninst, total, s);
+void lp_batch_cb(int ntp, int cb, int waves, const GemmArgs<TX, TY>* A, const int* off, int ninst,
+                 int total, hipStream_t s) {
+  if (waves == 8) {
+    if (cb == 1) lp_batch_dispatch<MODE, 1, 8>(ntp, A, off, ninst, total, s);
+    else lp_batch_dispatch<MODE, 2, 8>(ntp, A, off, ninst, total, s);
+  } else {
+    if (cb == 1) lp_batch_dispatch<MODE, 1, 4>(ntp, A, off, ninst, total, s);
+    else lp_batch_dispatch<MODE, 2, 4>(ntp, A, off, ninst, total, s);
+  }
 }
 
 template <typename TX, typename TY>
-void launch_gemm_batch(int mode, int ntp, int cb, const GemmArgs<TX, TY>* A, const int* off,
-                       int ninst, int total, hipStream_t s) {
-  if (mode == GM_F32) lp_batch_cb<GM_F32>(ntp, cb, A, off, ninst, total, s);
-  else if (mode == GM_F16) lp_batch_cb<GM_F16>(ntp, cb, A, off, ninst, total, s);
-  else lp_batch_cb<GM_BF16>(ntp, cb, A, off, ninst, total, s);
+void launch_gemm_batch(int mode, int ntp, int cb, int waves, const GemmArgs<TX, TY>* A,
+                       const int* off, int ninst, int total, hipStream_t s) {
+  if (mode == GM_F32) lp_batch_cb<GM_F32>(ntp, cb, waves, A, off, ninst, total, s);
+  else if (mode == GM_F16) lp_batch_cb<GM_F16>(ntp, cb, waves, A, off, ninst, total, s);
+  else lp_batch_cb<GM_BF16>(ntp, cb, waves, A, off, ninst, total, s);
 }
 
 template GemmArgs<double, float> batch_gemm_args(const Plan&, int, const double*, float*, int,
@@ -767,9 +774,9 @@ template GemmArgs<double, float> batch_gemm_args(const Plan&, int, const double*
 template GemmArgs<float, double> batch_gemm_args(const Plan&, int, const float*, double*, int,
                                                  const double*, const double*, const double*,
                                                  int*);
-template void launch_gemm_batch(int, int, int, const GemmArgs<double, float>*, const int*, int,
-                                int, hipStream_t);
-template void launch_gemm_batch(int, int, int, const GemmArgs<float, double>*, const int*, int,
-                                int, hipStream_t);
+template void launch_gemm_batch(int, int, int, int, const GemmArgs<double, float>*, const int*,
+                                int, int, hipStream_t);
+template void launch_gemm_batch(int, int, int, int, const GemmArgs<float, double>*, const int*,
+                                int, int, hipStream_t);
 
 }  // namespace mfg

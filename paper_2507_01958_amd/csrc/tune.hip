@@ -121,13 +121,13 @@ int time_unit(Plan& P, int unit, hipEvent_t a, hipEvent_t b, int reps, int trial
 
 }  // namespace
 
-// Launch shapes the batched kernels support: the blocked time GEMM with
-// 4-wave blocks and one column-block count for both directions, the default
-// A-kernel tile.
+// Launch shapes the batched kernels support: the blocked time GEMM with one
+// shape (column blocks per wave, waves per block) for both directions, the
+// default A-kernel tile.
 void batch_shape(Tune& t) {
   t.tgemm_pers = 0;
   t.aat_big = Tune{}.aat_big;
-  t.lp_waves = t.lp_waves_i = 4;
+  t.lp_waves_i = t.lp_waves;
   t.lp_cb_i = t.lp_cb;
 }
 
@@ -188,8 +188,13 @@ int autotune(Plan& P, int effort, bool allow_pers) {
                                        {{2, 4}, {1, 4}, {2, 8}, {1, 8}})});
     params.push_back({U_PRECOND, joint(&Tune::lp_cb_i, &Tune::lp_waves_i,
                                        {{2, 4}, {1, 4}, {2, 8}, {1, 8}})});
-  } else {  // batched GEMMs: 4-wave blocks, one column-block count for both directions
-    params.push_back({U_PRECOND, joint(&Tune::lp_cb, &Tune::lp_cb_i, {{2, 2}, {1, 1}})});
+  } else {  // batched GEMMs: one shape for both directions
+    std::vector<Setting> both;
+    for (auto cw : {std::make_pair(2, 4), std::make_pair(1, 4), std::make_pair(2, 8),
+                    std::make_pair(1, 8)})
+      both.push_back(Setting{{&Tune::lp_cb, cw.first}, {&Tune::lp_waves, cw.second},
+                             {&Tune::lp_cb_i, cw.first}, {&Tune::lp_waves_i, cw.second}});
+    params.push_back({U_PRECOND, both});
   }
   if (P.ntp > 0 && allow_pers) params.push_back({U_PRECOND, single(&Tune::tgemm_pers, {0, 1})});
   params.push_back({U_PRECOND, single(&Tune::fft_reg, {1, 0})});
@@ -233,7 +238,7 @@ int autotune(Plan& P, int effort, bool allow_pers) {
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (rc) return rc;
-  if (!allow_pers) batch_shape(P.tune);  // both GEMM directions share the tuned lp_cb
+  if (!allow_pers) batch_shape(P.tune);  // both GEMM directions share the tuned shape
   store(P, P.tune);
   return MFG_OK;
 }
