@@ -45,13 +45,21 @@ def kernel_sources_hash():
     return h.hexdigest()[:16]
 
 
-def algorithmic(kernel, inst, variant):
-    """Algorithmic work of ONE launch of `kernel` on this workload: the minimal
-    HBM bytes of a fused implementation, or the flops of the float64 time GEMM
-    (matrix-core bound: 2 N_t flops per element against 16 bytes)."""
+def algorithmic(kernel, inst, variant, its=1.0, steps=1):
+    """Algorithmic work of ONE launch of `kernel` on this workload (averaged
+    over the launches of a `steps`-step CP call with `its` PCG iterations per
+    solve where the launches differ): the minimal HBM bytes of a fused
+    implementation, or the flops of the float64 time GEMM (matrix-core bound:
+    2 N_t flops per element against 16 bytes)."""
     n = inst.n
     nb = 1 + 2 * inst.d  # primal blocks
     flex = variant in ("mixed_fp16", "mixed_bf16")  # PCG form with that preconditioner
+    # the first update of a solve writes x without reading it; inside a call the
+    # right-hand side reads z = xi + sigma ybar and the back-projection writes z
+    # instead of xi and ybar, except on the call's first / last step
+    upd = (6 * its - 1) / its
+    rhs = ((steps - 1) * (nb + 1) + (2 * nb + 1)) / steps
+    bp = ((steps - 1) * (1 + 3 * nb) + (1 + 4 * nb)) / steps
     if kernel.startswith("tgemm_f64"):
         return "mfma", 2.0 * inst.nt * inst.nt * inst.M, "fp64"
     for base in ("rows_fwd", "rows_inv", "rows_solve", "cols_solve"):
@@ -61,11 +69,11 @@ def algorithmic(kernel, inst, variant):
     table = {
         "aat_fused": 4 * 8 * n,      # read z, p_old; write p_new, q
         "aat": 2 * 8 * n,
-        "update": 6 * 8 * n,         # read x, r, p, q; write x, r
-        "pcg_init": 3 * 8 * n,
+        "update": upd * 8 * n,       # read x, r, p, q; write x, r
+        "pcg_init": 2 * 8 * n,       # read b; write r
         "residual": 2 * 8 * n,
-        "rhs": (2 * nb + 1) * 8 * n,             # read xi, ybar; write b
-        "backproj_prox": (1 + 4 * nb) * 8 * n,   # read u, y; write xi, y, ybar
+        "rhs": rhs * 8 * n,          # read z (or xi, ybar); write r
+        "backproj_prox": bp * 8 * n,  # read u, y; write y, z (or y, xi, ybar)
         "cp_init": 3 * nb * 8 * n,
         "adj_prox": (4 * nb + 1) * 8 * n,        # read gy, gybar, v, gxi; write gy, gxi, gV
     }
@@ -78,13 +86,13 @@ def algorithmic(kernel, inst, variant):
     return None, None, None
 
 
-def roofline(report, inst, variant):
+def roofline(report, inst, variant, its, steps):
     """Roofline object of the dominant kernel (largest total time)."""
     cands = {k: v for k, v in report.items() if k != "finish"}
     dom = max(cands, key=lambda k: cands[k]["total_ms"])
     calls = cands[dom]["calls"]
     avg_s = cands[dom]["total_ms"] / 1e3 / calls
-    bound, work, dtype = algorithmic(dom, inst, variant)
+    bound, work, dtype = algorithmic(dom, inst, variant, its, steps)
     out = {"kernel": dom, "bound": bound, "calls": calls, "avg_us": avg_s * 1e6}
     if bound == "mfma":
         out.update(achieved=work / avg_s / 1e12, peak=PEAK_TFLOPS[dtype], unit="TFLOP/s",
@@ -371,7 +379,9 @@ def main():
         results[variant] = dict(cp_iters_per_s=cp_rate, ms_per_cp_iter=1e3 * dt / args.steps,
                                 mean_pcg_iters=float(np.mean(stats["pcg_iters"])),
                                 max_pcg_iters=int(np.max(stats["pcg_iters"])),
-                                pcg=pcg, roofline=roofline(report, inst, variant),
+                                pcg=pcg,
+                                roofline=roofline(report, inst, variant,
+                                                  float(np.mean(stats["pcg_iters"])), args.steps),
                                 kernels_us={k: round(1e3 * v["total_ms"] / v["calls"], 2)
                                             for k, v in report.items()})
         P.close()
