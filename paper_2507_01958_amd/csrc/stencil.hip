@@ -47,15 +47,19 @@ __device__ __forceinline__ double Kop(const double* __restrict__ v, const Geom& 
 }
 
 // (D^1 w)_i and (D^2 w)_i along one axis for the value accessor f(index).
+// Neumann: the terms that do not enter are loaded from a valid index and
+// dropped by a select, so no load sits behind a branch.
 template <bool NEU, class F>
 __device__ __forceinline__ double D1w(F f, int i, int n) {
   if (!NEU) return f(i) - f(i == 0 ? n - 1 : i - 1);
-  return (i <= n - 2 ? f(i) : 0.0) - (i >= 1 ? f(i - 1) : 0.0);
+  const double a = f(i <= n - 2 ? i : n - 2), b = f(i >= 1 ? i - 1 : 0);
+  return (i <= n - 2 ? a : 0.0) - (i >= 1 ? b : 0.0);
 }
 template <bool NEU, class F>
 __device__ __forceinline__ double D2w(F f, int i, int n) {
   if (!NEU) return f(i + 1 == n ? 0 : i + 1) - f(i);
-  return (i <= n - 2 ? f(i + 1) : 0.0) - (i >= 1 ? f(i) : 0.0);
+  const double a = f(i <= n - 2 ? i + 1 : n - 1), b = f(i >= 1 ? i : 0);
+  return (i <= n - 2 ? a : 0.0) - (i >= 1 ? b : 0.0);
 }
 
 // Calls F<HAS0, NEU>::run(args...) for the geometry's axis count and boundary.
@@ -602,7 +606,7 @@ RhsArgs rhs_args(const Plan& P, const double* xi, const double* ybar, double sig
 }
 
 // (capped so that the b.b partials of a PCG start stay few)
-int rhs_grid(const Plan& P) { return grid_for(P.g.n, 4096); }
+int rhs_grid(const Plan& P) { return grid_for(P.g.n, 8192); }
 
 void launch_rhs(const Plan& P, const double* xi, const double* ybar, double sigma,
                 const double* m0, double* b, hipStream_t s, const double* zin, double init_rtol) {
