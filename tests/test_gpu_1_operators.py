@@ -190,6 +190,25 @@ def test_AAt_big_tiles(case, tc, monkeypatch):
         assert np.abs(res[big][1] - res[0][1]).max() <= 1e-11 * np.abs(res[0][1]).max()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
+def test_pcg_zero_rhs(precision):
+    """b = 0: the solve ends at the b.b test before any update (which is what
+    writes x, the solve starting from x = 0), and x must come back as exactly
+    zero whatever the buffer held."""
+    import torch
+    inst = _inst(CASES[4])
+    say(f"pcg b = 0 {precision}")
+    with plan_of(inst, precision=precision) as P:
+        u = torch.full((inst.n,), float("nan"), dtype=torch.float64, device="cuda")
+        its, rel, _ = mfg.mfg_pcg(P, dev(np.zeros(inst.n)), u, 1e-10, 50)
+        assert its == 0 and rel == 0.0
+        assert np.array_equal(host(u), np.zeros(inst.n))
+        # a regular solve right after still converges from zero
+        b = np.random.default_rng(8).standard_normal(inst.n)
+        its, rel, _ = mfg.mfg_pcg(P, dev(b), u, 1e-10, 200)
+        assert 0 < its <= 30 and rel <= 1e-10
+
+
 # Mixed precision: the preconditioner is approximate; its normwise error
 # against the exact float64 P^{-1} is bounded by the arithmetic of each mode
 # (float32 spatial solves everywhere; the time transform in float32, float16
