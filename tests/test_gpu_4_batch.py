@@ -159,3 +159,26 @@ def test_batch_autotuned_bitwise_equals_single():
         ref = _single(inst, "mixed_fp32", [5], 1e-10, 300)
         assert it == ref[5]
         assert np.array_equal(y, ref[1]), inst.name
+
+
+def test_batch_with_a_settled_instance():
+    """An instance at its fixed point (uniform m0, V = 0) has a zero first
+    right-hand side: its PCG ends before any update, u must come back as zero,
+    and it must not disturb the other instances of the batch."""
+    insts = _instances()[:3]
+    flat = wl.small_instance(26, 2, 16, 12, 8, "periodic", 0.1)
+    flat.V = np.zeros_like(flat.V)
+    flat.m0 = np.ones_like(flat.m0)
+    insts.append(flat)
+    say("batch with a settled instance")
+    # one step: xi' = Cr^T u must be exactly zero for the settled instance
+    got = _batched(insts, "mixed_fp32", [1], 1e-10, 300, False)
+    assert got[-1][5] == [0]
+    assert not np.any(got[-1][0])
+    # more steps (graph replays included): still bitwise the single-plan runs
+    got = _batched(insts, "mixed_fp32", [1, 3], 1e-10, 300, True)
+    for inst, b in zip(insts, got):
+        ref = _single(inst, "mixed_fp32", [1, 3], 1e-10, 300)
+        assert b[5] == ref[5], (inst.name, b[5], ref[5])
+        for x, y in zip(b[:3], ref[:3]):
+            assert np.array_equal(x, y), inst.name
