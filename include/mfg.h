@@ -60,13 +60,15 @@ typedef enum { MFG_BC_PERIODIC = 0, MFG_BC_NEUMANN = 1 } mfg_bc_t;
  * the reduced-matrix products, the right-hand side and the prox are float64
  * in every mode. MIXED modes run the spatial solves (Algorithm 2) in float32
  * and the time transform (Algorithm 1) on the matrix cores with float16/
- * bfloat16 (or float32) inputs and float32 accumulation. With float16 and
- * bfloat16 PCG takes its flexible (Polak-Ribiere) form; with float32 the
- * preconditioner is symmetric to float32 rounding and PCG keeps the standard
- * form. */
+ * bfloat16 inputs (or float32 operands carried as two float16 terms) and
+ * float32 accumulation. With float16 and bfloat16 PCG takes its flexible
+ * (Polak-Ribiere) form; with float32 the preconditioner is symmetric to
+ * float32 rounding and PCG keeps the standard form. */
 typedef enum {
   MFG_FP64 = 0,
-  MFG_MIXED_FP32 = 1,  /* time transform fp32 inputs, spatial solves fp32 */
+  MFG_MIXED_FP32 = 1,  /* time transform at fp32 accuracy (fp32 operands split into two fp16
+                          terms, three fp16 matrix-core products, fp32 accumulate), spatial
+                          solves fp32 */
   MFG_MIXED_FP16 = 2,  /* time transform fp16 inputs / fp32 accumulate */
   MFG_MIXED_BF16 = 3   /* time transform bf16 inputs / fp32 accumulate */
 } mfg_precision_t;

@@ -294,6 +294,7 @@ static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const d
     P.ntp = ntp;
     std::vector<float> p32((size_t)ntp * ntp, 0.0f);
     std::vector<_Float16> p16((size_t)ntp * ntp, (_Float16)0.0f);
+    std::vector<_Float16> p16s(2 * (size_t)ntp * ntp, (_Float16)0.0f);
     std::vector<unsigned short> pbf((size_t)ntp * ntp, 0);
     std::vector<double> p64((size_t)ntp * ntp, 0.0);
     for (int k = 0; k < nt; ++k)
@@ -302,10 +303,13 @@ static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const d
         p64[(size_t)t * ntp + k] = v;
         p32[(size_t)k * ntp + t] = (float)v;
         p16[(size_t)k * ntp + t] = (_Float16)v;
+        const _Float16 hi = (_Float16)(v * kVSplitScale);
+        p16s[(size_t)k * ntp + t] = hi;
+        p16s[((size_t)ntp + k) * ntp + t] = (_Float16)(v * kVSplitScale - (double)hi);
         pbf[(size_t)k * ntp + t] = to_bf16((float)v);
       }
     if ((rc = upload(P, &P.Vp64, p64)) || (rc = upload(P, &P.Vp32, p32)) ||
-        (rc = upload(P, &P.Vp16, p16)) ||
+        (rc = upload(P, &P.Vp16, p16)) || (rc = upload(P, &P.Vp16s, p16s)) ||
         (rc = upload(P, &P.Vpbf, pbf)))
       return rc;
   }

@@ -78,6 +78,13 @@ enum FinishOp {
 
 constexpr int kStreamGrid = 2048;  // blocks of the streaming kernels
 
+// The float32 time transform of the blocked kernel runs on the float16 matrix
+// cores at float32 accuracy: operands and V are split into a float16 term and
+// a float16 remainder, and three products (hi hi, hi lo, lo hi; the lo lo term
+// is below float32 rounding) accumulate in float32. V is scaled by 2^8 before
+// the split so that its remainder stays in the float16 normal range.
+constexpr double kVSplitScale = 256.0;
+
 // One spatial transform axis (Algorithm 2): real-to-real transform built on a
 // complex Stockham FFT of length N with two real lines packed per complex one.
 struct Axis {

@@ -84,6 +84,10 @@ struct Plan {
   double* Vp64 = nullptr;  // float64 copy: Vp64[t * ntp + k] = V[k][t]
   float* Vp32 = nullptr;
   _Float16* Vp16 = nullptr;
+  // float32-accurate split for the blocked float32 kernel: rows 0..ntp-1 the
+  // float16 rounding hi of 2^8 V, rows ntp..2ntp-1 the float16 rounding of
+  // 2^8 V - hi
+  _Float16* Vp16s = nullptr;
   unsigned short* Vpbf = nullptr;
 
   // spatial transforms (Algorithm 2)

@@ -169,10 +169,9 @@ template <int MODE>
 struct LpTraits;
 template <>
 struct LpTraits<GM_F32> {
-  // 16 t per step like the 16-bit types: lane group kq holds t = 16 ks + 4 kq + j
-  // (j < 4), and the four float32 products of a step take k-slice j each, so a
-  // lane's four A values are contiguous (one 16-byte LDS read).
-  using VT = float;
+  // float32 accuracy from float16 products: V as 2 NTP rows (hi, then lo) of
+  // float16, operands split the same way per k-step (see kVSplitScale)
+  using VT = _Float16;
   static constexpr int KSTEP = 16;
 };
 template <>
@@ -203,7 +202,10 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
   constexpr int NKS = NTP / KSTEP;  // k-steps
   constexpr int NKB = NTP / 16;     // output row blocks
   constexpr int PER = KSTEP / 4;    // operand values per lane per k-step (1 or 4)
-  __shared__ __align__(16) VT Vs[NTP * NTP];  // Vs[k * NTP + t] = V[k][t]
+  constexpr bool SPLIT = MODE == GM_F32;      // hi / lo float16 terms
+  constexpr bool SCALED = MODE == GM_F16 || SPLIT;  // per-block power-of-2 operand scale
+  constexpr int VROWS = SPLIT ? 2 * NTP : NTP;
+  __shared__ __align__(16) VT Vs[VROWS * NTP];  // Vs[k * NTP + t] = V[k][t] (+ lo rows)
   __shared__ float smax[WPB];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int kq = lane >> 4;
@@ -224,22 +226,24 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
         amax = fmaxf(amax, fabsf(v));
       }
   }
-  // stage V (zero-padded NTP x NTP copy, row k = V[k][.]) after the operand
-  // loads are in flight: an unrolled 16-byte copy
+  // stage V (zero-padded NTP x NTP copy, row k = V[k][.]; with SPLIT the lo
+  // rows follow) after the operand loads are in flight: a 16-byte copy
   {
-    constexpr int NV16 = NTP * NTP * (int)sizeof(VT) / 16;
+    constexpr int NV16 = VROWS * NTP * (int)sizeof(VT) / 16;
     const uint4* src = reinterpret_cast<const uint4*>(Vg);
     uint4* dst = reinterpret_cast<uint4*>(Vs);
     for (int i = threadIdx.x; i < NV16; i += WPB * 64) dst[VsLayout<NTP, VT>::chunk(i)] = src[i];
   }
-  float scale = 1.0f, unscale = 1.0f;
-  if (MODE == GM_F16) {
+  // V's split scale is undone with the operands' scale
+  const float vunscale = SPLIT ? (float)(1.0 / kVSplitScale) : 1.0f;
+  float scale = 1.0f, unscale = vunscale;
+  if (SCALED) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
     if (lane == 0) smax[wave] = amax;
   }
   __syncthreads();
-  if (MODE == GM_F16) {
+  if (SCALED) {
     float bm = smax[0];
 #pragma unroll
     for (int w = 1; w < WPB; ++w) bm = fmaxf(bm, smax[w]);
@@ -248,7 +252,7 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
       frexpf(bm, &e);             // bm < 2^e
       e = e < -100 ? -100 : e;    // keep 2^(14 - e) finite in float32
       scale = ldexpf(1.0f, 14 - e);
-      unscale = ldexpf(1.0f, e - 14);
+      unscale = ldexpf(1.0f, e - 14) * vunscale;
     }
   }
   v4f acc[CB][NKB];
@@ -258,17 +262,29 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
     for (int kb = 0; kb < NKB; ++kb) acc[cb][kb] = (v4f){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int ks = 0; ks < NKS; ++ks) {
-    if constexpr (MODE == GM_F32) {
+    if constexpr (SPLIT) {
+      // x s = hi + lo exactly up to lo's rounding (x s is float32, hi float16)
+      v4h bh[CB], bl[CB];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float xv = xs[cb][ks][j] * scale;
+          const _Float16 h = (_Float16)xv;
+          bh[cb][j] = h;
+          bl[cb][j] = (_Float16)(xv - (float)h);
+        }
 #pragma unroll
       for (int kb = 0; kb < NKB; ++kb) {
-        const v4f a = *reinterpret_cast<const v4f*>(
-            &Vs[VsLayout<NTP, VT>::idx(kb * 16 + (lane & 15), KSTEP * ks + PER * kq)]);
+        const int r = kb * 16 + (lane & 15), t = KSTEP * ks + PER * kq;
+        const v4h ah = *reinterpret_cast<const v4h*>(&Vs[VsLayout<NTP, VT>::idx(r, t)]);
+        const v4h al = *reinterpret_cast<const v4h*>(&Vs[VsLayout<NTP, VT>::idx(r + NTP, t)]);
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            acc[cb][kb] =
-                __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], xs[cb][ks][j], acc[cb][kb], 0, 0, 0);
+        for (int cb = 0; cb < CB; ++cb) {
+          acc[cb][kb] = __builtin_amdgcn_mfma_f32_16x16x16f16(al, bh[cb], acc[cb][kb], 0, 0, 0);
+          acc[cb][kb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bl[cb], acc[cb][kb], 0, 0, 0);
+          acc[cb][kb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bh[cb], acc[cb][kb], 0, 0, 0);
+        }
       }
     } else if constexpr (MODE == GM_F16) {
       v4h b[CB];
@@ -606,7 +622,7 @@ int pers_dispatch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* 
 }
 
 const void* lp_table(const Plan& P, int mode) {
-  return (mode == GM_F32) ? (const void*)P.Vp32
+  return (mode == GM_F32) ? (const void*)P.Vp16s
          : (mode == GM_F16) ? (const void*)P.Vp16 : (const void*)P.Vpbf;
 }
 
