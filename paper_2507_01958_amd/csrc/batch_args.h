@@ -25,6 +25,7 @@ struct InitArgs {
   const double* b;
   double* r;
   RedBuf rb;
+  double tol2;  // (rtol)^2 for the status reset
 };
 
 // npq, nrz: partial counts of the p.q site (the A kernel's grid) and of the
@@ -155,7 +156,7 @@ __device__ __forceinline__ int batch_instance(const int* off, int ninst, int b) 
 
 // ---- host-side builders and batched launchers (defined next to each kernel) ----
 struct Plan;
-InitArgs pcg_init_args(const Plan& P, const double* b, double* r);
+InitArgs pcg_init_args(const Plan& P, const double* b, double* r, double rtol);
 int pcg_init_grid(const Plan& P);
 UpdArgs update_args(const Plan& P, double* x, double* r, const double* p, const double* q,
                     bool first);

@@ -24,8 +24,16 @@ int grid_for(long long n) {
 
 }  // namespace
 
-// r = b (the residual of x = 0, which the first update writes); partial b.b.
+// r = b (the residual of x = 0, which the first update writes); partial b.b;
+// block 0 resets the PCG status.
 __device__ void pcg_init_body(const InitArgs& a, int bid, int nb) {
+  if (bid == 0 && threadIdx.x == 0) {
+    double* S = a.rb.scal;
+    S[S_TOL2] = a.tol2;
+    S[S_BAD] = 0.0;
+    S[S_DONE] = 0.0;
+    S[S_ITS] = 0.0;
+  }
   double acc[1] = {0.0};
   for (long long i = (long long)bid * blockDim.x + threadIdx.x; i < a.n;
        i += (long long)nb * blockDim.x) {
@@ -132,15 +140,6 @@ __global__ __launch_bounds__(kThreads) void k_fill(double* __restrict__ x, long 
     x[i] = v;
 }
 
-__global__ __launch_bounds__(64) void k_set_scalars(double* scal, double tol2) {
-  if (threadIdx.x == 0) {
-    scal[S_TOL2] = tol2;
-    scal[S_BAD] = 0.0;
-    scal[S_DONE] = 0.0;
-    scal[S_ITS] = 0.0;
-  }
-}
-
 // xi = 0; y = ybar = (m0 at every slice, w = 0).
 __global__ __launch_bounds__(kThreads) void k_cp_init(Geom g, const double* __restrict__ m0,
                                                       double* __restrict__ xi,
@@ -173,22 +172,18 @@ void launch_finish(const Plan& P, int site, int nblocks, int op, hipStream_t s) 
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, finish_args(P, site, nblocks, op));
 }
 
-InitArgs pcg_init_args(const Plan& P, const double* b, double* r) {
-  return InitArgs{P.g.n, b, r, P.red};
+InitArgs pcg_init_args(const Plan& P, const double* b, double* r, double rtol) {
+  return InitArgs{P.g.n, b, r, P.red, rtol * rtol};
 }
 
 int pcg_init_grid(const Plan& P) { return grid_for(P.g.n); }
 
-void launch_set_scalars(const Plan& P, double rtol, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, P.red.scal, rtol * rtol);
-}
-
 void launch_pcg_init(const Plan& P, const double* b, double* r, double rtol, hipStream_t s) {
-  launch_set_scalars(P, rtol, s);
   const int grid = pcg_init_grid(P);
   {
     ProfScope ps(P, "pcg_init", s);
-    hipLaunchKernelGGL(k_pcg_init, dim3(grid), dim3(kThreads), 0, s, pcg_init_args(P, b, r));
+    hipLaunchKernelGGL(k_pcg_init, dim3(grid), dim3(kThreads), 0, s,
+                       pcg_init_args(P, b, r, rtol));
   }
   launch_finish(P, T_BB, grid, OP_BB, s);
 }
