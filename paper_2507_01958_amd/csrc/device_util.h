@@ -70,9 +70,10 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
 
 // Store this block's partial sums (slot k of `site` at index bid, the block's
 // id within its instance).
-// A separate single-block finisher kernel sums them in block order after the
-// producing kernel has completed, so no device-scope fence is needed here (on
-// a multi-XCD part such a fence writes back the whole L2 of the XCD).
+// A later kernel (a one-block finisher, or the consumer through
+// fold_partials) sums them after the producing kernel has completed, so no
+// device-scope fence is needed here (on a multi-XCD part such a fence writes
+// back the whole L2 of the XCD).
 template <int NV>
 __device__ __forceinline__ void reduce_store(double (&v)[NV], const RedBuf& rb, int site,
                                              int bid) {

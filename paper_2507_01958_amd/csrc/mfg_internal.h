@@ -33,8 +33,8 @@ struct Geom {
   double nu, dt, idt, idt2;
 };
 
-// Deterministic two-level reduction: per-block partials, then one finisher
-// block sums them in block order.
+// Deterministic two-level reduction: per-block partials, then a sum in a fixed
+// order, by a one-block finisher kernel or inside the kernel that consumes it.
 struct RedBuf {
   double* partials;   // [slot][block]
   double* scal;       // device scalar block
@@ -56,7 +56,7 @@ enum ScalarSlot {
   S_DM = 10,    // ||m' - m||^2 of the last CP step
   S_AUX0 = 11,
   S_AUX1 = 12,
-  S_ITS = 13,   // PCG iterations done (counted by the r.r finisher)
+  S_ITS = 13,   // PCG iterations done (counted by the r.r stopping test)
   S_SIGMA = 14, // CP step sizes of the current iteration (graph-driven runs)
   S_TAU = 15,
   S_THETA = 16,
