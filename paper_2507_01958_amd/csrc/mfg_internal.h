@@ -77,6 +77,8 @@ enum FinishOp {
 };
 
 constexpr int kStreamGrid = 2048;  // blocks of the streaming kernels
+constexpr int kFinishThreads = 1024;  // threads of a one-block finisher (16 waves)
+constexpr int kFinishDepth = 16;     // partials each finisher thread loads at once
 
 // The float32 time transform of the blocked kernel runs on the float16 matrix
 // cores at float32 accuracy: operands and V are split into a float16 term and

@@ -74,16 +74,33 @@ __device__ void update_body(const UpdArgs& a, int bid, int nb) {
   reduce_store<1>(acc, a.rb, T_RR, bid);
 }
 
-// Sum the partials of one site in block order (one block) and apply `op`.
+// Sum the partials of one site (one block of kFinishThreads) and apply `op`.
+// Thread t adds entries t, t + T, t + 2T, ... in order (T threads); the loads
+// are issued kFinishDepth at a time so that a site of 32768 partials takes two
+// rounds of memory latency rather than one per entry. Only OP_AUX reads the
+// second slot.
 __device__ void finish_body(const FinishArgs& f) {
   const RedBuf& rb = f.rb;
   if (f.done && *f.done != 0.0) return;
   __shared__ double sh[2 * 16];
   const double* part = rb.partials + (size_t)f.site * kSlotsPerSite * rb.max_blocks;
+  const int nslot = (f.op == OP_AUX) ? 2 : 1;
+  const int T = blockDim.x;
   double v[2] = {0.0, 0.0};
-  for (int b = threadIdx.x; b < f.nblocks; b += blockDim.x) {
-    v[0] += part[b];
-    v[1] += part[(size_t)rb.max_blocks + b];
+  for (int k = 0; k < nslot; ++k) {
+    const double* pk = part + (size_t)k * rb.max_blocks;
+    double acc = 0.0;
+    for (int b0 = threadIdx.x; b0 < f.nblocks; b0 += T * kFinishDepth) {
+      double t[kFinishDepth];
+#pragma unroll
+      for (int u = 0; u < kFinishDepth; ++u) {
+        const int b = b0 + u * T;
+        t[u] = (b < f.nblocks) ? pk[b] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kFinishDepth; ++u) acc += t[u];
+    }
+    v[k] = acc;
   }
   block_sum<2>(v, sh);
   if (threadIdx.x != 0) return;
@@ -132,7 +149,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(long long n, const double
   reduce_store<2>(acc, rb, T_AUX, blockIdx.x);
 }
 
-__global__ __launch_bounds__(256) void k_finish(FinishArgs f) { finish_body(f); }
+__global__ __launch_bounds__(kFinishThreads) void k_finish(FinishArgs f) { finish_body(f); }
 
 __global__ __launch_bounds__(kThreads) void k_fill(double* __restrict__ x, long long n, double v) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -169,7 +186,8 @@ FinishArgs finish_args(const Plan& P, int site, int nblocks, int op) {
 
 void launch_finish(const Plan& P, int site, int nblocks, int op, hipStream_t s) {
   ProfScope ps(P, "finish", s);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, finish_args(P, site, nblocks, op));
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishThreads), 0, s,
+                     finish_args(P, site, nblocks, op));
 }
 
 InitArgs pcg_init_args(const Plan& P, const double* b, double* r, double rtol) {
@@ -237,7 +255,7 @@ __global__ __launch_bounds__(kThreads) void k_update_batch(const UpdArgs* A, con
 }
 
 // one block per instance
-__global__ __launch_bounds__(256) void k_finish_batch(const FinishArgs* F) {
+__global__ __launch_bounds__(kFinishThreads) void k_finish_batch(const FinishArgs* F) {
   finish_body(F[blockIdx.x]);
 }
 
@@ -264,7 +282,7 @@ void launch_update_batch(const UpdArgs* A, const int* off, int ninst, int total,
 }
 
 void launch_finish_batch(const FinishArgs* F, int ninst, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish_batch, dim3(ninst), dim3(256), 0, s, F);
+  hipLaunchKernelGGL(k_finish_batch, dim3(ninst), dim3(kFinishThreads), 0, s, F);
 }
 
 void launch_cp_advance_batch(double* scal, int stride, int ninst, const double* sched, int maxit,
