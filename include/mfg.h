@@ -63,7 +63,11 @@ typedef enum { MFG_BC_PERIODIC = 0, MFG_BC_NEUMANN = 1 } mfg_bc_t;
  * bfloat16 inputs (or float32 operands carried as two float16 terms) and
  * float32 accumulation. With float16 and bfloat16 PCG takes its flexible
  * (Polak-Ribiere) form; with float32 the preconditioner is symmetric to
- * float32 rounding and PCG keeps the standard form. */
+ * float32 rounding and PCG keeps the standard form. The low-precision time
+ * transform holds all of V in LDS and serves N_t <= 128; for longer horizons
+ * every mode runs the time transform with float64 products (float32 input or
+ * output in the MIXED modes), so the MIXED modes then differ from FP64 only in
+ * their float32 spatial solves. */
 typedef enum {
   MFG_FP64 = 0,
   MFG_MIXED_FP32 = 1,  /* time transform at fp32 accuracy (fp32 operands split into two fp16

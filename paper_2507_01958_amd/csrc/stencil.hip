@@ -550,6 +550,9 @@ int aat_chunk(const Geom& g, int ntile, int max_blocks, int want) {
   if (tc > 64) tc = 64;
   const long long need = ((long long)g.nt * ntile + max_blocks - 1) / max_blocks;
   if (tc < need) tc = need;
+  // the last chunk of a tile may be partial: grow tc until ntile * ceil(nt / tc)
+  // fits (ends by tc = nt, where the grid is ntile <= 1024 blocks)
+  while (tc < g.nt && (long long)ntile * ((g.nt + tc - 1) / tc) > max_blocks) ++tc;
   return (int)tc;
 }
 
