@@ -6,6 +6,10 @@
          --cal-fetch DB --cal-write DB --out FILE.json [--merge]
       HBM bytes per launch from FETCH_SIZE / WRITE_SIZE passes, each scaled by
       what the same counter reads for a plain device copy of known size
+  python -m paper_2507_01958_amd.profiling counters DB --variant V \
+         --counters MfmaUtil MfmaFlops [--active MfmaFlops] --out FILE.json [--merge]
+      per-kernel averages of counters from a --pmc run (rows of one dispatch
+      summed), e.g. matrix-core busy percentage and matrix-core flops
 
 Kernels are reported under the names the library's own profiler uses
 (tgemm_f64_fwd, aat_fused, cols_solve, ...): a dispatch of a template kernel
@@ -93,8 +97,11 @@ def _dispatches(db, counter=None):
     if counter is None:
         rows = con.execute("select name, start, end from kernels order by start").fetchall()
         return [(n, (e - s) / 1e3) for n, s, e in rows]
-    rows = con.execute("select name, counter_value, start from pmc_events where counter_name=? "
-                       "order by start", (counter,)).fetchall()
+    # a counter without a reduction in its expression has one row per shader
+    # engine: sum the rows of each dispatch
+    rows = con.execute("select name, sum(counter_value), min(start) from pmc_events "
+                       "where counter_name=? group by pid, dispatch_id order by min(start)",
+                       (counter,)).fetchall()
     return [(n, v) for n, v, _ in rows]
 
 
@@ -167,6 +174,49 @@ def cmd_traffic(args):
     print(json.dumps(kernels, indent=1))
 
 
+def cmd_counters(args):
+    # per dispatch, all counters side by side (every counter of a pass sees the
+    # same dispatches in the same order)
+    cols = {c: _dispatches(args.db, c) for c in args.counters}
+    first = cols[args.counters[0]]
+    names = classify([n for n, _ in first])
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    for i, name in enumerate(names):
+        vals = {c: cols[c][i][1] for c in args.counters}
+        # launches that found the solve finished return at once: with --active C
+        # they are left out of the averages (C = 0)
+        if args.active and vals[args.active] == 0:
+            continue
+        for c, v in vals.items():
+            acc[name][c].append(v)
+    kernels = {k: dict({c: sum(v) / len(v) for c, v in d.items()},
+                       launches=len(next(iter(d.values()))))
+               for k, d in acc.items()}
+    data = {}
+    if args.merge and os.path.exists(args.out):
+        with open(args.out) as f:
+            data = json.load(f)
+    data.setdefault("variants", {})[args.variant] = kernels
+    with open(args.out, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    if args.md:
+        cnames = sorted({c for v in data["variants"].values() for k in v.values() for c in k
+                         if c != "launches"})
+        lines = [f"# Counters: {args.title}", "", "Command (one pass per variant):", "", "```",
+                 args.cmd, "```", "",
+                 "Averages per launch over the launches counted (`launches`); rows of one "
+                 "dispatch (one per shader engine) are summed.", "",
+                 "| variant | kernel | launches | " + " | ".join(cnames) + " |",
+                 "|---|---|---:|" + "---:|" * len(cnames)]
+        for var, ks in data["variants"].items():
+            for k, v in sorted(ks.items()):
+                lines.append(f"| {var} | {k} | {v['launches']} | " +
+                             " | ".join(f"{v.get(c, float('nan')):.6g}" for c in cnames) + " |")
+        with open(args.md, "w") as f:
+            f.write("\n".join(lines) + "\n")
+    print(json.dumps(kernels, indent=1))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -183,9 +233,21 @@ def main(argv=None):
     b.add_argument("--cal-write", required=True)
     b.add_argument("--out", required=True)
     b.add_argument("--merge", action="store_true")
+    c = sub.add_parser("counters")
+    c.add_argument("db")
+    c.add_argument("--variant", required=True)
+    c.add_argument("--counters", nargs="+", required=True)
+    c.add_argument("--active", help="average only over dispatches where this counter is > 0")
+    c.add_argument("--out", required=True)
+    c.add_argument("--merge", action="store_true")
+    c.add_argument("--md", help="also write a markdown table of every variant in --out")
+    c.add_argument("--cmd", default="")
+    c.add_argument("--title", default="")
     args = ap.parse_args(argv)
     if args.cmd_name == "stats":
         cmd_stats(args)
+    elif args.cmd_name == "counters":
+        cmd_counters(args)
     else:
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
         sys.path.insert(0, root)
