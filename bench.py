@@ -154,9 +154,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--nt", type=int, default=128)
-    ap.add_argument("--workload", default="neumann256", choices=["neumann256", "batch", "grad"],
+    ap.add_argument("--workload", default="neumann256",
+                    choices=["neumann256", "batch", "grad", "adaptive"],
                     help="neumann256: the headline line; batch: 32 uneven periodic instances, "
-                         "batched vs one plan at a time; grad: gradient through 50 CP iterations")
+                         "batched vs one plan at a time; grad: gradient through 50 CP "
+                         "iterations; adaptive: time to solution with the Section 5 "
+                         "stopping and inner-tolerance rules")
     ap.add_argument("--batch", type=int, default=32, help="instances of the batch workload")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of tuning them first")
@@ -305,6 +308,56 @@ def bench_grad(args):
     print(json.dumps(out))
 
 
+def bench_adaptive(args):
+    """Time to solution on the 256^2 x 128 Neumann workload with the Section 5
+    rules: CP until ||m_{l+1} - m_l|| <= 1e-4 ||m0||, each projection by PCG to
+    min(1e-4, max(1e-6, 1e-4 r)), from the initial point; FP64 and the FP32
+    preconditioner. `steps` solves are timed after `warmup` untimed ones."""
+    import numpy as np
+    import torch
+
+    from paper_2507_01958_amd import mfg
+    from paper_2507_01958_amd import workloads as wl
+
+    inst = wl.neumann_square(n=args.size, nt=args.nt)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    V = torch.from_numpy(inst.V).to(dev)
+    m0 = torch.from_numpy(inst.m0).to(dev)
+    cp_tol = 1e-4 * float(np.linalg.norm(inst.m0))
+    res = {}
+    for variant in ["fp64", "mixed_fp32"]:
+        with mfg.mfg_plan(_problem(inst, variant), V, m0) as P:
+            if not args.no_autotune:
+                mfg.mfg_autotune(P, 1)
+            st = mfg.CPState(P)
+            times = []
+            for rep in range(args.warmup + args.steps):
+                mfg.mfg_cp_init(P, st)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                out = mfg.mfg_cp_solve_tol(P, st, 5000, cp_tol, 1000)
+                torch.cuda.synchronize()
+                if rep >= args.warmup:
+                    times.append(time.perf_counter() - t0)
+            t = sum(times) / len(times)
+            res[variant] = {"seconds": t, "cp_iters": out["n_done"],
+                            "pcg_iters_total": int(sum(out["pcg_iters"])),
+                            "final_dm": out["dm"][-1], "cp_iters_per_s": out["n_done"] / t}
+    best = min(res, key=lambda k: res[k]["seconds"])
+    print(json.dumps({
+        "metric": "time to solution, CP to ||dm|| <= 1e-4 ||m0|| with the CGtol rule (2D 256^2x128)",
+        "value": res[best]["seconds"], "unit": "s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * res[best]["seconds"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+fp32" if best == "mixed_fp32" else "f64", "data": "synthetic (seeded)",
+        "config": {"workload": f"neumann2d_{inst.nx}x{inst.ny}x{inst.nt}_nu{inst.nu:g}_adaptive",
+                   "cp_tol": cp_tol, "variant": best},
+        "variants": res, "roofline": None, "cpu_baseline": None,
+    }))
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -319,6 +372,9 @@ def main():
         return
     if args.workload == "grad":
         bench_grad(args)
+        return
+    if args.workload == "adaptive":
+        bench_adaptive(args)
         return
     import numpy as np
     import torch

@@ -193,6 +193,20 @@ int mfg_cp_init(mfg_plan_t plan, mfg_state_t* st);
 int mfg_cp_solve(mfg_plan_t plan, mfg_state_t* st, int n_iter, double pcg_rtol,
                  int pcg_maxit, mfg_stats_t* stats);
 
+/* Chambolle-Pock iterations as in mfg_cp_solve, with the stopping and
+ * inner-tolerance rules of Section 5: iteration l+1 solves its projection by
+ * PCG to the relative residual min(1e-4, max(1e-6, 1e-4 r_l)), where
+ * r_l = ||m_l - m_{l-1}||_2 is the change made by the iteration before it
+ * (1e-4 for the first iteration of the call), and the loop ends after the
+ * first iteration with r <= cp_tol, or after max_iter iterations. The paper
+ * takes cp_tol = 1e-4 ||m0||_2. *n_done (HOST, may be NULL) receives the
+ * number of iterations run; stats arrays need max_iter entries, of which the
+ * first *n_done are written. Reads the change back to the host after every
+ * iteration. MFG_ERR_NOT_CONVERGED (after the loop) if some PCG solve hit
+ * pcg_maxit. */
+int mfg_cp_solve_tol(mfg_plan_t plan, mfg_state_t* st, int max_iter, double cp_tol,
+                     int pcg_maxit, int* n_done, mfg_stats_t* stats);
+
 /* Reverse-mode gradient through n_iter Chambolle-Pock iterations started at
  * mfg_cp_init: given gy = dJ/dy_N (device primal vector) for a scalar J of the
  * final primal iterate, writes dJ/dm0 and dJ/dV (device, M values each).

@@ -108,3 +108,37 @@ def cp_solve(g: Grid, V: np.ndarray, m0: np.ndarray, iters: int, method: str = "
             info.pop("b")
         log.append(info)
     return st, log
+
+
+def cg_tolerance(r_prev: float | None) -> float:
+    """Inner tolerance of Section 5 for the next projection from the latest
+    CP change r (relative PCG residual): min(1e-4, max(1e-6, 1e-4 r)); with no
+    r yet (the first iteration) the loosest value, 1e-4."""
+    if r_prev is None:
+        return 1e-4
+    return min(1e-4, max(1e-6, 1e-4 * r_prev))
+
+
+def cp_solve_tol(g: Grid, V: np.ndarray, m0: np.ndarray, max_iter: int, cp_tol: float,
+                 maxit: int = 100000, state: CPState | None = None):
+    """CP iterations with the stopping and inner-tolerance rules of Section 5:
+    iteration l+1 solves its projection by PCG (Algorithms 1+2) to
+    cg_tolerance(r_l), r_l = ||m_l - m_{l-1}||_2 of the previous iteration,
+    and the loop ends after the first iteration whose r is <= cp_tol (the
+    paper takes cp_tol = 1e-4 ||m_0||), or after max_iter iterations.
+    Returns (state, per-iteration diagnostics with the tolerance used)."""
+    S = ops.Spatial(g)
+    st = state.copy() if state is not None else cp_init(g, m0)
+    log = []
+    r_prev = None
+    for _ in range(max_iter):
+        tol = cg_tolerance(r_prev)
+        info = cp_step(g, S, st, V, m0, Projector(g, S, "pcg", tol, maxit))
+        info.pop("u")
+        info.pop("b")
+        info["cg_tol"] = tol
+        log.append(info)
+        r_prev = info["dm"]
+        if r_prev <= cp_tol:
+            break
+    return st, log

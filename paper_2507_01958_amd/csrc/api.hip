@@ -739,6 +739,45 @@ int mfg_cp_solve(mfg_plan_t plan, mfg_state_t* st, int n_iter, double pcg_rtol, 
   return MFG_OK;
 }
 
+// Section 5: the loop ends after the first iteration whose change in m is
+// below cp_tol; iteration l+1 solves to min(1e-4, max(1e-6, 1e-4 r_l)) with
+// r_l the change of the iteration before it (1e-4 for the first of the call).
+// Every step writes xi and ybar (no z hand-off: whether another step follows
+// is known only after its change has been read back).
+int mfg_cp_solve_tol(mfg_plan_t plan, mfg_state_t* st, int max_iter, double cp_tol,
+                     int pcg_maxit, int* n_done, mfg_stats_t* stats) {
+  if (!plan || !st || !st->xi || !st->y || !st->ybar)
+    return fail(MFG_ERR_INVALID_ARG, "NULL argument");
+  if (max_iter < 0 || pcg_maxit < 1 || !(cp_tol >= 0.0) || !std::isfinite(cp_tol))
+    return fail(MFG_ERR_INVALID_ARG, "bad iteration arguments");
+  if (!(st->sigma > 0.0) || !(st->tau > 0.0)) return fail(MFG_ERR_INVALID_ARG, "bad step sizes");
+  mfg::Plan& P = plan->P;
+  if (n_done) *n_done = 0;
+  int final_rc = MFG_OK, rc = MFG_OK;
+  double r_prev = -1.0;
+  for (int it = 0; it < max_iter; ++it) {
+    const double tol = (r_prev < 0.0) ? 1e-4 : std::min(1e-4, std::max(1e-6, 1e-4 * r_prev));
+    int its = 0;
+    double rel = 0.0;
+    rc = mfg::cp_step(P, st, tol, pcg_maxit, &its, &rel, nullptr);
+    if (rc == MFG_ERR_NOT_CONVERGED) final_rc = rc;
+    else if (rc) break;
+    if ((rc = mfg::read_scalars(P))) break;
+    const double r = std::sqrt(P.host_scal[mfg::S_DM]);
+    if (n_done) *n_done = it + 1;
+    if (stats) {
+      if (stats->pcg_iters) stats->pcg_iters[it] = its;
+      if (stats->pcg_relres) stats->pcg_relres[it] = rel;
+      if (stats->dm) stats->dm[it] = r;
+    }
+    r_prev = r;
+    if (r <= cp_tol) break;
+  }
+  if (rc) return rc;
+  if (final_rc) return fail(final_rc, "some PCG solve reached maxit");
+  return MFG_OK;
+}
+
 int mfg_cp_adjoint(mfg_plan_t plan, const mfg_state_t* ckpts, int n_ckpt, int every, int n_iter,
                    const double* gy_final, double pcg_rtol, int pcg_maxit, double* g_m0,
                    double* g_V) {

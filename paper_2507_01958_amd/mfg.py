@@ -59,6 +59,8 @@ SIGNATURES = {
                         POINTER(c_double)]),
     "mfg_cp_init": (c_int, [c_void_p, POINTER(State)]),
     "mfg_cp_solve": (c_int, [c_void_p, POINTER(State), c_int, c_double, c_int, POINTER(Stats)]),
+    "mfg_cp_solve_tol": (c_int, [c_void_p, POINTER(State), c_int, c_double, c_int,
+                                 POINTER(c_int), POINTER(Stats)]),
     "mfg_cp_adjoint": (c_int, [c_void_p, POINTER(State), c_int, c_int, c_int, c_void_p, c_double,
                                c_int, c_void_p, c_void_p]),
     "mfg_autotune": (c_int, [c_void_p, c_int]),
@@ -294,6 +296,28 @@ def mfg_cp_solve(plan: Plan, st: CPState, n_iter: int, pcg_rtol: float, pcg_maxi
         out = dict(pcg_iters=list(its), pcg_relres=list(rel), dm=list(dm))
     out["status"] = rc
     return out
+
+
+def mfg_cp_solve_tol(plan: Plan, st: CPState, max_iter: int, cp_tol: float, pcg_maxit: int,
+                     raise_not_converged: bool = True):
+    """CP iterations with the Section 5 stopping and inner-tolerance rules;
+    returns dict with n_done and the per-iteration statistics."""
+    st._sync_ptrs()
+    n = max(int(max_iter), 1)
+    its = (c_int * n)()
+    rel = (c_double * n)()
+    dm = (c_double * n)()
+    s = Stats()
+    s.pcg_iters = ctypes.cast(its, POINTER(c_int))
+    s.pcg_relres = ctypes.cast(rel, POINTER(c_double))
+    s.dm = ctypes.cast(dm, POINTER(c_double))
+    done = c_int(0)
+    rc = load().mfg_cp_solve_tol(plan.handle, ctypes.byref(st.c), int(max_iter), float(cp_tol),
+                                 int(pcg_maxit), ctypes.byref(done), ctypes.byref(s))
+    _check(rc, allow=() if raise_not_converged else (3,))
+    k = done.value
+    return dict(n_done=k, pcg_iters=list(its)[:k], pcg_relres=list(rel)[:k], dm=list(dm)[:k],
+                status=rc)
 
 
 def mfg_cp_adjoint(plan: Plan, ckpts, every: int, n_iter: int, gy, pcg_rtol: float,

@@ -1,0 +1,91 @@
+"""GPU parity of the Section 5 stopping and inner-tolerance rules
+(mfg_cp_solve_tol) against the oracle's cp_solve_tol.
+
+FP64: the same number of CP iterations, the same PCG iteration count for
+every projection (each solve meets the same relative tolerance, computed from
+changes that agree to rounding), per-iteration changes to 1e-9 relative or
+2e-10 ||m|| (a change between nearly equal iterates carries twice the state
+error), and
+the final state to 1e-9 of each block's max norm (PCG stops at 1e-4..1e-6, so
+both sides run the same truncated Krylov iterations and differ by rounding
+only). With the FP32 preconditioner the Krylov iterates differ at the
+preconditioner's accuracy, so the run must satisfy the rules on its own
+numbers and end within 10 CPtol (2-norm of m) of the oracle's solution.
+"""
+import numpy as np
+import pytest
+
+from _gpu import grid_of, host, plan_of, say
+from oracle import cp as ocp
+from paper_2507_01958_amd import mfg
+from paper_2507_01958_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(2, 24, 18, 12, "neumann", 0.05), (2, 32, 32, 32, "periodic", 0.01),
+         (1, 64, 1, 32, "periodic", 0.1)]
+
+
+def _ids(c):
+    return f"d{c[0]}_{c[1]}x{c[2]}x{c[3]}_{c[4]}_nu{c[5]}"
+
+
+def _run(inst, precision, cp_tol, max_iter=400):
+    with plan_of(inst, precision=precision) as P:
+        st = mfg.CPState(P)
+        mfg.mfg_cp_init(P, st)
+        out = mfg.mfg_cp_solve_tol(P, st, max_iter, cp_tol, 500)
+        return out, host(st.xi), host(st.y)
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_cp_tol_fp64_matches_oracle(case):
+    inst = wl.small_instance(500, *case)
+    g = grid_of(inst)
+    say(f"cp_tol fp64 {_ids(case)}")
+    cp_tol = 1e-4 * np.linalg.norm(inst.m0)
+    ref, log = ocp.cp_solve_tol(g, inst.V, inst.m0, 400, cp_tol, 500)
+    out, xi, y = _run(inst, "fp64", cp_tol)
+    assert out["n_done"] == len(log)
+    assert out["pcg_iters"] == [l["pcg_iters"] for l in log]
+    n = g.n
+    # a change between nearly equal iterates: its error is bounded by twice the
+    # state error (1e-10 ||m||), not relative to the small late values
+    mnorm = np.linalg.norm(ref.y[:n])
+    np.testing.assert_allclose(out["dm"], [l["dm"] for l in log], rtol=1e-9, atol=2e-10 * mnorm)
+    for name, a, rb in [("xi", xi, ref.xi), ("y", y, ref.y)]:
+        for blk in range(1 + g.ncomp):
+            ga, r = a[blk * n:(blk + 1) * n], rb[blk * n:(blk + 1) * n]
+            err = np.abs(ga - r).max() / max(np.abs(r).max(), 1e-300)
+            assert err <= 1e-9, (name, blk, err)
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_cp_tol_mixed_fp32_reaches_the_solution(case):
+    inst = wl.small_instance(500, *case)
+    g = grid_of(inst)
+    say(f"cp_tol mixed_fp32 {_ids(case)}")
+    cp_tol = 1e-4 * np.linalg.norm(inst.m0)
+    ref, log = ocp.cp_solve_tol(g, inst.V, inst.m0, 400, cp_tol, 500)
+    out, xi, y = _run(inst, "mixed_fp32", cp_tol)
+    dm = out["dm"]
+    assert 1 <= out["n_done"] < 400
+    assert all(d > cp_tol for d in dm[:-1]) and dm[-1] <= cp_tol
+    tol = [1e-4] + [min(1e-4, max(1e-6, 1e-4 * d)) for d in dm[:-1]]
+    assert all(r <= t for r, t in zip(out["pcg_relres"], tol))
+    assert np.linalg.norm(y[: g.n] - ref.y[: g.n]) <= 10 * cp_tol
+    assert y[: g.n].min() >= 0.0
+
+
+def test_cp_tol_zero_iterations_and_bad_arguments():
+    inst = wl.small_instance(501, *CASES[0])
+    with plan_of(inst) as P:
+        st = mfg.CPState(P)
+        mfg.mfg_cp_init(P, st)
+        y0 = host(st.y).copy()
+        out = mfg.mfg_cp_solve_tol(P, st, 0, 1e-3, 100)
+        assert out["n_done"] == 0 and np.array_equal(host(st.y), y0)
+        with pytest.raises(mfg.MFGError):
+            mfg.mfg_cp_solve_tol(P, st, 10, -1.0, 100)
+        with pytest.raises(mfg.MFGError):
+            mfg.mfg_cp_solve_tol(P, st, 10, 1e-3, 0)
