@@ -29,6 +29,8 @@ PCG_MAXIT = 200
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_neumann256x256x128.json")
+# the grid the stored counter readings were taken on (d, N_x, N_y, N_t, bc)
+TRAFFIC_GRID = (2, 256, 256, 128, "neumann")
 
 
 def kernel_sources_hash():
@@ -107,7 +109,8 @@ def roofline(report, inst, variant, its, steps):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
         kern = tr.get("variants", {}).get(variant, {})
-        if tr.get("sources_hash") == kernel_sources_hash() and dom in kern:
+        same_grid = (inst.d, inst.nx, inst.ny, inst.nt, inst.bc) == TRAFFIC_GRID
+        if same_grid and tr.get("sources_hash") == kernel_sources_hash() and dom in kern:
             out["traffic"] = kern[dom]["bytes_per_launch"]
     except (OSError, ValueError):
         pass
