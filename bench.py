@@ -62,7 +62,8 @@ def algorithmic(kernel, inst, variant, its=1.0, steps=1):
     upd = (6 * its - 1) / its
     rhs = ((steps - 1) * (nb + 1) + (2 * nb + 1)) / steps
     bp = ((steps - 1) * (1 + 3 * nb) + (1 + 4 * nb)) / steps
-    if kernel.startswith("tgemm_f64"):
+    # above N_t = 128 every mode's time transform runs with float64 products
+    if kernel.startswith("tgemm_f64") or (kernel.startswith("tgemm_") and inst.nt > 128):
         return "mfma", 2.0 * inst.nt * inst.nt * inst.M, "fp64"
     for base in ("rows_fwd", "rows_inv", "rows_solve", "cols_solve"):
         if kernel in (base + "_f64", base + "_f32"):

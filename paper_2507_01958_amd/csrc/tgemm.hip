@@ -60,7 +60,9 @@ __device__ void tgemm64_body(const GemmArgs<TX, TY>& ga, int bid) {
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) acc[cb][kb] = (v4d){0.0, 0.0, 0.0, 0.0};
   double vreg[VPER];
-  double xn[CB][4];
+  // prefetched operands stay in their input type until used, so a float input
+  // is not converted (and waited for) right after its load is issued
+  TX xn[CB][4];
   auto fetch = [&](int t0) {
 #pragma unroll
     for (int e = 0; e < VPER; ++e) {
@@ -75,7 +77,7 @@ __device__ void tgemm64_body(const GemmArgs<TX, TY>& ga, int bid) {
       for (int ks = 0; ks < 4; ++ks) {
         const int t = t0 + 4 * ks + kq;
         const int col = col0 + cb * 16;
-        xn[cb][ks] = (t < nt && col < M) ? (double)X[(size_t)t * M + col] : 0.0;
+        xn[cb][ks] = (t < nt && col < M) ? X[(size_t)t * M + col] : TX(0);
       }
   };
   const int nchunk = (nt + TK - 1) / TK;
@@ -88,7 +90,7 @@ __device__ void tgemm64_body(const GemmArgs<TX, TY>& ga, int bid) {
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) xc[cb][ks] = xn[cb][ks];
+      for (int ks = 0; ks < 4; ++ks) xc[cb][ks] = (double)xn[cb][ks];
     __syncthreads();
     if (c + 1 < nchunk) fetch((c + 1) * TK);
 #pragma unroll
