@@ -174,3 +174,27 @@ def test_two_time_steps(case):
         got = host(z)
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
     _cp_compare(inst, 5, 1e-10)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
+def test_long_horizon_autotune_keeps_results(precision, tmp_path, monkeypatch):
+    """Autotuning a long-horizon plan (the streaming float64 time kernel, whose
+    tuned shape may take two column blocks per wave) changes only how the work
+    is split: the tuned preconditioner equals the untuned one to rounding, and
+    a CP iteration after tuning still matches the oracle."""
+    monkeypatch.setenv("MFG_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    case = (2, 16, 16, 2048, "periodic", 0.01)
+    inst = _inst(case)
+    g = grid_of(inst)
+    say(f"long autotune {precision} {_ids(case)}")
+    r = np.random.default_rng(16).standard_normal(g.n)
+    with plan_of(inst, precision=precision) as P:
+        z0 = empty(g.n)
+        mfg.mfg_precond(P, dev(r), z0)
+        mfg.mfg_autotune(P, 2)
+        z1 = empty(g.n)
+        mfg.mfg_precond(P, dev(r), z1)
+        a, b = host(z0), host(z1)
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
+    if precision == "fp64":
+        _cp_compare(inst, 2, 1e-10 * max(1.0, (inst.nt / 1024) ** 2))
