@@ -12,11 +12,14 @@ Field Games", arXiv 2507.01958), cited by section / equation / algorithm:
 * operators.py  Section 2 difference operators, Section 3 matrices A, B, C
                 (eq. ABC), the reduced system (eq. largeA), Section 4.3
                 divergence factors D^1, D^2 and the negative Laplacian K
-* prox.py       Section 3 proximal step of the cost b-hat + F (per cell)
+* prox.py       Section 3 proximal step of the cost b-hat + F (per cell), with
+                the couplings and terminal cost of Section 2.1 / Section 5
 * cg.py         Section 3/4 conjugate gradients on the reduced system
 * precond.py    Section 4 preconditioner (eq. prec, eqs. eigs/precrec,
                 Algorithms 1 and 2, eq. pstrec)
 * cp.py         Section 3 Chambolle-Pock iteration (eq. pasosChamPock) with
                 the Section 5 step-size schedule
 * adjoint.py    reverse-mode derivative of a fixed number of CP iterations
+* value.py      value function from the CP multiplier and the residual of the
+                discrete HJB equation of the scheme (MFG_T^2_h), Section 2
 """

@@ -20,8 +20,9 @@ and at l = 0, y_0 = ybar_0 = (m0 at every slice, w = 0) adds the m-parts of
 g_y_0 + g_ybar_0, summed over slices, to g_m0.
 
 The prox Jacobian follows from the implicit-function theorem on
-h'(m) = -a/(2 s^2) + (1 + 1/tau) m + V - mbar/tau = 0 (s = m + tau,
-a = |w~|^2, w~ = P_K(wbar)), with g = h''(m) = a/s^3 + 1 + 1/tau, on the active
+h'(m) = -a/(2 s^2) + c2 m^2 + (c1 + 1/tau) m + V - mbar/tau = 0 (s = m + tau,
+a = |w~|^2, w~ = P_K(wbar); c1, V per cell, the terminal term included on the
+last slice), with g = h''(m) = a/s^3 + 2 c2 m + c1 + 1/tau, on the active
 branch m > 0:
   dm/dmbar = 1/(tau g),  dm/dV = -1/g,  dm/dwbar_c = chi_c w~_c / (s^2 g),
   w_c = (m/s) w~_c  =>  dw_c = (tau/s^2) w~_c dm + (m/s) chi_c dwbar_c,
@@ -35,23 +36,24 @@ import numpy as np
 from . import operators as ops
 from .cp import Projector, cp_init, cp_step
 from .grid import Grid
-from .prox import project_cone
+from .prox import LINEAR, Coupling, cell_coefficients, project_cone
 
 
-def prox_vjp(g: Grid, v: np.ndarray, V: np.ndarray, tau: float, gy: np.ndarray):
+def prox_vjp(g: Grid, v: np.ndarray, V: np.ndarray, tau: float, gy: np.ndarray,
+             cost: Coupling = LINEAR):
     """J_prox(v)^T gy for a whole primal vector; returns (g_v, g_V (length M))."""
     from .prox import prox_cells
     nb = 1 + g.ncomp
-    Vt = np.tile(V, g.nt)
+    c1, Vt = cell_coefficients(g, V, cost)
     vv = v.reshape(nb, -1)
     gyy = gy.reshape(nb, -1)
-    m, w = prox_cells(vv[0], vv[1:], Vt, tau)
+    m, w = prox_cells(vv[0], vv[1:], Vt, tau, c1=c1, c2=cost.c2)
     wt = project_cone(vv[1:])
     chi = ((wt != 0.0) & (wt == vv[1:])).astype(float)
     a = np.sum(wt * wt, axis=0)
     act = m > 0.0
     s = m + tau
-    gpp = a / s ** 3 + 1.0 + 1.0 / tau
+    gpp = a / s ** 3 + 2.0 * cost.c2 * m + c1 + 1.0 / tau
     gm_tot = gyy[0] + np.sum(gyy[1:] * (tau / s ** 2) * wt, axis=0)
     gmb = np.where(act, gm_tot / (tau * gpp), 0.0)
     gVc = np.where(act, -gm_tot / gpp, 0.0)
@@ -62,7 +64,8 @@ def prox_vjp(g: Grid, v: np.ndarray, V: np.ndarray, tau: float, gy: np.ndarray):
     return gv, gV
 
 
-def forward_record(g: Grid, V, m0, iters, method="direct", rtol=1e-13, maxit=100000):
+def forward_record(g: Grid, V, m0, iters, method="direct", rtol=1e-13, maxit=100000,
+                   cost: Coupling = LINEAR):
     """Forward CP keeping, per iteration, (sigma, tau, theta, v)."""
     S = ops.Spatial(g)
     st = cp_init(g, m0)
@@ -70,15 +73,16 @@ def forward_record(g: Grid, V, m0, iters, method="direct", rtol=1e-13, maxit=100
     tape = []
     for _ in range(iters):
         sigma, tau, y_old = st.sigma, st.tau, st.y.copy()
-        cp_step(g, S, st, V, m0, proj)
+        cp_step(g, S, st, V, m0, proj, cost)
         v = y_old - tau * st.xi
         tape.append((sigma, tau, st.theta, v))
     return st, tape, S, proj
 
 
-def cp_gradient(g: Grid, V, m0, iters, gy_final, method="direct", rtol=1e-13):
+def cp_gradient(g: Grid, V, m0, iters, gy_final, method="direct", rtol=1e-13,
+                cost: Coupling = LINEAR):
     """Gradient of <gy_final, y_N> with respect to (m0, V)."""
-    st, tape, S, proj = forward_record(g, V, m0, iters, method, rtol)
+    st, tape, S, proj = forward_record(g, V, m0, iters, method, rtol, cost=cost)
     nb = 1 + g.ncomp
     gxi = np.zeros(nb * g.n)
     gy = np.array(gy_final, dtype=float, copy=True)
@@ -88,7 +92,7 @@ def cp_gradient(g: Grid, V, m0, iters, gy_final, method="direct", rtol=1e-13):
     for sigma, tau, theta, v in reversed(tape):
         gy_new = gy + (1.0 + theta) * gyb
         gy_prev = -theta * gyb
-        gv, gVl = prox_vjp(g, v, V, tau, gy_new)
+        gv, gVl = prox_vjp(g, v, V, tau, gy_new, cost)
         gV += gVl
         gy_prev += gv
         gxi_tot = gxi - tau * gv

@@ -11,6 +11,8 @@ iteration; after iteration l, theta = (1 + 2 gamma tau_l)^{-1/2},
 tau_{l+1} = theta tau_l, sigma_{l+1} = sigma_l / theta, and the extrapolation
 uses that theta (the ordering of Chambolle and Pock's accelerated scheme).
 Initial point: xi_0 = 0, y_0 = ybar_0 = (m_0 at every time slice, w = 0).
+The cost phi is b-hat + F with the coupling and terminal cost given by a
+prox.Coupling (default f = m + V, g = 0).
 """
 from __future__ import annotations
 
@@ -23,7 +25,7 @@ from . import cg as cgmod
 from . import operators as ops
 from .grid import Grid
 from .precond import apply_Pinv_fast
-from .prox import prox_primal
+from .prox import LINEAR, Coupling, prox_primal
 
 
 @dataclasses.dataclass
@@ -73,13 +75,13 @@ class Projector:
 
 
 def cp_step(g: Grid, S: ops.Spatial, st: CPState, V: np.ndarray, m0: np.ndarray,
-            proj: Projector) -> dict:
+            proj: Projector, cost: Coupling = LINEAR) -> dict:
     """One CP iteration in place; returns per-iteration diagnostics."""
     z = st.xi + st.sigma * st.ybar
     b = ops.apply_Cr(g, S, z) - st.sigma * ops.rhs_d(g, m0)
     u, its, relres = proj.solve(b)
     xi_new = ops.apply_CrT(g, S, u)
-    y_new = prox_primal(g, st.y - st.tau * xi_new, V, st.tau)
+    y_new = prox_primal(g, st.y - st.tau * xi_new, V, st.tau, cost)
     theta = 1.0 / np.sqrt(1.0 + 2.0 * g.gamma * st.tau)
     ybar = y_new + theta * (y_new - st.y)
     dm = float(np.linalg.norm(y_new[: g.n] - st.y[: g.n]))
@@ -94,7 +96,7 @@ def cp_step(g: Grid, S: ops.Spatial, st: CPState, V: np.ndarray, m0: np.ndarray,
 
 def cp_solve(g: Grid, V: np.ndarray, m0: np.ndarray, iters: int, method: str = "cg",
              rtol: float = 1e-10, maxit: int = 100000, state: CPState | None = None,
-             keep_info: bool = False):
+             keep_info: bool = False, cost: Coupling = LINEAR):
     """Run `iters` CP iterations from cp_init (or from `state`). Returns
     (state, list of per-iteration diagnostics)."""
     S = ops.Spatial(g)
@@ -102,7 +104,7 @@ def cp_solve(g: Grid, V: np.ndarray, m0: np.ndarray, iters: int, method: str = "
     proj = Projector(g, S, method, rtol, maxit)
     log = []
     for _ in range(iters):
-        info = cp_step(g, S, st, V, m0, proj)
+        info = cp_step(g, S, st, V, m0, proj, cost)
         if not keep_info:
             info.pop("u")
             info.pop("b")
@@ -120,7 +122,8 @@ def cg_tolerance(r_prev: float | None) -> float:
 
 
 def cp_solve_tol(g: Grid, V: np.ndarray, m0: np.ndarray, max_iter: int, cp_tol: float,
-                 maxit: int = 100000, state: CPState | None = None):
+                 maxit: int = 100000, state: CPState | None = None,
+                 cost: Coupling = LINEAR):
     """CP iterations with the stopping and inner-tolerance rules of Section 5:
     iteration l+1 solves its projection by PCG (Algorithms 1+2) to
     cg_tolerance(r_l), r_l = ||m_l - m_{l-1}||_2 of the previous iteration,
@@ -133,7 +136,7 @@ def cp_solve_tol(g: Grid, V: np.ndarray, m0: np.ndarray, max_iter: int, cp_tol: 
     r_prev = None
     for _ in range(max_iter):
         tol = cg_tolerance(r_prev)
-        info = cp_step(g, S, st, V, m0, Projector(g, S, "pcg", tol, maxit))
+        info = cp_step(g, S, st, V, m0, Projector(g, S, "pcg", tol, maxit), cost)
         info.pop("u")
         info.pop("b")
         info["cg_tol"] = tol

@@ -6,7 +6,8 @@ holds none of the solver's arithmetic, so both the plain CPU checker and the
 GPU path can take their inputs from here without sharing any method code.
 
 The paper's own workloads are analytic (Section 5.1, Problem 1; Section 5.2,
-Problem 2). The shapes below follow the configurations the GPU library is
+Problem 2) and are given here without random draws (paper_problem1/2). The
+other shapes below follow the configurations the GPU library is
 measured on: a 1-D torus with 64 nodes and 32 time steps, a 128x128 torus with
 64 time steps, the 256x256 Neumann square with 128 time steps, a batch of 32
 uneven periodic instances, and a 256x256 torus with 100 time steps for the
@@ -215,6 +216,35 @@ def small_instance(seed: int, d: int, nx: int, ny: int, nt: int, bc: str, nu: fl
         gamma = 5e-4 if bc == PERIODIC else 5e-3
     return Instance(d, nx, ny, nt, bc, nu, gamma, 1.0, lo, hi, V, m0, l=l,
                     name=f"small_{d}d_{bc}_{nx}x{ny}x{nt}")
+
+
+def paper_problem1(n: int, nt: int, nu: float) -> Instance:
+    """Problem 1 of Section 5.1 on the unit torus (d = 2, N_x = N_y = n): the
+    coupling f = (m^2 - sin 2 pi y - sin 2 pi x - cos 4 pi x)/2, written as
+    m^2/2 + V with V = -(sin 2 pi y + sin 2 pi x + cos 4 pi x)/2; m0 = 1; g = 0;
+    gamma = 5e-4. x is axis 0 (i), y axis 1 (j). No random draws."""
+    X, Y = _mesh(2, n, n, PERIODIC)
+    V = -0.5 * (np.sin(2.0 * np.pi * Y) + np.sin(2.0 * np.pi * X) + np.cos(4.0 * np.pi * X))
+    m0 = np.ones(n * n)
+    lo, hi = _bounds(2)
+    return Instance(2, n, n, nt, PERIODIC, nu, 5e-4, 1.0, lo, hi, V.reshape(-1), m0,
+                    name=f"problem1_{n}x{n}x{nt}_nu{nu:g}")
+
+
+def paper_problem2(n: int, nt: int, nu: float):
+    """Problem 2 of Section 5.2: Neumann on [-1/2, 1/2]^2 (interior nodes
+    -1/2 + i/(n+1), i = 1..n), f = 0 (V = 0), gamma = 5e-3, and the Gaussians
+    m0 = 3 exp(-2^7 ((x + 1/4)^2 + (y - 1/4)^2)) and the target
+    mbar = 3 exp(-2^7 ((x - 1/4)^2 + (y + 1/4)^2)) of the terminal penalty
+    g = (m - mbar)/beta, beta = 1e-3. No random draws.
+    Returns (Instance, mbar, beta)."""
+    x = node_coords(n, NEUMANN, -0.5, 0.5)
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    m0 = 3.0 * np.exp(-128.0 * ((X + 0.25) ** 2 + (Y - 0.25) ** 2))
+    mbar = 3.0 * np.exp(-128.0 * ((X - 0.25) ** 2 + (Y + 0.25) ** 2))
+    inst = Instance(2, n, n, nt, NEUMANN, nu, 5e-3, 1.0, (-0.5, -0.5), (0.5, 0.5),
+                    np.zeros(n * n), m0.reshape(-1), name=f"problem2_{n}x{n}x{nt}_nu{nu:g}")
+    return inst, mbar.reshape(-1), 1e-3
 
 
 def random_vector(seed: int, size: int) -> np.ndarray:
