@@ -187,7 +187,8 @@ int mfg_cp_init(mfg_plan_t plan, mfg_state_t* st);
  * z = xi + sigma ybar in plan workspace (the right-hand side needs nothing
  * else); the last iteration writes them back, so the state after the call is
  * bitwise that of n_iter single-iteration calls. If the call fails with an
- * error other than MFG_ERR_NOT_CONVERGED, the state's vectors are unspecified.
+ * error other than MFG_ERR_NOT_CONVERGED, the state's vectors are unspecified
+ * and st->iter is set to -1 (the state must be re-initialised).
  * Returns MFG_ERR_NOT_CONVERGED (after finishing all iterations) if some PCG
  * solve hit pcg_maxit. */
 int mfg_cp_solve(mfg_plan_t plan, mfg_state_t* st, int n_iter, double pcg_rtol,
@@ -272,7 +273,8 @@ int mfg_batch_destroy(mfg_batch_t batch);
  * HIP graph for each step after the first one of the batch's life; 0 issues
  * the same launches eagerly. pcg_iters (host, may be NULL): n_iter * count
  * entries, [iteration][instance]. Returns MFG_ERR_NOT_CONVERGED (after all
- * iterations) if some solve reached pcg_maxit. */
+ * iterations) if some solve reached pcg_maxit. On any other error every
+ * state's vectors are unspecified and its iter is set to -1. */
 int mfg_batch_cp_solve(mfg_batch_t batch, mfg_state_t* states, int n_iter, double pcg_rtol,
                        int pcg_maxit, int use_graph, int* pcg_iters);
 

@@ -36,7 +36,7 @@ static bool size_ok(int N) {
   return n == 1;
 }
 
-static void radices(int N, int* r, int* np) {
+void radices(int N, int* r, int* np) {
   int n = N, k = 0;
   while (n % 4 == 0) { r[k++] = 4; n /= 4; }
   while (n % 2 == 0) { r[k++] = 2; n /= 2; }
@@ -177,8 +177,9 @@ static void read_tune_env(Tune& t) {
   }
 }
 
-static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const double* m0,
-                      hipStream_t stream) {
+// Validate the problem and fill the plan's geometry and scalars (no device
+// allocation, no table).
+int setup_problem(Plan& P, const mfg_problem_t* pb, hipStream_t stream) {
   if (!pb) return fail(MFG_ERR_INVALID_ARG, "problem is NULL");
   if (pb->d != 1 && pb->d != 2) return fail(MFG_ERR_INVALID_ARG, "d must be 1 or 2");
   for (int a = 0; a < pb->d; ++a) {
@@ -254,8 +255,23 @@ static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const d
   }
   g.M = g.n0 * g.n1;
   g.n = (long long)g.nt * g.M;
+  return MFG_OK;
+}
 
-  int rc = check_fields(P, V, m0, true);
+static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const double* m0,
+                      hipStream_t stream) {
+  int rc = setup_problem(P, pb, stream);
+  if (rc) return rc;
+  const Geom& g = P.g;
+  const bool neu = pb->bc == MFG_BC_NEUMANN;
+  auto spacing = [&](int a) {
+    const double L = pb->hi[a] - pb->lo[a];
+    return neu ? L / (pb->n[a] + 1) : L / pb->n[a];
+  };
+  // V and m0 may come from work queued on the caller's stream
+  if (stream) HIP_TRY(hipStreamSynchronize(stream));
+  else HIP_TRY(hipDeviceSynchronize());
+  rc = check_fields(P, V, m0, true);
   if (rc) return rc;
 
   // problem data
@@ -409,7 +425,7 @@ void prof_end(const Plan& Pc, int id, hipStream_t s) {
   (void)hipEventRecord(P.prof.pending[id].b, s);
 }
 
-static int read_scalars(Plan& P) {
+int read_scalars(Plan& P) {
   HIP_TRY(hipMemcpyAsync(P.host_scal, P.red.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
                          P.stream));
   HIP_TRY(hipStreamSynchronize(P.stream));
@@ -424,8 +440,8 @@ static int read_scalars(Plan& P) {
 // long as the previous solve on this plan; later ones are single iterations.
 // r_ready: the start (r = b, b.b, status reset) was already done by the
 // kernel that formed b (b is then not needed).
-static int run_pcg(Plan& P, const double* b, double* x, double rtol, int maxit, int* iters_out,
-                   double* relres_rec, double* relres_true, bool r_ready = false) {
+int run_pcg(Plan& P, const double* b, double* x, double rtol, int maxit, int* iters_out,
+            double* relres_rec, double* relres_true, bool r_ready) {
   hipStream_t s = P.stream;
   P.pcg_done = P.red.scal + S_DONE;
   if (!r_ready) launch_pcg_init(P, b, P.r, rtol, s);
@@ -734,7 +750,12 @@ int mfg_cp_solve(mfg_plan_t plan, mfg_state_t* st, int n_iter, double pcg_rtol, 
       for (int it = 0; it < n_iter; ++it) stats->dm[it] = std::sqrt(dm_host[it]);
     (void)hipHostFree(dm_host);
   }
-  if (rc) return rc;
+  if (rc) {
+    // a step after the first may have left xi and ybar only in the z hand-off
+    // buffer: the state is marked unusable
+    st->iter = -1;
+    return rc;
+  }
   if (final_rc) return fail(final_rc, "some PCG solve reached maxit");
   return MFG_OK;
 }

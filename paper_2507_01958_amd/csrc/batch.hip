@@ -504,41 +504,47 @@ int batch_cp_solve(Batch& B, mfg_state_t* st, int n_iter, double rtol, int maxit
   hipLaunchKernelGGL(k_batch_set, dim3((n + 63) / 64), dim3(64), 0, s, B.scal_all, S_COUNT, n,
                      (int)S_ZMODE, 0.0);
   int final_rc = MFG_OK;
+  // an error inside the loop leaves the states part-way through a step (the
+  // device vectors moved, the scalars not): they are marked unusable
+  auto abandon = [&](int code, const std::string& msg) {
+    for (int i = 0; i < n; ++i) st[i].iter = -1;
+    return fail(code, msg);
+  };
   for (int it = 0; it < n_iter; ++it) {
     int K = std::min(B.graph_k > 0 ? B.graph_k : 8, maxit);
     if (use_graph && !B.exec && it > 0) {
       // capture with the iteration count the first steps needed
       if (hipStreamBeginCapture(s, hipStreamCaptureModeGlobal) != hipSuccess)
-        return fail(MFG_ERR_HIP, "graph capture failed to start");
+        return abandon(MFG_ERR_HIP, "graph capture failed to start");
       step_head(B, K, B.sched_cap, s);
       if (hipStreamEndCapture(s, &B.graph) != hipSuccess ||
           hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0) != hipSuccess) {
         release_graph(B);
-        return fail(MFG_ERR_HIP, "graph instantiation failed");
+        return abandon(MFG_ERR_HIP, "graph instantiation failed");
       }
       B.graph_k = K;
     }
     if (use_graph && B.exec) {
-      if (hipGraphLaunch(B.exec, s) != hipSuccess) return fail(MFG_ERR_HIP, "graph launch failed");
+      if (hipGraphLaunch(B.exec, s) != hipSuccess) return abandon(MFG_ERR_HIP, "graph launch failed");
     } else {
       step_head(B, K, B.sched_cap, s);
     }
     int rc = read_all(B);
-    if (rc) return rc;
+    if (rc) return abandon(rc, mfg_last_error());
     int k = K;
     int maxits = 0;
     while (true) {
       bool all = true;
       for (int i = 0; i < n; ++i) {
         const double* S = B.host_scal + (size_t)i * S_COUNT;
-        if (S[S_BAD] == 2.0) return fail(MFG_ERR_NONFINITE, "non-finite value in a batched PCG");
-        if (S[S_BAD] == 1.0) return fail(MFG_ERR_BREAKDOWN, "breakdown in a batched PCG");
+        if (S[S_BAD] == 2.0) return abandon(MFG_ERR_NONFINITE, "non-finite value in a batched PCG");
+        if (S[S_BAD] == 1.0) return abandon(MFG_ERR_BREAKDOWN, "breakdown in a batched PCG");
         if (S[S_DONE] == 0.0) all = false;
       }
       if (all || k >= maxit) break;
       ++k;
       pcg_iteration(B, k, s);
-      if ((rc = read_all(B))) return rc;
+      if ((rc = read_all(B))) return abandon(rc, mfg_last_error());
     }
     for (int i = 0; i < n; ++i) {
       const double* S = B.host_scal + (size_t)i * S_COUNT;

@@ -126,6 +126,18 @@ inline bool pcg_flexible(const Plan& P) {
   return P.precision != MFG_MIXED_FP32;
 }
 
+// api.hip: validate a problem and fill the plan's geometry (no allocation);
+// PCG on the plan's workspace (r_ready: the start r = b, b.b, status reset was
+// already done by the kernel that formed b); copy the device scalars to
+// P.host_scal (synchronises the plan's stream).
+int setup_problem(Plan& P, const mfg_problem_t* pb, hipStream_t stream);
+int run_pcg(Plan& P, const double* b, double* x, double rtol, int maxit, int* iters_out,
+            double* relres_rec, double* relres_true, bool r_ready = false);
+int read_scalars(Plan& P);
+int fail(int code, const std::string& msg);
+// Radix sequence (4s, then 2s, then 3s) of a spatial FFT of length N.
+void radices(int N, int* r, int* np);
+
 // Launch-shape autotuner (tune.hip): cached choice for the plan's key, and
 // measurement of the candidates (allow_pers = false excludes the persistent
 // time GEMM, which batched launches do not use).

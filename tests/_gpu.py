@@ -41,3 +41,18 @@ def empty(n):
 
 def say(msg):
     print(msg, flush=True)
+
+
+def fp64_floor(g):
+    """u * kappa(A) for the reduced matrix of eq. largeA: the scale of the
+    forward error of any backward-stable float64 solve with it (u = 2^-53).
+    lambda_max is bounded by the largest absolute row sum (Gershgorin) of the
+    block rows C + I/dt^2 and -L/dt twice; lambda_min = lambda_1(l = 1)/dt^2,
+    attained on spatially constant vectors."""
+    from oracle import operators as ops
+    from oracle import precond as pc
+    S = ops.Spatial(g)
+    rows = (np.asarray(abs(S.C).sum(axis=1)).ravel() + 1.0 / g.dt ** 2
+            + 2.0 * np.asarray(abs(S.L).sum(axis=1)).ravel() / g.dt)
+    lmin = pc.time_eigs(g.nt, 1)[0] / g.dt ** 2
+    return 0.5 * np.finfo(float).eps * rows.max() / lmin
