@@ -290,6 +290,24 @@ int mfg_profile(mfg_plan_t plan, int enable);
  * small. */
 int mfg_profile_report(mfg_plan_t plan, char* buf, int len);
 
+/* ---- Without device allocation ------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * mfg_pcg_noalloc solves A u = b as mfg_pcg does (same kernels, same stopping
+ * rule; the tables are computed on the device, so results agree with mfg_pcg
+ * to rounding), for the problem *pb, with no plan. It allocates nothing: the
+ * preconditioner's tables, the PCG workspace (6 n-vectors) and the reduction
+ * buffers live in a 64 MiB device array of the library that each GPU it runs
+ * on holds until the process ends. Limits: N_t <= 128 and about 2^20 cells
+ * (n = N_t N_x N_y), MFG_ERR_UNSUPPORTED beyond. b, u: device n-vectors (must
+ * not alias); runs on `stream` (0: the null stream) of the current device and
+ * synchronises it (iters, relres as for mfg_pcg). Every call on a GPU uses
+ * that GPU's one array and overwrites what the previous call left there:
+ * calls that overlap on one GPU (other threads, other streams) race and must
+ * be serialised by the caller. */
+int mfg_pcg_noalloc(const mfg_problem_t* pb, const double* b, double* u, double rtol, int maxit,
+                    hipStream_t stream, int* iters, double* relres);
+
 /* Human-readable description of the last error on this thread. */
 const char* mfg_last_error(void);
 

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmfg.so")
 SOURCES = ["api.hip", "stencil.hip", "vec.hip", "precond.hip", "tgemm.hip", "adjoint.hip",
-           "batch.hip", "tune.hip"]
+           "batch.hip", "tune.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

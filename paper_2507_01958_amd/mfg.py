@@ -71,6 +71,8 @@ SIGNATURES = {
     "mfg_batch_destroy": (c_int, [c_void_p]),
     "mfg_batch_cp_solve": (c_int, [c_void_p, POINTER(State), c_int, c_double, c_int, c_int,
                                    POINTER(c_int)]),
+    "mfg_pcg_noalloc": (c_int, [POINTER(Problem), c_void_p, c_void_p, c_double, c_int, c_void_p,
+                                POINTER(c_int), POINTER(c_double)]),
     "mfg_profile": (c_int, [c_void_p, c_int]),
     "mfg_profile_report": (c_int, [c_void_p, ctypes.c_char_p, c_int]),
     "mfg_last_error": (c_char_p, []),
@@ -226,6 +228,18 @@ def mfg_pcg(plan: Plan, b, u, rtol: float, maxit: int, true_residual: bool = Tru
                         ctypes.byref(rel) if true_residual else None)
     _check(rc, allow=() if raise_not_converged else (3,))
     return its.value, (rel.value if true_residual else None), rc
+
+
+def mfg_pcg_noalloc(problem: Problem, b, u, rtol: float, maxit: int, stream=None,
+                    raise_not_converged: bool = True):
+    """PCG without a plan or any device allocation. Returns (iterations, true
+    relative residual, status)."""
+    its = c_int(0)
+    rel = c_double(0.0)
+    rc = load().mfg_pcg_noalloc(ctypes.byref(problem), _ptr(b), _ptr(u), float(rtol), int(maxit),
+                                _stream(stream), ctypes.byref(its), ctypes.byref(rel))
+    _check(rc, allow=() if raise_not_converged else (3,))
+    return its.value, rel.value, rc
 
 
 class CPState:
