@@ -160,11 +160,12 @@ def parse():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--nt", type=int, default=128)
     ap.add_argument("--workload", default="neumann256",
-                    choices=["neumann256", "batch", "grad", "adaptive"],
+                    choices=["neumann256", "batch", "grad", "adaptive", "paper"],
                     help="neumann256: the headline line; batch: 32 uneven periodic instances, "
                          "batched vs one plan at a time; grad: gradient through 50 CP "
                          "iterations; adaptive: time to solution with the Section 5 "
-                         "stopping and inner-tolerance rules")
+                         "stopping and inner-tolerance rules; paper: the paper's Problems 1 "
+                         "and 2 at N_x = 64, N_t = 512 with those rules")
     ap.add_argument("--batch", type=int, default=32, help="instances of the batch workload")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of tuning them first")
@@ -363,6 +364,78 @@ def bench_adaptive(args):
     }))
 
 
+# The paper's own runs at N_x = 64, N_t = 512, nu = 1e-2 (Tables 5.1 and 5.3, the
+# DCT-VIII preconditioner, 32 CPU cores): CP iterations, average CG iterations
+# per projection and total seconds. Context, not a target: another machine and a
+# CPU implementation.
+PAPER_CONTEXT = {"problem1": {"cp_iters": 70, "avg_cg": 2.4, "seconds": 234.78,
+                              "table": "5.1"},
+                 "problem2": {"cp_iters": 532, "avg_cg": 3.6, "seconds": 641.61,
+                              "table": "5.3"}}
+
+
+def bench_paper(args):
+    """The paper's two problems (Section 5.1: periodic, f = m^2/2 + V with the
+    trigonometric V, m0 = 1; Section 5.2: Neumann on [-1/2, 1/2]^2, f = 0, terminal
+    cost (m - mbar)/beta with beta = 1e-3, Gaussian m0 and mbar) at the shape of
+    Tables 5.1 / 5.3, N_x = N_y = 64, N_t = 8 N_x = 512, nu = 1e-2, solved with the
+    Section 5 rules (CP until ||dm|| <= 1e-4 ||m0||, CGtol rule), FP64 and the FP32
+    preconditioner; time to solution after one untimed solve."""
+    import numpy as np
+    import torch
+
+    from paper_2507_01958_amd import mfg
+    from paper_2507_01958_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, nt, nu = args.size if args.size != 256 else 64, args.nt if args.nt != 128 else 512, 1e-2
+    res = {}
+    for prob in ("problem1", "problem2"):
+        if prob == "problem1":
+            inst, coupling, beta, mbar = wl.paper_problem1(n, nt, nu), "quadratic", 0.0, None
+        else:
+            inst, mbar, beta = wl.paper_problem2(n, nt, nu)
+            coupling = "potential"
+        V = torch.from_numpy(inst.V).to(dev)
+        m0 = torch.from_numpy(inst.m0).to(dev)
+        cp_tol = 1e-4 * float(np.linalg.norm(inst.m0))
+        res[prob] = {"paper": PAPER_CONTEXT[prob]}
+        for variant in ("fp64", "mixed_fp32"):
+            pb = mfg.make_problem(2, inst.nx, inst.ny, inst.nt, inst.bc, inst.nu, inst.gamma,
+                                  l=1, precision=variant, T=inst.T, lo=inst.lo, hi=inst.hi,
+                                  coupling=coupling, beta=beta)
+            with mfg.mfg_plan(pb, V, m0) as P:
+                if mbar is not None:
+                    mfg.mfg_set_target(P, torch.from_numpy(mbar).to(dev))
+                if not args.no_autotune:
+                    mfg.mfg_autotune(P, 1)
+                st = mfg.CPState(P)
+                for rep in range(2):
+                    mfg.mfg_cp_init(P, st)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    out = mfg.mfg_cp_solve_tol(P, st, 6000, cp_tol, 1000)
+                    torch.cuda.synchronize()
+                    t = time.perf_counter() - t0
+            k = out["n_done"]
+            res[prob][variant] = {"seconds": t, "cp_iters": k,
+                                  "avg_pcg_iters": float(np.mean(out["pcg_iters"])),
+                                  "converged": out["dm"][-1] <= cp_tol, "final_dm": out["dm"][-1],
+                                  "cp_iters_per_s": k / t}
+    best = min(("fp64", "mixed_fp32"), key=lambda v: res["problem1"][v]["seconds"])
+    print(json.dumps({
+        "metric": "time to solution of the paper's Problem 1 (64^2x512, nu=1e-2, Section 5 rules)",
+        "value": res["problem1"][best]["seconds"], "unit": "s",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1e3 * res["problem1"][best]["seconds"] / res["problem1"][best]["cp_iters"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+fp32" if best == "mixed_fp32" else "f64", "data": "analytic (Section 5)",
+        "config": {"workload": f"paper_problems_{n}x{n}x{nt}_nu{nu:g}", "variant": best},
+        "problems": res, "roofline": None, "cpu_baseline": None,
+    }))
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -381,6 +454,9 @@ def main():
     if args.workload == "adaptive":
         bench_adaptive(args)
         return
+    if args.workload == "paper":
+        bench_paper(args)
+        return
     import numpy as np
     import torch
 
@@ -393,6 +469,19 @@ def main():
     V = torch.from_numpy(inst.V).to(dev)
     m0 = torch.from_numpy(inst.m0).to(dev)
     stream = torch.cuda.current_stream()
+
+    # the right-hand side of CP iteration 50 of the float64 run (the PCG
+    # solves/s are measured on it, on the first one, and on a N(0,1) vector)
+    with mfg.mfg_plan(_problem(inst, "fp64"), V, m0, stream) as P:
+        st = mfg.CPState(P)
+        mfg.mfg_cp_init(P, st)
+        mfg.mfg_cp_solve(P, st, 49, RTOL, PCG_MAXIT, stats=False)
+        z = st.xi + st.sigma * st.ybar
+        b50 = torch.empty(inst.n, dtype=torch.float64, device=dev)
+        mfg.mfg_apply_C(P, z, b50)
+        b50[: inst.M] -= st.sigma * m0 * (inst.nt / inst.T)
+        torch.cuda.synchronize()
+        del st, z
 
     results = {}
     for variant in args.variants.split(","):
@@ -411,8 +500,9 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         cp_rate = args.steps / dt
-        # PCG solves: seeded N(0,1) right-hand side and the first projection's
-        # right-hand side Cr ybar0 - dr (ybar0 = (m0 at every slice, w = 0)).
+        # PCG solves: seeded N(0,1) right-hand side, the first projection's
+        # right-hand side Cr ybar0 - dr (ybar0 = (m0 at every slice, w = 0)) and
+        # the one of CP iteration 50 (from the float64 run above).
         rhs = {}
         rhs["randn"] = torch.from_numpy(wl.random_vector(33, inst.n)).to(dev)
         y0 = torch.zeros(P.nprimal, dtype=torch.float64, device=dev)
@@ -421,6 +511,7 @@ def main():
         mfg.mfg_apply_C(P, y0, b1)
         b1[: inst.M] -= m0 * (inst.nt / inst.T)
         rhs["cp_iter1"] = b1
+        rhs["cp_iter50"] = b50
         u = torch.empty(inst.n, dtype=torch.float64, device=dev)
         pcg = {}
         for name, b in rhs.items():

@@ -56,6 +56,12 @@ typedef enum {
 
 typedef enum { MFG_BC_PERIODIC = 0, MFG_BC_NEUMANN = 1 } mfg_bc_t;
 
+/* Coupling f(x, m) of the running cost F = integral of f dm (Section 2.1):
+ * LINEAR f = m + V(x); QUADRATIC f = m^2/2 + V(x), the crowd-aversion coupling
+ * of Problem 1 (Section 5.1, where V = -(sin 2 pi y + sin 2 pi x + cos 4 pi x)/2);
+ * POTENTIAL f = V(x), independent of m (Problem 2 of Section 5.2 has V = 0). */
+typedef enum { MFG_F_LINEAR = 0, MFG_F_QUADRATIC = 1, MFG_F_POTENTIAL = 2 } mfg_coupling_t;
+
 /* Arithmetic of the preconditioner inside PCG. The outer PCG recurrences,
  * the reduced-matrix products, the right-hand side and the prox are float64
  * in every mode. MIXED modes run the spatial solves (Algorithm 2) in float32
@@ -96,16 +102,22 @@ typedef struct {
   int l;             /* time preconditioner of eq. prec: 1 = DCT-VIII (exact
                         at nu = 0), 2 = DST-I */
   int precision;     /* mfg_precision_t */
+  int coupling;      /* mfg_coupling_t (0: f = m + V) */
+  double beta;       /* terminal cost g(x, m) = (m - mbar(x))/beta of Section 5.2
+                        when beta > 0 (it enters the objective as G/dt on the last
+                        time slice, G the primitive of g); 0: g = 0. mbar is set by
+                        mfg_set_target and is zero until then. */
 } mfg_problem_t;
 
 typedef struct mfg_plan_s* mfg_plan_t;
 
 /* Build a plan: validate the problem, compute the grid constants and the
  * eigenvalue / transform tables (eqs. eigs, lambda1, lambda2) and allocate the
- * plan's workspace (about 8 n-vectors plus one primal vector). V (the potential of the coupling
- * f(x, m) = m + V(x), M values) and m0 (initial density, M values, >= 0 and
- * finite) are device pointers; the plan copies them. stream may be 0 (the
- * null stream). The coupling is f = m + V and the terminal cost g = 0. */
+ * plan's workspace (about 8 n-vectors plus one primal vector). V (the potential
+ * of the coupling, M values) and m0 (initial density, M values, >= 0 and
+ * finite) are device pointers; the plan copies them after synchronising
+ * `stream` (work queued there may produce them). stream may be 0 (the null
+ * stream). */
 int mfg_plan(const mfg_problem_t* pb, const double* V, const double* m0,
              hipStream_t stream, mfg_plan_t* out);
 
@@ -119,9 +131,15 @@ int mfg_set_stream(mfg_plan_t plan, hipStream_t stream);
  * values; NULL keeps the current one). */
 int mfg_set_data(mfg_plan_t plan, const double* V, const double* m0);
 
-/* Proximal step of Section 3: y = prox_{tau phi}(v) for phi = B-hat + F, cell by
- * cell, with F(m) = m^2/2 + V m (primitive of f = m + V) and b-hat(m, w) =
- * |w|^2/(2m) on the cone. v, y: primal vectors; y may alias v. tau > 0. */
+/* Target density mbar of the terminal cost g = (m - mbar)/beta (Section 5.2):
+ * device pointer, M finite values, copied. MFG_ERR_INVALID_ARG if the problem
+ * has no terminal cost (beta = 0). */
+int mfg_set_target(mfg_plan_t plan, const double* mbar);
+
+/* Proximal step of Section 3: y = prox_{tau phi}(v) for phi = B-hat + F (+ G/dt
+ * on the last time slice), cell by cell, with F the primitive of the coupling
+ * f (mfg_coupling_t), G that of the terminal cost, and b-hat(m, w) = |w|^2/(2m)
+ * on the cone. v, y: primal vectors; y may alias v. tau > 0. */
 int mfg_prox(mfg_plan_t plan, const double* v, double tau, double* y);
 
 /* q = A u with A = Cr Cr^T the reduced matrix of eq. largeA (u, q: n-vectors;
@@ -171,6 +189,11 @@ typedef struct {
   int* pcg_iters;     /* PCG iterations of each projection */
   double* pcg_relres; /* final recursive relative residual of each PCG */
   double* dm;         /* ||m_{l+1} - m_l||_2 */
+  double* mass_drift; /* max over time slices t of |h^d sum_i m^{t+1}_i - h^d sum_i m0_i|
+                         for the primal iterate y after the iteration (h^d the cell
+                         measure); its projection conserves the mass up to the PCG
+                         residual, y itself up to the CP convergence. Costs one
+                         read of the m block per iteration. */
 } mfg_stats_t;
 
 /* Initial point: xi = 0, y = ybar = (m0 at every time slice, w = 0),
@@ -224,6 +247,26 @@ int mfg_cp_solve_tol(mfg_plan_t plan, mfg_state_t* st, int max_iter, double cp_t
 int mfg_cp_adjoint(mfg_plan_t plan, const mfg_state_t* ckpts, int n_ckpt, int every, int n_iter,
                    const double* gy, double pcg_rtol, int pcg_maxit, double* g_m0,
                    double* g_V);
+
+/* Value function of the discrete MFG system (Section 2, scheme MFG_T^2_h)
+ * read off a Chambolle-Pock state: the multiplier lam of the reduced
+ * constraint solves A lam = Cr xi (eq. largeA; PCG to pcg_rtol, at most
+ * pcg_maxit iterations, from zero), and u^k = -lam_k for k < N_t, u^{N_t} =
+ * g(x, m^{N_t}) (0 without a terminal cost). At a fixed point of the
+ * iteration this u and the state's (m, w) satisfy the scheme: the HJB
+ * equation (see mfg_hjb_residual) and w^k = m^{k+1} P_K(-[D_h u^k]).
+ * u: device array of (N_t + 1) M values, [k][i][j]. MFG_ERR_NOT_CONVERGED if
+ * the solve reached pcg_maxit (u still written). */
+int mfg_value_function(mfg_plan_t plan, const mfg_state_t* st, double pcg_rtol, int pcg_maxit,
+                       double* u);
+
+/* Residual of the HJB equation of (MFG_T^2_h) per cell, for k = 0..N_t-1:
+ *   R^k = (u^k - u^{k+1})/dt + nu K u^k + |P_K(-[D_h u^k])|^2 / 2 - f(x, m^{k+1}),
+ * K the negative discrete Laplacian, -[D_h u] the four one-sided differences of
+ * Section 2 (zero across a Neumann boundary), f the coupling. It vanishes where
+ * m > 0 and is <= 0 where m = 0 at a solution. y: primal vector (its m block is
+ * used), u: (N_t + 1) M values as from mfg_value_function, R: n-vector. */
+int mfg_hjb_residual(mfg_plan_t plan, const double* y, const double* u, double* R);
 
 /* Autotune the plan's launch shapes (how the preconditioner passes split
  * work among thread blocks: rows per block of the row transforms, column

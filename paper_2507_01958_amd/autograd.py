@@ -7,6 +7,8 @@ with respect to m0 and V. The forward pass keeps a copy of the state every
 `every` iterations; the backward pass is the library's reverse sweep
 (mfg_cp_adjoint): it recomputes each segment from its checkpoint and runs one
 solve with the symmetric reduced matrix (the same PCG) per reverse step.
+The coupling and terminal cost are the problem's; `mbar` is the target density
+of a terminal cost (problem.beta > 0), held fixed (not differentiated).
 """
 from __future__ import annotations
 
@@ -17,8 +19,10 @@ from . import mfg
 
 class _CPSolve(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, m0, V, problem, n_iter, every, rtol, maxit):
+    def forward(ctx, m0, V, problem, n_iter, every, rtol, maxit, mbar):
         plan = mfg.mfg_plan(problem, V.detach().contiguous(), m0.detach().contiguous())
+        if mbar is not None:
+            mfg.mfg_set_target(plan, mbar.detach().contiguous())
         st = mfg.CPState(plan)
         mfg.mfg_cp_init(plan, st)
         ckpts = []
@@ -43,13 +47,13 @@ class _CPSolve(torch.autograd.Function):
         mfg.mfg_cp_adjoint(plan, ctx.ckpts, every, n_iter, gy.contiguous(), rtol, maxit, g_m0,
                            g_V)
         ctx.ckpts = None
-        return g_m0, g_V, None, None, None, None, None
+        return g_m0, g_V, None, None, None, None, None, None
 
 
 def cp_solve(problem, m0, V, n_iter: int, rtol: float = 1e-10, maxit: int = 500,
-             every: int = 10):
+             every: int = 10, mbar=None):
     """Final primal iterate after n_iter CP iterations; differentiable in m0, V."""
-    return _CPSolve.apply(m0, V, problem, int(n_iter), int(every), float(rtol), int(maxit))
+    return _CPSolve.apply(m0, V, problem, int(n_iter), int(every), float(rtol), int(maxit), mbar)
 
 
 def terminal_m(problem, y):

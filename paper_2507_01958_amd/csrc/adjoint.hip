@@ -13,12 +13,14 @@
 // m-parts of g_y_0 + g_ybar_0, summed over slices, to g_m0.
 //
 // Prox Jacobian (implicit function theorem on h'(m) = 0, active branch m > 0,
-// s = m + tau, a = |w~|^2, g = a/s^3 + 1 + 1/tau):
+// s = m + tau, a = |w~|^2, g = a/s^3 + 2 c2 m + c1 + 1/tau with the cell's
+// coupling coefficients, the terminal cost included on the last slice):
 //   dm/dmbar = 1/(tau g), dm/dV = -1/g, dm/dwbar_c = chi_c w~_c/(s^2 g),
 //   dw_c = (tau/s^2) w~_c dm + (m/s) chi_c dwbar_c   (chi_c: wbar_c strictly
 //   inside its half-line); zero on the inactive branch.
 #include "device_util.h"
 #include "plan.h"
+#include "prox_cell.h"
 
 namespace mfg {
 
@@ -33,31 +35,8 @@ int grid_for(long long n) {
   return (int)b;
 }
 
-// Same arithmetic as the forward prox (stencil.hip) so that the root m is
-// reproduced exactly; returns m and leaves w~ (the projected wbar) in w.
-__device__ __forceinline__ double prox_root(double mbar, double* w, int ncomp, double V,
-                                            double tau, double& a_out) {
-  double a = 0.0;
-  for (int c = 0; c < ncomp; ++c) {
-    double v = w[c];
-    v = (c & 1) ? fmin(v, 0.0) : fmax(v, 0.0);
-    w[c] = v;
-    a += v * v;
-  }
-  a_out = a;
-  if (2.0 * tau * tau * V - 2.0 * tau * mbar - a >= 0.0) return 0.0;
-  double m = fmax(0.0, (mbar - tau * V) / (1.0 + tau));
-  const double k1 = 1.0 + 1.0 / tau;
-  for (int it = 0; it < 64; ++it) {
-    const double s = m + tau;
-    const double hp = -a / (2.0 * s * s) + k1 * m + V - mbar / tau;
-    const double hpp = a / (s * s * s) + k1;
-    const double mn = m - hp / hpp;
-    if (!(mn > m)) break;
-    m = mn;
-  }
-  return m;
-}
+// The root m is recomputed with the forward prox's own code (prox_cell.h), so
+// it is reproduced exactly.
 
 // Fused reverse of extrapolation + prox + (v = y - tau xi') for one step.
 // In place: gy <- g_y (previous iterate), gxi <- g_xi' - tau g_v. gVc[p] is the
@@ -66,6 +45,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_prox(Geom g, double* __restric
                                                        const double* __restrict__ gyb,
                                                        const double* __restrict__ v,
                                                        const double* __restrict__ Vpot,
+                                                       const double* __restrict__ VT,
                                                        double tau, double theta,
                                                        double* __restrict__ gxi,
                                                        double* __restrict__ gVc) {
@@ -73,10 +53,17 @@ __global__ __launch_bounds__(kThreads) void k_adj_prox(Geom g, double* __restric
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
        p += (long long)gridDim.x * blockDim.x) {
     const int rem = (int)((unsigned)p % (unsigned)g.M);  // n < 2^31
+    const bool lastslice = (unsigned)p >= (unsigned)(g.nt - 1) * (unsigned)g.M;
+    const double c1 = lastslice ? g.c1T : g.c1;
     double wb[4], wt[4], gyn[5], gv[5];
-    for (int c = 0; c < g.ncomp; ++c) wb[c] = wt[c] = v[(size_t)(c + 1) * n + p];
-    double a;
-    const double m = prox_root(v[p], wt, g.ncomp, Vpot[rem], tau, a);
+    double a = 0.0;
+    for (int c = 0; c < g.ncomp; ++c) {
+      const double x = v[(size_t)(c + 1) * n + p];
+      wb[c] = x;
+      wt[c] = (c & 1) ? fmin(x, 0.0) : fmax(x, 0.0);
+      a += wt[c] * wt[c];
+    }
+    const double m = prox_root(v[p], a, lastslice ? VT[rem] : Vpot[rem], tau, c1, g.c2);
     for (int c = 0; c <= g.ncomp; ++c) {
       const size_t o = (size_t)c * n + p;
       gyn[c] = gy[o] + (1.0 + theta) * gyb[o];
@@ -84,7 +71,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_prox(Geom g, double* __restric
     double gV = 0.0;
     if (m > 0.0) {
       const double s = m + tau;
-      const double gpp = a / (s * s * s) + 1.0 + 1.0 / tau;
+      const double gpp = a / (s * s * s) + 2.0 * g.c2 * m + c1 + 1.0 / tau;
       double gm_tot = gyn[0];
       for (int c = 0; c < g.ncomp; ++c) gm_tot += gyn[1 + c] * (tau / (s * s)) * wt[c];
       gv[0] = gm_tot / (tau * gpp);
@@ -135,7 +122,7 @@ void launch_adj_prox(const Plan& P, double* gy, const double* gyb, const double*
                      double theta, double* gxi, double* gVc, hipStream_t s) {
   ProfScope ps(P, "adj_prox", s);
   hipLaunchKernelGGL(k_adj_prox, dim3(grid_for(P.g.n)), dim3(kThreads), 0, s, P.g, gy, gyb, v,
-                     (const double*)P.V, tau, theta, gxi, gVc);
+                     (const double*)P.V, (const double*)P.VT, tau, theta, gxi, gVc);
 }
 
 void launch_sum_slices(const Plan& P, const double* in, const double* in2, double* out,

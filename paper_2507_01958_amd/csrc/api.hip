@@ -206,6 +206,10 @@ int setup_problem(Plan& P, const mfg_problem_t* pb, hipStream_t stream) {
   if (pb->l != 1 && pb->l != 2) return fail(MFG_ERR_INVALID_ARG, "l must be 1 or 2");
   if (pb->precision < MFG_FP64 || pb->precision > MFG_MIXED_BF16)
     return fail(MFG_ERR_INVALID_ARG, "unknown precision");
+  if (pb->coupling < MFG_F_LINEAR || pb->coupling > MFG_F_POTENTIAL)
+    return fail(MFG_ERR_INVALID_ARG, "unknown coupling");
+  if (!(pb->beta >= 0.0) || !std::isfinite(pb->beta))
+    return fail(MFG_ERR_INVALID_ARG, "beta must be >= 0 (0: no terminal cost)");
 
   P.pb = *pb;
   P.stream = stream;
@@ -255,6 +259,12 @@ int setup_problem(Plan& P, const mfg_problem_t* pb, hipStream_t stream) {
   }
   g.M = g.n0 * g.n1;
   g.n = (long long)g.nt * g.M;
+  // coupling f = c2 m^2 + c1 m + V; the terminal cost adds 1/(beta dt) to the
+  // last slice's linear coefficient
+  g.c2 = pb->coupling == MFG_F_QUADRATIC ? 0.5 : 0.0;
+  g.c1 = pb->coupling == MFG_F_LINEAR ? 1.0 : 0.0;
+  g.c1T = pb->beta > 0.0 ? g.c1 + 1.0 / (pb->beta * g.dt) : g.c1;
+  P.beta = pb->beta;
   return MFG_OK;
 }
 
@@ -274,10 +284,15 @@ static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const d
   rc = check_fields(P, V, m0, true);
   if (rc) return rc;
 
-  // problem data
-  if ((rc = dalloc(P, &P.V, g.M)) || (rc = dalloc(P, &P.m0, g.M))) return rc;
+  // problem data; the terminal target starts at zero
+  if ((rc = dalloc(P, &P.V, g.M)) || (rc = dalloc(P, &P.m0, g.M)) ||
+      (rc = dalloc(P, &P.mbar, g.M)) || (rc = dalloc(P, &P.VT, g.M)))
+    return rc;
   HIP_TRY(hipMemcpy(P.V, V, g.M * sizeof(double), hipMemcpyDeviceToDevice));
   HIP_TRY(hipMemcpy(P.m0, m0, g.M * sizeof(double), hipMemcpyDeviceToDevice));
+  HIP_TRY(hipMemset(P.mbar, 0, g.M * sizeof(double)));
+  launch_terminal_potential(P, nullptr);
+  HIP_TRY(hipGetLastError());
 
   // time transform (eq. eigs and the DCT-VIII / DST-I of Section 4.1)
   const int nt = g.nt;
@@ -644,9 +659,55 @@ int mfg_set_data(mfg_plan_t plan, const double* V, const double* m0) {
   HIP_TRY(hipStreamSynchronize(P.stream));
   int rc = mfg::check_fields(P, V, m0, false);
   if (rc) return rc;
-  if (V) HIP_TRY(hipMemcpyAsync(P.V, V, P.g.M * sizeof(double), hipMemcpyDeviceToDevice, P.stream));
+  if (V) {
+    HIP_TRY(hipMemcpyAsync(P.V, V, P.g.M * sizeof(double), hipMemcpyDeviceToDevice, P.stream));
+    mfg::launch_terminal_potential(P, P.stream);
+    HIP_TRY(hipGetLastError());
+  }
   if (m0)
     HIP_TRY(hipMemcpyAsync(P.m0, m0, P.g.M * sizeof(double), hipMemcpyDeviceToDevice, P.stream));
+  return MFG_OK;
+}
+
+int mfg_set_target(mfg_plan_t plan, const double* mbar) {
+  if (!plan || !mbar) return fail(MFG_ERR_INVALID_ARG, "NULL argument");
+  mfg::Plan& P = plan->P;
+  if (!(P.beta > 0.0)) return fail(MFG_ERR_INVALID_ARG, "the problem has no terminal cost (beta = 0)");
+  HIP_TRY(hipStreamSynchronize(P.stream));
+  {
+    std::vector<double> h(P.g.M);
+    HIP_TRY(hipMemcpy(h.data(), mbar, P.g.M * sizeof(double), hipMemcpyDeviceToHost));
+    for (double x : h)
+      if (!std::isfinite(x)) return fail(MFG_ERR_NONFINITE, "mbar has a non-finite entry");
+  }
+  HIP_TRY(hipMemcpyAsync(P.mbar, mbar, P.g.M * sizeof(double), hipMemcpyDeviceToDevice, P.stream));
+  mfg::launch_terminal_potential(P, P.stream);
+  HIP_TRY(hipGetLastError());
+  return MFG_OK;
+}
+
+int mfg_value_function(mfg_plan_t plan, const mfg_state_t* st, double pcg_rtol, int pcg_maxit,
+                       double* u) {
+  if (!plan || !st || !st->xi || !st->y || !u) return fail(MFG_ERR_INVALID_ARG, "NULL argument");
+  if (!(pcg_rtol >= 0.0) || pcg_maxit < 1)
+    return fail(MFG_ERR_INVALID_ARG, "need rtol >= 0, maxit >= 1");
+  mfg::Plan& P = plan->P;
+  // the multiplier: A lam = Cr xi (least-squares solution of Cr^T lam = xi)
+  mfg::launch_apply_C(P, st->xi, P.b, P.stream);
+  int its = 0;
+  double rel = 0.0;
+  const int rc = mfg::run_pcg(P, P.b, P.u, pcg_rtol, pcg_maxit, &its, &rel, nullptr);
+  if (rc && rc != MFG_ERR_NOT_CONVERGED) return rc;
+  mfg::launch_value(P, P.u, st->y, u, P.stream);
+  HIP_TRY(hipGetLastError());
+  if (rc) return fail(rc, "the multiplier's PCG solve reached maxit");
+  return MFG_OK;
+}
+
+int mfg_hjb_residual(mfg_plan_t plan, const double* y, const double* u, double* R) {
+  if (!plan || !y || !u || !R) return fail(MFG_ERR_INVALID_ARG, "NULL argument");
+  mfg::launch_hjb_residual(plan->P, y, u, R, plan->P.stream);
+  HIP_TRY(hipGetLastError());
   return MFG_OK;
 }
 
@@ -718,9 +779,11 @@ int mfg_cp_solve(mfg_plan_t plan, mfg_state_t* st, int n_iter, double pcg_rtol, 
   mfg::Plan& P = plan->P;
   // ||m' - m||^2 of each step is copied to pinned host memory in stream order
   // (no host wait between steps) and read once at the end
+  // (and the mass drift, when asked for)
   double* dm_host = nullptr;
-  if (stats && stats->dm && n_iter > 0 &&
-      hipHostMalloc(reinterpret_cast<void**>(&dm_host), (size_t)n_iter * sizeof(double)) !=
+  const bool want_dm = stats && (stats->dm || stats->mass_drift) && n_iter > 0;
+  if (want_dm &&
+      hipHostMalloc(reinterpret_cast<void**>(&dm_host), 2 * (size_t)n_iter * sizeof(double)) !=
           hipSuccess) {
     (void)hipGetLastError();
     return fail(MFG_ERR_OOM, "pinned statistics buffer");
@@ -741,13 +804,24 @@ int mfg_cp_solve(mfg_plan_t plan, mfg_state_t* st, int n_iter, double pcg_rtol, 
         rc = fail(MFG_ERR_HIP, "statistics copy failed");
         break;
       }
+      if (dm_host && stats->mass_drift) {
+        mfg::launch_mass_drift(P, st->y, P.stream);
+        if (hipMemcpyAsync(dm_host + n_iter + it, P.red.scal + mfg::S_MASS, sizeof(double),
+                           hipMemcpyDeviceToHost, P.stream) != hipSuccess) {
+          rc = fail(MFG_ERR_HIP, "statistics copy failed");
+          break;
+        }
+      }
     }
   }
   if (dm_host) {
     if (hipStreamSynchronize(P.stream) != hipSuccess && !rc)
       rc = fail(MFG_ERR_HIP, "stream synchronisation failed");
     if (!rc)
-      for (int it = 0; it < n_iter; ++it) stats->dm[it] = std::sqrt(dm_host[it]);
+      for (int it = 0; it < n_iter; ++it) {
+        if (stats->dm) stats->dm[it] = std::sqrt(dm_host[it]);
+        if (stats->mass_drift) stats->mass_drift[it] = dm_host[n_iter + it];
+      }
     (void)hipHostFree(dm_host);
   }
   if (rc) {
@@ -790,6 +864,11 @@ int mfg_cp_solve_tol(mfg_plan_t plan, mfg_state_t* st, int max_iter, double cp_t
       if (stats->pcg_iters) stats->pcg_iters[it] = its;
       if (stats->pcg_relres) stats->pcg_relres[it] = rel;
       if (stats->dm) stats->dm[it] = r;
+      if (stats->mass_drift) {
+        mfg::launch_mass_drift(P, st->y, P.stream);
+        if ((rc = mfg::read_scalars(P))) break;
+        stats->mass_drift[it] = P.host_scal[mfg::S_MASS];
+      }
     }
     r_prev = r;
     if (r <= cp_tol) break;

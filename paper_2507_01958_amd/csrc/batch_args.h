@@ -92,6 +92,7 @@ struct BackprojArgs {
   double* y;
   double* ybar;
   const double* V;
+  const double* VT;  // potential of the last time slice (terminal cost folded in)
   double tau, theta;
   const double* tau_dev;
   const double* theta_dev;

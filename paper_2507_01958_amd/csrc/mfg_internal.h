@@ -31,6 +31,10 @@ struct Geom {
   double ih0, ih1;     // 1/h per axis (0 when absent)
   double ih0sq, ih1sq; // 1/h^2 per axis (0 when absent)
   double nu, dt, idt, idt2;
+  // coupling f(x, m) = c2 m^2 + c1 m + V(x); on the last time slice the
+  // terminal cost g = (m - mbar)/beta makes the linear coefficient c1T
+  // (= c1 + 1/(beta dt), or c1 without a terminal cost) and the potential VT
+  double c2, c1, c1T;
 };
 
 // Deterministic two-level reduction: per-block partials, then a sum in a fixed
@@ -62,6 +66,7 @@ enum ScalarSlot {
   S_THETA = 16,
   S_CPIT = 17,  // CP iterations done (graph-driven runs)
   S_ZMODE = 18, // 1 while the right-hand side's input z is in the plan's buffer
+  S_MASS = 19,  // mass drift of the primal iterate (statistics)
   S_COUNT = 24
 };
 
@@ -117,6 +122,12 @@ void launch_AAt(const Plan& P, const double* u, double* q, bool reduce_pq, hipSt
 void launch_pdir_AAt(const Plan& P, const double* z, const double* pold, double* pnew, double* q,
                      bool first, hipStream_t s);
 void launch_prox(const Plan& P, const double* v, double tau, double* y, hipStream_t s);
+// VT = V - mbar/(beta dt) (V without a terminal cost)
+void launch_terminal_potential(const Plan& P, hipStream_t s);
+// value function from the multiplier lam: u[k] = -lam[k] (k < N_t), u[N_t] = g(m^{N_t})
+void launch_value(const Plan& P, const double* lam, const double* y, double* u, hipStream_t s);
+void launch_hjb_residual(const Plan& P, const double* y, const double* u, double* R,
+                         hipStream_t s);
 // vout (optional): stores v = y - tau xi' (the prox input) for the reverse sweep;
 // zout (optional): stores z = xi' + (sigma / theta) ybar' in place of xi', ybar'
 void launch_backproj_prox(const Plan& P, const double* u, double* xi, double* y, double* ybar,
@@ -132,6 +143,9 @@ void launch_residual(const Plan& P, const double* b, const double* Ax, hipStream
 void launch_finish(const Plan& P, int site, int nblocks, int op, hipStream_t s);
 void launch_fill(double* x, long long n, double v, hipStream_t s);
 void launch_cp_init(const Plan& P, double* xi, double* y, double* ybar, hipStream_t s);
+// max over time slices of |h^d sum_i m^{t+1}_i - h^d sum_i m0_i| for the m block
+// of y, into the device scalar S_MASS
+void launch_mass_drift(const Plan& P, const double* y, hipStream_t s);
 // adjoint.hip
 void launch_adj_prox(const Plan& P, double* gy, const double* gyb, const double* v, double tau,
                      double theta, double* gxi, double* gVc, hipStream_t s);

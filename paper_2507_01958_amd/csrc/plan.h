@@ -71,6 +71,11 @@ struct Plan {
   // problem data (plan-owned copies)
   double* V = nullptr;   // M
   double* m0 = nullptr;  // M
+  // terminal cost g = (m - mbar)/beta (beta = 0: none): the target density and
+  // the last slice's potential VT = V - mbar/(beta dt)
+  double beta = 0.0;
+  double* mbar = nullptr;  // M
+  double* VT = nullptr;    // M
 
   // time transform (Algorithm 1): Vt[t][k] = V[k][t] (V is symmetric)
   double* Vt64 = nullptr;

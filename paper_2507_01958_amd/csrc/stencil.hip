@@ -18,6 +18,7 @@
 #include "batch_args.h"
 #include "device_util.h"
 #include "plan.h"
+#include "prox_cell.h"
 
 namespace mfg {
 
@@ -364,57 +365,102 @@ __device__ void aat_body(const AatArgs& a, int bid, int nb) {
   }
 }
 
-// Per-cell prox of Section 3 (derivation in the oracle's prox module):
-// w~ = P_K(wbar), a = |w~|^2; m = 0 if 2 tau^2 V - 2 tau mbar - a >= 0, else the
-// root of h'(m) = -a/(2(m+tau)^2) + (1 + 1/tau) m + V - mbar/tau by Newton from
-// max(0, (mbar - tau V)/(1 + tau)) while the iterate still increases (<= 64);
-// w = m/(m + tau) w~.
-// NC: flux components (2d).
-template <int NC>
-__device__ __forceinline__ double prox_cell(double mbar, double* w, double V, double tau) {
-  double a = 0.0;
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    double v = w[c];
-    v = (c & 1) ? fmin(v, 0.0) : fmax(v, 0.0);
-    w[c] = v;
-    a += v * v;
-  }
-  if (2.0 * tau * tau * V - 2.0 * tau * mbar - a >= 0.0) {
-#pragma unroll
-    for (int c = 0; c < NC; ++c) w[c] = 0.0;
-    return 0.0;
-  }
-  double m = fmax(0.0, (mbar - tau * V) / (1.0 + tau));
-  const double k1 = 1.0 + 1.0 / tau;
-  for (int it = 0; it < 64; ++it) {
-    const double s = m + tau;
-    const double hp = -a / (2.0 * s * s) + k1 * m + V - mbar / tau;
-    const double hpp = a / (s * s * s) + k1;
-    const double mn = m - hp / hpp;
-    if (!(mn > m)) break;
-    m = mn;
-  }
-  const double f = m / (m + tau);
-#pragma unroll
-  for (int c = 0; c < NC; ++c) w[c] *= f;
-  return m;
-}
-
+// The per-cell prox of Section 3 is prox_cell (prox_cell.h): the coupling's
+// coefficients are g.c2 and, per slice, (g.c1, V) or, on the last slice,
+// (g.c1T, VT).
 __global__ __launch_bounds__(kThreads) void k_prox(Geom g, const double* __restrict__ v,
-                                                   const double* __restrict__ Vpot, double tau,
+                                                   const double* __restrict__ Vpot,
+                                                   const double* __restrict__ VT, double tau,
                                                    double* __restrict__ y) {
   const long long n = g.n;
+  const unsigned last = (unsigned)(g.nt - 1) * (unsigned)g.M;  // n < 2^31
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
        p += (long long)gridDim.x * blockDim.x) {
-    const int rem = (int)((unsigned)p % (unsigned)g.M);  // n < 2^31
+    const int rem = (int)((unsigned)p % (unsigned)g.M);
+    const bool lastslice = (unsigned)p >= last;
+    const double Vc = lastslice ? VT[rem] : Vpot[rem];
+    const double c1 = lastslice ? g.c1T : g.c1;
     double w[4];
     for (int c = 0; c < g.ncomp; ++c) w[c] = v[(size_t)(c + 1) * n + p];
-    const double m = g.has0 ? prox_cell<4>(v[p], w, Vpot[rem], tau)
-                            : prox_cell<2>(v[p], w, Vpot[rem], tau);
+    const double m = g.has0 ? prox_cell<4>(v[p], w, Vc, tau, c1, g.c2)
+                            : prox_cell<2>(v[p], w, Vc, tau, c1, g.c2);
     y[p] = m;
     for (int c = 0; c < g.ncomp; ++c) y[(size_t)(c + 1) * n + p] = w[c];
   }
+}
+
+// VT = V - w mbar with w = 1/(beta dt): the last slice's potential once the
+// terminal cost G/dt = (m^2/2 - mbar m)/(beta dt) is folded in (w = 0 without it).
+__global__ __launch_bounds__(kThreads) void k_terminal_potential(int M, const double* __restrict__ V,
+                                                                 const double* __restrict__ mbar,
+                                                                 double w,
+                                                                 double* __restrict__ VT) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < M; i += gridDim.x * blockDim.x)
+    VT[i] = (w == 0.0) ? V[i] : V[i] - w * mbar[i];
+}
+
+// Value function of the scheme (MFG_T^2_h) from the multiplier lam of the
+// reduced constraint: u^k = -lam_k for k < N_t and u^{N_t} = g(m^{N_t}) =
+// (m^{N_t} - mbar)/beta (ib = 1/beta; 0 without a terminal cost). u holds
+// N_t + 1 slices.
+__global__ __launch_bounds__(kThreads) void k_value(Geom g, const double* __restrict__ lam,
+                                                    const double* __restrict__ y,
+                                                    const double* __restrict__ mbar, double ib,
+                                                    double* __restrict__ u) {
+  const long long n = g.n, tot = n + g.M;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < tot;
+       p += (long long)gridDim.x * blockDim.x) {
+    if (p < n) {
+      u[p] = -lam[p];
+    } else {
+      const long long i = p - n;
+      u[p] = (ib == 0.0) ? 0.0 : (y[n - g.M + i] - mbar[i]) * ib;
+    }
+  }
+}
+
+// Residual of the discrete HJB equation of (MFG_T^2_h) at cell (t, i0, i1):
+//   R = (u^t - u^{t+1})/dt + nu K u^t + |P_K(-[D_h u^t])|^2 / 2 - f(x, m^{t+1}),
+// where -[D_h u] is the flux part of Cr^T u (B_c^T u per component) and
+// f = c2 m^2 + c1 m + V; u has N_t + 1 slices, m is the primal's first block.
+template <bool HAS0, bool NEU>
+struct HjbCells {
+  __device__ static void run(const Geom& g, const double* __restrict__ y,
+                             const double* __restrict__ u, const double* __restrict__ Vpot,
+                             double* __restrict__ R) {
+    const long long n = g.n;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (long long)gridDim.x * blockDim.x) {
+      const unsigned pu = (unsigned)p;  // n < 2^31
+      const int t = (int)(pu / (unsigned)g.M);
+      const int rem = (int)(pu - (unsigned)t * (unsigned)g.M);
+      const int i0 = (int)((unsigned)rem / (unsigned)g.n1), i1 = rem - i0 * g.n1;
+      const double uc = u[at(g, t, i0, i1)];
+      double ham = 0.0;
+      {
+        const double up = u[at(g, t, i0, nbr1(i1 + 1, g.n1, NEU))];
+        const double um = u[at(g, t, i0, nbr1(i1 - 1, g.n1, NEU))];
+        const double e = fmax((uc - up) * g.ih1, 0.0), o = fmin((um - uc) * g.ih1, 0.0);
+        ham += e * e + o * o;
+      }
+      if (HAS0) {
+        const double up = u[at(g, t, nbr1(i0 + 1, g.n0, NEU), i1)];
+        const double um = u[at(g, t, nbr1(i0 - 1, g.n0, NEU), i1)];
+        const double e = fmax((uc - up) * g.ih0, 0.0), o = fmin((um - uc) * g.ih0, 0.0);
+        ham += e * e + o * o;
+      }
+      const double m = y[p];
+      const double f = (g.c2 * m + g.c1) * m + Vpot[rem];
+      R[p] = (uc - u[p + g.M]) * g.idt + g.nu * Kop<HAS0, NEU>(u, g, t, i0, i1) + 0.5 * ham - f;
+    }
+  }
+};
+
+__global__ __launch_bounds__(kThreads) void k_hjb(Geom g, const double* __restrict__ y,
+                                                  const double* __restrict__ u,
+                                                  const double* __restrict__ Vpot,
+                                                  double* __restrict__ R) {
+  geom_dispatch<HjbCells>(g, g, y, u, Vpot, R);
 }
 
 // One CP iteration after the projection solve:
@@ -431,6 +477,7 @@ struct BackprojCells {
     double* __restrict__ y = a.y;
     double* __restrict__ ybar = a.ybar;
     const double* __restrict__ Vpot = a.V;
+    const double* __restrict__ VT = a.VT;
     double* __restrict__ vout = a.vout;
     double* __restrict__ zout = a.zout;
     const long long n = g.n;
@@ -453,7 +500,9 @@ struct BackprojCells {
 #pragma unroll
         for (int c = 0; c < NC; ++c) vout[(size_t)(c + 1) * n + p] = w[c];
       }
-      const double m = prox_cell<NC>(mbar, w, Vpot[rem], tau);
+      const bool lastslice = t == g.nt - 1;
+      const double m = prox_cell<NC>(mbar, w, lastslice ? VT[rem] : Vpot[rem], tau,
+                                     lastslice ? g.c1T : g.c1, g.c2);
       // streaming stores: the new state is read again only by the next step
       const double mb = m + theta * (m - yo[0]);
       __builtin_nontemporal_store(m, &y[p]);
@@ -652,13 +701,32 @@ void launch_pdir_AAt(const Plan& P, const double* z, const double* pold, double*
 void launch_prox(const Plan& P, const double* v, double tau, double* y, hipStream_t s) {
   ProfScope ps(P, "prox", s);
   hipLaunchKernelGGL(k_prox, dim3(grid_for(P.g.n, 1 << 20)), dim3(kThreads), 0, s, P.g,
-                     v, (const double*)P.V, tau, y);
+                     v, (const double*)P.V, (const double*)P.VT, tau, y);
+}
+
+void launch_terminal_potential(const Plan& P, hipStream_t s) {
+  const double w = P.beta > 0.0 ? 1.0 / (P.beta * P.g.dt) : 0.0;
+  hipLaunchKernelGGL(k_terminal_potential, dim3(grid_for(P.g.M)), dim3(kThreads), 0, s, P.g.M,
+                     (const double*)P.V, (const double*)P.mbar, w, P.VT);
+}
+
+void launch_value(const Plan& P, const double* lam, const double* y, double* u, hipStream_t s) {
+  const double ib = P.beta > 0.0 ? 1.0 / P.beta : 0.0;
+  hipLaunchKernelGGL(k_value, dim3(grid_for(P.g.n + P.g.M)), dim3(kThreads), 0, s, P.g, lam, y,
+                     (const double*)P.mbar, ib, u);
+}
+
+void launch_hjb_residual(const Plan& P, const double* y, const double* u, double* R,
+                         hipStream_t s) {
+  ProfScope ps(P, "hjb_residual", s);
+  hipLaunchKernelGGL(k_hjb, dim3(grid_for(P.g.n)), dim3(kThreads), 0, s, P.g, y, u,
+                     (const double*)P.V, R);
 }
 
 BackprojArgs backproj_args(const Plan& P, const double* u, double* xi, double* y, double* ybar,
                            double tau, double theta, const double* tau_dev,
                            const double* theta_dev, double* vout) {
-  return BackprojArgs{P.g,      u,         xi,   y,       ybar,    P.V,     tau,    theta,
+  return BackprojArgs{P.g,      u,         xi,   y,       ybar,    P.V,     P.VT,   tau,    theta,
                       tau_dev,  theta_dev, P.red, vout, nullptr, 0.0, nullptr, nullptr};
 }
 

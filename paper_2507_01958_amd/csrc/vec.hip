@@ -157,6 +157,36 @@ __global__ __launch_bounds__(kThreads) void k_fill(double* __restrict__ x, long 
     x[i] = v;
 }
 
+// Per-slice sums of the m block of y (blocks 0..N_t-1) and of m0 (block N_t),
+// each in a fixed order.
+__global__ __launch_bounds__(kThreads) void k_slice_mass(Geom g, const double* __restrict__ y,
+                                                         const double* __restrict__ m0,
+                                                         double* __restrict__ sums) {
+  const int b = blockIdx.x;
+  const double* src = (b < g.nt) ? y + (size_t)b * g.M : m0;
+  double v[1] = {0.0};
+  for (int i = threadIdx.x; i < g.M; i += blockDim.x) v[0] += src[i];
+  __shared__ double sh[16];
+  block_sum<1>(v, sh);
+  if (threadIdx.x == 0) sums[b] = v[0];
+}
+
+// max_t |sums[t] - sums[N_t]| * hd (hd = h^d, the cell measure).
+__global__ __launch_bounds__(kThreads) void k_mass_drift(int nt, const double* __restrict__ sums,
+                                                         double hd, double* __restrict__ out) {
+  double mx = 0.0;
+  for (int t = threadIdx.x; t < nt; t += blockDim.x) mx = fmax(mx, fabs(sums[t] - sums[nt]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  __shared__ double sh[16];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) mx = fmax(mx, sh[w]);
+    *out = mx * hd;
+  }
+}
+
 // xi = 0; y = ybar = (m0 at every slice, w = 0).
 __global__ __launch_bounds__(kThreads) void k_cp_init(Geom g, const double* __restrict__ m0,
                                                       double* __restrict__ xi,
@@ -233,6 +263,17 @@ void launch_residual(const Plan& P, const double* b, const double* Ax, hipStream
     hipLaunchKernelGGL(k_residual, dim3(grid), dim3(kThreads), 0, s, P.g.n, b, Ax, P.red);
   }
   launch_finish(P, T_AUX, grid, OP_AUX, s);
+}
+
+void launch_mass_drift(const Plan& P, const double* y, hipStream_t s) {
+  const Geom& g = P.g;
+  // N_t + 1 sums in the T_AUX partials (4 * max_blocks >= 4097 slots)
+  double* sums = P.red.partials + (size_t)T_AUX * kSlotsPerSite * P.red.max_blocks;
+  const double hd = 1.0 / (g.ih1 * (g.has0 ? g.ih0 : 1.0));
+  hipLaunchKernelGGL(k_slice_mass, dim3(g.nt + 1), dim3(kThreads), 0, s, g, y,
+                     (const double*)P.m0, sums);
+  hipLaunchKernelGGL(k_mass_drift, dim3(1), dim3(kThreads), 0, s, g.nt, (const double*)sums, hd,
+                     P.red.scal + S_MASS);
 }
 
 void launch_fill(double* x, long long n, double v, hipStream_t s) {

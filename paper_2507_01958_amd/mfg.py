@@ -20,6 +20,7 @@ STATUS = {0: "MFG_OK", 1: "MFG_ERR_INVALID_ARG", 2: "MFG_ERR_UNSUPPORTED",
           6: "MFG_ERR_HIP", 7: "MFG_ERR_OOM"}
 BC = {"periodic": 0, "neumann": 1}
 PRECISION = {"fp64": 0, "mixed_fp32": 1, "mixed_fp16": 2, "mixed_bf16": 3}
+COUPLING = {"linear": 0, "quadratic": 1, "potential": 2}
 
 
 class MFGError(RuntimeError):
@@ -31,7 +32,8 @@ class MFGError(RuntimeError):
 class Problem(ctypes.Structure):
     _fields_ = [("d", c_int), ("n", c_int * 2), ("nt", c_int), ("T", c_double),
                 ("lo", c_double * 2), ("hi", c_double * 2), ("bc", c_int), ("nu", c_double),
-                ("qprime", c_double), ("gamma", c_double), ("l", c_int), ("precision", c_int)]
+                ("qprime", c_double), ("gamma", c_double), ("l", c_int), ("precision", c_int),
+                ("coupling", c_int), ("beta", c_double)]
 
 
 class State(ctypes.Structure):
@@ -41,7 +43,7 @@ class State(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("pcg_iters", POINTER(c_int)), ("pcg_relres", POINTER(c_double)),
-                ("dm", POINTER(c_double))]
+                ("dm", POINTER(c_double)), ("mass_drift", POINTER(c_double))]
 
 
 # name -> (restype, argtypes); the exported API of include/mfg.h
@@ -50,6 +52,9 @@ SIGNATURES = {
     "mfg_destroy": (c_int, [c_void_p]),
     "mfg_set_stream": (c_int, [c_void_p, c_void_p]),
     "mfg_set_data": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "mfg_set_target": (c_int, [c_void_p, c_void_p]),
+    "mfg_value_function": (c_int, [c_void_p, POINTER(State), c_double, c_int, c_void_p]),
+    "mfg_hjb_residual": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "mfg_prox": (c_int, [c_void_p, c_void_p, c_double, c_void_p]),
     "mfg_apply_AAt": (c_int, [c_void_p, c_void_p, c_void_p]),
     "mfg_apply_C": (c_int, [c_void_p, c_void_p, c_void_p]),
@@ -121,7 +126,7 @@ def _stream(stream):
 
 
 def make_problem(d, nx, ny, nt, bc, nu, gamma, l=1, precision="fp64", T=1.0, lo=None, hi=None,
-                 qprime=2.0) -> Problem:
+                 qprime=2.0, coupling="linear", beta=0.0) -> Problem:
     pb = Problem()
     pb.d = d
     pb.n[0] = nx
@@ -138,6 +143,8 @@ def make_problem(d, nx, ny, nt, bc, nu, gamma, l=1, precision="fp64", T=1.0, lo=
     pb.gamma = gamma
     pb.l = l
     pb.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    pb.coupling = COUPLING[coupling] if isinstance(coupling, str) else int(coupling)
+    pb.beta = beta
     return pb
 
 
@@ -197,6 +204,10 @@ def mfg_set_stream(plan: Plan, stream):
 
 def mfg_set_data(plan: Plan, V=None, m0=None):
     _check(load().mfg_set_data(plan.handle, _ptr(V), _ptr(m0)))
+
+
+def mfg_set_target(plan: Plan, mbar):
+    _check(load().mfg_set_target(plan.handle, _ptr(mbar)))
 
 
 def mfg_prox(plan: Plan, v, tau: float, y):
@@ -289,8 +300,9 @@ def mfg_cp_init(plan: Plan, st: CPState):
 
 
 def mfg_cp_solve(plan: Plan, st: CPState, n_iter: int, pcg_rtol: float, pcg_maxit: int,
-                 stats: bool = True, raise_not_converged: bool = True):
-    """Runs n_iter CP iterations; returns dict of per-iteration statistics."""
+                 stats: bool = True, raise_not_converged: bool = True, mass: bool = False):
+    """Runs n_iter CP iterations; returns dict of per-iteration statistics
+    (with mass=True also the mass drift, at one extra read of m per iteration)."""
     st._sync_ptrs()
     out = {}
     sp = None
@@ -298,22 +310,27 @@ def mfg_cp_solve(plan: Plan, st: CPState, n_iter: int, pcg_rtol: float, pcg_maxi
         its = (c_int * n_iter)()
         rel = (c_double * n_iter)()
         dm = (c_double * n_iter)()
+        md = (c_double * n_iter)()
         s = Stats()
         s.pcg_iters = ctypes.cast(its, POINTER(c_int))
         s.pcg_relres = ctypes.cast(rel, POINTER(c_double))
         s.dm = ctypes.cast(dm, POINTER(c_double))
+        if mass:
+            s.mass_drift = ctypes.cast(md, POINTER(c_double))
         sp = ctypes.byref(s)
     rc = load().mfg_cp_solve(plan.handle, ctypes.byref(st.c), int(n_iter), float(pcg_rtol),
                              int(pcg_maxit), sp)
     _check(rc, allow=() if raise_not_converged else (3,))
     if sp is not None:
         out = dict(pcg_iters=list(its), pcg_relres=list(rel), dm=list(dm))
+        if mass:
+            out["mass_drift"] = list(md)
     out["status"] = rc
     return out
 
 
 def mfg_cp_solve_tol(plan: Plan, st: CPState, max_iter: int, cp_tol: float, pcg_maxit: int,
-                     raise_not_converged: bool = True):
+                     raise_not_converged: bool = True, mass: bool = False):
     """CP iterations with the Section 5 stopping and inner-tolerance rules;
     returns dict with n_done and the per-iteration statistics."""
     st._sync_ptrs()
@@ -325,13 +342,19 @@ def mfg_cp_solve_tol(plan: Plan, st: CPState, max_iter: int, cp_tol: float, pcg_
     s.pcg_iters = ctypes.cast(its, POINTER(c_int))
     s.pcg_relres = ctypes.cast(rel, POINTER(c_double))
     s.dm = ctypes.cast(dm, POINTER(c_double))
+    md = (c_double * n)()
+    if mass:
+        s.mass_drift = ctypes.cast(md, POINTER(c_double))
     done = c_int(0)
     rc = load().mfg_cp_solve_tol(plan.handle, ctypes.byref(st.c), int(max_iter), float(cp_tol),
                                  int(pcg_maxit), ctypes.byref(done), ctypes.byref(s))
     _check(rc, allow=() if raise_not_converged else (3,))
     k = done.value
-    return dict(n_done=k, pcg_iters=list(its)[:k], pcg_relres=list(rel)[:k], dm=list(dm)[:k],
-                status=rc)
+    out = dict(n_done=k, pcg_iters=list(its)[:k], pcg_relres=list(rel)[:k], dm=list(dm)[:k],
+               status=rc)
+    if mass:
+        out["mass_drift"] = list(md)[:k]
+    return out
 
 
 def mfg_cp_adjoint(plan: Plan, ckpts, every: int, n_iter: int, gy, pcg_rtol: float,
@@ -349,6 +372,20 @@ def mfg_cp_adjoint(plan: Plan, ckpts, every: int, n_iter: int, gy, pcg_rtol: flo
                                float(pcg_rtol), int(pcg_maxit), _ptr(g_m0), _ptr(g_V))
     _check(rc, allow=() if raise_not_converged else (3,))
     return rc
+
+
+def mfg_value_function(plan: Plan, st: "CPState", pcg_rtol: float, pcg_maxit: int, u,
+                       raise_not_converged: bool = True):
+    """Writes u ((N_t + 1) M values) from the state's multiplier; returns the status."""
+    st._sync_ptrs()
+    rc = load().mfg_value_function(plan.handle, ctypes.byref(st.c), float(pcg_rtol),
+                                   int(pcg_maxit), _ptr(u))
+    _check(rc, allow=() if raise_not_converged else (3,))
+    return rc
+
+
+def mfg_hjb_residual(plan: Plan, y, u, R):
+    _check(load().mfg_hjb_residual(plan.handle, _ptr(y), _ptr(u), _ptr(R)))
 
 
 class Batch:
