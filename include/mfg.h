@@ -170,6 +170,15 @@ int mfg_precond(mfg_plan_t plan, const double* r, double* z);
 int mfg_pcg(mfg_plan_t plan, const double* b, double* u, double rtol, int maxit,
             int* iters, double* relres);
 
+/* Warm start of the CP projections (enable != 0): each PCG solve of
+ * mfg_cp_solve / mfg_cp_solve_tol starts from the previous projection's
+ * solution on this plan instead of zero (the residual is then b - A u_prev;
+ * the stopping rule stays ||r|| <= rtol ||b||). The first projection after
+ * mfg_cp_init starts from zero. Off by default, as in the paper's setup, and
+ * not used by batched solves; mfg_cp_adjoint refuses to run while it is on
+ * (its recomputed steps start cold). */
+int mfg_set_warm_start(mfg_plan_t plan, int enable);
+
 /* Chambolle-Pock state (Section 3, Section 5 schedule). The three vectors are
  * caller-owned device primal vectors ((1+2d) n values each): the dual variable
  * xi, the primal y = (m, w) and its extrapolation ybar. sigma, tau, theta are

@@ -36,17 +36,18 @@ def cg(apply_A, b: np.ndarray, rtol: float, maxit: int, x0=None):
 
 
 def pcg(apply_A, apply_Pinv, b: np.ndarray, rtol: float, maxit: int,
-        flexible: bool = False):
-    """Preconditioned CG from x0 = 0. Returns (x, iters, relres_recursive).
+        flexible: bool = False, x0=None):
+    """Preconditioned CG from x0 (default 0). Returns (x, iters, relres_recursive).
+    The stopping rule is ||r|| <= rtol ||b|| whatever the start.
 
     Standard: beta = (r'.z')/(r.z). Flexible: beta = z'.(r' - r)/(r.z),
     evaluated as -alpha (z'.q)/(r.z) since r' - r = -alpha q.
     """
-    x = np.zeros_like(b)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
     bnorm = np.linalg.norm(b)
     if bnorm == 0.0:
-        return x, 0, 0.0
-    r = b.copy()
+        return np.zeros_like(b), 0, 0.0
+    r = b.copy() if x0 is None else b - apply_A(x)
     z = apply_Pinv(r)
     p = z.copy()
     rho = float(r @ z)
@@ -54,7 +55,7 @@ def pcg(apply_A, apply_Pinv, b: np.ndarray, rtol: float, maxit: int,
     rn = bnorm
     while it < maxit:
         q = apply_A(p)
-        alpha = rho / float(p @ q)
+        alpha = rho / float(p @ q) if rho != 0.0 else 0.0
         x += alpha * p
         r -= alpha * q
         it += 1

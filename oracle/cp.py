@@ -62,24 +62,26 @@ class Projector:
         if method == "direct":
             self._lu = spla.splu(ops.assemble_AAt_blocks(g, S).tocsc())
 
-    def solve(self, b):
+    def solve(self, b, x0=None):
         g, S = self.g, self.S
         A = lambda v: ops.apply_AAt(g, S, v)
         if self.method == "direct":
             return self._lu.solve(b), 0, 0.0
         if self.method == "cg":
-            return cgmod.cg(A, b, self.rtol, self.maxit)
+            return cgmod.cg(A, b, self.rtol, self.maxit, x0=x0)
         if self.method == "pcg":
-            return cgmod.pcg(A, lambda r: apply_Pinv_fast(g, r), b, self.rtol, self.maxit)
+            return cgmod.pcg(A, lambda r: apply_Pinv_fast(g, r), b, self.rtol, self.maxit,
+                             x0=x0)
         raise ValueError(self.method)
 
 
 def cp_step(g: Grid, S: ops.Spatial, st: CPState, V: np.ndarray, m0: np.ndarray,
-            proj: Projector, cost: Coupling = LINEAR) -> dict:
-    """One CP iteration in place; returns per-iteration diagnostics."""
+            proj: Projector, cost: Coupling = LINEAR, u0=None) -> dict:
+    """One CP iteration in place; returns per-iteration diagnostics. u0: the
+    initial guess of the projection's solve (warm start), else zero."""
     z = st.xi + st.sigma * st.ybar
     b = ops.apply_Cr(g, S, z) - st.sigma * ops.rhs_d(g, m0)
-    u, its, relres = proj.solve(b)
+    u, its, relres = proj.solve(b, u0)
     xi_new = ops.apply_CrT(g, S, u)
     y_new = prox_primal(g, st.y - st.tau * xi_new, V, st.tau, cost)
     theta = 1.0 / np.sqrt(1.0 + 2.0 * g.gamma * st.tau)
@@ -123,20 +125,25 @@ def cg_tolerance(r_prev: float | None) -> float:
 
 def cp_solve_tol(g: Grid, V: np.ndarray, m0: np.ndarray, max_iter: int, cp_tol: float,
                  maxit: int = 100000, state: CPState | None = None,
-                 cost: Coupling = LINEAR):
+                 cost: Coupling = LINEAR, warm: bool = False):
     """CP iterations with the stopping and inner-tolerance rules of Section 5:
     iteration l+1 solves its projection by PCG (Algorithms 1+2) to
     cg_tolerance(r_l), r_l = ||m_l - m_{l-1}||_2 of the previous iteration,
     and the loop ends after the first iteration whose r is <= cp_tol (the
-    paper takes cp_tol = 1e-4 ||m_0||), or after max_iter iterations.
+    paper takes cp_tol = 1e-4 ||m_0||), or after max_iter iterations. warm:
+    each projection's PCG starts from the previous projection's solution (the
+    first from zero).
     Returns (state, per-iteration diagnostics with the tolerance used)."""
     S = ops.Spatial(g)
     st = state.copy() if state is not None else cp_init(g, m0)
     log = []
     r_prev = None
+    u_prev = None
     for _ in range(max_iter):
         tol = cg_tolerance(r_prev)
-        info = cp_step(g, S, st, V, m0, Projector(g, S, "pcg", tol, maxit), cost)
+        info = cp_step(g, S, st, V, m0, Projector(g, S, "pcg", tol, maxit), cost,
+                       u0=u_prev if warm else None)
+        u_prev = info["u"]
         info.pop("u")
         info.pop("b")
         info["cg_tol"] = tol

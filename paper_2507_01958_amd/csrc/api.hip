@@ -447,7 +447,9 @@ int read_scalars(Plan& P) {
   return MFG_OK;
 }
 
-// PCG from x = 0 (flexible form where pcg_flexible says so). Iterations are
+// PCG from x = 0, or from the x it is given when warm (the residual is then
+// r = b - A x, and the first update adds to x) (flexible form where
+// pcg_flexible says so). Iterations are
 // launched in chunks without a host round trip: every kernel of an iteration
 // tests the device `done` flag (set by the r.r stopping test on convergence,
 // breakdown or a non-finite value) and returns at once when it is set, so
@@ -456,10 +458,15 @@ int read_scalars(Plan& P) {
 // r_ready: the start (r = b, b.b, status reset) was already done by the
 // kernel that formed b (b is then not needed).
 int run_pcg(Plan& P, const double* b, double* x, double rtol, int maxit, int* iters_out,
-            double* relres_rec, double* relres_true, bool r_ready) {
+            double* relres_rec, double* relres_true, bool r_ready, bool warm) {
   hipStream_t s = P.stream;
   P.pcg_done = P.red.scal + S_DONE;
   if (!r_ready) launch_pcg_init(P, b, P.r, rtol, s);
+  if (warm) {
+    // r = b - A x0 (b.b and the status come from the start above)
+    launch_AAt(P, x, P.q, false, s);
+    launch_axpby(P.g.n, -1.0, P.q, 1.0, P.r, s);
+  }
   launch_precond(P, P.r, P.z, true, nullptr, s);
   double* pold = P.p2;
   double* pnew = P.p;
@@ -470,7 +477,7 @@ int run_pcg(Plan& P, const double* b, double* x, double rtol, int maxit, int* it
     for (int j = 0; j < todo; ++j) {
       ++k;
       launch_pdir_AAt(P, P.z, pold, pnew, P.q, k == 1, s);
-      launch_update_precond(P, x, P.r, pnew, P.q, P.z, k == 1, s);
+      launch_update_precond(P, x, P.r, pnew, P.q, P.z, k == 1 && !warm, s);
       std::swap(pold, pnew);
     }
     const hipError_t le = hipGetLastError();
@@ -518,10 +525,16 @@ int run_pcg(Plan& P, const double* b, double* x, double rtol, int maxit, int* it
 static int cp_step(Plan& P, mfg_state_t* st, double rtol, int maxit, int* its, double* rel,
                    double* vout, bool z_in = false, bool z_out = false) {
   hipStream_t s = P.stream;
-  // the right-hand side goes straight into the PCG residual and starts the solve
+  // the right-hand side goes straight into the PCG residual and starts the
+  // solve (from the previous projection's solution with a warm start)
   launch_rhs(P, st->xi, st->ybar, st->sigma, P.m0, P.r, s, z_in ? P.zn : nullptr, rtol);
-  int rc = run_pcg(P, nullptr, P.u, rtol, maxit, its, rel, nullptr, true);
-  if (rc && rc != MFG_ERR_NOT_CONVERGED) return rc;
+  int rc = run_pcg(P, nullptr, P.u, rtol, maxit, its, rel, nullptr, true,
+                   P.warm_start && P.u_valid);
+  if (rc && rc != MFG_ERR_NOT_CONVERGED) {
+    P.u_valid = false;
+    return rc;
+  }
+  P.u_valid = true;
   const double theta = 1.0 / std::sqrt(1.0 + 2.0 * P.gamma * st->tau);
   launch_backproj_prox(P, P.u, st->xi, st->y, st->ybar, st->tau, theta, s, vout,
                        z_out ? P.zn : nullptr, st->sigma);
@@ -696,6 +709,7 @@ int mfg_value_function(mfg_plan_t plan, const mfg_state_t* st, double pcg_rtol, 
   mfg::launch_apply_C(P, st->xi, P.b, P.stream);
   int its = 0;
   double rel = 0.0;
+  P.u_valid = false;  // P.u now holds the multiplier, not a projection's solution
   const int rc = mfg::run_pcg(P, P.b, P.u, pcg_rtol, pcg_maxit, &its, &rel, nullptr);
   if (rc && rc != MFG_ERR_NOT_CONVERGED) return rc;
   mfg::launch_value(P, P.u, st->y, u, P.stream);
@@ -708,6 +722,12 @@ int mfg_hjb_residual(mfg_plan_t plan, const double* y, const double* u, double* 
   if (!plan || !y || !u || !R) return fail(MFG_ERR_INVALID_ARG, "NULL argument");
   mfg::launch_hjb_residual(plan->P, y, u, R, plan->P.stream);
   HIP_TRY(hipGetLastError());
+  return MFG_OK;
+}
+
+int mfg_set_warm_start(mfg_plan_t plan, int enable) {
+  if (!plan) return fail(MFG_ERR_INVALID_ARG, "plan is NULL");
+  plan->P.warm_start = enable != 0;
   return MFG_OK;
 }
 
@@ -762,6 +782,7 @@ int mfg_cp_init(mfg_plan_t plan, mfg_state_t* st) {
     return fail(MFG_ERR_INVALID_ARG, "NULL argument");
   mfg::launch_cp_init(plan->P, st->xi, st->y, st->ybar, plan->P.stream);
   HIP_TRY(hipGetLastError());
+  plan->P.u_valid = false;  // the first projection starts from zero
   st->sigma = 1.0;
   st->tau = 1.0;
   st->theta = 1.0;
@@ -889,6 +910,10 @@ int mfg_cp_adjoint(mfg_plan_t plan, const mfg_state_t* ckpts, int n_ckpt, int ev
   for (int k = 0; k < n_ckpt; ++k)
     if (!ckpts[k].xi || !ckpts[k].y || !ckpts[k].ybar)
       return fail(MFG_ERR_INVALID_ARG, "checkpoint with NULL vectors");
+  if (plan->P.warm_start)
+    return fail(MFG_ERR_INVALID_ARG,
+                "the reverse sweep recomputes steps from checkpoints with cold PCG starts: "
+                "disable the warm start for the forward run and the gradient");
   return mfg::run_cp_adjoint(plan->P, ckpts, every, n_iter, gy_final, pcg_rtol, pcg_maxit, g_m0,
                              g_V);
 }

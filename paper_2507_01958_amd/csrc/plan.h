@@ -54,6 +54,9 @@ struct Plan {
   // the solve has converged (set only while mfg_pcg / a CP step iterates).
   const double* pcg_done = nullptr;
   int last_pcg_its = 0;  // iterations of the previous solve (launch chunking)
+  // CP projections start PCG from the previous projection's solution (kept in
+  // u) when warm_start is set and u holds one (u_valid)
+  bool warm_start = false, u_valid = false;
   // Grids of the last launches that stored p.q and r.z partials: the update
   // and the A kernel sum that many partials themselves.
   mutable int pq_blocks = 0, rz_blocks = 0;
@@ -137,7 +140,7 @@ inline bool pcg_flexible(const Plan& P) {
 // P.host_scal (synchronises the plan's stream).
 int setup_problem(Plan& P, const mfg_problem_t* pb, hipStream_t stream);
 int run_pcg(Plan& P, const double* b, double* x, double rtol, int maxit, int* iters_out,
-            double* relres_rec, double* relres_true, bool r_ready = false);
+            double* relres_rec, double* relres_true, bool r_ready = false, bool warm = false);
 int read_scalars(Plan& P);
 int fail(int code, const std::string& msg);
 // Radix sequence (4s, then 2s, then 3s) of a spatial FFT of length N.

@@ -53,8 +53,10 @@ __device__ void update_body(const UpdArgs& a, int bid, int nb) {
   double pq[1], rz[1];
   fold_partials<1>(a.rb, T_PQ, a.npq, pq);
   fold_partials<1>(a.rb, T_RZ, a.nrz, rz);
-  const int bad = !finite_d(pq[0]) ? 2 : (!(pq[0] > 0.0) ? 1 : 0);
-  const double alpha = bad ? 0.0 : rz[0] / pq[0];
+  // r.z = 0 means r = 0 (a warm start at the solution): a zero step, not a
+  // breakdown; the next r.r test ends the solve
+  const int bad = !finite_d(pq[0]) ? 2 : (!(pq[0] > 0.0) && rz[0] != 0.0 ? 1 : 0);
+  const double alpha = (bad || rz[0] == 0.0) ? 0.0 : rz[0] / pq[0];
   if (bid == 0 && threadIdx.x == 0) {
     double* S = a.rb.scal;
     S[S_PQ] = pq[0];

@@ -53,6 +53,7 @@ SIGNATURES = {
     "mfg_set_stream": (c_int, [c_void_p, c_void_p]),
     "mfg_set_data": (c_int, [c_void_p, c_void_p, c_void_p]),
     "mfg_set_target": (c_int, [c_void_p, c_void_p]),
+    "mfg_set_warm_start": (c_int, [c_void_p, c_int]),
     "mfg_value_function": (c_int, [c_void_p, POINTER(State), c_double, c_int, c_void_p]),
     "mfg_hjb_residual": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "mfg_prox": (c_int, [c_void_p, c_void_p, c_double, c_void_p]),
@@ -208,6 +209,10 @@ def mfg_set_data(plan: Plan, V=None, m0=None):
 
 def mfg_set_target(plan: Plan, mbar):
     _check(load().mfg_set_target(plan.handle, _ptr(mbar)))
+
+
+def mfg_set_warm_start(plan: Plan, enable: bool):
+    _check(load().mfg_set_warm_start(plan.handle, 1 if enable else 0))
 
 
 def mfg_prox(plan: Plan, v, tau: float, y):

@@ -89,3 +89,47 @@ def test_cp_tol_zero_iterations_and_bad_arguments():
             mfg.mfg_cp_solve_tol(P, st, 10, -1.0, 100)
         with pytest.raises(mfg.MFGError):
             mfg.mfg_cp_solve_tol(P, st, 10, 1e-3, 0)
+
+
+@pytest.mark.parametrize("case", CASES[:2], ids=_ids)
+def test_cp_tol_warm_start_matches_oracle(case):
+    """With warm-started projections both sides start each PCG from their
+    previous solution: the same CP and per-solve PCG counts, the state to 1e-9."""
+    inst = wl.small_instance(500, *case)
+    g = grid_of(inst)
+    say(f"cp_tol warm start fp64 {_ids(case)}")
+    cp_tol = 1e-4 * np.linalg.norm(inst.m0)
+    ref, log = ocp.cp_solve_tol(g, inst.V, inst.m0, 400, cp_tol, 500, warm=True)
+    cold, log_cold = ocp.cp_solve_tol(g, inst.V, inst.m0, 400, cp_tol, 500)
+    with plan_of(inst) as P:
+        mfg.mfg_set_warm_start(P, True)
+        st = mfg.CPState(P)
+        mfg.mfg_cp_init(P, st)
+        out = mfg.mfg_cp_solve_tol(P, st, 400, cp_tol, 500)
+        xi, y = host(st.xi), host(st.y)
+    say(f"  PCG iterations warm {sum(out['pcg_iters'])} (oracle {sum(l['pcg_iters'] for l in log)}),"
+        f" cold {sum(l['pcg_iters'] for l in log_cold)}")
+    assert out["n_done"] == len(log)
+    assert out["pcg_iters"] == [l["pcg_iters"] for l in log]
+    n = g.n
+    for name, a, rb in [("xi", xi, ref.xi), ("y", y, ref.y)]:
+        for blk in range(1 + g.ncomp):
+            ga, r = a[blk * n:(blk + 1) * n], rb[blk * n:(blk + 1) * n]
+            err = np.abs(ga - r).max() / max(np.abs(r).max(), 1e-300)
+            assert err <= 1e-9, (name, blk, err)
+
+
+def test_warm_start_refused_by_the_adjoint():
+    inst = wl.small_instance(502, *CASES[0])
+    with plan_of(inst) as P:
+        mfg.mfg_set_warm_start(P, True)
+        st = mfg.CPState(P)
+        mfg.mfg_cp_init(P, st)
+        snap = st.snapshot()
+        mfg.mfg_cp_solve(P, st, 2, 1e-10, 100)
+        import torch
+        g0 = torch.empty(inst.M, dtype=torch.float64, device="cuda")
+        g1 = torch.empty(inst.M, dtype=torch.float64, device="cuda")
+        with pytest.raises(mfg.MFGError) as e:
+            mfg.mfg_cp_adjoint(P, [snap], 2, 2, st.y.clone(), 1e-10, 100, g0, g1)
+        assert e.value.code == 1

@@ -67,3 +67,21 @@ def test_flexible_converges_with_perturbed_preconditioner():
     x, it, rel = cg.pcg(lambda v: A @ v, lambda r: Pe @ r, b, 1e-10, 400, flexible=True)
     assert rel <= 1e-10
     assert np.linalg.norm(A @ x - b) <= 1e-9 * np.linalg.norm(b)
+
+
+def test_pcg_warm_start():
+    """From x0 the residual is b - A x0 and the stopping rule stays relative to
+    ||b||: a start at the (rounded) solution stops after one step; a start near it needs
+    fewer iterations than a cold start and reaches the same tolerance."""
+    rng = np.random.default_rng(5)
+    A = _spd(100, 1e4, rng)
+    Pinv = np.linalg.inv(A + _spd(100, 10, rng) * 0.5)
+    b = rng.standard_normal(100)
+    xs = np.linalg.solve(A, b)
+    x, it, rel = cg.pcg(lambda v: A @ v, lambda r: Pinv @ r, b, 1e-8, 200, x0=xs)
+    assert it == 1 and np.linalg.norm(A @ x - b) <= 1e-12 * np.linalg.norm(b)
+    x_cold, it_cold, _ = cg.pcg(lambda v: A @ v, lambda r: Pinv @ r, b, 1e-10, 200)
+    near = xs + 1e-6 * rng.standard_normal(100) * np.abs(xs).max()
+    x_warm, it_warm, rel = cg.pcg(lambda v: A @ v, lambda r: Pinv @ r, b, 1e-10, 200, x0=near)
+    assert rel <= 1e-10 and it_warm < it_cold
+    assert np.linalg.norm(A @ x_warm - b) <= 1.01e-10 * np.linalg.norm(b)

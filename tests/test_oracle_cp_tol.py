@@ -64,3 +64,20 @@ def test_inexact_projections_track_exact_ones():
     for blk in range(1 + g.ncomp):
         a, b = st.y[blk * n:(blk + 1) * n], ref.y[blk * n:(blk + 1) * n]
         assert np.abs(a - b).max() <= 1e-3 * np.abs(b).max()
+
+
+def test_warm_start_keeps_the_iteration_and_saves_pcg_work():
+    """Warm-started projections (the previous solution as initial guess) meet
+    the same relative tolerances, so the CP iterates stay within the inner
+    tolerances' scale of the cold-started ones; they take fewer PCG
+    iterations in all."""
+    inst = wl.small_instance(44, 2, 16, 12, 10, "neumann", 0.05)
+    g = _grid(inst)
+    cp_tol = 1e-4 * np.linalg.norm(inst.m0)
+    cold, lc = ocp.cp_solve_tol(g, inst.V, inst.m0, 300, cp_tol)
+    warm, lw = ocp.cp_solve_tol(g, inst.V, inst.m0, 300, cp_tol, warm=True)
+    assert lw[0]["pcg_iters"] == lc[0]["pcg_iters"]        # the first starts from zero
+    assert all(l["relres"] <= l["cg_tol"] for l in lw)
+    assert sum(l["pcg_iters"] for l in lw) < sum(l["pcg_iters"] for l in lc)
+    assert abs(len(lw) - len(lc)) <= 2
+    assert np.linalg.norm(warm.y[: g.n] - cold.y[: g.n]) <= 10 * cp_tol
