@@ -62,9 +62,15 @@ def algorithmic(kernel, inst, variant, its=1.0, steps=1):
     upd = (6 * its - 1) / its
     rhs = ((steps - 1) * (nb + 1) + (2 * nb + 1)) / steps
     bp = ((steps - 1) * (1 + 3 * nb) + (1 + 4 * nb)) / steps
-    # above N_t = 128 every mode's time transform runs with float64 products
-    if kernel.startswith("tgemm_f64") or (kernel.startswith("tgemm_") and inst.nt > 128):
+    if kernel.startswith("tgemm_f64"):
         return "mfma", 2.0 * inst.nt * inst.nt * inst.M, "fp64"
+    # above N_t = 128 the low-precision transforms stream V and are priced on
+    # the float16 / bfloat16 matrix cores (2 N_t flops per element against 12
+    # or 16 bytes: about the ridge); the float32 mode is a two-term float16
+    # split, three products per element pair
+    if kernel.startswith("tgemm_") and inst.nt > 128:
+        mult = 3.0 if kernel.startswith("tgemm_f32") else 1.0
+        return "mfma", mult * 2.0 * inst.nt * inst.nt * inst.M, "fp16"
     for base in ("rows_fwd", "rows_inv", "rows_solve", "cols_solve"):
         if kernel in (base + "_f64", base + "_f32"):
             # one read and one write of the intermediate in the solve's precision

@@ -172,6 +172,7 @@ static void read_tune_env(Tune& t) {
       else if (k == "aat_tc" && v >= 0 && v <= 64) t.aat_tc = v;
       else if (k == "aat_big" && v >= 0 && v <= 2) t.aat_big = v;
       else if (k == "flex" && (v >= -1 && v <= 1)) t.flex = v;
+      else if (k == "lp_stream" && (v == 0 || v == 1)) t.lp_stream = v;
     }
     pos = end + 1;
   }
@@ -343,6 +344,37 @@ static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const d
         (rc = upload(P, &P.Vp16, p16)) || (rc = upload(P, &P.Vp16s, p16s)) ||
         (rc = upload(P, &P.Vpbf, pbf)))
       return rc;
+  }
+  if (nt > 128 && P.precision != MFG_FP64) {
+    // streaming low-precision V (row k contiguous in t), only the table of the
+    // plan's precision
+    const int ns = (nt + 127) / 128 * 128;
+    P.ntps = ns;
+    if (P.precision == MFG_MIXED_BF16) {
+      std::vector<unsigned short> tb((size_t)ns * ns, 0);
+      for (int k = 0; k < nt; ++k)
+        for (int t = 0; t < nt; ++t) tb[(size_t)k * ns + t] = to_bf16((float)Vm[(size_t)k * nt + t]);
+      unsigned short* d = nullptr;
+      if ((rc = upload(P, &d, tb))) return rc;
+      P.Vs_lp = d;
+    } else {
+      const bool split = P.precision == MFG_MIXED_FP32;
+      std::vector<_Float16> th((size_t)(split ? 2 : 1) * ns * ns, (_Float16)0.0f);
+      for (int k = 0; k < nt; ++k)
+        for (int t = 0; t < nt; ++t) {
+          const double v = Vm[(size_t)k * nt + t];
+          if (split) {
+            const _Float16 hi = (_Float16)(v * kVSplitScale);
+            th[(size_t)k * ns + t] = hi;
+            th[((size_t)ns + k) * ns + t] = (_Float16)(v * kVSplitScale - (double)hi);
+          } else {
+            th[(size_t)k * ns + t] = (_Float16)v;
+          }
+        }
+      _Float16* d = nullptr;
+      if ((rc = upload(P, &d, th))) return rc;
+      P.Vs_lp = d;
+    }
   }
   if ((rc = upload(P, &P.Vt64, Vt)) || (rc = upload(P, &P.Vt32, Vt32)) ||
       (rc = upload(P, &P.Vt16, Vt16)) || (rc = upload(P, &P.Vtbf, Vtbf)) ||

@@ -142,6 +142,7 @@ struct GemmArgs {
   RedBuf rb;
   const double* done;
   int nrr;  // > 0: first take the PCG r.r check over that many partials
+  int ldv;  // row stride of the streamed low-precision V table (N_t > 128)
 };
 
 // Instance that owns block b of a batched launch (off[0] = 0 <= b < off[ninst]).

@@ -30,6 +30,9 @@ struct Tune {
   // preconditioner is symmetric to float32 rounding; flexible for float16 and
   // bfloat16)
   int flex = -1;
+  // time GEMM with low-precision products also when N_t > 128 (V streamed
+  // through LDS); 0: float64 products there
+  int lp_stream = 1;
 };
 
 // Optional per-kernel timing with HIP events recorded on the plan's stream
@@ -97,6 +100,11 @@ struct Plan {
   // 2^8 V - hi
   _Float16* Vp16s = nullptr;
   unsigned short* Vpbf = nullptr;
+  // N_t > 128: the low-precision V of the plan's precision for the streaming
+  // kernel, V[k][t] at k * ntps + t, zero-padded to ntps (N_t rounded up to
+  // 128); the float32 split stores the lo rows after the hi rows
+  int ntps = 0;
+  const void* Vs_lp = nullptr;
 
   // spatial transforms (Algorithm 2)
   Axis ax0{}, ax1{};

@@ -356,6 +356,211 @@ __global__ __launch_bounds__(WPB * 64) void k_tgemm_lp_batch(const GemmArgs<TX, 
   tgemm_lp_body<MODE, NTP, CB, TX, TY, WPB>(A[i], blockIdx.x - off[i]);
 }
 
+// Low-precision products for N_t > 128 (k_tgemm_lps). V (the table of the
+// plan's precision, row k contiguous in t, zero-padded to ldv = N_t rounded up
+// to 128) is too large for LDS, so it is staged in chunks of TK = 32 time rows:
+// a block covers KB*16 output rows and 4 waves x CB tiles of 16 spatial nodes,
+// and walks t with the next chunk of V and of its operands fetched into
+// registers while the current one is multiplied. The float16 operands are
+// scaled per wave and chunk by a power of two that maps the chunk's largest
+// magnitude to about 2^14; when that scale changes the accumulators are
+// rescaled by the (exact) power-of-two ratio, so they always hold the sum in
+// units of the current scale. Blocks of one column block run on one XCD
+// (their operand reads share that L2).
+constexpr int kLpsTK = 32;           // time rows per chunk
+// padded LDS row of 36 halves (18 words): the 16 rows of an A-operand read
+// (8 bytes per lane) fall on distinct bank pairs
+constexpr int kLpsTKP = kLpsTK + 4;
+
+template <int MODE, int KB, int CB, typename TX, typename TY>
+__device__ void tgemm_lps_body(const GemmArgs<TX, TY>& ga, int bid, int nb) {
+  if (gemm_skip(ga, bid)) return;
+  using VT = typename LpTraits<MODE>::VT;
+  constexpr bool SPLIT = MODE == GM_F32;
+  constexpr bool SCALED = MODE == GM_F16 || SPLIT;
+  constexpr int WPB = 4, KW = KB * 16, TK = kLpsTK, TKP = kLpsTKP, NKS = TK / 16;
+  constexpr int NV = SPLIT ? 2 : 1;                  // V terms (hi, lo)
+  constexpr int CHUNK16 = NV * KW * TK * 2 / 16;     // 16-byte pieces per V chunk
+  constexpr int VPT = CHUNK16 / (WPB * 64);          // per thread
+  static_assert(CHUNK16 % (WPB * 64) == 0, "V chunk must split evenly over the block");
+  const VT* __restrict__ Vg = static_cast<const VT*>(ga.V);
+  const TX* __restrict__ X = ga.X;
+  TY* __restrict__ Y = ga.Y;
+  const int nt = ga.nt, M = ga.M, ldv = ga.ldv, dotmode = ga.dotmode;
+  const int nkc = ldv / KW;
+  const int logical = xcd_remap(bid, nb);
+  const int cbk = logical / nkc, kc = logical - cbk * nkc;
+  const int kbase = kc * KW;
+  __shared__ __align__(16) VT Vs[NV * KW * TKP];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int kq = lane >> 4, cl = lane & 15;
+  const int col0 = (cbk * WPB + wave) * CB * 16 + cl;
+  // V chunk pieces: piece i covers row (i / 4) of term (i / (4 KW)) and 8
+  // consecutive t (16 bytes)
+  uint4 vreg[VPT];
+  TX xn[CB][NKS][4];
+  auto fetch = [&](int t0) {
+#pragma unroll
+    for (int e = 0; e < VPT; ++e) {
+      const int i = threadIdx.x + WPB * 64 * e;
+      const int term = i / (4 * KW), rem = i - term * 4 * KW;
+      const int r = rem >> 2, q = rem & 3;
+      const size_t src = ((size_t)term * ldv + kbase + r) * ldv + t0 + 8 * q;
+      vreg[e] = *reinterpret_cast<const uint4*>(Vg + src);
+    }
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int t = t0 + 16 * ks + 4 * kq + j;
+          const int col = col0 + cb * 16;
+          xn[cb][ks][j] = (t < nt && col < M) ? X[(size_t)t * M + col] : TX(0);
+        }
+  };
+  v4f acc[CB][KB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) acc[cb][kb] = (v4f){0.f, 0.f, 0.f, 0.f};
+  float scale = 0.0f;  // current operand scale (0: none chosen yet)
+  const int nchunk = (nt + TK - 1) / TK;
+  fetch(0);
+  for (int c = 0; c < nchunk; ++c) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < VPT; ++e) {
+      const int i = threadIdx.x + WPB * 64 * e;
+      const int term = i / (4 * KW), rem = i - term * 4 * KW;
+      const int r = rem >> 2, q = rem & 3;
+      // two 8-byte stores: the padded rows (72 bytes) are 8-byte aligned only
+      uint2* d = reinterpret_cast<uint2*>(&Vs[(term * KW + r) * TKP + 8 * q]);
+      d[0] = make_uint2(vreg[e].x, vreg[e].y);
+      d[1] = make_uint2(vreg[e].z, vreg[e].w);
+    }
+    float xc[CB][NKS][4];
+    float amax = 0.0f;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          xc[cb][ks][j] = (float)xn[cb][ks][j];
+          amax = fmaxf(amax, fabsf(xc[cb][ks][j]));
+        }
+    __syncthreads();
+    if (c + 1 < nchunk) fetch((c + 1) * TK);
+    if constexpr (SCALED) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
+      if (amax > 0.0f && __builtin_isfinite(amax)) {
+        int e;
+        frexpf(amax, &e);           // amax < 2^e
+        e = e < -100 ? -100 : e;    // keep 2^(14 - e) finite in float32
+        const float sn = ldexpf(1.0f, 14 - e);
+        if (scale != 0.0f && sn != scale) {
+          const float ratio = sn / scale;  // a power of two: exact
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) acc[cb][kb] *= ratio;
+        }
+        scale = sn;
+      }
+    }
+    const float sc = (SCALED && scale != 0.0f) ? scale : 1.0f;
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      if constexpr (SPLIT) {
+        v4h bh[CB], bl[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float xv = xc[cb][ks][j] * sc;
+            const _Float16 h = (_Float16)xv;
+            bh[cb][j] = h;
+            bl[cb][j] = (_Float16)(xv - (float)h);
+          }
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+          const int r = kb * 16 + cl;
+          const v4h ah = *reinterpret_cast<const v4h*>(&Vs[r * TKP + 16 * ks + 4 * kq]);
+          const v4h al = *reinterpret_cast<const v4h*>(&Vs[(KW + r) * TKP + 16 * ks + 4 * kq]);
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            acc[cb][kb] = __builtin_amdgcn_mfma_f32_16x16x16f16(al, bh[cb], acc[cb][kb], 0, 0, 0);
+            acc[cb][kb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bl[cb], acc[cb][kb], 0, 0, 0);
+            acc[cb][kb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bh[cb], acc[cb][kb], 0, 0, 0);
+          }
+        }
+      } else if constexpr (MODE == GM_F16) {
+        v4h b[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) b[cb][j] = (_Float16)(xc[cb][ks][j] * sc);
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+          const v4h a =
+              *reinterpret_cast<const v4h*>(&Vs[(kb * 16 + cl) * TKP + 16 * ks + 4 * kq]);
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+            acc[cb][kb] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b[cb], acc[cb][kb], 0, 0, 0);
+        }
+      } else {
+        v4s b[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) b[cb][j] = f2bf(xc[cb][ks][j]);
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+          const v4s a =
+              *reinterpret_cast<const v4s*>(&Vs[(kb * 16 + cl) * TKP + 16 * ks + 4 * kq]);
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+            acc[cb][kb] =
+                __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[cb], acc[cb][kb], 0, 0, 0);
+        }
+      }
+    }
+  }
+  const float vunscale = SPLIT ? (float)(1.0 / kVSplitScale) : 1.0f;
+  const float unscale = ((SCALED && scale != 0.0f) ? 1.0f / scale : 1.0f) * vunscale;
+  double dots[2] = {0.0, 0.0};
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    const int col = col0 + cb * 16;
+    if (col >= M) continue;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int jr = 0; jr < 4; ++jr) {
+        // float32-accumulating 16x16 results: register jr of lane l holds row
+        // 4 (l / 16) + jr, column l % 16
+        const int k = kbase + kb * 16 + 4 * kq + jr;
+        if (k < nt) {
+          const size_t o = (size_t)k * M + col;
+          const double v = (double)(acc[cb][kb][jr] * unscale);
+          Y[o] = (TY)v;
+          if (dotmode != DOT_NONE) {
+            dots[0] += ga.rvec[o] * v;
+            if (dotmode == DOT_FLEX) dots[1] += ga.qvec[o] * v;
+          }
+        }
+      }
+  }
+  if (dotmode != DOT_NONE) reduce_store<2>(dots, ga.rb, T_RZ, bid);
+}
+
+template <int MODE, int KB, int CB, typename TX, typename TY>
+__global__ __launch_bounds__(256) void k_tgemm_lps(GemmArgs<TX, TY> a) {
+  tgemm_lps_body<MODE, KB, CB, TX, TY>(a, blockIdx.x, gridDim.x);
+}
+
 // Streaming persistent form for N_t <= 128 (NTP = N_t rounded up to 16):
 // each block stages all of V in LDS once; each wave then streams 16-node
 // column tiles (tile w, w + #waves, ...) with two operand register sets, so
@@ -684,10 +889,35 @@ int f64_launch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r, 
 }
 
 
+template <int MODE, typename TX, typename TY>
+int lps_launch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r, const double* q,
+               hipStream_t s) {
+  // the float32 split of float64 operands (its forward transform) takes one
+  // 16-node tile per wave: its prefetched registers would otherwise leave one
+  // wave per SIMD (221 against 275 us at 64^2 x 2048); float16 and bfloat16
+  // keep two (117 against 147 us)
+  constexpr int KB = 8, CB = (MODE == GM_F32 && sizeof(TX) == 8) ? 1 : 2;
+  const int M = P.g.M;
+  const int ncolblk = (M + 4 * CB * 16 - 1) / (4 * CB * 16);
+  const int grid = ncolblk * (P.ntps / (KB * 16));
+  GemmArgs<TX, TY> a{P.Vs_lp, X, Y, P.g.nt, M, ncolblk, dotmode, r, q, P.red, P.pcg_done,
+                     P.rr_gate};
+  a.ldv = P.ntps;
+  hipLaunchKernelGGL((k_tgemm_lps<MODE, KB, CB, TX, TY>), dim3(grid), dim3(256), 0, s, a);
+  return grid;
+}
+
 template <typename TX, typename TY>
 int tgemm_launch(const Plan& P, int mode, const TX* X, TY* Y, int dotmode, const double* r,
                  const double* q, hipStream_t s) {
   const int nt = P.g.nt;
+  if constexpr (!std::is_same<TX, double>::value || !std::is_same<TY, double>::value) {
+    if (mode != GM_F64 && P.ntp == 0 && P.ntps > 0 && P.tune.lp_stream) {
+      if (mode == GM_F32) return lps_launch<GM_F32>(P, X, Y, dotmode, r, q, s);
+      if (mode == GM_F16) return lps_launch<GM_F16>(P, X, Y, dotmode, r, q, s);
+      return lps_launch<GM_BF16>(P, X, Y, dotmode, r, q, s);
+    }
+  }
   if (P.ntp > 0 && P.tune.tgemm_pers) {
     if (mode == GM_F64) return pers_dispatch<GM_F64>(P, X, Y, dotmode, r, q, s);
     if (mode == GM_F32) return pers_dispatch<GM_F32>(P, X, Y, dotmode, r, q, s);

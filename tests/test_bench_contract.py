@@ -29,10 +29,13 @@ def test_cost_model_bounds():
     assert (bound, dtype) == ("mfma", "fp64") and work == 2.0 * inst.nt * n
     # the low-precision GEMMs stream their operands at N_t <= 128 ...
     assert bench.algorithmic("tgemm_f32_fwd", inst, "mixed_fp32")[0] == "hbm"
-    # ... and run with float64 products above it
+    # ... and above it are priced on the float16 matrix cores (three products
+    # per element pair for the float32 split)
     long = wl.neumann_square(n=64, nt=2048)
     bound, work, dtype = bench.algorithmic("tgemm_f32_inv", long, "mixed_fp32")
-    assert (bound, dtype) == ("mfma", "fp64") and work == 2.0 * long.nt * long.n
+    assert (bound, dtype) == ("mfma", "fp16") and work == 3 * 2.0 * long.nt * long.n
+    bound, work, dtype = bench.algorithmic("tgemm_f16_fwd", long, "mixed_fp16")
+    assert (bound, dtype) == ("mfma", "fp16") and work == 2.0 * long.nt * long.n
 
 
 @pytest.mark.parametrize("kernel", ["rows_fwd_f32", "cols_solve_f64", "rhs", "backproj_prox"])

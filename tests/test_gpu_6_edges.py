@@ -1,12 +1,15 @@
 """GPU parity at the edges of the accepted problems, against the oracle.
 
-* Long horizons, N_t > 128: the time transform leaves the LDS-resident kernel
-  for the streaming float64 one in every precision. Cases: 200 steps (one full
+* Long horizons, N_t > 128: the time transform leaves the LDS-resident kernels
+  for the streaming ones (V through LDS in chunks of 16 or 32 time rows):
+  float64 products in FP64, float16 / bfloat16 products (the float32 mode as
+  a two-term float16 split) in the MIXED modes. Cases: 200 steps (one full
   and one partial block of 128 output rows, ragged spatial axis 12), the
   N_t = 2048 of the paper's long-horizon runs (Table 5.5), and the largest
   N_t a plan accepts, 4096. Bounds as for the short cases: operator products
   1e-12 of |Op| |x| entrywise, the float64 preconditioner 1e-12 of max |z|,
-  the MIXED ones 2e-5 normwise (their spatial solves are float32), PCG to its
+  the MIXED ones normwise by the arithmetic of each mode (2e-5 with the
+  float32 split, 1e-2 float16, 5e-2 bfloat16, as at N_t <= 128), PCG to its
   rtol with the true residual formed by the oracle. CP iterates: both sides
   stop PCG at a 1e-13 relative residual; the bound is 1e-10 of each block's
   max norm, or the float64 rounding floor u kappa(A) of a solve with A where
@@ -74,7 +77,10 @@ def test_long_operators(case):
         assert np.all(err <= 1e-12 * scale + 1e-300), (err / scale).max()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32", "mixed_fp16"])
+MIXED_TOL = {"mixed_fp32": 2e-5, "mixed_fp16": 1e-2, "mixed_bf16": 5e-2}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32", "mixed_fp16", "mixed_bf16"])
 @pytest.mark.parametrize("l", [1, 2])
 @pytest.mark.parametrize("case", LONG, ids=_ids)
 def test_long_precond(case, l, precision):
@@ -91,10 +97,33 @@ def test_long_precond(case, l, precision):
         assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
     else:
         err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-        assert err <= 2e-5, err
+        say(f"  normwise error {err:.2e}")
+        assert err <= MIXED_TOL[precision], err
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_fp16", "mixed_bf16"])
+def test_long_lowprec_gemm_against_float64_products(precision, monkeypatch):
+    """The streaming low-precision time transform (N_t > 128) against the same
+    plan with float64 products there (MFG_TUNE lp_stream=0): the difference is
+    the products' rounding only, within each mode's bound."""
+    case = (2, 16, 16, 2048, "periodic", 0.01)
+    inst = _inst(case)
+    g = grid_of(inst)
+    say(f"long lp gemm vs f64 products {precision}")
+    r = np.random.default_rng(17).standard_normal(g.n)
+    out = []
+    for lp in ("1", "0"):
+        monkeypatch.setenv("MFG_TUNE", f"lp_stream={lp}")
+        with plan_of(inst, precision=precision) as P:
+            z = empty(g.n)
+            mfg.mfg_precond(P, dev(r), z)
+            out.append(host(z))
+    err = np.linalg.norm(out[0] - out[1]) / np.linalg.norm(out[1])
+    say(f"  normwise difference {err:.2e}")
+    assert err <= MIXED_TOL[precision], err
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32", "mixed_fp16"])
 @pytest.mark.parametrize("case", LONG, ids=_ids)
 def test_long_pcg(case, precision):
     inst = _inst(case)
@@ -107,7 +136,7 @@ def test_long_pcg(case, precision):
         its, rel, _ = mfg.mfg_pcg(P, dev(b), u, 1e-10, 300)
         got = host(u)
     assert rel <= 2e-10
-    assert its <= 40
+    assert its <= (80 if precision == "mixed_fp16" else 40), its
     res = np.linalg.norm(ops.apply_AAt(g, S, got) - b)
     floor = np.finfo(float).eps * np.linalg.norm(ops.abs_AAt_bound(g, S, got))
     assert res <= 2e-10 * np.linalg.norm(b) + 50 * floor, res / np.linalg.norm(b)
