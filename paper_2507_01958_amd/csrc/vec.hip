@@ -67,9 +67,11 @@ __device__ void update_body(const UpdArgs& a, int bid, int nb) {
   double acc[1] = {0.0};
   for (long long i = (long long)bid * blockDim.x + threadIdx.x; i < a.n;
        i += (long long)nb * blockDim.x) {
-    if (a.first) a.x[i] = alpha * a.p[i];
-    else a.x[i] += alpha * a.p[i];
-    const double ri = a.r[i] - alpha * a.q[i];
+    // explicit fused multiply-adds, so the operations do not depend on the
+    // compiler's contraction choices in this kernel
+    const double pv = a.p[i];
+    a.x[i] = a.first ? alpha * pv : __builtin_fma(alpha, pv, a.x[i]);
+    const double ri = __builtin_fma(-alpha, a.q[i], a.r[i]);
     a.r[i] = ri;
     acc[0] += ri * ri;
   }
