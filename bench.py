@@ -166,12 +166,17 @@ def parse():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--nt", type=int, default=128)
     ap.add_argument("--workload", default="neumann256",
-                    choices=["neumann256", "batch", "grad", "adaptive", "paper"],
+                    choices=["neumann256", "batch", "grad", "adaptive", "paper", "torus1d",
+                             "nu_sweep"],
                     help="neumann256: the headline line; batch: 32 uneven periodic instances, "
                          "batched vs one plan at a time; grad: gradient through 50 CP "
                          "iterations; adaptive: time to solution with the Section 5 "
                          "stopping and inner-tolerance rules; paper: the paper's Problems 1 "
-                         "and 2 at N_x = 64, N_t = 512 with those rules")
+                         "and 2 at N_x = 64, N_t = 512 with those rules; torus1d: 200 CP "
+                         "iterations on the 1-D torus 64x32 at rtol 1e-10; nu_sweep: 500 CP "
+                         "iterations on the 2-D torus 128^2x64 for four nu, FP64 vs FP32")
+    ap.add_argument("--cp-iters", type=int, default=0,
+                    help="CP iterations of the torus1d / nu_sweep runs (0: 200 / 500)")
     ap.add_argument("--batch", type=int, default=32, help="instances of the batch workload")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of tuning them first")
@@ -373,6 +378,112 @@ def bench_adaptive(args):
     }))
 
 
+def _run_fixed(inst, variant, n_iter, rtol, warmup_runs=1):
+    """n_iter CP iterations from the initial point at PCG tolerance rtol, timed
+    after `warmup_runs` untimed identical runs; returns (seconds, stats, state)."""
+    import torch
+
+    from paper_2507_01958_amd import mfg
+    dev = torch.device("cuda:0")
+    V = torch.from_numpy(inst.V).to(dev)
+    m0 = torch.from_numpy(inst.m0).to(dev)
+    P = mfg.mfg_plan(_problem(inst, variant), V, m0)
+    st = mfg.CPState(P)
+    for rep in range(warmup_runs + 1):
+        mfg.mfg_cp_init(P, st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = mfg.mfg_cp_solve(P, st, n_iter, rtol, 1000)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+    y = st.y.clone()
+    xi = st.xi.clone()
+    P.close()
+    return t, stats, y, xi
+
+
+def bench_torus1d(args):
+    """The 1-D torus workload (N_x = 64, N_t = 32, nu = 0.1, V = sin(2 pi x)/2,
+    three Gaussian bumps): 200 CP iterations with PCG to rtol 1e-10, FP64 and the
+    FP32 preconditioner; CP iterations per second of the whole run."""
+    import numpy as np
+    import torch
+
+    from paper_2507_01958_amd import workloads as wl
+    torch.cuda.set_device(0)
+    inst = wl.torus_1d()
+    n_iter = args.cp_iters or 200
+    res = {}
+    for variant in ("fp64", "mixed_fp32"):
+        t, stats, y, xi = _run_fixed(inst, variant, n_iter, 1e-10, args.warmup and 1)
+        res[variant] = {"seconds": t, "cp_iters_per_s": n_iter / t,
+                        "mean_pcg_iters": float(np.mean(stats["pcg_iters"])), "y": y}
+    ref = res["fp64"].pop("y")
+    dev = (res["mixed_fp32"].pop("y") - ref).abs().max().item() / ref.abs().max().item()
+    res["mixed_fp32"]["deviation_vs_fp64"] = dev
+    print(json.dumps({
+        "metric": "CP iters/s, 1-D torus 64x32, 200 CP iterations at PCG rtol 1e-10",
+        "value": res["fp64"]["cp_iters_per_s"], "unit": "CP iters/s",
+        "n_gpus": 1, "steps": n_iter, "warmup": 1,
+        "ms_per_step": 1e3 * res["fp64"]["seconds"] / n_iter,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic (seeded)",
+        "config": {"workload": f"torus1d_{inst.nx}x{inst.nt}_nu{inst.nu:g}", "pcg_rtol": 1e-10,
+                   "cp_iters": n_iter},
+        "variants": res, "roofline": None, "cpu_baseline": None,
+    }))
+
+
+def bench_nu_sweep(args):
+    """The 2-D torus 128^2 x 64 with V = sin(2 pi x) cos(2 pi y) over
+    nu in {1e-3, 1e-2, 1e-1, 1}: 500 CP iterations with PCG to rtol 1e-8, FP64
+    against the FP32 preconditioner; CP iterations per second, mean PCG
+    iterations, and the deviation of the mixed run's final iterate (max-norm,
+    relative, per block: m, w, and the multiplier xi)."""
+    import numpy as np
+    import torch
+
+    from paper_2507_01958_amd import workloads as wl
+    torch.cuda.set_device(0)
+    n_iter = args.cp_iters or 500
+    res = {}
+    tot = {"fp64": [0, 0.0], "mixed_fp32": [0, 0.0]}
+    for nu in (1e-3, 1e-2, 1e-1, 1.0):
+        inst = wl.torus_2d_trig(nu=nu)
+        r = {}
+        for variant in ("fp64", "mixed_fp32"):
+            t, stats, y, xi = _run_fixed(inst, variant, n_iter, RTOL, args.warmup and 1)
+            r[variant] = {"seconds": t, "cp_iters_per_s": n_iter / t,
+                          "mean_pcg_iters": float(np.mean(stats["pcg_iters"])),
+                          "_y": y, "_xi": xi}
+            tot[variant][0] += n_iter
+            tot[variant][1] += t
+        n = inst.n
+        a, b = r["mixed_fp32"], r["fp64"]
+        rel = lambda u, v: (u - v).abs().max().item() / max(v.abs().max().item(), 1e-300)
+        a["deviation_vs_fp64"] = {"m": rel(a["_y"][:n], b["_y"][:n]),
+                                  "w": rel(a["_y"][n:], b["_y"][n:]),
+                                  "xi": rel(a["_xi"], b["_xi"])}
+        for v in r.values():
+            v.pop("_y")
+            v.pop("_xi")
+        res[f"nu={nu:g}"] = r
+    rates = {k: c / t for k, (c, t) in tot.items()}
+    best = max(rates, key=rates.get)
+    print(json.dumps({
+        "metric": "CP iters/s over the nu sweep, 2-D torus 128^2x64, 500 CP iterations, "
+                  "PCG rtol 1e-8",
+        "value": rates[best], "unit": "CP iters/s",
+        "n_gpus": 1, "steps": 4 * n_iter, "warmup": 1,
+        "ms_per_step": 1e3 / rates[best],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if best == "fp64" else "f64+fp32", "data": "synthetic (seeded)",
+        "config": {"workload": "torus2d_128x128x64_nu_sweep", "pcg_rtol": RTOL,
+                   "cp_iters_per_nu": n_iter, "variant": best},
+        "sweep_cp_iters_per_s": rates, "per_nu": res, "roofline": None, "cpu_baseline": None,
+    }))
+
+
 # The paper's own runs at N_x = 64, N_t = 512, nu = 1e-2 (Tables 5.1 and 5.3, the
 # DCT-VIII preconditioner, 32 CPU cores): CP iterations, average CG iterations
 # per projection and total seconds. Context, not a target: another machine and a
@@ -466,6 +577,12 @@ def main():
     if args.workload == "paper":
         bench_paper(args)
         return
+    if args.workload == "torus1d":
+        bench_torus1d(args)
+        return
+    if args.workload == "nu_sweep":
+        bench_nu_sweep(args)
+        return
     import numpy as np
     import torch
 
@@ -480,17 +597,20 @@ def main():
     stream = torch.cuda.current_stream()
 
     # the right-hand side of CP iteration 50 of the float64 run (the PCG
-    # solves/s are measured on it, on the first one, and on a N(0,1) vector)
-    with mfg.mfg_plan(_problem(inst, "fp64"), V, m0, stream) as P:
-        st = mfg.CPState(P)
-        mfg.mfg_cp_init(P, st)
-        mfg.mfg_cp_solve(P, st, 49, RTOL, PCG_MAXIT, stats=False)
-        z = st.xi + st.sigma * st.ybar
-        b50 = torch.empty(inst.n, dtype=torch.float64, device=dev)
-        mfg.mfg_apply_C(P, z, b50)
-        b50[: inst.M] -= st.sigma * m0 * (inst.nt / inst.T)
-        torch.cuda.synchronize()
-        del st, z
+    # solves/s are measured on it, on the first one, and on a N(0,1) vector;
+    # --pcg-reps 0 leaves the PCG solves out, e.g. for counter runs)
+    b50 = None
+    if args.pcg_reps > 0:
+        with mfg.mfg_plan(_problem(inst, "fp64"), V, m0, stream) as P:
+            st = mfg.CPState(P)
+            mfg.mfg_cp_init(P, st)
+            mfg.mfg_cp_solve(P, st, 49, RTOL, PCG_MAXIT, stats=False)
+            z = st.xi + st.sigma * st.ybar
+            b50 = torch.empty(inst.n, dtype=torch.float64, device=dev)
+            mfg.mfg_apply_C(P, z, b50)
+            b50[: inst.M] -= st.sigma * m0 * (inst.nt / inst.T)
+            torch.cuda.synchronize()
+            del st, z
 
     results = {}
     for variant in args.variants.split(","):
@@ -523,7 +643,7 @@ def main():
         rhs["cp_iter50"] = b50
         u = torch.empty(inst.n, dtype=torch.float64, device=dev)
         pcg = {}
-        for name, b in rhs.items():
+        for name, b in (rhs.items() if args.pcg_reps > 0 else ()):
             its, rel, _ = mfg.mfg_pcg(P, b, u, RTOL, PCG_MAXIT, true_residual=True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -566,7 +686,7 @@ def main():
         "data": "synthetic (seeded)",
         "config": {"workload": f"neumann2d_{inst.nx}x{inst.ny}x{inst.nt}_nu{inst.nu:g}",
                    "pcg_rtol": RTOL, "variant": best, "l": 1},
-        "pcg_solves_per_s": results[best]["pcg"]["cp_iter1"]["solves_per_s"],
+        "pcg_solves_per_s": results[best]["pcg"].get("cp_iter1", {}).get("solves_per_s"),
         "roofline": results[best]["roofline"],
         "cpu_baseline": cpu,
         "variants": results,

@@ -173,6 +173,7 @@ static void read_tune_env(Tune& t) {
       else if (k == "aat_big" && v >= 0 && v <= 2) t.aat_big = v;
       else if (k == "flex" && (v >= -1 && v <= 1)) t.flex = v;
       else if (k == "lp_stream" && (v == 0 || v == 1)) t.lp_stream = v;
+      else if (k == "rhs_tc" && v >= 0 && v <= 64) t.rhs_tc = v;
     }
     pos = end + 1;
   }

@@ -69,6 +69,8 @@ struct AatArgs {
 // init (PCG start fused into the right-hand side): b is the PCG residual r
 // (the solve starts at x = 0), block partials of b.b go to the T_BB site and
 // block 0 resets the PCG status with tol2 = rtol^2 (by value or from tol2_dev).
+// tc: time slices per block (each block owns 256 consecutive cells of a slice
+// and walks tc slices; the grid is ceil(M / 256) * ceil(N_t / tc) blocks).
 struct RhsArgs {
   Geom g;
   const double* xi;
@@ -83,6 +85,7 @@ struct RhsArgs {
   RedBuf rb;
   double tol2;
   const double* tol2_dev;
+  int tc;
 };
 
 struct BackprojArgs {

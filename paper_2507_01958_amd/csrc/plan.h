@@ -33,6 +33,9 @@ struct Tune {
   // time GEMM with low-precision products also when N_t > 128 (V streamed
   // through LDS); 0: float64 products there
   int lp_stream = 1;
+  // right-hand-side kernel: time slices walked per block (0: chosen from the
+  // geometry alone; not autotuned, so batched and single-plan runs agree)
+  int rhs_tc = 0;
 };
 
 // Optional per-kernel timing with HIP events recorded on the plan's stream

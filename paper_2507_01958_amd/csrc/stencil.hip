@@ -77,52 +77,77 @@ __device__ __forceinline__ void geom_dispatch(const Geom& g, A&&... args) {
 
 // b = Cr (xi + sigma ybar) - sigma [t==0] m0/dt. With ybar == nullptr this is
 // b = Cr xi (apply_C). ZM: z = xi + sigma ybar read ready-made from zin.
+//
+// Logical block lb owns the cells sb * 256 + threadIdx.x (+ k * nsp * 256) of
+// a slice (spatial block sb = lb % nsp) and walks a chunk of a.tc slices
+// (chunk lb / nsp); each thread keeps its cell's z_t of the m-component for the
+// next slice's -z_{t-1}/dt term, so only the chunk's first slice reads slice
+// t-1. The single-plan launch spreads logical blocks over the XCDs in
+// contiguous ranges, so the blocks that read a row's neighbour rows share an L2.
+constexpr int kRhsMaxSpatial = 8192;
+
+__host__ __device__ inline int rhs_nsp(const Geom& g) {
+  const int nsp = (g.M + kThreads - 1) / kThreads;
+  return nsp < kRhsMaxSpatial ? nsp : kRhsMaxSpatial;
+}
+
+// One cell's column of b over slices [t0, t1).
 template <bool HASBAR, bool ZM, bool HAS0, bool NEU>
-__device__ void rhs_cells(const RhsArgs& a, int bid, int nb, double& acc) {
-  const Geom g = a.g;
+__device__ __forceinline__ void rhs_column(const RhsArgs& a, int rem, int t0, int t1,
+                                           double& acc) {
+  const Geom& g = a.g;
   const double* __restrict__ xi = ZM ? a.zin : a.xi;
   const double* __restrict__ ybar = a.ybar;
-  const double* __restrict__ m0 = a.m0;
   double* __restrict__ b = a.b;
   const double sigma = a.sigma_dev ? *a.sigma_dev : a.sigma;
   const long long n = g.n;
-  for (long long p = (long long)bid * blockDim.x + threadIdx.x; p < n;
-       p += (long long)nb * blockDim.x) {
-    // n < 2^31 (checked by the plan): 32-bit index arithmetic
-    const unsigned pu = (unsigned)p;
-    const int t = (int)(pu / (unsigned)g.M);
-    const int rem = (int)(pu - (unsigned)t * (unsigned)g.M);
-    const int i0 = (int)((unsigned)rem / (unsigned)g.n1), i1 = rem - i0 * g.n1;
-    auto z = [&](int c, size_t idx) -> double {
-      const size_t k = (size_t)c * n + idx;
-      // one rounding (fma), as where z is formed by the back-projection
-      return (HASBAR && !ZM) ? __builtin_fma(sigma, ybar[k], xi[k]) : xi[k];
-    };
+  const int i0 = rem / g.n1, i1 = rem - i0 * g.n1;
+  const int row = i0 * g.n1;
+  const int j1p = row + nbr1(i1 + 1, g.n1, NEU), j1m = row + nbr1(i1 - 1, g.n1, NEU);
+  const int j0p = nbr1(i0 + 1, g.n0, NEU) * g.n1 + i1, j0m = nbr1(i0 - 1, g.n0, NEU) * g.n1 + i1;
+  auto z = [&](int c, size_t idx) -> double {
+    const size_t k = (size_t)c * n + idx;
+    // one rounding (fma), as where z is formed by the back-projection
+    return (HASBAR && !ZM) ? __builtin_fma(sigma, ybar[k], xi[k]) : xi[k];
+  };
+  double zprev = t0 >= 1 ? z(0, (size_t)(t0 - 1) * g.M + rem) : 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const size_t base = (size_t)t * g.M;
     // m-part: L z_t - [t>=1] z_{t-1}/dt
-    const double zc = z(0, at(g, t, i0, i1));
-    double Kz = (2.0 * zc - z(0, at(g, t, i0, nbr1(i1 + 1, g.n1, NEU))) -
-                 z(0, at(g, t, i0, nbr1(i1 - 1, g.n1, NEU)))) * g.ih1sq;
-    if (HAS0)
-      Kz += (2.0 * zc - z(0, at(g, t, nbr1(i0 + 1, g.n0, NEU), i1)) -
-             z(0, at(g, t, nbr1(i0 - 1, g.n0, NEU), i1))) * g.ih0sq;
+    const double zc = z(0, base + rem);
+    double Kz = (2.0 * zc - z(0, base + j1p) - z(0, base + j1m)) * g.ih1sq;
+    if (HAS0) Kz += (2.0 * zc - z(0, base + j0p) - z(0, base + j0m)) * g.ih0sq;
     double r = g.nu * Kz + zc * g.idt;
-    if (t >= 1) r -= z(0, at(g, t - 1, i0, i1)) * g.idt;
+    if (t >= 1) r -= zprev * g.idt;
     // flux part: sum_c B_c w^(c)_t
     {
       constexpr int ce = HAS0 ? 3 : 1, co = HAS0 ? 4 : 2;
-      auto fe = [&](int j) { return z(ce, at(g, t, i0, j)); };
-      auto fo = [&](int j) { return z(co, at(g, t, i0, j)); };
+      auto fe = [&](int j) { return z(ce, base + row + j); };
+      auto fo = [&](int j) { return z(co, base + row + j); };
       r += (D1w<NEU>(fe, i1, g.n1) + D2w<NEU>(fo, i1, g.n1)) * g.ih1;
     }
     if (HAS0) {
-      auto fe = [&](int i) { return z(1, at(g, t, i, i1)); };
-      auto fo = [&](int i) { return z(2, at(g, t, i, i1)); };
+      auto fe = [&](int i) { return z(1, base + (size_t)i * g.n1 + i1); };
+      auto fo = [&](int i) { return z(2, base + (size_t)i * g.n1 + i1); };
       r += (D1w<NEU>(fe, i0, g.n0) + D2w<NEU>(fo, i0, g.n0)) * g.ih0;
     }
-    if (HASBAR && t == 0) r -= sigma * m0[rem] * g.idt;
-    b[p] = r;
+    if (HASBAR && t == 0) r -= sigma * a.m0[rem] * g.idt;
+    b[base + rem] = r;
     if (HASBAR) acc += r * r;
+    zprev = zc;
   }
+}
+
+template <bool HASBAR, bool ZM, bool HAS0, bool NEU>
+__device__ void rhs_cells(const RhsArgs& a, int lb, int nb, double& acc) {
+  (void)nb;
+  const Geom g = a.g;
+  const int nsp = rhs_nsp(g);
+  const int chunk = lb / nsp;
+  const int t0 = chunk * a.tc, t1 = min(g.nt, t0 + a.tc);
+  for (int rem = (lb - chunk * nsp) * kThreads + (int)threadIdx.x; rem < g.M;
+       rem += nsp * kThreads)
+    rhs_column<HASBAR, ZM, HAS0, NEU>(a, rem, t0, t1, acc);
 }
 
 template <bool HASBAR, bool ZM>
@@ -136,12 +161,7 @@ struct RhsCells {
 };
 
 template <bool HASBAR>
-__device__ void rhs_body(const RhsArgs& a, int bid, int nb) {
-  double acc[1] = {0.0};
-  if (HASBAR && a.zin && (!a.zmode_dev || *a.zmode_dev != 0.0))
-    geom_dispatch<RhsCells<HASBAR, true>::template F>(a.g, a, bid, nb, acc[0]);
-  else
-    geom_dispatch<RhsCells<HASBAR, false>::template F>(a.g, a, bid, nb, acc[0]);
+__device__ void rhs_finish(const RhsArgs& a, int bid, double (&acc)[1]) {
   if (HASBAR && a.init) {
     // PCG start: x = 0 (written by the first update), r = b, b.b partials,
     // status reset
@@ -154,6 +174,17 @@ __device__ void rhs_body(const RhsArgs& a, int bid, int nb) {
     }
     reduce_store<1>(acc, a.rb, T_BB, bid);
   }
+}
+
+// Batched form: the z source and the geometry are chosen per instance.
+template <bool HASBAR>
+__device__ void rhs_body(const RhsArgs& a, int bid, int nb) {
+  double acc[1] = {0.0};
+  if (HASBAR && a.zin && (!a.zmode_dev || *a.zmode_dev != 0.0))
+    geom_dispatch<RhsCells<HASBAR, true>::template F>(a.g, a, bid, nb, acc[0]);
+  else
+    geom_dispatch<RhsCells<HASBAR, false>::template F>(a.g, a, bid, nb, acc[0]);
+  rhs_finish<HASBAR>(a, bid, acc);
 }
 
 // Components of Cr^T u at one cell: out[0] = m-part, out[1+c] = B_c^T u_t.
@@ -532,30 +563,56 @@ struct BackprojCells {
   }
 };
 
+// GEO: 0 = geometry chosen per block (batched form), else 1 + 2 HAS0 + NEU.
+template <int GEO>
 __device__ void backproj_body(const BackprojArgs& a, int bid, int nb) {
   const double tau = a.tau_dev ? *a.tau_dev : a.tau;
   const double theta = a.theta_dev ? *a.theta_dev : a.theta;
   const double sig_next = a.zout ? (a.sigma_dev ? *a.sigma_dev : a.sigma) / theta : 0.0;
   if (a.zflag && bid == 0 && threadIdx.x == 0) *a.zflag = a.zout ? 1.0 : 0.0;
   double acc[1] = {0.0};
-  geom_dispatch<BackprojCells>(a.g, a, bid, nb, tau, theta, sig_next, acc[0]);
+  if constexpr (GEO == 0)
+    geom_dispatch<BackprojCells>(a.g, a, bid, nb, tau, theta, sig_next, acc[0]);
+  else
+    BackprojCells<((GEO - 1) & 2) != 0, ((GEO - 1) & 1) != 0>::run(a, bid, nb, tau, theta,
+                                                                   sig_next, acc[0]);
   reduce_store<1>(acc, a.rb, T_DM, bid);
 }
 
+// Single-plan form, one specialisation per geometry. Logical blocks in
+// contiguous ranges per XCD: the blocks that read a row's neighbour rows of u
+// (and slice t+1) mostly share an L2.
+template <int GEO>
 __global__ __launch_bounds__(kThreads) void k_backproj_prox(BackprojArgs a) {
-  backproj_body(a, blockIdx.x, gridDim.x);
+  backproj_body<GEO>(a, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
 __global__ __launch_bounds__(kThreads) void k_backproj_prox_batch(const BackprojArgs* A,
                                                                   const int* off, int ninst) {
   const int i = batch_instance(off, ninst, blockIdx.x);
   const BackprojArgs a = A[i];
-  backproj_body(a, blockIdx.x - off[i], off[i + 1] - off[i]);
+  backproj_body<0>(a, blockIdx.x - off[i], off[i + 1] - off[i]);
 }
 
-template <bool HASBAR>
+// Single-plan form: one specialisation per z source and geometry (chosen on
+// the host), so each carries only its own path's registers.
+template <bool HASBAR, bool ZM, bool HAS0, bool NEU>
 __global__ __launch_bounds__(kThreads) void k_rhs(RhsArgs a) {
-  rhs_body<HASBAR>(a, blockIdx.x, gridDim.x);
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  double acc[1] = {0.0};
+  rhs_cells<HASBAR, ZM, HAS0, NEU>(a, lb, gridDim.x, acc[0]);
+  rhs_finish<HASBAR>(a, lb, acc);
+}
+
+template <bool HASBAR, bool ZM>
+void rhs_launch(const RhsArgs& a, int grid, hipStream_t s) {
+  if (a.g.has0) {
+    if (a.g.neumann) hipLaunchKernelGGL((k_rhs<HASBAR, ZM, true, true>), dim3(grid), dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((k_rhs<HASBAR, ZM, true, false>), dim3(grid), dim3(kThreads), 0, s, a);
+  } else {
+    if (a.g.neumann) hipLaunchKernelGGL((k_rhs<HASBAR, ZM, false, true>), dim3(grid), dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((k_rhs<HASBAR, ZM, false, false>), dim3(grid), dim3(kThreads), 0, s, a);
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_rhs_batch(const RhsArgs* A, const int* off,
@@ -651,14 +708,30 @@ void aat_launch(const Plan& P, const double* src, const double* pold, double* pn
 
 }  // namespace
 
+// Time slices per block of the right-hand-side kernel: about 4096 blocks (at
+// most 4096 + 8192, so the b.b partials of a PCG start stay few). A function of
+// the geometry only, so batched and single-plan runs sum b.b in the same order.
+static int rhs_tc(const Plan& P) {
+  const Geom& g = P.g;
+  const long long nsp = rhs_nsp(g);
+  long long tc = P.tune.rhs_tc > 0 ? P.tune.rhs_tc : (nsp * g.nt + 4095) / 4096;
+  // the grid stays within the reduction's partial-sum capacity
+  while (tc < g.nt && nsp * ((g.nt + tc - 1) / tc) > P.red.max_blocks) ++tc;
+  return (int)(tc < 1 ? 1 : tc > g.nt ? g.nt : tc);
+}
+
 RhsArgs rhs_args(const Plan& P, const double* xi, const double* ybar, double sigma,
                  const double* sigma_dev, double* b, const double* zin,
                  const double* zmode_dev) {
-  return RhsArgs{P.g, xi, ybar, sigma, sigma_dev, P.m0, b, zin, zmode_dev, 0, P.red, 0.0, nullptr};
+  return RhsArgs{P.g,  xi,    ybar, sigma,   sigma_dev,    P.m0, b, zin, zmode_dev, 0,
+                 P.red, 0.0, nullptr, rhs_tc(P)};
 }
 
-// (capped so that the b.b partials of a PCG start stay few)
-int rhs_grid(const Plan& P) { return grid_for(P.g.n, 8192); }
+int rhs_grid(const Plan& P) {
+  const Geom& g = P.g;
+  const int tc = rhs_tc(P);
+  return rhs_nsp(g) * ((g.nt + tc - 1) / tc);
+}
 
 void launch_rhs(const Plan& P, const double* xi, const double* ybar, double sigma,
                 const double* m0, double* b, hipStream_t s, const double* zin, double init_rtol) {
@@ -669,16 +742,17 @@ void launch_rhs(const Plan& P, const double* xi, const double* ybar, double sigm
   const int grid = rhs_grid(P);
   {
     ProfScope ps(P, "rhs", s);
-    hipLaunchKernelGGL(k_rhs<true>, dim3(grid), dim3(kThreads), 0, s, a);
+    if (zin) rhs_launch<true, true>(a, grid, s);
+    else rhs_launch<true, false>(a, grid, s);
   }
   if (a.init) launch_finish(P, T_BB, grid, OP_BB, s);
 }
 
 void launch_apply_C(const Plan& P, const double* y, double* b, hipStream_t s) {
   ProfScope ps(P, "apply_C", s);
-  const RhsArgs a{P.g, y, nullptr, 0.0, nullptr, nullptr, b, nullptr, nullptr, 0, P.red, 0.0,
-                  nullptr};
-  hipLaunchKernelGGL(k_rhs<false>, dim3(rhs_grid(P)), dim3(kThreads), 0, s, a);
+  const RhsArgs a{P.g,   y,   nullptr, 0.0, nullptr,       nullptr, b, nullptr, nullptr, 0,
+                  P.red, 0.0, nullptr, rhs_tc(P)};
+  rhs_launch<false, false>(a, rhs_grid(P), s);
 }
 
 void launch_apply_CT(const Plan& P, const double* u, double* y, hipStream_t s) {
@@ -741,7 +815,13 @@ void launch_backproj_prox(const Plan& P, const double* u, double* xi, double* y,
     BackprojArgs a = backproj_args(P, u, xi, y, ybar, tau, theta, nullptr, nullptr, vout);
     a.zout = zout;
     a.sigma = sigma;
-    hipLaunchKernelGGL(k_backproj_prox, dim3(grid), dim3(kThreads), 0, s, a);
+    const int geo = 1 + 2 * (P.g.has0 ? 1 : 0) + (P.g.neumann ? 1 : 0);
+    switch (geo) {
+      case 1: hipLaunchKernelGGL(k_backproj_prox<1>, dim3(grid), dim3(kThreads), 0, s, a); break;
+      case 2: hipLaunchKernelGGL(k_backproj_prox<2>, dim3(grid), dim3(kThreads), 0, s, a); break;
+      case 3: hipLaunchKernelGGL(k_backproj_prox<3>, dim3(grid), dim3(kThreads), 0, s, a); break;
+      default: hipLaunchKernelGGL(k_backproj_prox<4>, dim3(grid), dim3(kThreads), 0, s, a);
+    }
   }
   launch_finish(P, T_DM, grid, OP_DM, s);
 }

@@ -65,15 +65,32 @@ __device__ void update_body(const UpdArgs& a, int bid, int nb) {
     if (bad) S[S_BAD] = (double)bad;
   }
   double acc[1] = {0.0};
-  for (long long i = (long long)bid * blockDim.x + threadIdx.x; i < a.n;
-       i += (long long)nb * blockDim.x) {
-    // explicit fused multiply-adds, so the operations do not depend on the
-    // compiler's contraction choices in this kernel
-    const double pv = a.p[i];
-    a.x[i] = a.first ? alpha * pv : __builtin_fma(alpha, pv, a.x[i]);
-    const double ri = __builtin_fma(-alpha, a.q[i], a.r[i]);
-    a.r[i] = ri;
-    acc[0] += ri * ri;
+  // explicit fused multiply-adds, so the operations do not depend on the
+  // compiler's contraction choices in this kernel; the first update of a solve
+  // (x = 0) writes x without reading it
+  // (x, r, p, q are distinct buffers: every load of an element is issued
+  // before its stores)
+  double* __restrict__ x = a.x;
+  double* __restrict__ r = a.r;
+  const double* __restrict__ p = a.p;
+  const double* __restrict__ q = a.q;
+  const long long i0 = (long long)bid * blockDim.x + threadIdx.x, di = (long long)nb * blockDim.x;
+  if (a.first) {
+    for (long long i = i0; i < a.n; i += di) {
+      const double pv = p[i], qv = q[i], rv = r[i];
+      x[i] = alpha * pv;
+      const double ri = __builtin_fma(-alpha, qv, rv);
+      r[i] = ri;
+      acc[0] += ri * ri;
+    }
+  } else {
+    for (long long i = i0; i < a.n; i += di) {
+      const double pv = p[i], qv = q[i], rv = r[i], xv = x[i];
+      x[i] = __builtin_fma(alpha, pv, xv);
+      const double ri = __builtin_fma(-alpha, qv, rv);
+      r[i] = ri;
+      acc[0] += ri * ri;
+    }
   }
   reduce_store<1>(acc, a.rb, T_RR, bid);
 }

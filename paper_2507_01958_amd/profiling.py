@@ -60,8 +60,9 @@ def classify(seq):
         if s.startswith("k_AAt_tile"):
             out.append("aat_fused" if s.endswith("true>") else "aat")
         elif s.startswith("k_rhs"):
-            out.append("rhs" if "<true>" in s else "apply_C")
-        elif s.startswith(("k_tgemm64", "k_tgemm_lp<", "k_tgemm_stream")):
+            # k_rhs<HASBAR, ...>: the right-hand side with HASBAR, else C y
+            out.append("rhs" if _targs(s)[:1] == ["true"] else "apply_C")
+        elif s.startswith(("k_tgemm64", "k_tgemm_lp<", "k_tgemm_lps<", "k_tgemm_stream")):
             args = _targs(s)
             mode = "f64" if s.startswith("k_tgemm64") else MODES.get(args[0], "f64")
             tx, ty = args[-2], args[-1]
