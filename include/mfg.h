@@ -54,7 +54,17 @@ typedef enum {
   MFG_ERR_OOM = 7            /* device allocation failed */
 } mfg_status_t;
 
-typedef enum { MFG_BC_PERIODIC = 0, MFG_BC_NEUMANN = 1 } mfg_bc_t;
+/* Boundary conditions: periodic (the torus of Section 2) or Neumann (the
+ * no-flux problem MFG_Omega with the Section 4.3 matrices), on every axis or,
+ * for d = 2, one type per axis (Section 4.3: the spatial solver allows
+ * different conditions in x and y; each axis takes its own spacing, one-axis
+ * operators and transform, DFT or DCT-II). */
+typedef enum {
+  MFG_BC_PERIODIC = 0,
+  MFG_BC_NEUMANN = 1,
+  MFG_BC_PERIODIC_X_NEUMANN_Y = 2, /* d = 2 only */
+  MFG_BC_NEUMANN_X_PERIODIC_Y = 3  /* d = 2 only */
+} mfg_bc_t;
 
 /* Coupling f(x, m) of the running cost F = integral of f dm (Section 2.1):
  * LINEAR f = m + V(x); QUADRATIC f = m^2/2 + V(x), the crowd-aversion coupling
@@ -69,11 +79,10 @@ typedef enum { MFG_F_LINEAR = 0, MFG_F_QUADRATIC = 1, MFG_F_POTENTIAL = 2 } mfg_
  * bfloat16 inputs (or float32 operands carried as two float16 terms) and
  * float32 accumulation. With float16 and bfloat16 PCG takes its flexible
  * (Polak-Ribiere) form; with float32 the preconditioner is symmetric to
- * float32 rounding and PCG keeps the standard form. The low-precision time
- * transform holds all of V in LDS and serves N_t <= 128; for longer horizons
- * every mode runs the time transform with float64 products (float32 input or
- * output in the MIXED modes), so the MIXED modes then differ from FP64 only in
- * their float32 spatial solves. */
+ * float32 rounding and PCG keeps the standard form. Up to N_t = 128 the
+ * low-precision time transform holds all of V in LDS; for longer horizons it
+ * streams V through LDS in chunks of 32 time rows, with the float16 operands
+ * scaled per chunk by powers of two. */
 typedef enum {
   MFG_FP64 = 0,
   MFG_MIXED_FP32 = 1,  /* time transform at fp32 accuracy (fp32 operands split into two fp16
@@ -93,8 +102,8 @@ typedef struct {
                         spatial node count must be below 2^31 */
   double T;          /* horizon T > 0; dt = T / N_t */
   double lo[2], hi[2]; /* domain [a,b] x [c,d]: periodic dx = (b-a)/N_x,
-                          Neumann dx = (b-a)/(N_x+1) (Section 2) */
-  int bc;            /* mfg_bc_t, applied on every axis */
+                          Neumann dx = (b-a)/(N_x+1) (Section 2), per axis */
+  int bc;            /* mfg_bc_t */
   double nu;         /* viscosity nu >= 0 */
   double qprime;     /* Hamiltonian |p|^q'/q' (eq. power_hamiltonian); only 2 */
   double gamma;      /* strong-convexity constant of the accelerated CP

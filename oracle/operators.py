@@ -76,14 +76,15 @@ class Spatial:
 
     def __init__(self, g: Grid):
         self.g = g
-        Kx = neg_laplacian_1d(g.nx, g.bc, g.dx)
-        D1x, D2x = divergence_factors(g.nx, g.bc)
+        bx, by = g.bcs
+        Kx = neg_laplacian_1d(g.nx, bx, g.dx)
+        D1x, D2x = divergence_factors(g.nx, bx)
         if g.d == 1:
             self.K = Kx
             self.B = [D1x / g.dx, D2x / g.dx]
         else:
-            Ky = neg_laplacian_1d(g.ny, g.bc, g.dy)
-            D1y, D2y = divergence_factors(g.ny, g.bc)
+            Ky = neg_laplacian_1d(g.ny, by, g.dy)
+            D1y, D2y = divergence_factors(g.ny, by)
             Ix = sp.identity(g.nx, format="csr")
             Iy = sp.identity(g.ny, format="csr")
             self.K = (sp.kron(Kx, Iy) + sp.kron(Ix, Ky)).tocsr()

@@ -94,35 +94,31 @@ def spatial_solve(g: Grid, y: np.ndarray, lam: float) -> np.ndarray:
 
     R = lambda_x/dx^2 + lambda_y/dy^2 (tiled), S = nu^2 R*R + 2R + (nu lambda/dt) R
     + lambda/dt^2; transform along y then x, divide entrywise by S, invert.
-    Periodic uses the DFT, Neumann the orthonormal DCT-II.
+    Each axis takes the transform of its boundary type: the DFT (periodic) or
+    the orthonormal DCT-II (Neumann).
     """
-    lx = laplacian_eigs(g.nx, g.bc) / g.dx ** 2
+    bx, by = g.bcs
+    lx = laplacian_eigs(g.nx, bx) / g.dx ** 2
     if g.d == 1:
         R = lx
         Y = y
-        axes = (0,)
+        axes = ((0, bx),)
     else:
-        ly = laplacian_eigs(g.ny, g.bc) / g.dy ** 2
+        ly = laplacian_eigs(g.ny, by) / g.dy ** 2
         R = lx[:, None] + ly[None, :]
         Y = y.reshape(g.nx, g.ny)
-        axes = (1, 0)
+        axes = ((1, by), (0, bx))
     S = g.nu ** 2 * R * R + 2.0 * R + (g.nu * lam / g.dt) * R + lam / g.dt ** 2
-    if g.bc == "periodic":
-        Yh = Y
-        for ax in axes:
-            Yh = sfft.fft(Yh, axis=ax)
-        Xh = Yh / S
-        for ax in reversed(axes):
-            Xh = sfft.ifft(Xh, axis=ax)
-        X = Xh.real
-    else:
-        Yh = Y
-        for ax in axes:
-            Yh = sfft.dct(Yh, type=2, norm="ortho", axis=ax)
-        Xh = Yh / S
-        for ax in reversed(axes):
-            Xh = sfft.idct(Xh, type=2, norm="ortho", axis=ax)
-        X = Xh
+    Yh = Y
+    for ax, bc in axes:
+        Yh = sfft.fft(Yh, axis=ax) if bc == "periodic" else \
+            sfft.dct(Yh, type=2, norm="ortho", axis=ax)
+    Xh = Yh / S
+    for ax, bc in reversed(axes):
+        Xh = sfft.ifft(Xh, axis=ax) if bc == "periodic" else \
+            sfft.idct(Xh, type=2, norm="ortho", axis=ax)
+    # the result is real (complex only through a DFT axis)
+    X = np.real(Xh)
     return np.asarray(X).reshape(-1)
 
 

@@ -179,6 +179,20 @@ static void read_tune_env(Tune& t) {
   }
 }
 
+bool axis_neumann(const mfg_problem_t* pb, int a) {
+  switch (pb->bc) {
+    case MFG_BC_NEUMANN: return true;
+    case MFG_BC_PERIODIC_X_NEUMANN_Y: return a == 1;
+    case MFG_BC_NEUMANN_X_PERIODIC_Y: return a == 0;
+    default: return false;
+  }
+}
+
+double axis_spacing(const mfg_problem_t* pb, int a) {
+  const double L = pb->hi[a] - pb->lo[a];
+  return axis_neumann(pb, a) ? L / (pb->n[a] + 1) : L / pb->n[a];
+}
+
 // Validate the problem and fill the plan's geometry and scalars (no device
 // allocation, no table).
 int setup_problem(Plan& P, const mfg_problem_t* pb, hipStream_t stream) {
@@ -199,8 +213,10 @@ int setup_problem(Plan& P, const mfg_problem_t* pb, hipStream_t stream) {
       return fail(MFG_ERR_UNSUPPORTED, "grid too large: N_t times the spatial nodes must be below 2^31");
   }
   if (!(pb->T > 0.0) || !std::isfinite(pb->T)) return fail(MFG_ERR_INVALID_ARG, "T must be > 0");
-  if (pb->bc != MFG_BC_PERIODIC && pb->bc != MFG_BC_NEUMANN)
-    return fail(MFG_ERR_INVALID_ARG, "bc must be periodic or neumann");
+  if (pb->bc < MFG_BC_PERIODIC || pb->bc > MFG_BC_NEUMANN_X_PERIODIC_Y)
+    return fail(MFG_ERR_INVALID_ARG, "unknown boundary condition");
+  if (pb->d == 1 && pb->bc > MFG_BC_NEUMANN)
+    return fail(MFG_ERR_INVALID_ARG, "a boundary type per axis needs d = 2");
   if (!(pb->nu >= 0.0) || !std::isfinite(pb->nu)) return fail(MFG_ERR_INVALID_ARG, "nu must be >= 0");
   if (pb->qprime != 2.0) return fail(MFG_ERR_UNSUPPORTED, "only q' = 2 is implemented");
   if (!(pb->gamma > 0.0) || !std::isfinite(pb->gamma))
@@ -225,12 +241,10 @@ int setup_problem(Plan& P, const mfg_problem_t* pb, hipStream_t stream) {
   P.l = pb->l;
   P.gamma = pb->gamma;
   Geom& g = P.g;
-  const bool neu = pb->bc == MFG_BC_NEUMANN;
-  auto spacing = [&](int a) {
-    const double L = pb->hi[a] - pb->lo[a];
-    return neu ? L / (pb->n[a] + 1) : L / pb->n[a];
-  };
-  g.neumann = neu ? 1 : 0;
+  auto spacing = [&](int a) { return axis_spacing(pb, a); };
+  // internal axis 1 (j) is y when d = 2 and x when d = 1; axis 0 (i) is x
+  g.bcm = pb->d == 2 ? (axis_neumann(pb, 1) ? 1 : 0) | (axis_neumann(pb, 0) ? 2 : 0)
+                     : (axis_neumann(pb, 0) ? 1 : 0);
   g.nt = pb->nt;
   g.nu = pb->nu;
   g.dt = pb->T / pb->nt;
@@ -384,10 +398,13 @@ static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const d
 
   // spatial axes
   if (g.has0) {
-    if ((rc = build_axis(P, P.ax0, g.n0, neu, spacing(0)))) return rc;
-    if ((rc = build_axis(P, P.ax1, g.n1, neu, spacing(1)))) return rc;
+    if ((rc = build_axis(P, P.ax0, g.n0, axis_neumann(&P.pb, 0), axis_spacing(&P.pb, 0))))
+      return rc;
+    if ((rc = build_axis(P, P.ax1, g.n1, axis_neumann(&P.pb, 1), axis_spacing(&P.pb, 1))))
+      return rc;
   } else {
-    if ((rc = build_axis(P, P.ax1, g.n1, neu, spacing(0)))) return rc;
+    if ((rc = build_axis(P, P.ax1, g.n1, axis_neumann(&P.pb, 0), axis_spacing(&P.pb, 0))))
+      return rc;
   }
 
   // workspace

@@ -25,7 +25,7 @@ struct Geom {
   int nt, M;       // time steps, nodes per slice
   long long n;     // nt * M
   int has0;        // axis 0 present (d = 2)
-  int neumann;     // 1: Neumann, 0: periodic (all axes)
+  int bcm;         // Neumann axes: bit 0 axis 1 (j), bit 1 axis 0 (i); else periodic
   int ncomp;       // 2d flux components
   int cb1;         // first flux component acting along axis 1 (2 if d=2, 0 if d=1)
   double ih0, ih1;     // 1/h per axis (0 when absent)

@@ -207,16 +207,11 @@ extern "C" int mfg_pcg_noalloc(const mfg_problem_t* pb, const double* b, double*
   P.Vp16 = tt.Vp16;
   P.Vp16s = tt.Vp16s;
   P.Vpbf = tt.Vpbf;
-  const bool neu = pb->bc == MFG_BC_NEUMANN;
-  auto spacing = [&](int a) {
-    const double L = pb->hi[a] - pb->lo[a];
-    return neu ? L / (pb->n[a] + 1) : L / pb->n[a];
-  };
   if (g.has0) {
-    carve_axis(C, P.ax0, g.n0, neu, spacing(0), s);
-    carve_axis(C, P.ax1, g.n1, neu, spacing(1), s);
+    carve_axis(C, P.ax0, g.n0, axis_neumann(pb, 0), axis_spacing(pb, 0), s);
+    carve_axis(C, P.ax1, g.n1, axis_neumann(pb, 1), axis_spacing(pb, 1), s);
   } else {
-    carve_axis(C, P.ax1, g.n1, neu, spacing(0), s);
+    carve_axis(C, P.ax1, g.n1, axis_neumann(pb, 0), axis_spacing(pb, 0), s);
   }
   if (!C.ok) return fail(MFG_ERR_UNSUPPORTED, "problem too large for the no-allocation entry point");
   // the scalar block starts at zero on every call (earlier calls left theirs)

@@ -150,6 +150,10 @@ inline bool pcg_flexible(const Plan& P) {
 // already done by the kernel that formed b); copy the device scalars to
 // P.host_scal (synchronises the plan's stream).
 int setup_problem(Plan& P, const mfg_problem_t* pb, hipStream_t stream);
+// Boundary type of axis a of the problem (0 = x, 1 = y): true for Neumann.
+bool axis_neumann(const mfg_problem_t* pb, int a);
+// Spacing of axis a (Section 2): (b - a)/N periodic, (b - a)/(N + 1) Neumann.
+double axis_spacing(const mfg_problem_t* pb, int a);
 int run_pcg(Plan& P, const double* b, double* x, double rtol, int maxit, int* iters_out,
             double* relres_rec, double* relres_true, bool r_ready = false, bool warm = false);
 int read_scalars(Plan& P);

@@ -31,19 +31,20 @@ __device__ __forceinline__ size_t at(const Geom& g, int t, int i0, int i1) {
 }
 
 // The per-cell stencils below are specialised on the axis count (HAS0: d = 2)
-// and the boundary type (NEU: Neumann) so the cell loops carry no branches on
-// them; *_dispatch picks the specialisation once per block.
+// and the boundary types (BC: bit 0 set when axis 1 is Neumann, bit 1 when
+// axis 0 is; periodic otherwise) so the cell loops carry no branches on them;
+// *_dispatch picks the specialisation once per block.
 
 // (K v)(i0, i1) in slice t of v.
-template <bool HAS0, bool NEU>
+template <bool HAS0, int BC>
 __device__ __forceinline__ double Kop(const double* __restrict__ v, const Geom& g, int t, int i0,
                                       int i1) {
   const double c = v[at(g, t, i0, i1)];
-  double r = (2.0 * c - v[at(g, t, i0, nbr1(i1 + 1, g.n1, NEU))] -
-              v[at(g, t, i0, nbr1(i1 - 1, g.n1, NEU))]) * g.ih1sq;
+  double r = (2.0 * c - v[at(g, t, i0, nbr1(i1 + 1, g.n1, BC & 1))] -
+              v[at(g, t, i0, nbr1(i1 - 1, g.n1, BC & 1))]) * g.ih1sq;
   if (HAS0)
-    r += (2.0 * c - v[at(g, t, nbr1(i0 + 1, g.n0, NEU), i1)] -
-          v[at(g, t, nbr1(i0 - 1, g.n0, NEU), i1)]) * g.ih0sq;
+    r += (2.0 * c - v[at(g, t, nbr1(i0 + 1, g.n0, BC & 2), i1)] -
+          v[at(g, t, nbr1(i0 - 1, g.n0, BC & 2), i1)]) * g.ih0sq;
   return r;
 }
 
@@ -63,15 +64,19 @@ __device__ __forceinline__ double D2w(F f, int i, int n) {
   return (i <= n - 2 ? a : 0.0) - (i >= 1 ? b : 0.0);
 }
 
-// Calls F<HAS0, NEU>::run(args...) for the geometry's axis count and boundary.
-template <template <bool, bool> class F, class... A>
+// Calls F<HAS0, BC>::run(args...) for the geometry's axis count and boundaries.
+template <template <bool, int> class F, class... A>
 __device__ __forceinline__ void geom_dispatch(const Geom& g, A&&... args) {
   if (g.has0) {
-    if (g.neumann) F<true, true>::run(args...);
-    else F<true, false>::run(args...);
+    switch (g.bcm) {
+      case 0: F<true, 0>::run(args...); break;
+      case 1: F<true, 1>::run(args...); break;
+      case 2: F<true, 2>::run(args...); break;
+      default: F<true, 3>::run(args...);
+    }
   } else {
-    if (g.neumann) F<false, true>::run(args...);
-    else F<false, false>::run(args...);
+    if (g.bcm & 1) F<false, 1>::run(args...);
+    else F<false, 0>::run(args...);
   }
 }
 
@@ -92,7 +97,7 @@ __host__ __device__ inline int rhs_nsp(const Geom& g) {
 }
 
 // One cell's column of b over slices [t0, t1).
-template <bool HASBAR, bool ZM, bool HAS0, bool NEU>
+template <bool HASBAR, bool ZM, bool HAS0, int BC>
 __device__ __forceinline__ void rhs_column(const RhsArgs& a, int rem, int t0, int t1,
                                            double& acc) {
   const Geom& g = a.g;
@@ -103,8 +108,9 @@ __device__ __forceinline__ void rhs_column(const RhsArgs& a, int rem, int t0, in
   const long long n = g.n;
   const int i0 = rem / g.n1, i1 = rem - i0 * g.n1;
   const int row = i0 * g.n1;
-  const int j1p = row + nbr1(i1 + 1, g.n1, NEU), j1m = row + nbr1(i1 - 1, g.n1, NEU);
-  const int j0p = nbr1(i0 + 1, g.n0, NEU) * g.n1 + i1, j0m = nbr1(i0 - 1, g.n0, NEU) * g.n1 + i1;
+  constexpr bool NEU1 = (BC & 1) != 0, NEU0 = (BC & 2) != 0;
+  const int j1p = row + nbr1(i1 + 1, g.n1, NEU1), j1m = row + nbr1(i1 - 1, g.n1, NEU1);
+  const int j0p = nbr1(i0 + 1, g.n0, NEU0) * g.n1 + i1, j0m = nbr1(i0 - 1, g.n0, NEU0) * g.n1 + i1;
   auto z = [&](int c, size_t idx) -> double {
     const size_t k = (size_t)c * n + idx;
     // one rounding (fma), as where z is formed by the back-projection
@@ -124,12 +130,12 @@ __device__ __forceinline__ void rhs_column(const RhsArgs& a, int rem, int t0, in
       constexpr int ce = HAS0 ? 3 : 1, co = HAS0 ? 4 : 2;
       auto fe = [&](int j) { return z(ce, base + row + j); };
       auto fo = [&](int j) { return z(co, base + row + j); };
-      r += (D1w<NEU>(fe, i1, g.n1) + D2w<NEU>(fo, i1, g.n1)) * g.ih1;
+      r += (D1w<NEU1>(fe, i1, g.n1) + D2w<NEU1>(fo, i1, g.n1)) * g.ih1;
     }
     if (HAS0) {
       auto fe = [&](int i) { return z(1, base + (size_t)i * g.n1 + i1); };
       auto fo = [&](int i) { return z(2, base + (size_t)i * g.n1 + i1); };
-      r += (D1w<NEU>(fe, i0, g.n0) + D2w<NEU>(fo, i0, g.n0)) * g.ih0;
+      r += (D1w<NEU0>(fe, i0, g.n0) + D2w<NEU0>(fo, i0, g.n0)) * g.ih0;
     }
     if (HASBAR && t == 0) r -= sigma * a.m0[rem] * g.idt;
     b[base + rem] = r;
@@ -138,7 +144,7 @@ __device__ __forceinline__ void rhs_column(const RhsArgs& a, int rem, int t0, in
   }
 }
 
-template <bool HASBAR, bool ZM, bool HAS0, bool NEU>
+template <bool HASBAR, bool ZM, bool HAS0, int BC>
 __device__ void rhs_cells(const RhsArgs& a, int lb, int nb, double& acc) {
   (void)nb;
   const Geom g = a.g;
@@ -147,15 +153,15 @@ __device__ void rhs_cells(const RhsArgs& a, int lb, int nb, double& acc) {
   const int t0 = chunk * a.tc, t1 = min(g.nt, t0 + a.tc);
   for (int rem = (lb - chunk * nsp) * kThreads + (int)threadIdx.x; rem < g.M;
        rem += nsp * kThreads)
-    rhs_column<HASBAR, ZM, HAS0, NEU>(a, rem, t0, t1, acc);
+    rhs_column<HASBAR, ZM, HAS0, BC>(a, rem, t0, t1, acc);
 }
 
 template <bool HASBAR, bool ZM>
 struct RhsCells {
-  template <bool HAS0, bool NEU>
+  template <bool HAS0, int BC>
   struct F {
     __device__ static void run(const RhsArgs& a, int bid, int nb, double& acc) {
-      rhs_cells<HASBAR, ZM, HAS0, NEU>(a, bid, nb, acc);
+      rhs_cells<HASBAR, ZM, HAS0, BC>(a, bid, nb, acc);
     }
   };
 };
@@ -188,29 +194,29 @@ __device__ void rhs_body(const RhsArgs& a, int bid, int nb) {
 }
 
 // Components of Cr^T u at one cell: out[0] = m-part, out[1+c] = B_c^T u_t.
-template <bool HAS0, bool NEU>
+template <bool HAS0, int BC>
 __device__ __forceinline__ void CT_cell(const Geom& g, const double* __restrict__ u, int t, int i0,
                                         int i1, double* out) {
   const double uc = u[at(g, t, i0, i1)];
-  double m = g.nu * Kop<HAS0, NEU>(u, g, t, i0, i1) + uc * g.idt;
+  double m = g.nu * Kop<HAS0, BC>(u, g, t, i0, i1) + uc * g.idt;
   if (t <= g.nt - 2) m -= u[at(g, t + 1, i0, i1)] * g.idt;
   out[0] = m;
   {
     constexpr int cb1 = HAS0 ? 2 : 0;
-    const double up = u[at(g, t, i0, nbr1(i1 + 1, g.n1, NEU))];
-    const double um = u[at(g, t, i0, nbr1(i1 - 1, g.n1, NEU))];
+    const double up = u[at(g, t, i0, nbr1(i1 + 1, g.n1, BC & 1))];
+    const double um = u[at(g, t, i0, nbr1(i1 - 1, g.n1, BC & 1))];
     out[1 + cb1] = (uc - up) * g.ih1;
     out[2 + cb1] = (um - uc) * g.ih1;
   }
   if (HAS0) {
-    const double up = u[at(g, t, nbr1(i0 + 1, g.n0, NEU), i1)];
-    const double um = u[at(g, t, nbr1(i0 - 1, g.n0, NEU), i1)];
+    const double up = u[at(g, t, nbr1(i0 + 1, g.n0, BC & 2), i1)];
+    const double um = u[at(g, t, nbr1(i0 - 1, g.n0, BC & 2), i1)];
     out[1] = (uc - up) * g.ih0;
     out[2] = (um - uc) * g.ih0;
   }
 }
 
-template <bool HAS0, bool NEU>
+template <bool HAS0, int BC>
 struct ApplyCT {
   __device__ static void run(const Geom& g, const double* __restrict__ u,
                              double* __restrict__ y) {
@@ -224,7 +230,7 @@ struct ApplyCT {
       const int rem = (int)(pu - (unsigned)t * (unsigned)g.M);
       const int i0 = (int)((unsigned)rem / (unsigned)g.n1), i1 = rem - i0 * g.n1;
       double out[5];
-      CT_cell<HAS0, NEU>(g, u, t, i0, i1, out);
+      CT_cell<HAS0, BC>(g, u, t, i0, i1, out);
 #pragma unroll
       for (int c = 0; c <= NC; ++c) y[(size_t)c * n + p] = out[c];
     }
@@ -322,8 +328,8 @@ __device__ void aat_body(const AatArgs& a, int bid, int nb) {
       rp[e] = 0.0;
       if (idx < NS && t >= 0 && t < g.nt) {
         const int ii = idx / C::SJ - C::HI, jj = idx % C::SJ - 2;
-        const int gi = HAS0 ? nbr_tile(i0 + ii, g.n0, g.neumann) : 0;
-        const int gj = nbr_tile(j0 + jj, g.n1, g.neumann);
+        const int gi = HAS0 ? nbr_tile(i0 + ii, g.n0, g.bcm & 2) : 0;
+        const int gj = nbr_tile(j0 + jj, g.n1, g.bcm & 1);
         const size_t o = (size_t)t * g.M + (size_t)gi * g.n1 + gj;
         rz[e] = src[o];
         if (FUSE && !first) rp[e] = pold[o];
@@ -454,7 +460,7 @@ __global__ __launch_bounds__(kThreads) void k_value(Geom g, const double* __rest
 //   R = (u^t - u^{t+1})/dt + nu K u^t + |P_K(-[D_h u^t])|^2 / 2 - f(x, m^{t+1}),
 // where -[D_h u] is the flux part of Cr^T u (B_c^T u per component) and
 // f = c2 m^2 + c1 m + V; u has N_t + 1 slices, m is the primal's first block.
-template <bool HAS0, bool NEU>
+template <bool HAS0, int BC>
 struct HjbCells {
   __device__ static void run(const Geom& g, const double* __restrict__ y,
                              const double* __restrict__ u, const double* __restrict__ Vpot,
@@ -469,20 +475,20 @@ struct HjbCells {
       const double uc = u[at(g, t, i0, i1)];
       double ham = 0.0;
       {
-        const double up = u[at(g, t, i0, nbr1(i1 + 1, g.n1, NEU))];
-        const double um = u[at(g, t, i0, nbr1(i1 - 1, g.n1, NEU))];
+        const double up = u[at(g, t, i0, nbr1(i1 + 1, g.n1, BC & 1))];
+        const double um = u[at(g, t, i0, nbr1(i1 - 1, g.n1, BC & 1))];
         const double e = fmax((uc - up) * g.ih1, 0.0), o = fmin((um - uc) * g.ih1, 0.0);
         ham += e * e + o * o;
       }
       if (HAS0) {
-        const double up = u[at(g, t, nbr1(i0 + 1, g.n0, NEU), i1)];
-        const double um = u[at(g, t, nbr1(i0 - 1, g.n0, NEU), i1)];
+        const double up = u[at(g, t, nbr1(i0 + 1, g.n0, BC & 2), i1)];
+        const double um = u[at(g, t, nbr1(i0 - 1, g.n0, BC & 2), i1)];
         const double e = fmax((uc - up) * g.ih0, 0.0), o = fmin((um - uc) * g.ih0, 0.0);
         ham += e * e + o * o;
       }
       const double m = y[p];
       const double f = (g.c2 * m + g.c1) * m + Vpot[rem];
-      R[p] = (uc - u[p + g.M]) * g.idt + g.nu * Kop<HAS0, NEU>(u, g, t, i0, i1) + 0.5 * ham - f;
+      R[p] = (uc - u[p + g.M]) * g.idt + g.nu * Kop<HAS0, BC>(u, g, t, i0, i1) + 0.5 * ham - f;
     }
   }
 };
@@ -497,7 +503,7 @@ __global__ __launch_bounds__(kThreads) void k_hjb(Geom g, const double* __restri
 // One CP iteration after the projection solve:
 //   xi' = Cr^T u;  y' = prox_{tau phi}(y - tau xi');  ybar = y' + theta (y' - y);
 // partial ||m' - m||^2 reduced into the device scalar S_DM.
-template <bool HAS0, bool NEU>
+template <bool HAS0, int BC>
 struct BackprojCells {
   __device__ static void run(const BackprojArgs& a, int bid, int nb, double tau, double theta,
                              double sig_next, double& acc) {
@@ -520,7 +526,7 @@ struct BackprojCells {
       const int rem = (int)(pu - (unsigned)t * (unsigned)g.M);
       const int i0 = (int)((unsigned)rem / (unsigned)g.n1), i1 = rem - i0 * g.n1;
       double x[5], yo[5], w[4];
-      CT_cell<HAS0, NEU>(g, u, t, i0, i1, x);
+      CT_cell<HAS0, BC>(g, u, t, i0, i1, x);
 #pragma unroll
       for (int c = 0; c <= NC; ++c) yo[c] = y[(size_t)c * n + p];
 #pragma unroll
@@ -563,7 +569,7 @@ struct BackprojCells {
   }
 };
 
-// GEO: 0 = geometry chosen per block (batched form), else 1 + 2 HAS0 + NEU.
+// GEO: 0 = geometry chosen per block (batched form), else 1 + 4 HAS0 + BC.
 template <int GEO>
 __device__ void backproj_body(const BackprojArgs& a, int bid, int nb) {
   const double tau = a.tau_dev ? *a.tau_dev : a.tau;
@@ -574,8 +580,8 @@ __device__ void backproj_body(const BackprojArgs& a, int bid, int nb) {
   if constexpr (GEO == 0)
     geom_dispatch<BackprojCells>(a.g, a, bid, nb, tau, theta, sig_next, acc[0]);
   else
-    BackprojCells<((GEO - 1) & 2) != 0, ((GEO - 1) & 1) != 0>::run(a, bid, nb, tau, theta,
-                                                                   sig_next, acc[0]);
+    BackprojCells<((GEO - 1) & 4) != 0, (GEO - 1) & 3>::run(a, bid, nb, tau, theta, sig_next,
+                                                            acc[0]);
   reduce_store<1>(acc, a.rb, T_DM, bid);
 }
 
@@ -596,22 +602,27 @@ __global__ __launch_bounds__(kThreads) void k_backproj_prox_batch(const Backproj
 
 // Single-plan form: one specialisation per z source and geometry (chosen on
 // the host), so each carries only its own path's registers.
-template <bool HASBAR, bool ZM, bool HAS0, bool NEU>
+template <bool HASBAR, bool ZM, bool HAS0, int BC>
 __global__ __launch_bounds__(kThreads) void k_rhs(RhsArgs a) {
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   double acc[1] = {0.0};
-  rhs_cells<HASBAR, ZM, HAS0, NEU>(a, lb, gridDim.x, acc[0]);
+  rhs_cells<HASBAR, ZM, HAS0, BC>(a, lb, gridDim.x, acc[0]);
   rhs_finish<HASBAR>(a, lb, acc);
 }
 
 template <bool HASBAR, bool ZM>
 void rhs_launch(const RhsArgs& a, int grid, hipStream_t s) {
+  const dim3 gd(grid), bd(kThreads);
   if (a.g.has0) {
-    if (a.g.neumann) hipLaunchKernelGGL((k_rhs<HASBAR, ZM, true, true>), dim3(grid), dim3(kThreads), 0, s, a);
-    else hipLaunchKernelGGL((k_rhs<HASBAR, ZM, true, false>), dim3(grid), dim3(kThreads), 0, s, a);
+    switch (a.g.bcm) {
+      case 0: hipLaunchKernelGGL((k_rhs<HASBAR, ZM, true, 0>), gd, bd, 0, s, a); break;
+      case 1: hipLaunchKernelGGL((k_rhs<HASBAR, ZM, true, 1>), gd, bd, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_rhs<HASBAR, ZM, true, 2>), gd, bd, 0, s, a); break;
+      default: hipLaunchKernelGGL((k_rhs<HASBAR, ZM, true, 3>), gd, bd, 0, s, a);
+    }
   } else {
-    if (a.g.neumann) hipLaunchKernelGGL((k_rhs<HASBAR, ZM, false, true>), dim3(grid), dim3(kThreads), 0, s, a);
-    else hipLaunchKernelGGL((k_rhs<HASBAR, ZM, false, false>), dim3(grid), dim3(kThreads), 0, s, a);
+    if (a.g.bcm & 1) hipLaunchKernelGGL((k_rhs<HASBAR, ZM, false, 1>), gd, bd, 0, s, a);
+    else hipLaunchKernelGGL((k_rhs<HASBAR, ZM, false, 0>), gd, bd, 0, s, a);
   }
 }
 
@@ -815,12 +826,14 @@ void launch_backproj_prox(const Plan& P, const double* u, double* xi, double* y,
     BackprojArgs a = backproj_args(P, u, xi, y, ybar, tau, theta, nullptr, nullptr, vout);
     a.zout = zout;
     a.sigma = sigma;
-    const int geo = 1 + 2 * (P.g.has0 ? 1 : 0) + (P.g.neumann ? 1 : 0);
-    switch (geo) {
-      case 1: hipLaunchKernelGGL(k_backproj_prox<1>, dim3(grid), dim3(kThreads), 0, s, a); break;
-      case 2: hipLaunchKernelGGL(k_backproj_prox<2>, dim3(grid), dim3(kThreads), 0, s, a); break;
-      case 3: hipLaunchKernelGGL(k_backproj_prox<3>, dim3(grid), dim3(kThreads), 0, s, a); break;
-      default: hipLaunchKernelGGL(k_backproj_prox<4>, dim3(grid), dim3(kThreads), 0, s, a);
+    const dim3 gd(grid), bd(kThreads);
+    switch (1 + 4 * (P.g.has0 ? 1 : 0) + P.g.bcm) {
+      case 1: hipLaunchKernelGGL(k_backproj_prox<1>, gd, bd, 0, s, a); break;
+      case 2: hipLaunchKernelGGL(k_backproj_prox<2>, gd, bd, 0, s, a); break;
+      case 5: hipLaunchKernelGGL(k_backproj_prox<5>, gd, bd, 0, s, a); break;
+      case 6: hipLaunchKernelGGL(k_backproj_prox<6>, gd, bd, 0, s, a); break;
+      case 7: hipLaunchKernelGGL(k_backproj_prox<7>, gd, bd, 0, s, a); break;
+      default: hipLaunchKernelGGL(k_backproj_prox<8>, gd, bd, 0, s, a);
     }
   }
   launch_finish(P, T_DM, grid, OP_DM, s);

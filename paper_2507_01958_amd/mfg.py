@@ -18,7 +18,9 @@ MFG_OK = 0
 STATUS = {0: "MFG_OK", 1: "MFG_ERR_INVALID_ARG", 2: "MFG_ERR_UNSUPPORTED",
           3: "MFG_ERR_NOT_CONVERGED", 4: "MFG_ERR_BREAKDOWN", 5: "MFG_ERR_NONFINITE",
           6: "MFG_ERR_HIP", 7: "MFG_ERR_OOM"}
-BC = {"periodic": 0, "neumann": 1}
+# one type on every axis, or (bc_x, bc_y) for d = 2
+BC = {"periodic": 0, "neumann": 1, ("periodic", "periodic"): 0, ("neumann", "neumann"): 1,
+      ("periodic", "neumann"): 2, ("neumann", "periodic"): 3}
 PRECISION = {"fp64": 0, "mixed_fp32": 1, "mixed_fp16": 2, "mixed_bf16": 3}
 COUPLING = {"linear": 0, "quadratic": 1, "potential": 2}
 
@@ -138,7 +140,8 @@ def make_problem(d, nx, ny, nt, bc, nu, gamma, l=1, precision="fp64", T=1.0, lo=
     hi = hi or (1.0, 1.0)
     pb.lo[0], pb.lo[1] = lo[0], (lo[1] if len(lo) > 1 else 0.0)
     pb.hi[0], pb.hi[1] = hi[0], (hi[1] if len(hi) > 1 else 1.0)
-    pb.bc = BC[bc] if isinstance(bc, str) else int(bc)
+    pb.bc = BC[bc] if isinstance(bc, str) else BC[tuple(bc)] if isinstance(bc, (tuple, list)) \
+        else int(bc)
     pb.nu = nu
     pb.qprime = qprime
     pb.gamma = gamma

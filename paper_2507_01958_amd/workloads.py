@@ -32,7 +32,7 @@ class Instance:
     nx: int
     ny: int            # 1 when d == 1
     nt: int
-    bc: str            # "periodic" or "neumann" (both axes)
+    bc: object         # "periodic" or "neumann" (both axes), or (bc_x, bc_y)
     nu: float
     gamma: float
     T: float
@@ -66,11 +66,17 @@ def node_coords(N: int, bc: str, a: float = 0.0, b: float = 1.0) -> np.ndarray:
     return a + (b - a) * np.arange(1, N + 1) / (N + 1)
 
 
+def axis_bcs(bc) -> tuple:
+    """(bc_x, bc_y) of a boundary specification (one type, or a per-axis pair)."""
+    return tuple(bc) if isinstance(bc, (tuple, list)) else (bc, bc)
+
+
 def _mesh(d, nx, ny, bc):
-    x = node_coords(nx, bc)
+    bx, by = axis_bcs(bc)
+    x = node_coords(nx, bx)
     if d == 1:
         return [x]
-    y = node_coords(ny, bc)
+    y = node_coords(ny, by)
     X, Y = np.meshgrid(x, y, indexing="ij")
     return [X, Y]
 
@@ -82,17 +88,18 @@ def gaussian_mixture(rng: np.random.Generator, d: int, nx: int, ny: int, bc: str
     centres = rng.uniform(0.0, 1.0, size=(K, d))
     sigmas = rng.uniform(0.05, 0.15, size=K)
     coords = _mesh(d, nx, ny, bc)
+    bcs = axis_bcs(bc)
     out = np.zeros(coords[0].shape)
     for r in range(K):
         dist2 = np.zeros_like(out)
         for ax in range(d):
             delta = coords[ax] - centres[r, ax]
-            if bc == PERIODIC:
+            if bcs[ax] == PERIODIC:
                 delta = delta - np.round(delta)
             dist2 += delta * delta
         out += np.exp(-dist2 / (2.0 * sigmas[r] ** 2))
-    dx = (1.0 / nx) if bc == PERIODIC else 1.0 / (nx + 1)
-    dy = 1.0 if d == 1 else ((1.0 / ny) if bc == PERIODIC else 1.0 / (ny + 1))
+    dx = (1.0 / nx) if bcs[0] == PERIODIC else 1.0 / (nx + 1)
+    dy = 1.0 if d == 1 else ((1.0 / ny) if bcs[1] == PERIODIC else 1.0 / (ny + 1))
     out /= out.sum() * dx * dy
     return out.reshape(-1).astype(np.float64)
 
@@ -216,6 +223,38 @@ def small_instance(seed: int, d: int, nx: int, ny: int, nt: int, bc: str, nu: fl
         gamma = 5e-4 if bc == PERIODIC else 5e-3
     return Instance(d, nx, ny, nt, bc, nu, gamma, 1.0, lo, hi, V, m0, l=l,
                     name=f"small_{d}d_{bc}_{nx}x{ny}x{nt}")
+
+
+def mixed_instance(seed: int, nx: int, ny: int, nt: int, bc_x: str, bc_y: str, nu: float,
+                   l: int = 1, K: int = 3, gamma: float = 5e-3, amp: float = 0.5,
+                   count: int = 6) -> Instance:
+    """2-D instance with a boundary type per axis. V = amp-normalised sum of
+    count products phi_p(x) psi_q(y), each factor cos(2 pi p x + phase) on a
+    periodic axis and cos(pi p x) on a Neumann axis (so V respects both
+    conditions); draws: (p, q) from {0..3}^2 minus (0,0) without replacement
+    (lexicographic list), then the coefficients ~ U[-1, 1], then the phases
+    ~ U[0, 2 pi) (x then y per term), then m0 (K bumps, minimal image on the
+    periodic axis only)."""
+    rng = np.random.default_rng(seed)
+    bc = (bc_x, bc_y)
+    pairs = [(p, q) for p in range(4) for q in range(4) if (p, q) != (0, 0)]
+    idx = rng.choice(len(pairs), size=count, replace=False)
+    a = rng.uniform(-1.0, 1.0, size=count)
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=(count, 2))
+    X, Y = _mesh(2, nx, ny, bc)
+
+    def factor(z, k, kind, phase):
+        return np.cos(2.0 * np.pi * k * z + phase) if kind == PERIODIC else np.cos(np.pi * k * z)
+
+    field = np.zeros_like(X)
+    for r, kk in enumerate(idx):
+        p, q = pairs[kk]
+        field += a[r] * factor(X, p, bc_x, ph[r, 0]) * factor(Y, q, bc_y, ph[r, 1])
+    V = (field * amp / np.abs(field).max()).reshape(-1)
+    m0 = gaussian_mixture(rng, 2, nx, ny, bc, K)
+    lo, hi = _bounds(2)
+    return Instance(2, nx, ny, nt, bc, nu, gamma, 1.0, lo, hi, V, m0, l=l,
+                    name=f"mixed_{bc_x[0]}{bc_y[0]}_{nx}x{ny}x{nt}")
 
 
 def paper_problem1(n: int, nt: int, nu: float) -> Instance:
