@@ -46,7 +46,7 @@ extern "C" {
 typedef enum {
   MFG_OK = 0,
   MFG_ERR_INVALID_ARG = 1,   /* bad shape, parameter or pointer */
-  MFG_ERR_UNSUPPORTED = 2,   /* valid but not implemented (q' != 2, FFT size) */
+  MFG_ERR_UNSUPPORTED = 2,   /* valid but not implemented (q' out of range, FFT size) */
   MFG_ERR_NOT_CONVERGED = 3, /* PCG hit maxit; iters/relres are still filled */
   MFG_ERR_BREAKDOWN = 4,     /* non-positive curvature or r.z in PCG */
   MFG_ERR_NONFINITE = 5,     /* NaN or Inf met in an input or a residual */
@@ -105,7 +105,10 @@ typedef struct {
                           Neumann dx = (b-a)/(N_x+1) (Section 2), per axis */
   int bc;            /* mfg_bc_t */
   double nu;         /* viscosity nu >= 0 */
-  double qprime;     /* Hamiltonian |p|^q'/q' (eq. power_hamiltonian); only 2 */
+  double qprime;     /* Hamiltonian |p|^q'/q' (eq. power_hamiltonian), 1.2 <= q' <= 6
+                        (2 in the paper's experiments); the flux cost is then
+                        |w|^q/(q m^(q-1)) with q = q'/(q'-1). mfg_cp_adjoint
+                        needs q' = 2. */
   double gamma;      /* strong-convexity constant of the accelerated CP
                         step sizes (Section 5); > 0 */
   int l;             /* time preconditioner of eq. prec: 1 = DCT-VIII (exact
@@ -310,7 +313,7 @@ typedef struct mfg_batch_s* mfg_batch_t;
 
 /* Build a batch of count >= 1 plans. pbs[i], V[i], m0[i] are as for mfg_plan
  * (V and m0 arrays are host arrays of device pointers). Requirements: d = 2,
- * N_t <= 128, and one MIXED precision shared by all instances (the
+ * N_t <= 128, q' = 2, and one MIXED precision shared by all instances (the
  * preconditioner of the batched path is the mixed one);
  * MFG_ERR_UNSUPPORTED otherwise. The instances' plans use `stream`; batched
  * solves run on an internal stream ordered after and before `stream` with

@@ -41,7 +41,10 @@ from .prox import LINEAR, Coupling, cell_coefficients, project_cone
 
 def prox_vjp(g: Grid, v: np.ndarray, V: np.ndarray, tau: float, gy: np.ndarray,
              cost: Coupling = LINEAR):
-    """J_prox(v)^T gy for a whole primal vector; returns (g_v, g_V (length M))."""
+    """J_prox(v)^T gy for a whole primal vector; returns (g_v, g_V (length M)).
+    Derived for q' = 2 (the closed-form reduction of the prox)."""
+    if cost.qprime != 2.0:
+        raise NotImplementedError("the prox derivative is derived for q' = 2")
     from .prox import prox_cells
     nb = 1 + g.ncomp
     c1, Vt = cell_coefficients(g, V, cost)

@@ -218,7 +218,8 @@ int setup_problem(Plan& P, const mfg_problem_t* pb, hipStream_t stream) {
   if (pb->d == 1 && pb->bc > MFG_BC_NEUMANN)
     return fail(MFG_ERR_INVALID_ARG, "a boundary type per axis needs d = 2");
   if (!(pb->nu >= 0.0) || !std::isfinite(pb->nu)) return fail(MFG_ERR_INVALID_ARG, "nu must be >= 0");
-  if (pb->qprime != 2.0) return fail(MFG_ERR_UNSUPPORTED, "only q' = 2 is implemented");
+  if (!(pb->qprime >= 1.2 && pb->qprime <= 6.0))
+    return fail(MFG_ERR_UNSUPPORTED, "q' must lie in [1.2, 6]");
   if (!(pb->gamma > 0.0) || !std::isfinite(pb->gamma))
     return fail(MFG_ERR_INVALID_ARG, "gamma must be > 0");
   if (pb->l != 1 && pb->l != 2) return fail(MFG_ERR_INVALID_ARG, "l must be 1 or 2");
@@ -277,6 +278,8 @@ int setup_problem(Plan& P, const mfg_problem_t* pb, hipStream_t stream) {
   g.n = (long long)g.nt * g.M;
   // coupling f = c2 m^2 + c1 m + V; the terminal cost adds 1/(beta dt) to the
   // last slice's linear coefficient
+  g.qp = pb->qprime;
+  g.q = pb->qprime == 2.0 ? 2.0 : pb->qprime / (pb->qprime - 1.0);
   g.c2 = pb->coupling == MFG_F_QUADRATIC ? 0.5 : 0.0;
   g.c1 = pb->coupling == MFG_F_LINEAR ? 1.0 : 0.0;
   g.c1T = pb->beta > 0.0 ? g.c1 + 1.0 / (pb->beta * g.dt) : g.c1;
@@ -964,6 +967,8 @@ int mfg_cp_adjoint(mfg_plan_t plan, const mfg_state_t* ckpts, int n_ckpt, int ev
     return fail(MFG_ERR_INVALID_ARG,
                 "the reverse sweep recomputes steps from checkpoints with cold PCG starts: "
                 "disable the warm start for the forward run and the gradient");
+  if (plan->P.pb.qprime != 2.0)
+    return fail(MFG_ERR_UNSUPPORTED, "the reverse sweep differentiates the q' = 2 prox only");
   return mfg::run_cp_adjoint(plan->P, ckpts, every, n_iter, gy_final, pcg_rtol, pcg_maxit, g_m0,
                              g_V);
 }

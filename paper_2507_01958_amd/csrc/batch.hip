@@ -387,6 +387,7 @@ int batch_create(Batch& B, const mfg_problem_t* pbs, const double* const* V,
     if (pbs[i].precision != prec) return fail(MFG_ERR_INVALID_ARG, "mixed precisions in a batch");
     if (pbs[i].d != 2) return fail(MFG_ERR_UNSUPPORTED, "batched solves need d = 2");
     if (pbs[i].nt > 128) return fail(MFG_ERR_UNSUPPORTED, "batched solves need N_t <= 128");
+    if (pbs[i].qprime != 2.0) return fail(MFG_ERR_UNSUPPORTED, "batched solves need q' = 2");
   }
   if (hipStreamCreateWithFlags(&B.stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&B.ev_in, hipEventDisableTiming) != hipSuccess ||

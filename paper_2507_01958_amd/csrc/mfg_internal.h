@@ -35,6 +35,9 @@ struct Geom {
   // terminal cost g = (m - mbar)/beta makes the linear coefficient c1T
   // (= c1 + 1/(beta dt), or c1 without a terminal cost) and the potential VT
   double c2, c1, c1T;
+  // Hamiltonian |p|^q'/q' (eq. power_hamiltonian): qp = q', q = q'/(q' - 1)
+  // the exponent of the flux cost b-hat
+  double q, qp;
 };
 
 // Deterministic two-level reduction: per-block partials, then a sum in a fixed

@@ -419,8 +419,12 @@ __global__ __launch_bounds__(kThreads) void k_prox(Geom g, const double* __restr
     const double c1 = lastslice ? g.c1T : g.c1;
     double w[4];
     for (int c = 0; c < g.ncomp; ++c) w[c] = v[(size_t)(c + 1) * n + p];
-    const double m = g.has0 ? prox_cell<4>(v[p], w, Vc, tau, c1, g.c2)
-                            : prox_cell<2>(v[p], w, Vc, tau, c1, g.c2);
+    const bool qg = g.q != 2.0;
+    const double m =
+        g.has0 ? (qg ? prox_cell<4, true>(v[p], w, Vc, tau, c1, g.c2, g.q, g.qp)
+                     : prox_cell<4>(v[p], w, Vc, tau, c1, g.c2))
+               : (qg ? prox_cell<2, true>(v[p], w, Vc, tau, c1, g.c2, g.q, g.qp)
+                     : prox_cell<2>(v[p], w, Vc, tau, c1, g.c2));
     y[p] = m;
     for (int c = 0; c < g.ncomp; ++c) y[(size_t)(c + 1) * n + p] = w[c];
   }
@@ -488,7 +492,9 @@ struct HjbCells {
       }
       const double m = y[p];
       const double f = (g.c2 * m + g.c1) * m + Vpot[rem];
-      R[p] = (uc - u[p + g.M]) * g.idt + g.nu * Kop<HAS0, BC>(u, g, t, i0, i1) + 0.5 * ham - f;
+      // Hamiltonian |P_K(-D u)|^q'/q' (ham holds the squared norm)
+      const double hq = g.qp == 2.0 ? 0.5 * ham : pow(ham, 0.5 * g.qp) / g.qp;
+      R[p] = (uc - u[p + g.M]) * g.idt + g.nu * Kop<HAS0, BC>(u, g, t, i0, i1) + hq - f;
     }
   }
 };
@@ -503,8 +509,9 @@ __global__ __launch_bounds__(kThreads) void k_hjb(Geom g, const double* __restri
 // One CP iteration after the projection solve:
 //   xi' = Cr^T u;  y' = prox_{tau phi}(y - tau xi');  ybar = y' + theta (y' - y);
 // partial ||m' - m||^2 reduced into the device scalar S_DM.
-template <bool HAS0, int BC>
-struct BackprojCells {
+// QG: general exponent q' of the Hamiltonian (prox_cell).
+template <bool HAS0, int BC, bool QG>
+struct BackprojCellsQ {
   __device__ static void run(const BackprojArgs& a, int bid, int nb, double tau, double theta,
                              double sig_next, double& acc) {
     constexpr int NC = HAS0 ? 4 : 2;
@@ -538,8 +545,8 @@ struct BackprojCells {
         for (int c = 0; c < NC; ++c) vout[(size_t)(c + 1) * n + p] = w[c];
       }
       const bool lastslice = t == g.nt - 1;
-      const double m = prox_cell<NC>(mbar, w, lastslice ? VT[rem] : Vpot[rem], tau,
-                                     lastslice ? g.c1T : g.c1, g.c2);
+      const double m = prox_cell<NC, QG>(mbar, w, lastslice ? VT[rem] : Vpot[rem], tau,
+                                         lastslice ? g.c1T : g.c1, g.c2, g.q, g.qp);
       // streaming stores: the new state is read again only by the next step
       const double mb = m + theta * (m - yo[0]);
       __builtin_nontemporal_store(m, &y[p]);
@@ -569,8 +576,12 @@ struct BackprojCells {
   }
 };
 
-// GEO: 0 = geometry chosen per block (batched form), else 1 + 4 HAS0 + BC.
-template <int GEO>
+template <bool HAS0, int BC>
+using BackprojCells = BackprojCellsQ<HAS0, BC, false>;
+
+// GEO: 0 = geometry chosen per block (batched form, q' = 2), else
+// 1 + 4 HAS0 + BC; QG: general exponent q'.
+template <int GEO, bool QG = false>
 __device__ void backproj_body(const BackprojArgs& a, int bid, int nb) {
   const double tau = a.tau_dev ? *a.tau_dev : a.tau;
   const double theta = a.theta_dev ? *a.theta_dev : a.theta;
@@ -580,17 +591,17 @@ __device__ void backproj_body(const BackprojArgs& a, int bid, int nb) {
   if constexpr (GEO == 0)
     geom_dispatch<BackprojCells>(a.g, a, bid, nb, tau, theta, sig_next, acc[0]);
   else
-    BackprojCells<((GEO - 1) & 4) != 0, (GEO - 1) & 3>::run(a, bid, nb, tau, theta, sig_next,
-                                                            acc[0]);
+    BackprojCellsQ<((GEO - 1) & 4) != 0, (GEO - 1) & 3, QG>::run(a, bid, nb, tau, theta,
+                                                                 sig_next, acc[0]);
   reduce_store<1>(acc, a.rb, T_DM, bid);
 }
 
 // Single-plan form, one specialisation per geometry. Logical blocks in
 // contiguous ranges per XCD: the blocks that read a row's neighbour rows of u
 // (and slice t+1) mostly share an L2.
-template <int GEO>
+template <int GEO, bool QG>
 __global__ __launch_bounds__(kThreads) void k_backproj_prox(BackprojArgs a) {
-  backproj_body<GEO>(a, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+  backproj_body<GEO, QG>(a, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
 __global__ __launch_bounds__(kThreads) void k_backproj_prox_batch(const BackprojArgs* A,
@@ -817,6 +828,19 @@ BackprojArgs backproj_args(const Plan& P, const double* u, double* xi, double* y
 
 int backproj_grid(const Plan& P) { return grid_for(P.g.n, P.red.max_blocks); }
 
+template <bool QG>
+void backproj_launch(const Geom& g, const BackprojArgs& a, int grid, hipStream_t s) {
+  const dim3 gd(grid), bd(kThreads);
+  switch (1 + 4 * (g.has0 ? 1 : 0) + g.bcm) {
+    case 1: hipLaunchKernelGGL((k_backproj_prox<1, QG>), gd, bd, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_backproj_prox<2, QG>), gd, bd, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_backproj_prox<5, QG>), gd, bd, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_backproj_prox<6, QG>), gd, bd, 0, s, a); break;
+    case 7: hipLaunchKernelGGL((k_backproj_prox<7, QG>), gd, bd, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_backproj_prox<8, QG>), gd, bd, 0, s, a);
+  }
+}
+
 void launch_backproj_prox(const Plan& P, const double* u, double* xi, double* y, double* ybar,
                           double tau, double theta, hipStream_t s, double* vout, double* zout,
                           double sigma) {
@@ -826,15 +850,8 @@ void launch_backproj_prox(const Plan& P, const double* u, double* xi, double* y,
     BackprojArgs a = backproj_args(P, u, xi, y, ybar, tau, theta, nullptr, nullptr, vout);
     a.zout = zout;
     a.sigma = sigma;
-    const dim3 gd(grid), bd(kThreads);
-    switch (1 + 4 * (P.g.has0 ? 1 : 0) + P.g.bcm) {
-      case 1: hipLaunchKernelGGL(k_backproj_prox<1>, gd, bd, 0, s, a); break;
-      case 2: hipLaunchKernelGGL(k_backproj_prox<2>, gd, bd, 0, s, a); break;
-      case 5: hipLaunchKernelGGL(k_backproj_prox<5>, gd, bd, 0, s, a); break;
-      case 6: hipLaunchKernelGGL(k_backproj_prox<6>, gd, bd, 0, s, a); break;
-      case 7: hipLaunchKernelGGL(k_backproj_prox<7>, gd, bd, 0, s, a); break;
-      default: hipLaunchKernelGGL(k_backproj_prox<8>, gd, bd, 0, s, a);
-    }
+    if (P.g.q != 2.0) backproj_launch<true>(P.g, a, grid, s);
+    else backproj_launch<false>(P.g, a, grid, s);
   }
   launch_finish(P, T_DM, grid, OP_DM, s);
 }

@@ -49,8 +49,14 @@ def test_version_and_error_without_gpu():
     assert rc == 1 and b"d must be" in lib.mfg_last_error()
     pb = mfg.make_problem(2, 10, 8, 4, "periodic", 0.1, 5e-4)
     assert lib.mfg_plan(ctypes.byref(pb), None, None, None, ctypes.byref(h)) == 2
-    pb = mfg.make_problem(2, 8, 8, 4, "periodic", 0.1, 5e-4, qprime=3.0)
-    assert lib.mfg_plan(ctypes.byref(pb), None, None, None, ctypes.byref(h)) == 2
+    for qp in (1.0, 1.1, 8.0):   # q' outside the supported range [1.2, 6]
+        pb = mfg.make_problem(2, 8, 8, 4, "periodic", 0.1, 5e-4, qprime=qp)
+        assert lib.mfg_plan(ctypes.byref(pb), None, None, None, ctypes.byref(h)) == 2
+    # a boundary type per axis needs d = 2; unknown codes are rejected
+    pb = mfg.make_problem(1, 8, 1, 4, ("periodic", "neumann"), 0.1, 5e-4)
+    assert lib.mfg_plan(ctypes.byref(pb), None, None, None, ctypes.byref(h)) == 1
+    pb = mfg.make_problem(2, 8, 8, 4, 4, 0.1, 5e-4)
+    assert lib.mfg_plan(ctypes.byref(pb), None, None, None, ctypes.byref(h)) == 1
     # cells of an n-vector are indexed with 32-bit arithmetic: n < 2^31
     pb = mfg.make_problem(2, 1024, 1024, 2048, "periodic", 0.1, 5e-4)
     assert lib.mfg_plan(ctypes.byref(pb), None, None, None, ctypes.byref(h)) == 2
