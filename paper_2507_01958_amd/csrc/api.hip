@@ -438,7 +438,7 @@ static int build_plan(Plan& P, const mfg_problem_t* pb, const double* V, const d
   {
     Tune t;
     if (tune_lookup(P, &t)) {
-      t.flex = P.tune.flex;
+      keep_untuned(P.tune, t);
       P.tune = t;
     }
   }

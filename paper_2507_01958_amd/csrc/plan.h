@@ -150,6 +150,8 @@ inline bool pcg_flexible(const Plan& P) {
 // already done by the kernel that formed b); copy the device scalars to
 // P.host_scal (synchronises the plan's stream).
 int setup_problem(Plan& P, const mfg_problem_t* pb, hipStream_t stream);
+// Copy the Tune fields that are not launch shapes (method choices, settings).
+void keep_untuned(const Tune& from, Tune& to);
 // Boundary type of axis a of the problem (0 = x, 1 = y): true for Neumann.
 bool axis_neumann(const mfg_problem_t* pb, int a);
 // Spacing of axis a (Section 2): (b - a)/N periodic, (b - a)/(N + 1) Neumann.

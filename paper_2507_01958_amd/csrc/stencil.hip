@@ -193,6 +193,180 @@ __device__ void rhs_body(const RhsArgs& a, int bid, int nb) {
   rhs_finish<HASBAR>(a, bid, acc);
 }
 
+// LDS-tiled right-hand side (b = Cr z - sigma [t==0] m0/dt with z = zin, or
+// z = xi + sigma ybar formed with one rounding). A block owns a TI x TJ spatial
+// tile and walks a chunk of a.tc time slices; per slice every component of z
+// on the tile plus a one-node halo (wrapped or mirrored at the boundary, as
+// nbr1 picks the neighbour) is staged in LDS with coalesced loads, and the
+// loads of slice t+1 are issued into registers before slice t is computed.
+// Each z value is read from global memory once per block (plus the halo), the
+// neighbours come from LDS, and each thread keeps its cells' m-component of
+// slice t for the next slice's -z_{t-1}/dt term. The per-cell arithmetic is
+// that of rhs_column, term for term.
+constexpr int kRThreads = 512;  // threads of a tiled right-hand-side block
+
+template <bool HAS0>
+struct RTile {
+  static constexpr int TI = HAS0 ? 16 : 1;     // tile rows (axis 0)
+  static constexpr int TJ = HAS0 ? 64 : 512;   // tile columns (axis 1)
+  static constexpr int H0 = HAS0 ? 1 : 0;      // halo rows
+  static constexpr int SI = TI + 2 * H0, SJ = TJ + 2;
+  static constexpr int NS = SI * SJ;           // staged values per component
+  static constexpr int NC = HAS0 ? 5 : 3;      // components of z
+  static constexpr int NPER = (NS + kRThreads - 1) / kRThreads;
+  static constexpr int CPT = TI * TJ / kRThreads;  // cells per thread
+};
+
+// ZMODE: 1 z read from zin, 0 z = xi + sigma ybar, -1 chosen per block (batched).
+// LDS of a tiled right-hand-side block (the d = 2 tile, the larger one)
+constexpr int kRhsLds = RTile<true>::NC * RTile<true>::NS;
+static_assert(RTile<false>::NC * RTile<false>::NS <= kRhsLds, "d = 1 tile exceeds the LDS size");
+
+template <int ZMODE, bool HAS0, int BC>
+__device__ void rhs_tile_body(const RhsArgs& a, int lb, double& acc, double* lds) {
+  using R = RTile<HAS0>;
+  constexpr bool NEU1 = (BC & 1) != 0, NEU0 = (BC & 2) != 0;
+  const Geom& g = a.g;
+  const bool zm = ZMODE == 1 || (ZMODE < 0 && a.zin && (!a.zmode_dev || *a.zmode_dev != 0.0));
+  const double* __restrict__ src = zm ? a.zin : a.xi;
+  const double* __restrict__ ybar = a.ybar;
+  double* __restrict__ b = a.b;
+  const double sigma = a.sigma_dev ? *a.sigma_dev : a.sigma;
+  const long long n = g.n;
+  const int tiles1 = (g.n1 + R::TJ - 1) / R::TJ;
+  const int tiles0 = HAS0 ? (g.n0 + R::TI - 1) / R::TI : 1;
+  const int tile = lb % (tiles0 * tiles1), chunk = lb / (tiles0 * tiles1);
+  const int i0 = (tile / tiles1) * R::TI, j0 = (tile % tiles1) * R::TJ;
+  const int t_lo = chunk * a.tc, t_hi = min(g.nt, t_lo + a.tc);
+  auto Zs = reinterpret_cast<double (*)[R::NS]>(lds);  // Zs[component][staged value]
+  // staged element e of this thread: byte offset within a slice (32 bits: a
+  // slice of M < 2^28 cells, checked by the plan), so the loads take a uniform
+  // base and a 32-bit per-lane offset
+  unsigned off[R::NPER];
+  bool has[R::NPER];
+#pragma unroll
+  for (int e = 0; e < R::NPER; ++e) {
+    const int idx = threadIdx.x + kRThreads * e;
+    has[e] = idx < R::NS;
+    off[e] = 0u;
+    if (has[e]) {
+      const int ii = idx / R::SJ - R::H0, jj = idx % R::SJ - 1;
+      const int gi = HAS0 ? nbr_tile(i0 + ii, g.n0, NEU0) : 0;
+      const int gj = nbr_tile(j0 + jj, g.n1, NEU1);
+      off[e] = (unsigned)(gi * g.n1 + gj) * 8u;
+    }
+  }
+  double rz[R::NC][R::NPER], ry[ZMODE == 1 ? 1 : R::NC][R::NPER];
+  auto issue = [&](int t) {
+    const size_t base = (size_t)t * g.M;
+#pragma unroll
+    for (int c = 0; c < R::NC; ++c) {
+      // uniform slice base per component, 32-bit byte offsets per element
+      const char* __restrict__ zc_ = reinterpret_cast<const char*>(src + (size_t)c * n + base);
+      const char* __restrict__ yc_ =
+          ZMODE == 1 ? nullptr : reinterpret_cast<const char*>(ybar + (size_t)c * n + base);
+#pragma unroll
+      for (int e = 0; e < R::NPER; ++e)
+        if (has[e]) {
+          rz[c][e] = *reinterpret_cast<const double*>(zc_ + off[e]);
+          if constexpr (ZMODE != 1) {
+            if (!zm) ry[c][e] = *reinterpret_cast<const double*>(yc_ + off[e]);
+          }
+        }
+    }
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int c = 0; c < R::NC; ++c)
+#pragma unroll
+      for (int e = 0; e < R::NPER; ++e)
+        if (has[e]) {
+          double v = rz[c][e];
+          // one rounding (fma), as where z is formed by the back-projection
+          if constexpr (ZMODE != 1) {
+            if (!zm) v = __builtin_fma(sigma, ry[c][e], v);
+          }
+          Zs[c][threadIdx.x + kRThreads * e] = v;
+        }
+  };
+  double zprev[R::CPT];
+  // the m-component of slice t_lo - 1 at this thread's cells
+#pragma unroll
+  for (int k = 0; k < R::CPT; ++k) {
+    const int idx = threadIdx.x + kRThreads * k;
+    const int ii = idx / R::TJ, jj = idx % R::TJ;
+    zprev[k] = 0.0;
+    if (t_lo >= 1 && i0 + ii < g.n0 && j0 + jj < g.n1) {
+      const size_t o = (size_t)(t_lo - 1) * g.M + (size_t)(i0 + ii) * g.n1 + j0 + jj;
+      zprev[k] = zm ? src[o] : __builtin_fma(sigma, ybar[o], src[o]);
+    }
+  }
+  constexpr int C1 = HAS0 ? 1 : 0, C2 = HAS0 ? 2 : 0;   // axis-0 flux components
+  constexpr int CE = HAS0 ? 3 : 1, CO = HAS0 ? 4 : 2;   // axis-1 flux components
+  if (t_lo < t_hi) issue(t_lo);
+  for (int t = t_lo; t < t_hi; ++t) {
+    commit();
+    __syncthreads();
+    if (t + 1 < t_hi) issue(t + 1);
+#pragma unroll
+    for (int k = 0; k < R::CPT; ++k) {
+      const int idx = threadIdx.x + kRThreads * k;
+      const int ii = idx / R::TJ, jj = idx % R::TJ;
+      const int gi = i0 + ii, gj = j0 + jj;
+      if (gi < g.n0 && gj < g.n1) {
+        const int c = (ii + R::H0) * R::SJ + jj + 1;
+        const double* Z0 = Zs[0];
+        const double zc = Z0[c];
+        double Kz = (2.0 * zc - Z0[c + 1] - Z0[c - 1]) * g.ih1sq;
+        if (HAS0) Kz += (2.0 * zc - Z0[c + R::SJ] - Z0[c - R::SJ]) * g.ih0sq;
+        double r = g.nu * Kz + zc * g.idt;
+        if (t >= 1) r -= zprev[k] * g.idt;
+        {
+          const double* E = Zs[CE];
+          const double* O = Zs[CO];
+          // D^1 w_e = w_i - w_{i-1}, D^2 w_o = w_{i+1} - w_i (Neumann: the
+          // terms across the boundary do not enter)
+          const double d1 = NEU1 ? (gj <= g.n1 - 2 ? E[c] : 0.0) - (gj >= 1 ? E[c - 1] : 0.0)
+                                 : E[c] - E[c - 1];
+          const double d2 = NEU1 ? (gj <= g.n1 - 2 ? O[c + 1] : 0.0) - (gj >= 1 ? O[c] : 0.0)
+                                 : O[c + 1] - O[c];
+          r += (d1 + d2) * g.ih1;
+        }
+        if (HAS0) {
+          const double* E = Zs[C1];
+          const double* O = Zs[C2];
+          const double d1 = NEU0 ? (gi <= g.n0 - 2 ? E[c] : 0.0) - (gi >= 1 ? E[c - R::SJ] : 0.0)
+                                 : E[c] - E[c - R::SJ];
+          const double d2 = NEU0 ? (gi <= g.n0 - 2 ? O[c + R::SJ] : 0.0) - (gi >= 1 ? O[c] : 0.0)
+                                 : O[c + R::SJ] - O[c];
+          r += (d1 + d2) * g.ih0;
+        }
+        const int rem = gi * g.n1 + gj;
+        if (t == 0) r -= sigma * a.m0[rem] * g.idt;
+        b[(size_t)t * g.M + rem] = r;
+        acc += r * r;
+        zprev[k] = zc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <bool HAS0, int BC>
+struct RhsTileBatch {
+  __device__ static void run(const RhsArgs& a, int lb, double& acc, double* lds) {
+    rhs_tile_body<-1, HAS0, BC>(a, lb, acc, lds);
+  }
+};
+
+// Batched form of the tiled right-hand side: z source and geometry per instance.
+__device__ void rhs_tile_batch_body(const RhsArgs& a, int bid) {
+  __shared__ double lds[kRhsLds];
+  double acc[1] = {0.0};
+  geom_dispatch<RhsTileBatch>(a.g, a, bid, acc[0], lds);
+  rhs_finish<true>(a, bid, acc);
+}
+
 // Components of Cr^T u at one cell: out[0] = m-part, out[1+c] = B_c^T u_t.
 template <bool HAS0, int BC>
 __device__ __forceinline__ void CT_cell(const Geom& g, const double* __restrict__ u, int t, int i0,
@@ -637,11 +811,37 @@ void rhs_launch(const RhsArgs& a, int grid, hipStream_t s) {
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_rhs_batch(const RhsArgs* A, const int* off,
-                                                        int ninst) {
+__global__ __launch_bounds__(kRThreads) void k_rhs_batch(const RhsArgs* A, const int* off,
+                                                         int ninst) {
   const int i = batch_instance(off, ninst, blockIdx.x);
   const RhsArgs a = A[i];  // one copy of the instance's arguments for every specialisation
-  rhs_body<true>(a, blockIdx.x - off[i], off[i + 1] - off[i]);
+  rhs_tile_batch_body(a, blockIdx.x - off[i]);
+}
+
+// Single-plan tiled right-hand side, one specialisation per z source and geometry.
+template <int ZMODE, bool HAS0, int BC>
+__global__ __launch_bounds__(kRThreads) void k_rhs_tile(RhsArgs a) {
+  __shared__ double lds[kRhsLds];
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  double acc[1] = {0.0};
+  rhs_tile_body<ZMODE, HAS0, BC>(a, lb, acc[0], lds);
+  rhs_finish<true>(a, lb, acc);
+}
+
+template <int ZMODE>
+void rhs_tile_launch(const RhsArgs& a, int grid, hipStream_t s) {
+  const dim3 gd(grid), bd(kRThreads);
+  if (a.g.has0) {
+    switch (a.g.bcm) {
+      case 0: hipLaunchKernelGGL((k_rhs_tile<ZMODE, true, 0>), gd, bd, 0, s, a); break;
+      case 1: hipLaunchKernelGGL((k_rhs_tile<ZMODE, true, 1>), gd, bd, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_rhs_tile<ZMODE, true, 2>), gd, bd, 0, s, a); break;
+      default: hipLaunchKernelGGL((k_rhs_tile<ZMODE, true, 3>), gd, bd, 0, s, a);
+    }
+  } else {
+    if (a.g.bcm & 1) hipLaunchKernelGGL((k_rhs_tile<ZMODE, false, 1>), gd, bd, 0, s, a);
+    else hipLaunchKernelGGL((k_rhs_tile<ZMODE, false, 0>), gd, bd, 0, s, a);
+  }
 }
 
 template <bool HAS0, bool FUSE, int BIG>
@@ -742,17 +942,34 @@ static int rhs_tc(const Plan& P) {
   return (int)(tc < 1 ? 1 : tc > g.nt ? g.nt : tc);
 }
 
+// Tiled right-hand side: spatial tiles and time slices per block (about 2048
+// blocks, within the partial-sum capacity). A function of the geometry only,
+// so batched and single-plan runs sum b.b in the same order.
+static int rhs_tiles(const Geom& g) {
+  if (g.has0)
+    return ((g.n0 + RTile<true>::TI - 1) / RTile<true>::TI) *
+           ((g.n1 + RTile<true>::TJ - 1) / RTile<true>::TJ);
+  return (g.n1 + RTile<false>::TJ - 1) / RTile<false>::TJ;
+}
+
+static int rhs_tile_tc(const Plan& P) {
+  const Geom& g = P.g;
+  const long long nt_ = g.nt, tiles = rhs_tiles(g);
+  long long tc = P.tune.rhs_tc > 0 ? P.tune.rhs_tc : (tiles * nt_ + 2047) / 2048;
+  while (tc < nt_ && tiles * ((nt_ + tc - 1) / tc) > P.red.max_blocks) ++tc;
+  return (int)(tc < 1 ? 1 : tc > nt_ ? nt_ : tc);
+}
+
 RhsArgs rhs_args(const Plan& P, const double* xi, const double* ybar, double sigma,
                  const double* sigma_dev, double* b, const double* zin,
                  const double* zmode_dev) {
   return RhsArgs{P.g,  xi,    ybar, sigma,   sigma_dev,    P.m0, b, zin, zmode_dev, 0,
-                 P.red, 0.0, nullptr, rhs_tc(P)};
+                 P.red, 0.0, nullptr, rhs_tile_tc(P)};
 }
 
 int rhs_grid(const Plan& P) {
-  const Geom& g = P.g;
-  const int tc = rhs_tc(P);
-  return rhs_nsp(g) * ((g.nt + tc - 1) / tc);
+  const int tc = rhs_tile_tc(P);
+  return rhs_tiles(P.g) * ((P.g.nt + tc - 1) / tc);
 }
 
 void launch_rhs(const Plan& P, const double* xi, const double* ybar, double sigma,
@@ -764,8 +981,8 @@ void launch_rhs(const Plan& P, const double* xi, const double* ybar, double sigm
   const int grid = rhs_grid(P);
   {
     ProfScope ps(P, "rhs", s);
-    if (zin) rhs_launch<true, true>(a, grid, s);
-    else rhs_launch<true, false>(a, grid, s);
+    if (zin) rhs_tile_launch<1>(a, grid, s);
+    else rhs_tile_launch<0>(a, grid, s);
   }
   if (a.init) launch_finish(P, T_BB, grid, OP_BB, s);
 }
@@ -774,7 +991,8 @@ void launch_apply_C(const Plan& P, const double* y, double* b, hipStream_t s) {
   ProfScope ps(P, "apply_C", s);
   const RhsArgs a{P.g,   y,   nullptr, 0.0, nullptr,       nullptr, b, nullptr, nullptr, 0,
                   P.red, 0.0, nullptr, rhs_tc(P)};
-  rhs_launch<false, false>(a, rhs_grid(P), s);
+  const int tc = rhs_tc(P);
+  rhs_launch<false, false>(a, rhs_nsp(P.g) * ((P.g.nt + tc - 1) / tc), s);
 }
 
 void launch_apply_CT(const Plan& P, const double* u, double* y, hipStream_t s) {
@@ -877,7 +1095,7 @@ void launch_aat_batch(bool has0, const AatArgs* A, const int* off, int ninst, in
 }
 
 void launch_rhs_batch(const RhsArgs* A, const int* off, int ninst, int total, hipStream_t s) {
-  hipLaunchKernelGGL(k_rhs_batch, dim3(total), dim3(kThreads), 0, s, A, off, ninst);
+  hipLaunchKernelGGL(k_rhs_batch, dim3(total), dim3(kRThreads), 0, s, A, off, ninst);
 }
 
 void launch_backproj_batch(const BackprojArgs* A, const int* off, int ninst, int total,

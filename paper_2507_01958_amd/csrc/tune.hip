@@ -140,13 +140,21 @@ bool tune_lookup(const Plan& P, Tune* out) {
   return true;
 }
 
+// The fields that are choices of method or fixed by the plan's settings, not
+// tuned launch shapes: a cached entry never replaces them.
+void keep_untuned(const Tune& from, Tune& to) {
+  to.flex = from.flex;
+  to.lp_stream = from.lp_stream;
+  to.rhs_tc = from.rhs_tc;
+}
+
 // allow_pers = false keeps the time GEMM in the form the batched launches use.
 int autotune(Plan& P, int effort, bool allow_pers) {
   if (effort < 2) {
     Tune t;
     if (tune_lookup(P, &t)) {
       if (!allow_pers) batch_shape(t);
-      t.flex = P.tune.flex;  // a choice of method, not a launch shape
+      keep_untuned(P.tune, t);
       P.tune = t;
       return MFG_OK;
     }
