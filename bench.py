@@ -223,21 +223,26 @@ def bench_batch(args):
     Vs = [torch.from_numpy(i.V).to(dev) for i in insts]
     m0s = [torch.from_numpy(i.m0).to(dev) for i in insts]
     prec = "mixed_fp32"
-    B = mfg.mfg_plan_batch([_problem(i, prec) for i in insts], Vs, m0s, stream)
-    if not args.no_autotune:
-        mfg.mfg_batch_autotune(B, 1)
-    states = [mfg.CPState(p) for p in B.plans]
-    for p, st in zip(B.plans, states):
-        mfg.mfg_cp_init(p, st)
-    mfg.mfg_batch_cp_solve(B, states, args.warmup, RTOL, PCG_MAXIT)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    its = mfg.mfg_batch_cp_solve(B, states, args.steps, RTOL, PCG_MAXIT)
-    torch.cuda.synchronize()
-    dt_batch = time.perf_counter() - t0
-    B.close()
-    del states
-    rate_batch = len(insts) * args.steps / dt_batch
+    batched = {}
+    for variant in (prec, "fp64"):
+        B = mfg.mfg_plan_batch([_problem(i, variant) for i in insts], Vs, m0s, stream)
+        if not args.no_autotune:
+            mfg.mfg_batch_autotune(B, 1)
+        states = [mfg.CPState(p) for p in B.plans]
+        for p, st in zip(B.plans, states):
+            mfg.mfg_cp_init(p, st)
+        mfg.mfg_batch_cp_solve(B, states, args.warmup, RTOL, PCG_MAXIT)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its_v = mfg.mfg_batch_cp_solve(B, states, args.steps, RTOL, PCG_MAXIT)
+        torch.cuda.synchronize()
+        dt_v = time.perf_counter() - t0
+        B.close()
+        del states
+        batched[variant] = len(insts) * args.steps / dt_v
+        if variant == prec:
+            its, dt_batch = its_v, dt_v
+    rate_batch = batched[prec]
     seq = {}
     for variant in ("fp64", prec):
         total = 0.0
@@ -267,8 +272,10 @@ def bench_batch(args):
         "config": {"workload": f"batch{len(insts)}_periodic_uneven", "pcg_rtol": RTOL,
                    "instances": [i.name for i in insts], "sum_n": n_total,
                    "variant": prec},
+        "batched_instance_cp_iters_per_s": batched,
         "sequential_instance_cp_iters_per_s": seq,
         "speedup_vs_sequential": {k: rate_batch / v for k, v in seq.items()},
+        "speedup_same_precision": {k: batched[k] / seq[k] for k in batched},
         "mean_pcg_iters": float(np.mean(its)), "max_pcg_iters": int(np.max(its)),
         "roofline": None, "cpu_baseline": None,
     }

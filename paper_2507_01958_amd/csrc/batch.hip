@@ -41,20 +41,27 @@ struct Phase {
   size_t shm = 0;
 };
 
-// Spatial launches of one FFT size class (0: LDS path, else the axis length).
+// Spatial launches of one FFT size class (0: LDS path, else the axis length);
+// T is the preconditioner's intermediate (float in the mixed modes, double in
+// FP64).
+template <typename T>
 struct SpatialGroup {
-  int cls = 0;
-  Phase<RowsArgs<float>> rows_fwd, rows_inv;
+  int cls = 0, threads = 256;
+  Phase<RowsArgs<T>> rows_fwd, rows_inv;
 };
+template <typename T>
 struct ColsGroup {
-  int cls = 0;
-  Phase<ColsArgs<float>> cols;
+  int cls = 0, threads = 256;
+  Phase<ColsArgs<T>> cols;
 };
 
+// One time-GEMM launch class: low precision (N_t padding class, column blocks
+// per wave, waves per block) or float64 (k rows per block kb, column blocks cb).
 struct GemmGroup {
-  int ntp = 0, cb = 2, waves = 4;
+  int ntp = 0, cb = 2, waves = 4, kb = 8;
   Phase<GemmArgs<double, float>> fwd_init, fwd;  // fwd: with the r.r stopping test
   Phase<GemmArgs<float, double>> inv_init, inv_iter;
+  Phase<GemmArgs<double, double>> fwd64_init, fwd64, inv64_init, inv64_iter;
 };
 
 }  // namespace
@@ -62,7 +69,7 @@ struct GemmGroup {
 struct Batch {
   std::vector<mfg_plan_t> plans;
   int count = 0;
-  int mode = GM_F32;
+  int mode = GM_F32;  // GM_F64: the float64 preconditioner
   hipStream_t user = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -74,8 +81,10 @@ struct Batch {
   std::vector<GemmGroup> groups;
   Phase<UpdArgs> upd_first, upd_odd, upd_even;
   Phase<AatArgs> aat_first, aat_odd, aat_even;
-  std::vector<SpatialGroup> rows;
-  std::vector<ColsGroup> cols;
+  std::vector<SpatialGroup<float>> rows;
+  std::vector<ColsGroup<float>> cols;
+  std::vector<SpatialGroup<double>> rows64;
+  std::vector<ColsGroup<double>> cols64;
   Phase<RhsArgs> rhs;
   // back-projection of the last step of a call (writes xi', ybar') and of the
   // other steps (hands z = xi' + sigma' ybar' to the next right-hand side)
@@ -147,23 +156,78 @@ int upload_finish(Batch& B, const std::vector<FinishArgs>& f, FinishArgs** out) 
 Plan& plan_of(Batch& B, int i) { return B.plans[i]->P; }
 const double* done_of(Batch& B, int i) { return B.scal_all + (size_t)i * S_COUNT + S_DONE; }
 
-// Build the argument arrays of the PCG phases (state independent).
-int build_pcg_phases(Batch& B) {
+// Spatial-solve launches of every instance, grouped by size class.
+template <typename T>
+int build_spatial(Batch& B, std::vector<SpatialGroup<T>>& rows_out,
+                  std::vector<ColsGroup<T>>& cols_out) {
   const int n = B.count;
-  std::vector<UpdArgs> u0, uo, ue;
-  std::vector<AatArgs> af, ao, ae;
-  std::vector<int> b_upd, b_aat;
-  std::vector<FinishArgs> fbb;
-  // spatial launches grouped by size class
-  std::vector<int> rcls(n), ccls(n);
-  std::vector<RowsArgs<float>> rf(n), ri(n);
-  std::vector<ColsArgs<float>> cl(n);
+  std::vector<int> rcls(n), ccls(n), rthr(n), cthr(n);
+  std::vector<RowsArgs<T>> rf(n), ri(n);
+  std::vector<ColsArgs<T>> cl(n);
   std::vector<int> b_rows(n), b_cols(n);
   std::vector<size_t> rshm(n), cshm(n);
   for (int i = 0; i < n; ++i) {
     Plan& P = plan_of(B, i);
     const double* done = done_of(B, i);
-    float* tmp = reinterpret_cast<float*>(P.tmp);
+    T* tmp = reinterpret_cast<T*>(P.tmp);
+    rcls[i] = batch_rows_args<T>(P, tmp, 0, done, &rf[i], &b_rows[i], &rshm[i], &rthr[i]);
+    batch_rows_args<T>(P, tmp, 1, done, &ri[i], &b_rows[i], &rshm[i], &rthr[i]);
+    ccls[i] = batch_cols_args<T>(P, tmp, done, &cl[i], &b_cols[i], &cshm[i], &cthr[i]);
+  }
+  int rc;
+  std::vector<int> classes(rcls);
+  std::sort(classes.begin(), classes.end());
+  classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
+  rows_out.assign(classes.size(), SpatialGroup<T>{});
+  for (size_t c = 0; c < classes.size(); ++c) {
+    std::vector<RowsArgs<T>> f, v;
+    std::vector<int> blocks;
+    size_t shm = 0;
+    for (int i = 0; i < n; ++i)
+      if (rcls[i] == classes[c]) {
+        f.push_back(rf[i]);
+        v.push_back(ri[i]);
+        blocks.push_back(b_rows[i]);
+        shm = std::max(shm, rshm[i]);
+        rows_out[c].threads = rthr[i];
+      }
+    rows_out[c].cls = classes[c];
+    if ((rc = upload_phase(B, f, blocks, rows_out[c].rows_fwd, shm)) ||
+        (rc = upload_phase(B, v, blocks, rows_out[c].rows_inv, shm)))
+      return rc;
+  }
+  classes = ccls;
+  std::sort(classes.begin(), classes.end());
+  classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
+  cols_out.assign(classes.size(), ColsGroup<T>{});
+  for (size_t c = 0; c < classes.size(); ++c) {
+    std::vector<ColsArgs<T>> f;
+    std::vector<int> blocks;
+    size_t shm = 0;
+    for (int i = 0; i < n; ++i)
+      if (ccls[i] == classes[c]) {
+        f.push_back(cl[i]);
+        blocks.push_back(b_cols[i]);
+        shm = std::max(shm, cshm[i]);
+        cols_out[c].threads = cthr[i];
+      }
+    cols_out[c].cls = classes[c];
+    if ((rc = upload_phase(B, f, blocks, cols_out[c].cols, shm))) return rc;
+  }
+  return MFG_OK;
+}
+
+// Build the argument arrays of the PCG phases (state independent).
+int build_pcg_phases(Batch& B) {
+  const int n = B.count;
+  const bool f64 = B.mode == GM_F64;
+  std::vector<UpdArgs> u0, uo, ue;
+  std::vector<AatArgs> af, ao, ae;
+  std::vector<int> b_upd, b_aat;
+  std::vector<FinishArgs> fbb;
+  for (int i = 0; i < n; ++i) {
+    Plan& P = plan_of(B, i);
+    const double* done = done_of(B, i);
     UpdArgs u1 = update_args(P, P.u, P.r, P.p, P.q, false);   // odd k: p_new = p
     UpdArgs u2 = update_args(P, P.u, P.r, P.p2, P.q, false);  // even k: p_new = p2
     u1.done = u2.done = done;
@@ -177,58 +241,27 @@ int build_pcg_phases(Batch& B) {
     ao.push_back(aat_args(P, P.z, P.p2, P.p, P.q, false, done, &g));
     ae.push_back(aat_args(P, P.z, P.p, P.p2, P.q, false, done, &g));
     b_aat.push_back(g);
-    rcls[i] = batch_rows_args(P, tmp, 0, done, &rf[i], &b_rows[i], &rshm[i]);
-    batch_rows_args(P, tmp, 1, done, &ri[i], &b_rows[i], &rshm[i]);
-    ccls[i] = batch_cols_args(P, tmp, done, &cl[i], &b_cols[i], &cshm[i]);
     u0.back().npq = uo.back().npq = ue.back().npq = g;
     // b.b partials come from the right-hand side kernel, which starts the solve
     fbb.push_back(finish_args(P, T_BB, rhs_grid(P), OP_BB));
   }
   int rc;
   if ((rc = upload_finish(B, fbb, &B.f_bb))) return rc;
-  {
-    std::vector<int> classes(rcls);
-    std::sort(classes.begin(), classes.end());
-    classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
-    B.rows.assign(classes.size(), SpatialGroup{});
-    for (size_t c = 0; c < classes.size(); ++c) {
-      std::vector<RowsArgs<float>> f, v;
-      std::vector<int> blocks;
-      size_t shm = 0;
-      for (int i = 0; i < n; ++i)
-        if (rcls[i] == classes[c]) {
-          f.push_back(rf[i]);
-          v.push_back(ri[i]);
-          blocks.push_back(b_rows[i]);
-          shm = std::max(shm, rshm[i]);
-        }
-      B.rows[c].cls = classes[c];
-      if ((rc = upload_phase(B, f, blocks, B.rows[c].rows_fwd, shm)) ||
-          (rc = upload_phase(B, v, blocks, B.rows[c].rows_inv, shm)))
-        return rc;
-    }
-    classes = ccls;
-    std::sort(classes.begin(), classes.end());
-    classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
-    B.cols.assign(classes.size(), ColsGroup{});
-    for (size_t c = 0; c < classes.size(); ++c) {
-      std::vector<ColsArgs<float>> f;
-      std::vector<int> blocks;
-      size_t shm = 0;
-      for (int i = 0; i < n; ++i)
-        if (ccls[i] == classes[c]) {
-          f.push_back(cl[i]);
-          blocks.push_back(b_cols[i]);
-          shm = std::max(shm, cshm[i]);
-        }
-      B.cols[c].cls = classes[c];
-      if ((rc = upload_phase(B, f, blocks, B.cols[c].cols, shm))) return rc;
-    }
-  }
-  // time GEMMs: one launch per (N_t padding class, column blocks per wave, waves)
+  if ((rc = f64 ? build_spatial<double>(B, B.rows64, B.cols64)
+                : build_spatial<float>(B, B.rows, B.cols)))
+    return rc;
+  // time GEMMs: one launch per class: low precision (N_t padding class,
+  // column blocks per wave, waves), float64 (k rows per block, column blocks)
   auto shape_of = [&](int i) {
-    const Tune& t = plan_of(B, i).tune;
-    return std::make_tuple(plan_of(B, i).ntp, t.lp_cb == 1 ? 1 : 2, t.lp_waves == 8 ? 8 : 4);
+    const Plan& P = plan_of(B, i);
+    if (f64) {
+      int blk, kb, cb;
+      (void)batch_gemm64_args(P, nullptr, nullptr, DOT_NONE, nullptr, nullptr, nullptr, &blk, &kb,
+                              &cb);
+      return std::make_tuple(kb, cb, 0);
+    }
+    const Tune& t = P.tune;
+    return std::make_tuple(P.ntp, t.lp_cb == 1 ? 1 : 2, t.lp_waves == 8 ? 8 : 4);
   };
   std::vector<std::tuple<int, int, int>> classes;
   for (int i = 0; i < n; ++i) classes.push_back(shape_of(i));
@@ -238,31 +271,53 @@ int build_pcg_phases(Batch& B) {
   std::vector<int> gemm_grid(n, 0);
   for (size_t gi = 0; gi < classes.size(); ++gi) {
     GemmGroup& G = B.groups[gi];
-    std::tie(G.ntp, G.cb, G.waves) = classes[gi];
+    if (f64) std::tie(G.kb, G.cb, G.waves) = classes[gi];
+    else std::tie(G.ntp, G.cb, G.waves) = classes[gi];
     std::vector<GemmArgs<double, float>> fw0, fw;
     std::vector<GemmArgs<float, double>> i0, i1;
+    std::vector<GemmArgs<double, double>> d0, d1, e0, e1;
     std::vector<int> blocks;
     for (int i = 0; i < n; ++i) {
       Plan& P = plan_of(B, i);
       if (shape_of(i) != classes[gi]) continue;
-      float* tmp = reinterpret_cast<float*>(P.tmp);
       int blk;
-      fw0.push_back(batch_gemm_args<double, float>(P, B.mode, P.r, tmp, DOT_NONE, nullptr,
-                                                   nullptr, done_of(B, i), &blk));
-      fw.push_back(fw0.back());
-      fw.back().nrr = update_grid(P);
-      i0.push_back(batch_gemm_args<float, double>(P, B.mode, tmp, P.z, DOT_INIT, P.r, nullptr,
-                                                  done_of(B, i), &blk));
-      i1.push_back(batch_gemm_args<float, double>(P, B.mode, tmp, P.z,
-                                                  pcg_flexible(P) ? DOT_FLEX : DOT_STD, P.r, P.q,
-                                                  done_of(B, i), &blk));
+      if (f64) {
+        int kb, cb;
+        d0.push_back(batch_gemm64_args(P, P.r, P.tmp, DOT_NONE, nullptr, nullptr, done_of(B, i),
+                                       &blk, &kb, &cb));
+        d1.push_back(d0.back());
+        d1.back().nrr = update_grid(P);
+        e0.push_back(batch_gemm64_args(P, P.tmp, P.z, DOT_INIT, P.r, nullptr, done_of(B, i), &blk,
+                                       &kb, &cb));
+        e1.push_back(batch_gemm64_args(P, P.tmp, P.z, DOT_STD, P.r, P.q, done_of(B, i), &blk, &kb,
+                                       &cb));
+      } else {
+        float* tmp = reinterpret_cast<float*>(P.tmp);
+        fw0.push_back(batch_gemm_args<double, float>(P, B.mode, P.r, tmp, DOT_NONE, nullptr,
+                                                     nullptr, done_of(B, i), &blk));
+        fw.push_back(fw0.back());
+        fw.back().nrr = update_grid(P);
+        i0.push_back(batch_gemm_args<float, double>(P, B.mode, tmp, P.z, DOT_INIT, P.r, nullptr,
+                                                    done_of(B, i), &blk));
+        i1.push_back(batch_gemm_args<float, double>(P, B.mode, tmp, P.z,
+                                                    pcg_flexible(P) ? DOT_FLEX : DOT_STD, P.r,
+                                                    P.q, done_of(B, i), &blk));
+      }
       blocks.push_back(blk);
       gemm_grid[i] = blk;
     }
-    if ((rc = upload_phase(B, fw0, blocks, G.fwd_init)) || (rc = upload_phase(B, fw, blocks, G.fwd)) ||
-        (rc = upload_phase(B, i0, blocks, G.inv_init)) ||
-        (rc = upload_phase(B, i1, blocks, G.inv_iter)))
+    if (f64) {
+      if ((rc = upload_phase(B, d0, blocks, G.fwd64_init)) ||
+          (rc = upload_phase(B, d1, blocks, G.fwd64)) ||
+          (rc = upload_phase(B, e0, blocks, G.inv64_init)) ||
+          (rc = upload_phase(B, e1, blocks, G.inv64_iter)))
+        return rc;
+    } else if ((rc = upload_phase(B, fw0, blocks, G.fwd_init)) ||
+               (rc = upload_phase(B, fw, blocks, G.fwd)) ||
+               (rc = upload_phase(B, i0, blocks, G.inv_init)) ||
+               (rc = upload_phase(B, i1, blocks, G.inv_iter))) {
       return rc;
+    }
   }
   // the update and the A kernel sum the inverse GEMM's r.z partials themselves
   for (int i = 0; i < n; ++i) {
@@ -311,21 +366,39 @@ int build_state_phases(Batch& B, mfg_state_t* st) {
   return MFG_OK;
 }
 
+template <typename T>
+void spatial_phase(const std::vector<SpatialGroup<T>>& rows, const std::vector<ColsGroup<T>>& cols,
+                   hipStream_t s) {
+  for (const auto& G : rows)
+    launch_rows_batch<T>(G.cls, G.rows_fwd.args, G.rows_fwd.off, G.rows_fwd.ninst,
+                         G.rows_fwd.total, G.rows_fwd.shm, G.threads, s);
+  for (const auto& G : cols)
+    launch_cols_batch<T>(G.cls, G.cols.args, G.cols.off, G.cols.ninst, G.cols.total, G.cols.shm,
+                         G.threads, s);
+  for (const auto& G : rows)
+    launch_rows_batch<T>(G.cls, G.rows_inv.args, G.rows_inv.off, G.rows_inv.ninst,
+                         G.rows_inv.total, G.rows_inv.shm, G.threads, s);
+}
+
 void precond_phase(Batch& B, bool init, hipStream_t s) {
+  if (B.mode == GM_F64) {
+    for (auto& G : B.groups) {
+      const auto& ph = init ? G.fwd64_init : G.fwd64;
+      launch_gemm64_batch(G.kb, G.cb, ph.args, ph.off, ph.ninst, ph.total, s);
+    }
+    spatial_phase<double>(B.rows64, B.cols64, s);
+    for (auto& G : B.groups) {
+      const auto& ph = init ? G.inv64_init : G.inv64_iter;
+      launch_gemm64_batch(G.kb, G.cb, ph.args, ph.off, ph.ninst, ph.total, s);
+    }
+    return;
+  }
   for (auto& G : B.groups) {
     const auto& ph = init ? G.fwd_init : G.fwd;
     launch_gemm_batch<double, float>(B.mode, G.ntp, G.cb, G.waves, ph.args, ph.off, ph.ninst,
                                      ph.total, s);
   }
-  for (const auto& G : B.rows)
-    launch_rows_batch_f32(G.cls, G.rows_fwd.args, G.rows_fwd.off, G.rows_fwd.ninst,
-                          G.rows_fwd.total, G.rows_fwd.shm, s);
-  for (const auto& G : B.cols)
-    launch_cols_batch_f32(G.cls, G.cols.args, G.cols.off, G.cols.ninst, G.cols.total, G.cols.shm,
-                          s);
-  for (const auto& G : B.rows)
-    launch_rows_batch_f32(G.cls, G.rows_inv.args, G.rows_inv.off, G.rows_inv.ninst,
-                          G.rows_inv.total, G.rows_inv.shm, s);
+  spatial_phase<float>(B.rows, B.cols, s);
   for (auto& G : B.groups) {
     const auto& ph = init ? G.inv_init : G.inv_iter;
     launch_gemm_batch<float, double>(B.mode, G.ntp, G.cb, G.waves, ph.args, ph.off, ph.ninst,
@@ -380,13 +453,15 @@ int batch_create(Batch& B, const mfg_problem_t* pbs, const double* const* V,
   B.count = count;
   B.user = stream;
   const int prec = pbs[0].precision;
-  if (prec == MFG_FP64)
-    return fail(MFG_ERR_UNSUPPORTED, "batched solves use a mixed-precision preconditioner");
-  B.mode = prec == MFG_MIXED_FP32 ? GM_F32 : (prec == MFG_MIXED_FP16 ? GM_F16 : GM_BF16);
+  B.mode = prec == MFG_FP64 ? GM_F64
+           : (prec == MFG_MIXED_FP32 ? GM_F32 : (prec == MFG_MIXED_FP16 ? GM_F16 : GM_BF16));
   for (int i = 0; i < count; ++i) {
     if (pbs[i].precision != prec) return fail(MFG_ERR_INVALID_ARG, "mixed precisions in a batch");
     if (pbs[i].d != 2) return fail(MFG_ERR_UNSUPPORTED, "batched solves need d = 2");
-    if (pbs[i].nt > 128) return fail(MFG_ERR_UNSUPPORTED, "batched solves need N_t <= 128");
+    // the batched low-precision time GEMM holds V in LDS; the float64 one
+    // takes the k rows in chunks (any N_t)
+    if (prec != MFG_FP64 && pbs[i].nt > 128)
+      return fail(MFG_ERR_UNSUPPORTED, "mixed-precision batched solves need N_t <= 128");
     if (pbs[i].qprime != 2.0) return fail(MFG_ERR_UNSUPPORTED, "batched solves need q' = 2");
   }
   if (hipStreamCreateWithFlags(&B.stream, hipStreamNonBlocking) != hipSuccess ||

@@ -177,15 +177,25 @@ BackprojArgs backproj_args(const Plan& P, const double* u, double* xi, double* y
 int backproj_grid(const Plan& P);
 AatArgs aat_args(const Plan& P, const double* z, const double* pold, double* pnew, double* q,
                  bool first, const double* done, int* grid);
-// return the size class of the instance's launch (0: LDS path, else N)
-int batch_rows_args(const Plan& P, float* data, int mode, const double* done, void* out,
-                    int* blocks, size_t* shm);
-int batch_cols_args(const Plan& P, float* data, const double* done, void* out, int* blocks,
-                    size_t* shm);
+// return the size class of the instance's launch (0: LDS path, else N); T is
+// the preconditioner's intermediate (float in the mixed modes, double in FP64)
+template <typename T>
+int batch_rows_args(const Plan& P, T* data, int mode, const double* done, RowsArgs<T>* out,
+                    int* blocks, size_t* shm, int* threads);
+template <typename T>
+int batch_cols_args(const Plan& P, T* data, const double* done, ColsArgs<T>* out, int* blocks,
+                    size_t* shm, int* threads);
 template <typename TX, typename TY>
 GemmArgs<TX, TY> batch_gemm_args(const Plan& P, int mode, const TX* X, TY* Y, int dotmode,
                                  const double* r, const double* q, const double* done,
                                  int* blocks);
+
+// float64 time GEMM: the (KB, CB) class of the instance's launch in kb, cb
+GemmArgs<double, double> batch_gemm64_args(const Plan& P, const double* X, double* Y, int dotmode,
+                                           const double* r, const double* q, const double* done,
+                                           int* blocks, int* kb, int* cb);
+void launch_gemm64_batch(int kb, int cb, const GemmArgs<double, double>* A, const int* off,
+                         int ninst, int total, hipStream_t s);
 
 void launch_update_batch(const UpdArgs* A, const int* off, int ninst, int total, hipStream_t s);
 void launch_finish_batch(const FinishArgs* F, int ninst, hipStream_t s);
@@ -196,10 +206,12 @@ void launch_aat_batch(bool has0, const AatArgs* A, const int* off, int ninst, in
 void launch_rhs_batch(const RhsArgs* A, const int* off, int ninst, int total, hipStream_t s);
 void launch_backproj_batch(const BackprojArgs* A, const int* off, int ninst, int total,
                            hipStream_t s);
-void launch_rows_batch_f32(int cls, const void* A, const int* off, int ninst, int total,
-                           size_t shm, hipStream_t s);
-void launch_cols_batch_f32(int cls, const void* A, const int* off, int ninst, int total,
-                           size_t shm, hipStream_t s);
+template <typename T>
+void launch_rows_batch(int cls, const RowsArgs<T>* A, const int* off, int ninst, int total,
+                       size_t shm, int threads, hipStream_t s);
+template <typename T>
+void launch_cols_batch(int cls, const ColsArgs<T>* A, const int* off, int ninst, int total,
+                       size_t shm, int threads, hipStream_t s);
 template <typename TX, typename TY>
 void launch_gemm_batch(int mode, int ntp, int cb, int waves, const GemmArgs<TX, TY>* A,
                        const int* off, int ninst, int total, hipStream_t s);

@@ -603,28 +603,52 @@ __device__ void cols_reg(const ColsArgs<T>& a, int bid, int nb, C2<T>* lds) {
   }
 }
 
+// The float64 LDS-path bodies are compiled once, as functions of their own,
+// and called by both the single-plan and the batched kernels: inlined into
+// each, the compiler contracted their multiply-adds differently, and batched
+// runs must take exactly the single-plan arithmetic.
+template <typename T>
+__device__ __noinline__ void rows_body_call(const RowsArgs<T>& a, int bid) {
+  rows_body<T>(a, bid);
+}
+template <typename T>
+__device__ __noinline__ void cols_body_call(const ColsArgs<T>& a, int bid, int nb) {
+  cols_body<T>(a, bid, nb);
+}
+
+template <typename T>
+__device__ __forceinline__ void rows_entry(const RowsArgs<T>& a, int bid) {
+  if constexpr (sizeof(T) == 8) rows_body_call<T>(a, bid);
+  else rows_body<T>(a, bid);
+}
+template <typename T>
+__device__ __forceinline__ void cols_entry(const ColsArgs<T>& a, int bid, int nb) {
+  if constexpr (sizeof(T) == 8) cols_body_call<T>(a, bid, nb);
+  else cols_body<T>(a, bid, nb);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_rows(RowsArgs<T> a) {
-  rows_body<T>(a, blockIdx.x);
+  rows_entry<T>(a, blockIdx.x);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_rows_batch(const RowsArgs<T>* A, const int* off,
                                                     int ninst) {
   const int i = batch_instance(off, ninst, blockIdx.x);
-  rows_body<T>(A[i], blockIdx.x - off[i]);
+  rows_entry<T>(A[i], blockIdx.x - off[i]);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_cols_solve(ColsArgs<T> a) {
-  cols_body<T>(a, blockIdx.x, gridDim.x);
+  cols_entry<T>(a, blockIdx.x, gridDim.x);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_cols_batch(const ColsArgs<T>* A, const int* off,
                                                     int ninst) {
   const int i = batch_instance(off, ninst, blockIdx.x);
-  cols_body<T>(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
+  cols_entry<T>(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
 }
 
 // Register path, one kernel per axis length (mode 0: forward, 1: inverse).
@@ -856,48 +880,65 @@ void launch_update_precond(const Plan& P, double* x, double* r, const double* p,
   launch_precond(P, r, z, true, q, s);
 }
 
-// ---- batched spatial solves: float32 data (mixed precision) ----
-int batch_rows_args(const Plan& P, float* data, int mode, const double* done, void* out,
-                    int* blocks, size_t* shm) {
-  const SpatialShape sh = spatial_shape<float>(P);
-  *reinterpret_cast<RowsArgs<float>*>(out) = rows_args<float>(P, sh, data, mode, done);
+// ---- batched spatial solves (float32 data in the mixed modes, float64 in FP64) ----
+template <typename T>
+int batch_rows_args(const Plan& P, T* data, int mode, const double* done, RowsArgs<T>* out,
+                    int* blocks, size_t* shm, int* threads) {
+  const SpatialShape sh = spatial_shape<T>(P);
+  *out = rows_args<T>(P, sh, data, mode, done);
   *blocks = sh.rblocks;
   *shm = sh.rshm;
+  *threads = sh.rthreads;
   return sh.rreg;
 }
 
-int batch_cols_args(const Plan& P, float* data, const double* done, void* out, int* blocks,
-                    size_t* shm) {
-  const SpatialShape sh = spatial_shape<float>(P);
-  *reinterpret_cast<ColsArgs<float>*>(out) = cols_args<float>(P, sh, data, done);
+template <typename T>
+int batch_cols_args(const Plan& P, T* data, const double* done, ColsArgs<T>* out, int* blocks,
+                    size_t* shm, int* threads) {
+  const SpatialShape sh = spatial_shape<T>(P);
+  *out = cols_args<T>(P, sh, data, done);
   *blocks = sh.cblocks;
   *shm = sh.cshm;
+  *threads = sh.cthreads;
   return sh.creg;
 }
 
-// float32 blocks have 256 threads on both paths
-void launch_rows_batch_f32(int cls, const void* A, const int* off, int ninst, int total,
-                           size_t shm, hipStream_t s) {
-  const auto* a = reinterpret_cast<const RowsArgs<float>*>(A);
-  const dim3 g(total), b(256);
+// the block size is that of the size class (every instance of a launch has it)
+template <typename T>
+void launch_rows_batch(int cls, const RowsArgs<T>* a, const int* off, int ninst, int total,
+                       size_t shm, int threads, hipStream_t s) {
+  const dim3 g(total), b(threads);
   switch (cls) {
-    case 64: hipLaunchKernelGGL((k_rows_reg_batch<float, 64>), g, b, shm, s, a, off, ninst); break;
-    case 128: hipLaunchKernelGGL((k_rows_reg_batch<float, 128>), g, b, shm, s, a, off, ninst); break;
-    case 256: hipLaunchKernelGGL((k_rows_reg_batch<float, 256>), g, b, shm, s, a, off, ninst); break;
-    default: hipLaunchKernelGGL(k_rows_batch<float>, g, b, shm, s, a, off, ninst);
+    case 64: hipLaunchKernelGGL((k_rows_reg_batch<T, 64>), g, b, shm, s, a, off, ninst); break;
+    case 128: hipLaunchKernelGGL((k_rows_reg_batch<T, 128>), g, b, shm, s, a, off, ninst); break;
+    case 256: hipLaunchKernelGGL((k_rows_reg_batch<T, 256>), g, b, shm, s, a, off, ninst); break;
+    default: hipLaunchKernelGGL(k_rows_batch<T>, g, b, shm, s, a, off, ninst);
   }
 }
 
-void launch_cols_batch_f32(int cls, const void* A, const int* off, int ninst, int total,
-                           size_t shm, hipStream_t s) {
-  const auto* a = reinterpret_cast<const ColsArgs<float>*>(A);
-  const dim3 g(total), b(256);
+template <typename T>
+void launch_cols_batch(int cls, const ColsArgs<T>* a, const int* off, int ninst, int total,
+                       size_t shm, int threads, hipStream_t s) {
+  const dim3 g(total), b(threads);
   switch (cls) {
-    case 64: hipLaunchKernelGGL((k_cols_reg_batch<float, 64>), g, b, shm, s, a, off, ninst); break;
-    case 128: hipLaunchKernelGGL((k_cols_reg_batch<float, 128>), g, b, shm, s, a, off, ninst); break;
-    case 256: hipLaunchKernelGGL((k_cols_reg_batch<float, 256>), g, b, shm, s, a, off, ninst); break;
-    default: hipLaunchKernelGGL(k_cols_batch<float>, g, b, shm, s, a, off, ninst);
+    case 64: hipLaunchKernelGGL((k_cols_reg_batch<T, 64>), g, b, shm, s, a, off, ninst); break;
+    case 128: hipLaunchKernelGGL((k_cols_reg_batch<T, 128>), g, b, shm, s, a, off, ninst); break;
+    case 256: hipLaunchKernelGGL((k_cols_reg_batch<T, 256>), g, b, shm, s, a, off, ninst); break;
+    default: hipLaunchKernelGGL(k_cols_batch<T>, g, b, shm, s, a, off, ninst);
   }
 }
+
+#define MFG_BATCH_SPATIAL(T)                                                                    \
+  template int batch_rows_args<T>(const Plan&, T*, int, const double*, RowsArgs<T>*, int*,      \
+                                  size_t*, int*);                                               \
+  template int batch_cols_args<T>(const Plan&, T*, const double*, ColsArgs<T>*, int*, size_t*,  \
+                                  int*);                                                        \
+  template void launch_rows_batch<T>(int, const RowsArgs<T>*, const int*, int, int, size_t, int, \
+                                     hipStream_t);                                              \
+  template void launch_cols_batch<T>(int, const ColsArgs<T>*, const int*, int, int, size_t, int, \
+                                     hipStream_t);
+MFG_BATCH_SPATIAL(float)
+MFG_BATCH_SPATIAL(double)
+#undef MFG_BATCH_SPATIAL
 
 }  // namespace mfg

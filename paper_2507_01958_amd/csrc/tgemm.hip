@@ -134,6 +134,13 @@ __global__ __launch_bounds__(256) void k_tgemm64(GemmArgs<TX, TY> a) {
   tgemm64_body<KB, CB, TX, TY>(a, blockIdx.x);
 }
 
+template <int KB, int CB>
+__global__ __launch_bounds__(256) void k_tgemm64_batch(const GemmArgs<double, double>* A,
+                                                       const int* off, int ninst) {
+  const int i = batch_instance(off, ninst, blockIdx.x);
+  tgemm64_body<KB, CB, double, double>(A[i], blockIdx.x - off[i]);
+}
+
 constexpr int pow2_floor(int c) {
   int m = 1;
   while (m * 2 <= c) m *= 2;
@@ -1014,6 +1021,33 @@ void launch_gemm_batch(int mode, int ntp, int cb, int waves, const GemmArgs<TX, 
   if (mode == GM_F32) lp_batch_cb<GM_F32>(ntp, cb, waves, A, off, ninst, total, s);
   else if (mode == GM_F16) lp_batch_cb<GM_F16>(ntp, cb, waves, A, off, ninst, total, s);
   else lp_batch_cb<GM_BF16>(ntp, cb, waves, A, off, ninst, total, s);
+}
+
+// ---- batched float64 time GEMM (one (KB, CB) class per launch) ----
+GemmArgs<double, double> batch_gemm64_args(const Plan& P, const double* X, double* Y, int dotmode,
+                                           const double* r, const double* q, const double* done,
+                                           int* blocks, int* kb, int* cb) {
+  // the single-plan choice of f64_launch (any N_t: the k rows come in chunks)
+  const int nt = P.g.nt, M = P.g.M;
+  *kb = nt <= 32 ? 2 : (nt <= 64 ? 4 : 8);
+  *cb = P.tune.f64_cb == 1 ? 1 : 2;
+  const int ncolblk = (M + 64 * *cb - 1) / (64 * *cb);
+  *blocks = ncolblk * ((nt + *kb * 16 - 1) / (*kb * 16));
+  return GemmArgs<double, double>{P.Vt64, X, Y, nt, M, ncolblk, dotmode, r, q, P.red, done, 0};
+}
+
+void launch_gemm64_batch(int kb, int cb, const GemmArgs<double, double>* A, const int* off,
+                         int ninst, int total, hipStream_t s) {
+  const dim3 g(total), b(256);
+  if (cb == 1) {
+    if (kb == 2) hipLaunchKernelGGL((k_tgemm64_batch<2, 1>), g, b, 0, s, A, off, ninst);
+    else if (kb == 4) hipLaunchKernelGGL((k_tgemm64_batch<4, 1>), g, b, 0, s, A, off, ninst);
+    else hipLaunchKernelGGL((k_tgemm64_batch<8, 1>), g, b, 0, s, A, off, ninst);
+  } else {
+    if (kb == 2) hipLaunchKernelGGL((k_tgemm64_batch<2, 2>), g, b, 0, s, A, off, ninst);
+    else if (kb == 4) hipLaunchKernelGGL((k_tgemm64_batch<4, 2>), g, b, 0, s, A, off, ninst);
+    else hipLaunchKernelGGL((k_tgemm64_batch<8, 2>), g, b, 0, s, A, off, ninst);
+  }
 }
 
 template GemmArgs<double, float> batch_gemm_args(const Plan&, int, const double*, float*, int,

@@ -65,7 +65,7 @@ def _batched(insts, precision, chunks, rtol, maxit, use_graph):
     return out
 
 
-@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_fp16"])
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_fp16", "fp64"])
 @pytest.mark.parametrize("use_graph", [True, False])
 def test_batch_bitwise_equals_single(precision, use_graph):
     insts = _instances()
@@ -99,8 +99,11 @@ def test_batch_rejects_unsupported():
     import torch
     inst = _instances()[0]
     V, m0 = _tensors(inst)
+    # the mixed-precision batched time GEMM holds V in LDS: N_t <= 128
+    long_inst = wl.small_instance(27, 2, 12, 12, 130, "periodic", 0.1)
+    Vl, m0l = _tensors(long_inst)
     with pytest.raises(mfg.MFGError) as e:
-        mfg.mfg_plan_batch([_problem(inst, "fp64")], [V], [m0])
+        mfg.mfg_plan_batch([_problem(long_inst, "mixed_fp32")], [Vl], [m0l])
     assert e.value.code == 2
     with pytest.raises(mfg.MFGError) as e:
         mfg.mfg_plan_batch([_problem(inst, "mixed_fp32"), _problem(inst, "mixed_fp16")],
@@ -182,3 +185,28 @@ def test_batch_with_a_settled_instance():
         assert b[5] == ref[5], (inst.name, b[5], ref[5])
         for x, y in zip(b[:3], ref[:3]):
             assert np.array_equal(x, y), inst.name
+
+
+def test_fp64_batch_long_horizons():
+    """The float64 batched preconditioner takes any N_t (its time GEMM walks the
+    k rows in chunks): instances with N_t above 128 and uneven shapes run
+    bitwise as single plans, and one matches the oracle's CP with exact
+    projections."""
+    insts = [wl.small_instance(28, 2, 16, 12, 200, "neumann", 0.05),
+             wl.small_instance(29, 2, 12, 18, 130, "periodic", 0.2),
+             wl.small_instance(30, 2, 24, 16, 40, "periodic", 0.01)]
+    say("fp64 batch long horizons x3")
+    got = _batched(insts, "fp64", [2, 3], 1e-12, 400, True)
+    for inst, b in zip(insts, got):
+        ref = _single(inst, "fp64", [2, 3], 1e-12, 400)
+        assert b[5] == ref[5], (inst.name, b[5], ref[5])
+        for name, x, y in zip(["xi", "y", "ybar"], b[:3], ref[:3]):
+            assert np.array_equal(x, y), (inst.name, name)
+    inst, b = insts[1], got[1]
+    g = grid_of(inst)
+    ref, _ = ocp.cp_solve(g, inst.V, inst.m0, 5, method="direct")
+    n = g.n
+    for blk in range(1 + g.ncomp):
+        r = ref.y[blk * n:(blk + 1) * n]
+        err = np.abs(b[1][blk * n:(blk + 1) * n] - r).max() / max(np.abs(r).max(), 1e-300)
+        assert err <= 1e-10, (blk, err)

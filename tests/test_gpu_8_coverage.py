@@ -91,7 +91,7 @@ def _batched(insts, precision, chunks, rtol, maxit, use_graph):
     return out
 
 
-@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_fp16"])
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_fp16", "fp64"])
 @pytest.mark.parametrize("use_graph", [True, False])
 def test_batch_big_axes_bitwise(precision, use_graph):
     insts = _big_axis_instances()
