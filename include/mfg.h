@@ -313,10 +313,10 @@ typedef struct mfg_batch_s* mfg_batch_t;
 
 /* Build a batch of count >= 1 plans. pbs[i], V[i], m0[i] are as for mfg_plan
  * (V and m0 arrays are host arrays of device pointers). Requirements: d = 2,
- * q' = 2 and one precision shared by all instances (MFG_ERR_INVALID_ARG
- * otherwise); in the MIXED precisions N_t <= 128 (the batched low-precision
- * time transform holds V in LDS), in FP64 any N_t; MFG_ERR_UNSUPPORTED
- * otherwise. The instances' plans use `stream`; batched
+ * q' = 2 (MFG_ERR_UNSUPPORTED otherwise) and one precision shared by all
+ * instances (MFG_ERR_INVALID_ARG otherwise); any N_t (above 128 the MIXED
+ * precisions take the streaming time transform, which MFG_TUNE lp_stream=0
+ * would switch off: MFG_ERR_UNSUPPORTED then). The instances' plans use `stream`; batched
  * solves run on an internal stream ordered after and before `stream` with
  * events. */
 int mfg_plan_batch(const mfg_problem_t* pbs, const double* const* V, const double* const* m0,

@@ -260,6 +260,7 @@ int build_pcg_phases(Batch& B) {
                               &cb);
       return std::make_tuple(kb, cb, 0);
     }
+    if (P.ntp == 0) return std::make_tuple(-1, 0, 0);  // N_t > 128: streaming V
     const Tune& t = P.tune;
     return std::make_tuple(P.ntp, t.lp_cb == 1 ? 1 : 2, t.lp_waves == 8 ? 8 : 4);
   };
@@ -276,11 +277,29 @@ int build_pcg_phases(Batch& B) {
     std::vector<GemmArgs<double, float>> fw0, fw;
     std::vector<GemmArgs<float, double>> i0, i1;
     std::vector<GemmArgs<double, double>> d0, d1, e0, e1;
-    std::vector<int> blocks;
+    std::vector<int> blocks, blocks_fwd;
     for (int i = 0; i < n; ++i) {
       Plan& P = plan_of(B, i);
       if (shape_of(i) != classes[gi]) continue;
       int blk;
+      if (!f64 && G.ntp < 0) {
+        // streaming V: the forward and inverse launches split differently
+        float* tmp = reinterpret_cast<float*>(P.tmp);
+        int bf;
+        fw0.push_back(batch_gemm_lps_args<double, float>(P, B.mode, P.r, tmp, DOT_NONE, nullptr,
+                                                         nullptr, done_of(B, i), &bf));
+        fw.push_back(fw0.back());
+        fw.back().nrr = update_grid(P);
+        i0.push_back(batch_gemm_lps_args<float, double>(P, B.mode, tmp, P.z, DOT_INIT, P.r,
+                                                        nullptr, done_of(B, i), &blk));
+        i1.push_back(batch_gemm_lps_args<float, double>(P, B.mode, tmp, P.z,
+                                                        pcg_flexible(P) ? DOT_FLEX : DOT_STD,
+                                                        P.r, P.q, done_of(B, i), &blk));
+        blocks_fwd.push_back(bf);
+        blocks.push_back(blk);
+        gemm_grid[i] = blk;
+        continue;
+      }
       if (f64) {
         int kb, cb;
         d0.push_back(batch_gemm64_args(P, P.r, P.tmp, DOT_NONE, nullptr, nullptr, done_of(B, i),
@@ -304,6 +323,7 @@ int build_pcg_phases(Batch& B) {
                                                     P.q, done_of(B, i), &blk));
       }
       blocks.push_back(blk);
+      blocks_fwd.push_back(blk);
       gemm_grid[i] = blk;
     }
     if (f64) {
@@ -312,8 +332,8 @@ int build_pcg_phases(Batch& B) {
           (rc = upload_phase(B, e0, blocks, G.inv64_init)) ||
           (rc = upload_phase(B, e1, blocks, G.inv64_iter)))
         return rc;
-    } else if ((rc = upload_phase(B, fw0, blocks, G.fwd_init)) ||
-               (rc = upload_phase(B, fw, blocks, G.fwd)) ||
+    } else if ((rc = upload_phase(B, fw0, blocks_fwd, G.fwd_init)) ||
+               (rc = upload_phase(B, fw, blocks_fwd, G.fwd)) ||
                (rc = upload_phase(B, i0, blocks, G.inv_init)) ||
                (rc = upload_phase(B, i1, blocks, G.inv_iter))) {
       return rc;
@@ -395,14 +415,18 @@ void precond_phase(Batch& B, bool init, hipStream_t s) {
   }
   for (auto& G : B.groups) {
     const auto& ph = init ? G.fwd_init : G.fwd;
-    launch_gemm_batch<double, float>(B.mode, G.ntp, G.cb, G.waves, ph.args, ph.off, ph.ninst,
-                                     ph.total, s);
+    if (G.ntp < 0) launch_gemm_lps_batch<double, float>(B.mode, ph.args, ph.off, ph.ninst,
+                                                        ph.total, s);
+    else launch_gemm_batch<double, float>(B.mode, G.ntp, G.cb, G.waves, ph.args, ph.off,
+                                          ph.ninst, ph.total, s);
   }
   spatial_phase<float>(B.rows, B.cols, s);
   for (auto& G : B.groups) {
     const auto& ph = init ? G.inv_init : G.inv_iter;
-    launch_gemm_batch<float, double>(B.mode, G.ntp, G.cb, G.waves, ph.args, ph.off, ph.ninst,
-                                     ph.total, s);
+    if (G.ntp < 0) launch_gemm_lps_batch<float, double>(B.mode, ph.args, ph.off, ph.ninst,
+                                                        ph.total, s);
+    else launch_gemm_batch<float, double>(B.mode, G.ntp, G.cb, G.waves, ph.args, ph.off,
+                                          ph.ninst, ph.total, s);
   }
 }
 
@@ -458,10 +482,7 @@ int batch_create(Batch& B, const mfg_problem_t* pbs, const double* const* V,
   for (int i = 0; i < count; ++i) {
     if (pbs[i].precision != prec) return fail(MFG_ERR_INVALID_ARG, "mixed precisions in a batch");
     if (pbs[i].d != 2) return fail(MFG_ERR_UNSUPPORTED, "batched solves need d = 2");
-    // the batched low-precision time GEMM holds V in LDS; the float64 one
-    // takes the k rows in chunks (any N_t)
-    if (prec != MFG_FP64 && pbs[i].nt > 128)
-      return fail(MFG_ERR_UNSUPPORTED, "mixed-precision batched solves need N_t <= 128");
+
     if (pbs[i].qprime != 2.0) return fail(MFG_ERR_UNSUPPORTED, "batched solves need q' = 2");
   }
   if (hipStreamCreateWithFlags(&B.stream, hipStreamNonBlocking) != hipSuccess ||
@@ -474,6 +495,10 @@ int batch_create(Batch& B, const mfg_problem_t* pbs, const double* const* V,
     if (rc) return rc;
     B.plans.push_back(h);
     batch_shape(h->P.tune);  // launch shapes the batched kernels support
+    // above N_t = 128 the batched low-precision time GEMM is the streaming one
+    if (prec != MFG_FP64 && h->P.ntp == 0 && !h->P.tune.lp_stream)
+      return fail(MFG_ERR_UNSUPPORTED,
+                  "batched mixed-precision solves above N_t = 128 need the streaming time GEMM");
   }
   int rc;
   void* p;

@@ -190,6 +190,15 @@ GemmArgs<TX, TY> batch_gemm_args(const Plan& P, int mode, const TX* X, TY* Y, in
                                  const double* r, const double* q, const double* done,
                                  int* blocks);
 
+// streaming low-precision time GEMM (N_t > 128); the block count differs
+// between directions (the float32 split's forward takes one tile per wave)
+template <typename TX, typename TY>
+GemmArgs<TX, TY> batch_gemm_lps_args(const Plan& P, int mode, const TX* X, TY* Y, int dotmode,
+                                     const double* r, const double* q, const double* done,
+                                     int* blocks);
+template <typename TX, typename TY>
+void launch_gemm_lps_batch(int mode, const GemmArgs<TX, TY>* A, const int* off, int ninst,
+                           int total, hipStream_t s);
 // float64 time GEMM: the (KB, CB) class of the instance's launch in kb, cb
 GemmArgs<double, double> batch_gemm64_args(const Plan& P, const double* X, double* Y, int dotmode,
                                            const double* r, const double* q, const double* done,

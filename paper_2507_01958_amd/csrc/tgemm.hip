@@ -568,6 +568,21 @@ __global__ __launch_bounds__(256) void k_tgemm_lps(GemmArgs<TX, TY> a) {
   tgemm_lps_body<MODE, KB, CB, TX, TY>(a, blockIdx.x, gridDim.x);
 }
 
+template <int MODE, int KB, int CB, typename TX, typename TY>
+__global__ __launch_bounds__(256) void k_tgemm_lps_batch(const GemmArgs<TX, TY>* A,
+                                                         const int* off, int ninst) {
+  const int i = batch_instance(off, ninst, blockIdx.x);
+  tgemm_lps_body<MODE, KB, CB, TX, TY>(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
+}
+
+// the streaming kernel's shape: 8 x 16 output rows per block; one 16-node tile
+// per wave for the float32 split of float64 operands, two otherwise
+template <int MODE, typename TX>
+constexpr int lps_cb() {
+  return (MODE == GM_F32 && sizeof(TX) == 8) ? 1 : 2;
+}
+constexpr int kLpsKB = 8;
+
 // Streaming persistent form for N_t <= 128 (NTP = N_t rounded up to 16):
 // each block stages all of V in LDS once; each wave then streams 16-node
 // column tiles (tile w, w + #waves, ...) with two operand register sets, so
@@ -903,7 +918,7 @@ int lps_launch(const Plan& P, const TX* X, TY* Y, int dotmode, const double* r, 
   // 16-node tile per wave: its prefetched registers would otherwise leave one
   // wave per SIMD (221 against 275 us at 64^2 x 2048); float16 and bfloat16
   // keep two (117 against 147 us)
-  constexpr int KB = 8, CB = (MODE == GM_F32 && sizeof(TX) == 8) ? 1 : 2;
+  constexpr int KB = kLpsKB, CB = lps_cb<MODE, TX>();
   const int M = P.g.M;
   const int ncolblk = (M + 4 * CB * 16 - 1) / (4 * CB * 16);
   const int grid = ncolblk * (P.ntps / (KB * 16));
@@ -1022,6 +1037,48 @@ void launch_gemm_batch(int mode, int ntp, int cb, int waves, const GemmArgs<TX, 
   else if (mode == GM_F16) lp_batch_cb<GM_F16>(ntp, cb, waves, A, off, ninst, total, s);
   else lp_batch_cb<GM_BF16>(ntp, cb, waves, A, off, ninst, total, s);
 }
+
+// ---- batched streaming low-precision time GEMM (N_t > 128) ----
+template <typename TX, typename TY>
+GemmArgs<TX, TY> batch_gemm_lps_args(const Plan& P, int mode, const TX* X, TY* Y, int dotmode,
+                                     const double* r, const double* q, const double* done,
+                                     int* blocks) {
+  const int cb = mode == GM_F32 ? (sizeof(TX) == 8 ? lps_cb<GM_F32, double>()
+                                                   : lps_cb<GM_F32, float>())
+                                : 2;
+  const int M = P.g.M;
+  const int ncolblk = (M + 4 * cb * 16 - 1) / (4 * cb * 16);
+  *blocks = ncolblk * (P.ntps / (kLpsKB * 16));
+  GemmArgs<TX, TY> a{P.Vs_lp, X, Y, P.g.nt, M, ncolblk, dotmode, r, q, P.red, done, 0};
+  a.ldv = P.ntps;
+  return a;
+}
+
+template <typename TX, typename TY>
+void launch_gemm_lps_batch(int mode, const GemmArgs<TX, TY>* A, const int* off, int ninst,
+                           int total, hipStream_t s) {
+  const dim3 g(total), b(256);
+  if (mode == GM_F32)
+    hipLaunchKernelGGL((k_tgemm_lps_batch<GM_F32, kLpsKB, lps_cb<GM_F32, TX>(), TX, TY>), g, b,
+                       0, s, A, off, ninst);
+  else if (mode == GM_F16)
+    hipLaunchKernelGGL((k_tgemm_lps_batch<GM_F16, kLpsKB, lps_cb<GM_F16, TX>(), TX, TY>), g, b,
+                       0, s, A, off, ninst);
+  else
+    hipLaunchKernelGGL((k_tgemm_lps_batch<GM_BF16, kLpsKB, lps_cb<GM_BF16, TX>(), TX, TY>), g,
+                       b, 0, s, A, off, ninst);
+}
+
+template GemmArgs<double, float> batch_gemm_lps_args(const Plan&, int, const double*, float*, int,
+                                                     const double*, const double*,
+                                                     const double*, int*);
+template GemmArgs<float, double> batch_gemm_lps_args(const Plan&, int, const float*, double*, int,
+                                                     const double*, const double*,
+                                                     const double*, int*);
+template void launch_gemm_lps_batch(int, const GemmArgs<double, float>*, const int*, int, int,
+                                    hipStream_t);
+template void launch_gemm_lps_batch(int, const GemmArgs<float, double>*, const int*, int, int,
+                                    hipStream_t);
 
 // ---- batched float64 time GEMM (one (KB, CB) class per launch) ----
 GemmArgs<double, double> batch_gemm64_args(const Plan& P, const double* X, double* Y, int dotmode,

@@ -99,12 +99,21 @@ def test_batch_rejects_unsupported():
     import torch
     inst = _instances()[0]
     V, m0 = _tensors(inst)
-    # the mixed-precision batched time GEMM holds V in LDS: N_t <= 128
+    # above N_t = 128 the batched mixed-precision time GEMM is the streaming one
     long_inst = wl.small_instance(27, 2, 12, 12, 130, "periodic", 0.1)
     Vl, m0l = _tensors(long_inst)
-    with pytest.raises(mfg.MFGError) as e:
-        mfg.mfg_plan_batch([_problem(long_inst, "mixed_fp32")], [Vl], [m0l])
-    assert e.value.code == 2
+    import os
+    old = os.environ.get("MFG_TUNE")
+    os.environ["MFG_TUNE"] = "lp_stream=0"
+    try:
+        with pytest.raises(mfg.MFGError) as e:
+            mfg.mfg_plan_batch([_problem(long_inst, "mixed_fp32")], [Vl], [m0l])
+        assert e.value.code == 2
+    finally:
+        if old is None:
+            del os.environ["MFG_TUNE"]
+        else:
+            os.environ["MFG_TUNE"] = old
     with pytest.raises(mfg.MFGError) as e:
         mfg.mfg_plan_batch([_problem(inst, "mixed_fp32"), _problem(inst, "mixed_fp16")],
                            [V, V], [m0, m0])
@@ -210,3 +219,20 @@ def test_fp64_batch_long_horizons():
         r = ref.y[blk * n:(blk + 1) * n]
         err = np.abs(b[1][blk * n:(blk + 1) * n] - r).max() / max(np.abs(r).max(), 1e-300)
         assert err <= 1e-10, (blk, err)
+
+
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_fp16", "mixed_bf16"])
+def test_mixed_batch_long_horizons(precision):
+    """Above N_t = 128 the batched low-precision time GEMM streams V through
+    LDS as the single-plan one does: batches mixing long and short horizons run
+    bitwise as single plans (graph replays included)."""
+    insts = [wl.small_instance(31, 2, 16, 12, 200, "neumann", 0.05),
+             wl.small_instance(32, 2, 12, 18, 130, "periodic", 0.2),
+             wl.small_instance(33, 2, 24, 16, 40, "periodic", 0.01)]
+    say(f"{precision} batch long horizons x3")
+    got = _batched(insts, precision, [2, 3], 1e-10, 400, True)
+    for inst, b in zip(insts, got):
+        ref = _single(inst, precision, [2, 3], 1e-10, 400)
+        assert b[5] == ref[5], (inst.name, b[5], ref[5])
+        for name, x, y in zip(["xi", "y", "ybar"], b[:3], ref[:3]):
+            assert np.array_equal(x, y), (inst.name, name)
