@@ -2,6 +2,11 @@
 
 Usage: python -m paper_2507_01958_amd.build   (or build() from Python).
 Every call recompiles; objects go to paper_2507_01958_amd/_build/.
+
+It also builds _build/asan/libmfg_host_asan.so: the same sources with the
+host code instrumented by AddressSanitizer (the device code is not; -O1), for
+the CPU tests of the C ABI's host paths (loaded with MFG_LIBRARY and the ASan
+runtime preloaded; see tests/test_abi_asan.py).
 """
 from __future__ import annotations
 
@@ -30,28 +35,44 @@ CFLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+ASAN_BUILD = os.path.join(BUILD, "asan")
+ASAN_LIB = os.path.join(ASAN_BUILD, "libmfg_host_asan.so")
+# host code only: each -fsanitize= goes to the host pass
+ASAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def _compile(src: str, asan: bool = False) -> str:
+    out_dir = ASAN_BUILD if asan else BUILD
+    obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
+    flags = [f if f != "-O3" else "-O1" for f in CFLAGS] + ASAN_FLAGS if asan else CFLAGS
+    cmd = [HIPCC, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+def _link(objs, out, extra=()):
+    tmp = out + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *extra, "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False, asan: bool = True) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    os.makedirs(ASAN_BUILD, exist_ok=True)
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    jobs = [(s, False) for s in srcs] + ([(s, True) for s in srcs] if asan else [])
+    with concurrent.futures.ThreadPoolExecutor(max_workers=8) as ex:
+        objs = list(ex.map(lambda j: _compile(*j), jobs))
+    _link(objs[: len(srcs)], LIB)
+    if asan:
+        _link(objs[len(srcs):], ASAN_LIB, ASAN_FLAGS[:2])
     if verbose:
-        print("built", LIB)
+        print("built", LIB + (" and " + ASAN_LIB if asan else ""))
     return LIB
 
 

@@ -91,13 +91,15 @@ _lib = None
 
 
 def load():
-    """Load libmfg.so (built in-tree by paper_2507_01958_amd.build). Raises if
+    """Load libmfg.so (built in-tree by paper_2507_01958_amd.build), or the
+    library file MFG_LIBRARY names (the host-AddressSanitizer build). Raises if
     it is missing: there is no fallback path."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2507_01958_amd.build`")
-        lib = ctypes.CDLL(LIB_PATH)
+        path = os.environ.get("MFG_LIBRARY") or LIB_PATH
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run `python -m paper_2507_01958_amd.build`")
+        lib = ctypes.CDLL(path)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)
             fn.restype = res
