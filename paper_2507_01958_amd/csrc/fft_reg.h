@@ -39,10 +39,15 @@ template <typename T>
 __device__ __forceinline__ C2<T> sub(C2<T> a, C2<T> b) {
   return {a.x - b.x, a.y - b.y};
 }
+// a b + c with one rounding (written out, so the result does not depend on
+// the compiler's contraction choices in the kernel it is compiled into)
+__device__ __forceinline__ float ffma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double ffma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // a * (c + i s)
 template <typename T>
 __device__ __forceinline__ C2<T> mul(C2<T> a, T c, T s) {
-  return {a.x * c - a.y * s, a.x * s + a.y * c};
+  return {ffma(a.x, c, -(a.y * s)), ffma(a.x, s, a.y * c)};
 }
 // a * (SIGN i)
 template <int SIGN, typename T>

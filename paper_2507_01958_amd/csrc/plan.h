@@ -36,6 +36,9 @@ struct Tune {
   // right-hand-side kernel: time slices walked per block (0: chosen from the
   // geometry alone; not autotuned, so batched and single-plan runs agree)
   int rhs_tc = 0;
+  // forward preconditioner pass fused (time GEMM + row transforms) where it
+  // applies (mixed modes, axis 1 of 256 nodes, N_t <= 128); 0: separate kernels
+  int fuse_fwd = 1;
 };
 
 // Optional per-kernel timing with HIP events recorded on the plan's stream

@@ -16,6 +16,7 @@
 #include "batch_args.h"
 #include "device_util.h"
 #include "fft_reg.h"
+#include "rows_reg.h"
 #include "plan.h"
 #include "tgemm.h"
 
@@ -24,19 +25,6 @@ namespace mfg {
 namespace {
 
 constexpr int kLoadBatch = 8;  // global loads per thread issued before their LDS stores
-
-template <typename T>
-__device__ __forceinline__ const T* tw_table(const Axis& ax);
-template <>
-__device__ __forceinline__ const double* tw_table<double>(const Axis& ax) { return ax.tw; }
-template <>
-__device__ __forceinline__ const float* tw_table<float>(const Axis& ax) { return ax.twf; }
-template <typename T>
-__device__ __forceinline__ const T* ct_table(const Axis& ax);
-template <>
-__device__ __forceinline__ const double* ct_table<double>(const Axis& ax) { return ax.ct; }
-template <>
-__device__ __forceinline__ const float* ct_table<float>(const Axis& ax) { return ax.ctf; }
 
 template <typename T>
 __device__ __forceinline__ C2<T> cmul(C2<T> a, T c, T s) {
@@ -115,10 +103,6 @@ __device__ C2<T>* fft_lds(C2<T>* a, C2<T>* b, int nlines, const Axis& ax, const 
 }
 
 // Makhoul's reordering for the DCT-II: v[n] = x[perm(n)].
-__device__ __forceinline__ int dct_perm(int n, int N) {
-  return (2 * n < N) ? 2 * n : 2 * (N - 1 - n) + 1;
-}
-
 // Real spectra of the two packed real lines from their complex FFT Z.
 // DHT: H_a = (p + r - q + s)/2, H_b = (q + s + p - r)/2 with Z[k] = p + iq,
 // Z[N-k] = r + is.  DCT-II: C = Re(e^{-i pi k/(2N)} V[k]) of each line.
@@ -379,45 +363,19 @@ template <typename T, int N>
 __device__ void rows_fwd_reg(const RowsArgs<T>& a, int bid, C2<T>* lds) {
   using Sh = fftr::Shape<T, N>;
   const int l = threadIdx.x / Sh::N2, p = threadIdx.x % Sh::N2;
-  const int line = bid * Sh::LPB + l;
-  const int ra = 2 * line, rb = ra + 1;
-  const bool hasa = ra < a.nrows, hasb = rb < a.nrows;
-  const bool dct = a.ax.kind == 1;
+  const RowPair rp = row_pair(bid * Sh::LPB + l, a.nrows, a.n0);
   T* __restrict__ data = a.data;
-  const T* __restrict__ tw = tw_table<T>(a.ax);
-  C2<T> v[16];
-#pragma unroll
-  for (int n1 = 0; n1 < 16; ++n1) {
-    const int n = p + Sh::N2 * n1;
-    const int src = dct ? dct_perm(n, N) : n;
-    v[n1].x = hasa ? data[(unsigned)ra * N + src] : (T)0;  // n < 2^31
-    v[n1].y = hasb ? data[(unsigned)rb * N + src] : (T)0;
-  }
-  fftr::fft4<T, N, -1>(v, lds + l * Sh::L, p, tw);
-  __syncthreads();
-  C2<T>* zb = lds + l * Sh::L2;
-#pragma unroll
-  for (int m = 0; m < 16; ++m) zb[p + Sh::N2 * m] = v[m];
-  __syncthreads();
-  const T* __restrict__ ct = ct_table<T>(a.ax);
-#pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int k = p + Sh::N2 * m;
-    const int kr = k ? N - k : 0;
-    const C2<T> z = v[m], zr = zb[kr];
-    const T pp = z.x, q = z.y, r = zr.x, s = zr.y;
-    T oa, ob;
-    if (!dct) {
-      oa = (T)0.5 * ((pp + r) - (q - s));
-      ob = (T)0.5 * ((q + s) + (pp - r));
-    } else {
-      const T c = ct[2 * k], sn = ct[2 * k + 1];
-      oa = (T)0.5 * (c * (pp + r) + sn * (q - s));
-      ob = (T)0.5 * (c * (q + s) + sn * (r - pp));
-    }
-    if (hasa) data[(unsigned)ra * N + k] = oa;
-    if (hasb) data[(unsigned)rb * N + k] = ob;
-  }
+  // n < 2^31: 32-bit offsets
+  auto ld = [&](int n) {
+    return C2<T>{rp.hasa ? data[(unsigned)rp.ra * N + n] : (T)0,
+                 rp.hasb ? data[(unsigned)rp.rb * N + n] : (T)0};
+  };
+  auto st = [&](int k, T oa, T ob) {
+    if (rp.hasa) data[(unsigned)rp.ra * N + k] = oa;
+    if (rp.hasb) data[(unsigned)rp.rb * N + k] = ob;
+  };
+  rows_fwd_line<T, N>(ld, st, a.ax.kind == 1, lds + l * Sh::L, lds + l * Sh::L2, p,
+                      tw_table<T>(a.ax), ct_table<T>(a.ax));
 }
 
 // Inverse real transform along the contiguous axis (times N): spectra in,
@@ -428,9 +386,9 @@ template <typename T, int N>
 __device__ void rows_inv_reg(const RowsArgs<T>& a, int bid, C2<T>* lds) {
   using Sh = fftr::Shape<T, N>;
   const int l = threadIdx.x / Sh::N2, p = threadIdx.x % Sh::N2;
-  const int line = bid * Sh::LPB + l;
-  const int ra = 2 * line, rb = ra + 1;
-  const bool hasa = ra < a.nrows, hasb = rb < a.nrows;
+  const RowPair rp = row_pair(bid * Sh::LPB + l, a.nrows, a.n0);
+  const int ra = rp.ra, rb = rp.rb;
+  const bool hasa = rp.hasa, hasb = rp.hasb;
   const bool dct = a.ax.kind == 1;
   T* __restrict__ data = a.data;
   const T* __restrict__ tw = tw_table<T>(a.ax);
@@ -454,8 +412,8 @@ __device__ void rows_inv_reg(const RowsArgs<T>& a, int bid, C2<T>* lds) {
         rb_ = (T)0;
       }
       const T c = ct[2 * k], sn = ct[2 * k + 1];
-      v[m].x = c * ca + sn * ra_ - (sn * cb - c * rb_);
-      v[m].y = (sn * ca - c * ra_) + c * cb + sn * rb_;
+      v[m].x = fftr::ffma(c, ca, sn * ra_) - fftr::ffma(sn, cb, -(c * rb_));
+      v[m].y = fftr::ffma(sn, ca, -(c * ra_)) + fftr::ffma(c, cb, sn * rb_);
     }
   }
   fftr::fft4<T, N, +1>(v, lds + l * Sh::L, p, tw);
@@ -564,23 +522,23 @@ __device__ void cols_reg(const ColsArgs<T>& a, int bid, int nb, C2<T>* lds) {
       // W = Z_a ia + i Z_b ib = (Z + conj Zr)/2 ia + (Z - conj Zr)/2 ib
       const C2<T> sp = {(T)0.5 * (z.x + zr.x), (T)0.5 * (z.y - zr.y)};
       const C2<T> sm = {(T)0.5 * (z.x - zr.x), (T)0.5 * (z.y + zr.y)};
-      v[m] = C2<T>{sp.x * ia + sm.x * ib, sp.y * ia + sm.y * ib};
+      v[m] = C2<T>{fftr::ffma(sp.x, ia, sm.x * ib), fftr::ffma(sp.y, ia, sm.y * ib)};
     } else {
       const T pp = z.x, q = z.y, r = zr.x, s = zr.y;
       const T c = ct[2 * k], sn = ct[2 * k + 1];
-      const T ca = (T)0.5 * (c * (pp + r) + sn * (q - s)) * ia;
-      const T cb = (T)0.5 * (c * (q + s) + sn * (r - pp)) * ib;
+      const T ca = (T)0.5 * fftr::ffma(c, pp + r, sn * (q - s)) * ia;
+      const T cb = (T)0.5 * fftr::ffma(c, q + s, sn * (r - pp)) * ib;
       T rca = (T)0, rcb = (T)0;
       if (k) {
         const T Rr = (T)sc.lam0[kr];
         const T ira = sym.inv(Rr + l1a);
         const T irb = sym.inv(Rr + l1b);
         const T cr = ct[2 * kr], snr = ct[2 * kr + 1];
-        rca = (T)0.5 * (cr * (r + pp) + snr * (s - q)) * ira;
-        rcb = (T)0.5 * (cr * (s + q) + snr * (pp - r)) * irb;
+        rca = (T)0.5 * fftr::ffma(cr, r + pp, snr * (s - q)) * ira;
+        rcb = (T)0.5 * fftr::ffma(cr, s + q, snr * (pp - r)) * irb;
       }
-      v[m].x = c * ca + sn * rca - (sn * cb - c * rcb);
-      v[m].y = (sn * ca - c * rca) + c * cb + sn * rcb;
+      v[m].x = fftr::ffma(c, ca, sn * rca) - fftr::ffma(sn, cb, -(c * rcb));
+      v[m].y = fftr::ffma(sn, ca, -(c * rca)) + fftr::ffma(c, cb, sn * rcb);
     }
   }
   __syncthreads();
@@ -749,6 +707,8 @@ SpatialShape spatial_shape(const Plan& P) {
   const bool use_reg = P.tune.fft_reg != 0;
   sh.rreg = (use_reg && g.has0 && fftr::has_reg_path(N1)) ? N1 : 0;
   if (sh.rreg) {
+    // register path: lines pair the time slices 2 tp, 2 tp + 1 (rows_reg.h)
+    const int rlines = reg_lines(nrows, g.n0);
     int lpb = 0, buf = 0;
     switch (N1) {
       case 64: lpb = fftr::Shape<T, 64>::LPB; buf = fftr::Shape<T, 64>::BUF; break;
@@ -756,7 +716,7 @@ SpatialShape spatial_shape(const Plan& P) {
       default: lpb = fftr::Shape<T, 256>::LPB; buf = fftr::Shape<T, 256>::BUF; break;
     }
     sh.lpb = lpb;
-    sh.rblocks = (nlines + lpb - 1) / lpb;
+    sh.rblocks = (rlines + lpb - 1) / lpb;
     sh.rthreads = fftr::Shape<T, 64>::NT;
     sh.rshm = (size_t)buf * sizeof(C2<T>);
   } else {
@@ -813,8 +773,9 @@ ColsArgs<T> cols_args(const Plan& P, const SpatialShape& sh, T* data, const doub
   return ColsArgs<T>{data, P.g, P.ax0, sh.cw, solve_ctx(P), done, sh.creg};
 }
 
+// skip_fwd: the forward row transforms were done by the fused forward pass.
 template <typename T>
-void spatial_solves(const Plan& P, T* data, hipStream_t s) {
+void spatial_solves(const Plan& P, T* data, hipStream_t s, bool skip_fwd = false) {
   const Geom& g = P.g;
   const SpatialShape sh = spatial_shape<T>(P);
   if (!g.has0) {
@@ -823,7 +784,7 @@ void spatial_solves(const Plan& P, T* data, hipStream_t s) {
                        rows_args<T>(P, sh, data, 2, P.pcg_done));
     return;
   }
-  {
+  if (!skip_fwd) {
     ProfScope ps(P, sizeof(T) == 8 ? "rows_fwd_f64" : "rows_fwd_f32", s);
     launch_rows_cls<T>(sh.rreg, dim3(sh.rblocks), dim3(sh.rthreads), sh.rshm, s,
                        rows_args<T>(P, sh, data, 0, P.pcg_done));
@@ -865,9 +826,21 @@ void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
                                      "tgemm_bf16_fwd"};
   static const char* inv_names[4] = {"tgemm_f64_inv", "tgemm_f32_inv", "tgemm_f16_inv",
                                      "tgemm_bf16_inv"};
-  tgemm<double, float>(P, mode, r, tmp, DOT_NONE, nullptr, nullptr, s, fwd_names[mode]);
-  P.rr_gate = 0;
-  spatial_solves<float>(P, tmp, s);
+  if (fused_fwd_ok(P)) {
+    static const char* fused_names[4] = {"", "tgemm_rows_f32_fwd", "tgemm_rows_f16_fwd",
+                                         "tgemm_rows_bf16_fwd"};
+    {
+      ProfScope ps(P, fused_names[mode], s);
+      launch_tgemm_rows_fwd(P, mode, r, tmp,
+                            rows_args<float>(P, spatial_shape<float>(P), tmp, 0, P.pcg_done), s);
+    }
+    P.rr_gate = 0;
+    spatial_solves<float>(P, tmp, s, true);
+  } else {
+    tgemm<double, float>(P, mode, r, tmp, DOT_NONE, nullptr, nullptr, s, fwd_names[mode]);
+    P.rr_gate = 0;
+    spatial_solves<float>(P, tmp, s);
+  }
   tgemm<float, double>(P, mode, tmp, z, dotmode, r, q, s, inv_names[mode]);
 }
 

@@ -5,6 +5,7 @@
 // the PCG scalars (summed by the kernels that consume them).
 #pragma once
 
+#include "batch_args.h"
 #include "device_util.h"
 #include "plan.h"
 
@@ -20,5 +21,15 @@ enum GemmMode { GM_F64 = 0, GM_F32 = 1, GM_F16 = 2, GM_BF16 = 3 };
 template <typename TX, typename TY>
 void tgemm(const Plan& P, int mode, const TX* X, TY* Y, int dotmode, const double* r,
            const double* q, hipStream_t s, const char* name);
+
+// The forward pass of the mixed-precision preconditioner fused: the time GEMM
+// of r (N_t <= 128) and the forward row transforms along axis 1 of length 256,
+// written to the float32 intermediate; one block per axis-0 row (all time
+// slices and all 256 nodes), the output staged through LDS. It computes the
+// bits of the separate kernels (the same operand scaling groups, row pairs and
+// transform arithmetic). Whether the plan can take it:
+bool fused_fwd_ok(const Plan& P);
+void launch_tgemm_rows_fwd(const Plan& P, int mode, const double* r, float* tmp,
+                           const RowsArgs<float>& ra, hipStream_t s);
 
 }  // namespace mfg

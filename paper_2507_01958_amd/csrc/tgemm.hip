@@ -16,6 +16,7 @@
 #include <type_traits>
 
 #include "batch_args.h"
+#include "rows_reg.h"
 #include "tgemm.h"
 
 namespace mfg {
@@ -194,84 +195,96 @@ struct LpTraits<GM_BF16> {
   static constexpr int KSTEP = 16;
 };
 
-// NTP: N_t padded to a multiple of 16 (<= 128). The block covers 4 waves x CB
-// blocks of 16 nodes and all N_t output rows.
-template <int MODE, int NTP, int CB, typename TX, typename TY, int WPB = 4>
-__device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
-  if (gemm_skip(ga, bid)) return;
+// Pieces of the low-precision time GEMM (N_t <= 128), shared by k_tgemm_lp and
+// the fused time-GEMM + row-transform kernel so both compute the same bits.
+// NTP: N_t padded to a multiple of 16 (<= 128); a wave owns CB blocks of 16
+// nodes (columns col0 + 16 cb) and all NTP output rows.
+template <int MODE, int NTP>
+struct LpShape {
   using VT = typename LpTraits<MODE>::VT;
-  const VT* __restrict__ Vg = static_cast<const VT*>(ga.V);
-  const TX* __restrict__ X = ga.X;
-  TY* __restrict__ Y = ga.Y;
-  const int nt = ga.nt, M = ga.M, dotmode = ga.dotmode;
-  const double* __restrict__ rvec = ga.rvec;
-  const double* __restrict__ qvec = ga.qvec;
-  const RedBuf rb = ga.rb;
-  constexpr int KSTEP = LpTraits<MODE>::KSTEP;
-  constexpr int NKS = NTP / KSTEP;  // k-steps
-  constexpr int NKB = NTP / 16;     // output row blocks
-  constexpr int PER = KSTEP / 4;    // operand values per lane per k-step (1 or 4)
-  constexpr bool SPLIT = MODE == GM_F32;      // hi / lo float16 terms
-  constexpr bool SCALED = MODE == GM_F16 || SPLIT;  // per-block power-of-2 operand scale
-  constexpr int VROWS = SPLIT ? 2 * NTP : NTP;
-  __shared__ __align__(16) VT Vs[VROWS * NTP];  // Vs[k * NTP + t] = V[k][t] (+ lo rows)
-  __shared__ float smax[WPB];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int kq = lane >> 4;
-  const int col0 = (bid * WPB + wave) * CB * 16 + (lane & 15);
-  // operands: t = KSTEP*ks + PER*kq + j
-  float xs[CB][NKS][PER];
+  static constexpr int KSTEP = LpTraits<MODE>::KSTEP;
+  static constexpr int NKS = NTP / KSTEP;  // k-steps
+  static constexpr int NKB = NTP / 16;     // output row blocks
+  static constexpr int PER = KSTEP / 4;    // operand values per lane per k-step (1 or 4)
+  static constexpr bool SPLIT = MODE == GM_F32;      // hi / lo float16 terms
+  static constexpr bool SCALED = MODE == GM_F16 || SPLIT;  // power-of-2 operand scale
+  static constexpr int VROWS = SPLIT ? 2 * NTP : NTP;
+};
+
+// Operands of the wave's CB tiles (t = KSTEP ks + PER kq + j); returns their
+// largest magnitude.
+template <int MODE, int NTP, int CB, typename TX>
+__device__ __forceinline__ float lp_load(const TX* __restrict__ X, int nt, int M, int col0,
+                                         int kq, float (&xs)[CB][LpShape<MODE, NTP>::NKS]
+                                                            [LpShape<MODE, NTP>::PER]) {
+  using L = LpShape<MODE, NTP>;
   float amax = 0.0f;
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb) {
     const int col = col0 + cb * 16;
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks)
+    for (int ks = 0; ks < L::NKS; ++ks)
 #pragma unroll
-      for (int j = 0; j < PER; ++j) {
-        const int t = KSTEP * ks + PER * kq + j;
+      for (int j = 0; j < L::PER; ++j) {
+        const int t = L::KSTEP * ks + L::PER * kq + j;
         const float v = (t < nt && col < M) ? (float)X[(size_t)t * M + col] : 0.0f;
         xs[cb][ks][j] = v;
         amax = fmaxf(amax, fabsf(v));
       }
   }
-  // stage V (zero-padded NTP x NTP copy, row k = V[k][.]; with SPLIT the lo
-  // rows follow) after the operand loads are in flight: a 16-byte copy
-  {
-    constexpr int NV16 = VROWS * NTP * (int)sizeof(VT) / 16;
-    const uint4* src = reinterpret_cast<const uint4*>(Vg);
-    uint4* dst = reinterpret_cast<uint4*>(Vs);
-    for (int i = threadIdx.x; i < NV16; i += WPB * 64) dst[VsLayout<NTP, VT>::chunk(i)] = src[i];
+  return amax;
+}
+
+// V (zero-padded NTP x NTP copy, row k = V[k][.]; with SPLIT the lo rows
+// follow) into LDS with 16-byte copies by nthreads threads.
+template <int MODE, int NTP>
+__device__ __forceinline__ void lp_stage_v(const typename LpShape<MODE, NTP>::VT* Vg,
+                                           typename LpShape<MODE, NTP>::VT* Vs, int nthreads) {
+  using L = LpShape<MODE, NTP>;
+  constexpr int NV16 = L::VROWS * NTP * (int)sizeof(typename L::VT) / 16;
+  const uint4* src = reinterpret_cast<const uint4*>(Vg);
+  uint4* dst = reinterpret_cast<uint4*>(Vs);
+  for (int i = threadIdx.x; i < NV16; i += nthreads)
+    dst[VsLayout<NTP, typename L::VT>::chunk(i)] = src[i];
+}
+
+// Operand scale and the output's unscale from the largest operand magnitude
+// bm of the scaling group: a power of two mapping bm to about 2^14 (float16
+// range); V's split scale is undone with it.
+template <int MODE, int NTP>
+__device__ __forceinline__ void lp_scales(float bm, float& scale, float& unscale) {
+  using L = LpShape<MODE, NTP>;
+  const float vunscale = L::SPLIT ? (float)(1.0 / kVSplitScale) : 1.0f;
+  scale = 1.0f;
+  unscale = vunscale;
+  if (L::SCALED && bm > 0.0f && __builtin_isfinite(bm)) {
+    int e;
+    frexpf(bm, &e);             // bm < 2^e
+    e = e < -100 ? -100 : e;    // keep 2^(14 - e) finite in float32
+    scale = ldexpf(1.0f, 14 - e);
+    unscale = ldexpf(1.0f, e - 14) * vunscale;
   }
-  // V's split scale is undone with the operands' scale
-  const float vunscale = SPLIT ? (float)(1.0 / kVSplitScale) : 1.0f;
-  float scale = 1.0f, unscale = vunscale;
-  if (SCALED) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
-    if (lane == 0) smax[wave] = amax;
-  }
-  __syncthreads();
-  if (SCALED) {
-    float bm = smax[0];
-#pragma unroll
-    for (int w = 1; w < WPB; ++w) bm = fmaxf(bm, smax[w]);
-    if (bm > 0.0f && __builtin_isfinite(bm)) {
-      int e;
-      frexpf(bm, &e);             // bm < 2^e
-      e = e < -100 ? -100 : e;    // keep 2^(14 - e) finite in float32
-      scale = ldexpf(1.0f, 14 - e);
-      unscale = ldexpf(1.0f, e - 14) * vunscale;
-    }
-  }
-  v4f acc[CB][NKB];
+}
+
+// The matrix-core products: acc[cb][kb] (rows 16 kb + 4 (lane / 16) + jr,
+// column lane % 16 of tile cb) = sum over t of V[row][t] x_t (scaled).
+template <int MODE, int NTP, int CB>
+__device__ __forceinline__ void lp_mma(const typename LpShape<MODE, NTP>::VT* Vs,
+                                       const float (&xs)[CB][LpShape<MODE, NTP>::NKS]
+                                                        [LpShape<MODE, NTP>::PER],
+                                       float scale, int lane,
+                                       v4f (&acc)[CB][LpShape<MODE, NTP>::NKB]) {
+  using L = LpShape<MODE, NTP>;
+  using VT = typename L::VT;
+  constexpr int KSTEP = L::KSTEP, PER = L::PER;
+  const int kq = lane >> 4;
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-    for (int kb = 0; kb < NKB; ++kb) acc[cb][kb] = (v4f){0.f, 0.f, 0.f, 0.f};
+    for (int kb = 0; kb < L::NKB; ++kb) acc[cb][kb] = (v4f){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int ks = 0; ks < NKS; ++ks) {
-    if constexpr (SPLIT) {
+  for (int ks = 0; ks < L::NKS; ++ks) {
+    if constexpr (L::SPLIT) {
       // x s = hi + lo exactly up to lo's rounding (x s is float32, hi float16)
       v4h bh[CB], bl[CB];
 #pragma unroll
@@ -284,7 +297,7 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
           bl[cb][j] = (_Float16)(xv - (float)h);
         }
 #pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) {
+      for (int kb = 0; kb < L::NKB; ++kb) {
         const int r = kb * 16 + (lane & 15), t = KSTEP * ks + PER * kq;
         const v4h ah = *reinterpret_cast<const v4h*>(&Vs[VsLayout<NTP, VT>::idx(r, t)]);
         const v4h al = *reinterpret_cast<const v4h*>(&Vs[VsLayout<NTP, VT>::idx(r + NTP, t)]);
@@ -302,7 +315,7 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) b[cb][j] = (_Float16)(xs[cb][ks][j] * scale);
 #pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) {
+      for (int kb = 0; kb < L::NKB; ++kb) {
         const v4h a = *reinterpret_cast<const v4h*>(
             &Vs[VsLayout<NTP, VT>::idx(kb * 16 + (lane & 15), KSTEP * ks + PER * kq)]);
 #pragma unroll
@@ -316,7 +329,7 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) b[cb][j] = f2bf(xs[cb][ks][j]);
 #pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) {
+      for (int kb = 0; kb < L::NKB; ++kb) {
         const v4s a = *reinterpret_cast<const v4s*>(
             &Vs[VsLayout<NTP, VT>::idx(kb * 16 + (lane & 15), KSTEP * ks + PER * kq)]);
 #pragma unroll
@@ -325,13 +338,53 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
       }
     }
   }
+}
+
+// The block covers WPB waves x CB blocks of 16 nodes and all N_t output rows;
+// the operand scale is the block's.
+template <int MODE, int NTP, int CB, typename TX, typename TY, int WPB = 4>
+__device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
+  if (gemm_skip(ga, bid)) return;
+  using L = LpShape<MODE, NTP>;
+  using VT = typename L::VT;
+  const VT* __restrict__ Vg = static_cast<const VT*>(ga.V);
+  TY* __restrict__ Y = ga.Y;
+  const int nt = ga.nt, M = ga.M, dotmode = ga.dotmode;
+  const double* __restrict__ rvec = ga.rvec;
+  const double* __restrict__ qvec = ga.qvec;
+  const RedBuf rb = ga.rb;
+  __shared__ __align__(16) VT Vs[L::VROWS * NTP];  // Vs[k * NTP + t] = V[k][t] (+ lo rows)
+  __shared__ float smax[WPB];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int kq = lane >> 4;
+  const int col0 = (bid * WPB + wave) * CB * 16 + (lane & 15);
+  float xs[CB][L::NKS][L::PER];
+  float amax = lp_load<MODE, NTP, CB>(ga.X, nt, M, col0, kq, xs);
+  // stage V after the operand loads are in flight
+  lp_stage_v<MODE, NTP>(Vg, Vs, WPB * 64);
+  if (L::SCALED) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
+    if (lane == 0) smax[wave] = amax;
+  }
+  __syncthreads();
+  float bm = 0.0f;
+  if (L::SCALED) {
+    bm = smax[0];
+#pragma unroll
+    for (int w = 1; w < WPB; ++w) bm = fmaxf(bm, smax[w]);
+  }
+  float scale, unscale;
+  lp_scales<MODE, NTP>(bm, scale, unscale);
+  v4f acc[CB][L::NKB];
+  lp_mma<MODE, NTP, CB>(Vs, xs, scale, lane, acc);
   double dots[2] = {0.0, 0.0};
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb) {
     const int col = col0 + cb * 16;
     if (col >= M) continue;
 #pragma unroll
-    for (int kb = 0; kb < NKB; ++kb)
+    for (int kb = 0; kb < L::NKB; ++kb)
 #pragma unroll
       for (int jr = 0; jr < 4; ++jr) {
         // float32-accumulating 16x16 results: register jr of lane l holds row
@@ -354,6 +407,93 @@ __device__ void tgemm_lp_body(const GemmArgs<TX, TY>& ga, int bid) {
 template <int MODE, int NTP, int CB, typename TX, typename TY, int WPB>
 __global__ __launch_bounds__(WPB * 64) void k_tgemm_lp(GemmArgs<TX, TY> a) {
   tgemm_lp_body<MODE, NTP, CB, TX, TY, WPB>(a, blockIdx.x);
+}
+
+// Fused forward pass (time GEMM + row transforms along axis 1, N = 256): the
+// block owns axis-0 row bid, all 256 nodes (8 waves x 2 tiles of 16) and all
+// time slices. The operands are scaled per group of gwaves waves, the columns
+// the separate GEMM's blocks cover. After the products, the output passes
+// through LDS in halves of 64 time slices, where 32 lines at a time (slices
+// 2 tp, 2 tp + 1) take the row transform, written to the intermediate.
+constexpr int kFusedThreads = 512;
+constexpr int kFusedN = 256;
+
+template <int MODE, int NTP>
+__global__ __launch_bounds__(kFusedThreads) void k_tgemm_rows_fwd(GemmArgs<double, float> ga,
+                                                                  RowsArgs<float> ra, int gwaves) {
+  const int bid = blockIdx.x;
+  if (gemm_skip(ga, bid)) return;
+  using L = LpShape<MODE, NTP>;
+  using VT = typename L::VT;
+  using Sh = fftr::Shape<float, kFusedN>;
+  constexpr int CB = 2, WAVES = kFusedThreads / 64;
+  static_assert(WAVES * CB * 16 == kFusedN, "a block covers one row of 256 nodes");
+  constexpr int HALF = 64;                                // time slices per row-transform pass
+  constexpr int TILE_BYTES = HALF * kFusedN * 4;
+  constexpr int VS_BYTES = L::VROWS * NTP * (int)sizeof(VT);
+  constexpr int A_BYTES = TILE_BYTES > VS_BYTES ? TILE_BYTES : VS_BYTES;
+  constexpr int LINES = kFusedThreads / Sh::N2;           // lines per pass (= HALF / 2)
+  static_assert(LINES * 2 == HALF, "one pass transforms the half tile");
+  constexpr int SCR = LINES * (Sh::L > Sh::L2 ? Sh::L : Sh::L2);
+  __shared__ __align__(16) unsigned char smem[A_BYTES + SCR * sizeof(C2<float>)];
+  __shared__ float smax[WAVES];
+  VT* Vs = reinterpret_cast<VT*>(smem);              // V during the products,
+  float* tile = reinterpret_cast<float*>(smem);      // then the output half tile
+  C2<float>* scr = reinterpret_cast<C2<float>*>(smem + A_BYTES);
+  const int nt = ga.nt, M = ga.M;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, kq = lane >> 4;
+  const int i0 = bid;
+  const int col0 = i0 * kFusedN + wave * CB * 16 + (lane & 15);
+  float xs[CB][L::NKS][L::PER];
+  float amax = lp_load<MODE, NTP, CB>(ga.X, nt, M, col0, kq, xs);
+  lp_stage_v<MODE, NTP>(static_cast<const VT*>(ga.V), Vs, kFusedThreads);
+  if (L::SCALED) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
+    if (lane == 0) smax[wave] = amax;
+  }
+  __syncthreads();
+  float bm = 0.0f;
+  if (L::SCALED) {
+    const int g0 = (wave / gwaves) * gwaves;
+    bm = smax[g0];
+    for (int w = 1; w < gwaves; ++w) bm = fmaxf(bm, smax[g0 + w]);
+  }
+  float scale, unscale;
+  lp_scales<MODE, NTP>(bm, scale, unscale);
+  v4f acc[CB][L::NKB];
+  lp_mma<MODE, NTP, CB>(Vs, xs, scale, lane, acc);
+  __syncthreads();  // V is no longer read: its LDS takes the output tile
+  const bool dct = ra.ax.kind == 1;
+  const float* __restrict__ tw = tw_table<float>(ra.ax);
+  const float* __restrict__ ct = ct_table<float>(ra.ax);
+  float* __restrict__ out = ra.data;
+  const int l = threadIdx.x / Sh::N2, p = threadIdx.x % Sh::N2;
+#pragma unroll
+  for (int h = 0; h * HALF < NTP; ++h) {
+    // output rows t in [h HALF, (h + 1) HALF) into the tile
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int kb = h * (HALF / 16); kb < (h + 1) * (HALF / 16) && kb < L::NKB; ++kb)
+#pragma unroll
+        for (int jr = 0; jr < 4; ++jr) {
+          const int tl = kb * 16 + 4 * kq + jr - h * HALF;
+          tile[tl * kFusedN + wave * CB * 16 + cb * 16 + (lane & 15)] = acc[cb][kb][jr] * unscale;
+        }
+    __syncthreads();
+    // rows of slices 2 tp and 2 tp + 1 (tile rows 2 l, 2 l + 1)
+    const RowPair rp = row_pair((h * LINES + l) * ra.n0 + i0, ra.nrows, ra.n0);
+    const float* ta = tile + (2 * l) * kFusedN;
+    const float* tb = ta + kFusedN;
+    auto ld = [&](int n) { return C2<float>{rp.hasa ? ta[n] : 0.0f, rp.hasb ? tb[n] : 0.0f}; };
+    auto st = [&](int k, float oa, float ob) {
+      if (rp.hasa) out[(unsigned)rp.ra * kFusedN + k] = oa;  // n < 2^31
+      if (rp.hasb) out[(unsigned)rp.rb * kFusedN + k] = ob;
+    };
+    rows_fwd_line<float, kFusedN>(ld, st, dct, scr + l * Sh::L, scr + l * Sh::L2, p, tw, ct);
+    __syncthreads();
+  }
 }
 
 template <int MODE, int NTP, int CB, typename TX, typename TY, int WPB>
@@ -981,6 +1121,40 @@ template void tgemm<double, float>(const Plan&, int, const double*, float*, int,
                                     const double*, const double*, hipStream_t, const char*);
 template void tgemm<float, double>(const Plan&, int, const float*, double*, int,
                                     const double*, const double*, hipStream_t, const char*);
+
+bool fused_fwd_ok(const Plan& P) {
+  return P.tune.fuse_fwd && P.precision != MFG_FP64 && P.g.has0 && P.g.n1 == kFusedN &&
+         P.tune.fft_reg && P.ntp > 0 && !P.tune.tgemm_pers;
+}
+
+template <int MODE>
+void fused_dispatch(const Plan& P, const GemmArgs<double, float>& ga, const RowsArgs<float>& ra,
+                    int gwaves, hipStream_t s) {
+  const dim3 g(P.g.n0), b(kFusedThreads);
+  switch (P.ntp) {
+    case 16: hipLaunchKernelGGL((k_tgemm_rows_fwd<MODE, 16>), g, b, 0, s, ga, ra, gwaves); break;
+    case 32: hipLaunchKernelGGL((k_tgemm_rows_fwd<MODE, 32>), g, b, 0, s, ga, ra, gwaves); break;
+    case 48: hipLaunchKernelGGL((k_tgemm_rows_fwd<MODE, 48>), g, b, 0, s, ga, ra, gwaves); break;
+    case 64: hipLaunchKernelGGL((k_tgemm_rows_fwd<MODE, 64>), g, b, 0, s, ga, ra, gwaves); break;
+    case 80: hipLaunchKernelGGL((k_tgemm_rows_fwd<MODE, 80>), g, b, 0, s, ga, ra, gwaves); break;
+    case 96: hipLaunchKernelGGL((k_tgemm_rows_fwd<MODE, 96>), g, b, 0, s, ga, ra, gwaves); break;
+    case 112: hipLaunchKernelGGL((k_tgemm_rows_fwd<MODE, 112>), g, b, 0, s, ga, ra, gwaves); break;
+    default: hipLaunchKernelGGL((k_tgemm_rows_fwd<MODE, 128>), g, b, 0, s, ga, ra, gwaves);
+  }
+}
+
+void launch_tgemm_rows_fwd(const Plan& P, int mode, const double* r, float* tmp,
+                           const RowsArgs<float>& ra, hipStream_t s) {
+  // operands scaled in the separate forward GEMM's groups: lp_waves x lp_cb
+  // tiles of 16 nodes, i.e. that many 32-node waves of this kernel
+  const int gwaves = (P.tune.lp_waves == 8 ? 8 : 4) * (P.tune.lp_cb == 1 ? 1 : 2) / 2;
+  const GemmArgs<double, float> ga{lp_table(P, mode), r,       tmp,   P.g.nt,     P.g.M, 0,
+                                   DOT_NONE,          nullptr, nullptr, P.red, P.pcg_done,
+                                   P.rr_gate};
+  if (mode == GM_F32) fused_dispatch<GM_F32>(P, ga, ra, gwaves, s);
+  else if (mode == GM_F16) fused_dispatch<GM_F16>(P, ga, ra, gwaves, s);
+  else fused_dispatch<GM_BF16>(P, ga, ra, gwaves, s);
+}
 
 // ---- batched low-precision time GEMM (one N_t padding class per launch) ----
 template <typename TX, typename TY>

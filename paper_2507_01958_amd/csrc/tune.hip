@@ -146,6 +146,7 @@ void keep_untuned(const Tune& from, Tune& to) {
   to.flex = from.flex;
   to.lp_stream = from.lp_stream;
   to.rhs_tc = from.rhs_tc;
+  to.fuse_fwd = from.fuse_fwd;
 }
 
 // allow_pers = false keeps the time GEMM in the form the batched launches use.

@@ -1,0 +1,67 @@
+"""The fused forward preconditioner pass against the separate kernels.
+
+With the mixed precisions, axis 1 of 256 nodes and N_t <= 128, the time GEMM
+of the residual and the forward row transforms of Algorithm 2 run as one
+kernel (MFG_TUNE fuse_fwd=1, the default); fuse_fwd=0 keeps the separate time
+GEMM and row-transform kernels, which the operator parity tests check against
+the oracle. The fused kernel scales its operands in the same column groups,
+pairs the same rows and runs the same transform arithmetic, so both give the
+same bits: checked on P^{-1} r and on whole PCG solves (where the forward pass
+also takes the r.r stopping test) for every mixed precision, both boundary
+conditions, several N_t (ragged time padding) and operand-scaling group
+widths.
+"""
+import numpy as np
+import pytest
+
+from _gpu import dev, empty, host, plan_of, say
+from paper_2507_01958_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+PRECISIONS = ["mixed_fp32", "mixed_fp16", "mixed_bf16"]
+
+
+def _run(monkeypatch, tune, inst, precision, r, b):
+    monkeypatch.setenv("MFG_TUNE", tune)
+    with plan_of(inst, precision) as P:
+        z = empty(r.size)
+        from paper_2507_01958_amd import mfg
+        mfg.mfg_precond(P, dev(r), z)
+        u = empty(r.size)
+        st = mfg.mfg_pcg(P, dev(b), u, 1e-9, 60, raise_not_converged=False)
+        return host(z), host(u), st
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("bc", ["periodic", "neumann"])
+@pytest.mark.parametrize("nx,nt", [(6, 5), (8, 70), (4, 128)])
+def test_fused_forward_bitwise(monkeypatch, precision, bc, nx, nt):
+    inst = wl.small_instance(71, 2, nx, 256, nt, bc, 0.1)
+    n = nt * nx * 256
+    rng = np.random.default_rng(72 + nt)
+    r = rng.standard_normal(n) * np.exp(rng.uniform(-3, 3, n))
+    b = rng.standard_normal(n)
+    say(f"fused fwd {precision} {bc} {nx}x256x{nt}")
+    z0, u0, s0 = _run(monkeypatch, "fuse_fwd=0", inst, precision, r, b)
+    z1, u1, s1 = _run(monkeypatch, "fuse_fwd=1", inst, precision, r, b)
+    assert np.array_equal(z0, z1), np.abs(z0 - z1).max()
+    assert np.array_equal(u0, u1), np.abs(u0 - u1).max()
+    assert s0 == s1
+
+
+@pytest.mark.parametrize("shape", ["lp_waves=4,lp_cb=1", "lp_waves=8,lp_cb=1",
+                                   "lp_waves=8,lp_cb=2"])
+def test_fused_forward_scale_groups(monkeypatch, shape):
+    # operand scale groups of 64, 128 and 256 columns; the operand magnitudes
+    # vary by column so that groups get different scales
+    inst = wl.small_instance(73, 2, 4, 256, 37, "neumann", 0.1)
+    n = 37 * 4 * 256
+    rng = np.random.default_rng(74)
+    r = rng.standard_normal(n) * np.exp(rng.uniform(-8, 8, n))
+    b = rng.standard_normal(n)
+    say(f"fused fwd groups {shape}")
+    z0, u0, _ = _run(monkeypatch, shape + ",fuse_fwd=0", inst, "mixed_fp32", r, b)
+    z1, u1, _ = _run(monkeypatch, shape + ",fuse_fwd=1", inst, "mixed_fp32", r, b)
+    assert np.array_equal(z0, z1), np.abs(z0 - z1).max()
+    assert np.array_equal(u0, u1), np.abs(u0 - u1).max()
