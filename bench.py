@@ -86,6 +86,10 @@ def algorithmic(kernel, inst, variant, its=1.0, steps=1):
         "cp_init": 3 * nb * 8 * n,
         "adj_prox": (4 * nb + 1) * 8 * n,        # read gy, gybar, v, gxi; write gy, gxi, gV
     }
+    if kernel.startswith("update_tgemm_rows_"):
+        # the update and the forward preconditioner pass in one launch: the
+        # update's bytes, then the float32 intermediate written
+        return "hbm", upd * 8 * n + 4 * n, None
     if kernel.startswith("tgemm_") and kernel.endswith("_fwd"):
         return "hbm", (8 + 4) * n, None          # read r (f64), write f32
     if kernel.startswith("tgemm_") and kernel.endswith("_inv"):

@@ -175,6 +175,7 @@ static void read_tune_env(Tune& t) {
       else if (k == "lp_stream" && (v == 0 || v == 1)) t.lp_stream = v;
       else if (k == "rhs_tc" && v >= 0 && v <= 64) t.rhs_tc = v;
       else if (k == "fuse_fwd" && (v == 0 || v == 1)) t.fuse_fwd = v;
+      else if (k == "fuse_upd" && (v == 0 || v == 1)) t.fuse_upd = v;
     }
     pos = end + 1;
   }

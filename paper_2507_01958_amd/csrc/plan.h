@@ -39,6 +39,9 @@ struct Tune {
   // forward preconditioner pass fused (time GEMM + row transforms) where it
   // applies (mixed modes, axis 1 of 256 nodes, N_t <= 128); 0: separate kernels
   int fuse_fwd = 1;
+  // inside PCG, the update (x += alpha p, r -= alpha q) runs in the fused
+  // forward pass too; 0: its own kernel
+  int fuse_upd = 1;
 };
 
 // Optional per-kernel timing with HIP events recorded on the plan's stream

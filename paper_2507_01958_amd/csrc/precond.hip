@@ -801,6 +801,24 @@ void spatial_solves(const Plan& P, T* data, hipStream_t s, bool skip_fwd = false
 
 }  // namespace
 
+namespace {
+
+int mixed_mode(const Plan& P) {
+  return P.precision == MFG_MIXED_FP32 ? GM_F32
+         : (P.precision == MFG_MIXED_FP16 ? GM_F16 : GM_BF16);
+}
+
+const char* const kFwdNames[4] = {"tgemm_f64_fwd", "tgemm_f32_fwd", "tgemm_f16_fwd",
+                                  "tgemm_bf16_fwd"};
+const char* const kInvNames[4] = {"tgemm_f64_inv", "tgemm_f32_inv", "tgemm_f16_inv",
+                                  "tgemm_bf16_inv"};
+const char* const kFusedNames[4] = {"", "tgemm_rows_f32_fwd", "tgemm_rows_f16_fwd",
+                                    "tgemm_rows_bf16_fwd"};
+const char* const kUpdFusedNames[4] = {"", "update_tgemm_rows_f32_fwd",
+                                       "update_tgemm_rows_f16_fwd", "update_tgemm_rows_bf16_fwd"};
+
+}  // namespace
+
 void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
                     const double* q, hipStream_t s) {
   int dotmode = DOT_NONE;
@@ -819,38 +837,54 @@ void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
   }
   // mixed: float32 intermediate and spatial solves; time transform in the
   // plan's matrix-core precision
-  const int mode = P.precision == MFG_MIXED_FP32 ? GM_F32
-                   : (P.precision == MFG_MIXED_FP16 ? GM_F16 : GM_BF16);
+  const int mode = mixed_mode(P);
   float* tmp = reinterpret_cast<float*>(P.tmp);
-  static const char* fwd_names[4] = {"tgemm_f64_fwd", "tgemm_f32_fwd", "tgemm_f16_fwd",
-                                     "tgemm_bf16_fwd"};
-  static const char* inv_names[4] = {"tgemm_f64_inv", "tgemm_f32_inv", "tgemm_f16_inv",
-                                     "tgemm_bf16_inv"};
   if (fused_fwd_ok(P)) {
-    static const char* fused_names[4] = {"", "tgemm_rows_f32_fwd", "tgemm_rows_f16_fwd",
-                                         "tgemm_rows_bf16_fwd"};
     {
-      ProfScope ps(P, fused_names[mode], s);
+      ProfScope ps(P, kFusedNames[mode], s);
       launch_tgemm_rows_fwd(P, mode, r, tmp,
-                            rows_args<float>(P, spatial_shape<float>(P), tmp, 0, P.pcg_done), s);
+                            rows_args<float>(P, spatial_shape<float>(P), tmp, 0, P.pcg_done),
+                            nullptr, s);
     }
     P.rr_gate = 0;
     spatial_solves<float>(P, tmp, s, true);
   } else {
-    tgemm<double, float>(P, mode, r, tmp, DOT_NONE, nullptr, nullptr, s, fwd_names[mode]);
+    tgemm<double, float>(P, mode, r, tmp, DOT_NONE, nullptr, nullptr, s, kFwdNames[mode]);
     P.rr_gate = 0;
     spatial_solves<float>(P, tmp, s);
   }
-  tgemm<float, double>(P, mode, tmp, z, dotmode, r, q, s, inv_names[mode]);
+  tgemm<float, double>(P, mode, tmp, z, dotmode, r, q, s, kInvNames[mode]);
 }
 
 // One PCG iteration's update and preconditioning: x += alpha p, r -= alpha q
 // (r.r partials), then z = P^{-1} r (r.r stopping test first) with the fused
-// r.z (and z.q) partials.
+// r.z (and z.q) partials. Where the fused forward pass applies, the update
+// runs inside it and the stopping test moves to the inverse time transform
+// (the spatial solves of the last iteration run before it sets the flag; their
+// output is not used).
 void launch_update_precond(const Plan& P, double* x, double* r, const double* p,
                            const double* q, double* z, bool first, hipStream_t s) {
-  launch_update(P, x, r, p, q, first, s);
-  launch_precond(P, r, z, true, q, s);
+  if (!(P.tune.fuse_upd && P.pcg_done && fused_fwd_ok(P))) {
+    launch_update(P, x, r, p, q, first, s);
+    launch_precond(P, r, z, true, q, s);
+    return;
+  }
+  const int mode = mixed_mode(P);
+  float* tmp = reinterpret_cast<float*>(P.tmp);
+  const UpdArgs ua = update_args(P, x, r, p, q, first);
+  {
+    ProfScope ps(P, kUpdFusedNames[mode], s);
+    launch_tgemm_rows_fwd(P, mode, r, tmp,
+                          rows_args<float>(P, spatial_shape<float>(P), tmp, 0, P.pcg_done), &ua,
+                          s);
+  }
+  P.rr_blocks = P.g.n0;  // one r.r partial per block (axis-0 row)
+  P.rr_gate = 0;
+  spatial_solves<float>(P, tmp, s, true);
+  P.rr_gate = P.rr_blocks;
+  tgemm<float, double>(P, mode, tmp, z, pcg_flexible(P) ? DOT_FLEX : DOT_STD, r, q, s,
+                       kInvNames[mode]);
+  P.rr_gate = 0;
 }
 
 // ---- batched spatial solves (float32 data in the mixed modes, float64 in FP64) ----

@@ -55,21 +55,28 @@ __host__ __device__ inline int reg_lines(int nrows, int n0) {
 
 // Forward real transform of one line along the contiguous axis: the DHT
 // (periodic) or DCT-II (Neumann, input read in Makhoul order), spectra in
-// natural order. ld(n) returns the two rows' elements n as a complex value
-// (row a real part, row b imaginary part); st(k, a, b) stores their spectra
-// at k. lds: the line's exchange area of fft4; zb: its pairing buffer
-// (Shape::L2 elements). Called by every thread of the block.
-template <typename T, int N, class LD, class ST>
-__device__ __forceinline__ void rows_fwd_line(LD ld, ST st, bool dct, C2<T>* lds, C2<T>* zb,
-                                              int p, const T* __restrict__ tw,
-                                              const T* __restrict__ ct) {
+// natural order. Split in two so a caller can synchronise between them (and
+// reuse the loads' source as the exchange area): rows_fwd_load takes the
+// thread's 16 inputs, ld(n) returning the two rows' elements n as a complex
+// value (row a real part, row b imaginary part); rows_fwd_xform transforms
+// them and calls st(k, a, b) with the two rows' spectra at k. lds: the line's
+// exchange area of fft4; zb: its pairing buffer (Shape::L2 elements). Called by
+// every thread of the block.
+template <typename T, int N, class LD>
+__device__ __forceinline__ void rows_fwd_load(LD ld, bool dct, int p, C2<T> (&v)[16]) {
   using Sh = fftr::Shape<T, N>;
-  C2<T> v[16];
 #pragma unroll
   for (int n1 = 0; n1 < 16; ++n1) {
     const int n = p + Sh::N2 * n1;
     v[n1] = ld(dct ? dct_perm(n, N) : n);
   }
+}
+
+template <typename T, int N, class ST>
+__device__ __forceinline__ void rows_fwd_xform(C2<T> (&v)[16], ST st, bool dct, C2<T>* lds,
+                                               C2<T>* zb, int p, const T* __restrict__ tw,
+                                               const T* __restrict__ ct) {
+  using Sh = fftr::Shape<T, N>;
   fftr::fft4<T, N, -1>(v, lds, p, tw);
   __syncthreads();
 #pragma unroll
@@ -92,6 +99,15 @@ __device__ __forceinline__ void rows_fwd_line(LD ld, ST st, bool dct, C2<T>* lds
     }
     st(k, oa, ob);
   }
+}
+
+template <typename T, int N, class LD, class ST>
+__device__ __forceinline__ void rows_fwd_line(LD ld, ST st, bool dct, C2<T>* lds, C2<T>* zb,
+                                              int p, const T* __restrict__ tw,
+                                              const T* __restrict__ ct) {
+  C2<T> v[16];
+  rows_fwd_load<T, N>(ld, dct, p, v);
+  rows_fwd_xform<T, N>(v, st, dct, lds, zb, p, tw, ct);
 }
 
 }  // namespace mfg

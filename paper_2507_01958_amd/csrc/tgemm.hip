@@ -16,6 +16,7 @@
 #include <type_traits>
 
 #include "batch_args.h"
+#include "pcg_update.h"
 #include "rows_reg.h"
 #include "tgemm.h"
 
@@ -409,44 +410,100 @@ __global__ __launch_bounds__(WPB * 64) void k_tgemm_lp(GemmArgs<TX, TY> a) {
   tgemm_lp_body<MODE, NTP, CB, TX, TY, WPB>(a, blockIdx.x);
 }
 
-// Fused forward pass (time GEMM + row transforms along axis 1, N = 256): the
-// block owns axis-0 row bid, all 256 nodes (8 waves x 2 tiles of 16) and all
-// time slices. The operands are scaled per group of gwaves waves, the columns
-// the separate GEMM's blocks cover. After the products, the output passes
-// through LDS in halves of 64 time slices, where 32 lines at a time (slices
-// 2 tp, 2 tp + 1) take the row transform, written to the intermediate.
-constexpr int kFusedThreads = 512;
-constexpr int kFusedN = 256;
+// The conjugate gradient update of the wave's tiles (x += alpha p, r -= alpha q,
+// the same multiply-adds as the update kernel), adding r.r to rr; the new r
+// values are the GEMM operands (as lp_load reads them). Returns their largest
+// magnitude.
+template <int MODE, int NTP, int CB>
+__device__ __forceinline__ float upd_load(const UpdArgs& a, double alpha, int nt, int M, int col0,
+                                          int kq, float (&xs)[CB][LpShape<MODE, NTP>::NKS]
+                                                             [LpShape<MODE, NTP>::PER],
+                                          double& rr) {
+  using L = LpShape<MODE, NTP>;
+  double* __restrict__ x = a.x;
+  double* __restrict__ r = a.r;
+  const double* __restrict__ p = a.p;
+  const double* __restrict__ q = a.q;
+  const bool first = a.first;
+  float amax = 0.0f;
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    const int col = col0 + cb * 16;
+#pragma unroll
+    for (int ks = 0; ks < L::NKS; ++ks)
+#pragma unroll
+      for (int j = 0; j < L::PER; ++j) {
+        const int t = L::KSTEP * ks + L::PER * kq + j;
+        float v = 0.0f;
+        if (t < nt && col < M) {
+          const size_t i = (size_t)t * M + col;
+          const double pv = p[i], qv = q[i], rv = r[i];
+          x[i] = first ? alpha * pv : __builtin_fma(alpha, pv, x[i]);
+          const double ri = __builtin_fma(-alpha, qv, rv);
+          r[i] = ri;
+          rr += ri * ri;
+          v = (float)ri;
+        }
+        xs[cb][ks][j] = v;
+        amax = fmaxf(amax, fabsf(v));
+      }
+  }
+  return amax;
+}
 
-template <int MODE, int NTP>
+// Fused forward pass (time GEMM + row transforms along axis 1, N = 256): the
+// block owns axis-0 row bid, all 256 nodes (16 waves x one tile of 16) and all
+// time slices. The operands are scaled per group of gwaves waves, the columns
+// the separate GEMM's blocks cover. The output goes to LDS (rows padded to
+// 272 floats: the four row groups of an accumulator store fall in distinct
+// banks); each of the 64 lines (slices 2 tp, 2 tp + 1) loads its two rows,
+// and after a barrier the same LDS serves the row transforms' exchanges.
+constexpr int kFusedThreads = 1024;
+constexpr int kFusedN = 256;
+constexpr int kFusedStride = kFusedN + 16;
+
+// UPD: the block first applies the conjugate gradient update to its columns
+// (ua; x, r and the r.r partials are written as by the update kernel) and
+// takes the new r as the GEMM operand.
+template <int MODE, int NTP, bool UPD>
 __global__ __launch_bounds__(kFusedThreads) void k_tgemm_rows_fwd(GemmArgs<double, float> ga,
-                                                                  RowsArgs<float> ra, int gwaves) {
+                                                                  RowsArgs<float> ra, UpdArgs ua,
+                                                                  int gwaves) {
   const int bid = blockIdx.x;
   if (gemm_skip(ga, bid)) return;
   using L = LpShape<MODE, NTP>;
   using VT = typename L::VT;
   using Sh = fftr::Shape<float, kFusedN>;
-  constexpr int CB = 2, WAVES = kFusedThreads / 64;
+  constexpr int CB = 1, WAVES = kFusedThreads / 64;
   static_assert(WAVES * CB * 16 == kFusedN, "a block covers one row of 256 nodes");
-  constexpr int HALF = 64;                                // time slices per row-transform pass
-  constexpr int TILE_BYTES = HALF * kFusedN * 4;
+  constexpr int LINES = kFusedThreads / Sh::N2;  // 64 lines: up to 128 time slices
+  static_assert(2 * LINES >= 128, "one pass transforms every time slice");
+  constexpr int TILE_BYTES = NTP * kFusedStride * 4;
   constexpr int VS_BYTES = L::VROWS * NTP * (int)sizeof(VT);
-  constexpr int A_BYTES = TILE_BYTES > VS_BYTES ? TILE_BYTES : VS_BYTES;
-  constexpr int LINES = kFusedThreads / Sh::N2;           // lines per pass (= HALF / 2)
-  static_assert(LINES * 2 == HALF, "one pass transforms the half tile");
-  constexpr int SCR = LINES * (Sh::L > Sh::L2 ? Sh::L : Sh::L2);
-  __shared__ __align__(16) unsigned char smem[A_BYTES + SCR * sizeof(C2<float>)];
+  constexpr int SCR_BYTES = LINES * (Sh::L > Sh::L2 ? Sh::L : Sh::L2) * (int)sizeof(C2<float>);
+  constexpr int A1 = TILE_BYTES > VS_BYTES ? TILE_BYTES : VS_BYTES;
+  constexpr int A_BYTES = A1 > SCR_BYTES ? A1 : SCR_BYTES;
+  __shared__ __align__(16) unsigned char smem[A_BYTES];
   __shared__ float smax[WAVES];
   VT* Vs = reinterpret_cast<VT*>(smem);              // V during the products,
-  float* tile = reinterpret_cast<float*>(smem);      // then the output half tile
-  C2<float>* scr = reinterpret_cast<C2<float>*>(smem + A_BYTES);
+  float* tile = reinterpret_cast<float*>(smem);      // then the output tile,
+  C2<float>* scr = reinterpret_cast<C2<float>*>(smem);  // then the exchange areas
   const int nt = ga.nt, M = ga.M;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, kq = lane >> 4;
   const int i0 = bid;
-  const int col0 = i0 * kFusedN + wave * CB * 16 + (lane & 15);
+  const int col0 = i0 * kFusedN + wave * 16 + (lane & 15);
   float xs[CB][L::NKS][L::PER];
-  float amax = lp_load<MODE, NTP, CB>(ga.X, nt, M, col0, kq, xs);
-  lp_stage_v<MODE, NTP>(static_cast<const VT*>(ga.V), Vs, kFusedThreads);
+  float amax;
+  if constexpr (UPD) {
+    const double alpha = pcg_alpha(ua, bid);
+    double rr[1] = {0.0};
+    amax = upd_load<MODE, NTP, CB>(ua, alpha, nt, M, col0, kq, xs, rr[0]);
+    lp_stage_v<MODE, NTP>(static_cast<const VT*>(ga.V), Vs, kFusedThreads);
+    reduce_store<1>(rr, ua.rb, T_RR, bid);
+  } else {
+    amax = lp_load<MODE, NTP, CB>(ga.X, nt, M, col0, kq, xs);
+    lp_stage_v<MODE, NTP>(static_cast<const VT*>(ga.V), Vs, kFusedThreads);
+  }
   if (L::SCALED) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
@@ -464,36 +521,32 @@ __global__ __launch_bounds__(kFusedThreads) void k_tgemm_rows_fwd(GemmArgs<doubl
   v4f acc[CB][L::NKB];
   lp_mma<MODE, NTP, CB>(Vs, xs, scale, lane, acc);
   __syncthreads();  // V is no longer read: its LDS takes the output tile
+#pragma unroll
+  for (int kb = 0; kb < L::NKB; ++kb)
+#pragma unroll
+    for (int jr = 0; jr < 4; ++jr)
+      tile[(kb * 16 + 4 * kq + jr) * kFusedStride + wave * 16 + (lane & 15)] =
+          acc[0][kb][jr] * unscale;
+  __syncthreads();
   const bool dct = ra.ax.kind == 1;
-  const float* __restrict__ tw = tw_table<float>(ra.ax);
-  const float* __restrict__ ct = ct_table<float>(ra.ax);
-  float* __restrict__ out = ra.data;
   const int l = threadIdx.x / Sh::N2, p = threadIdx.x % Sh::N2;
-#pragma unroll
-  for (int h = 0; h * HALF < NTP; ++h) {
-    // output rows t in [h HALF, (h + 1) HALF) into the tile
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-      for (int kb = h * (HALF / 16); kb < (h + 1) * (HALF / 16) && kb < L::NKB; ++kb)
-#pragma unroll
-        for (int jr = 0; jr < 4; ++jr) {
-          const int tl = kb * 16 + 4 * kq + jr - h * HALF;
-          tile[tl * kFusedN + wave * CB * 16 + cb * 16 + (lane & 15)] = acc[cb][kb][jr] * unscale;
-        }
-    __syncthreads();
-    // rows of slices 2 tp and 2 tp + 1 (tile rows 2 l, 2 l + 1)
-    const RowPair rp = row_pair((h * LINES + l) * ra.n0 + i0, ra.nrows, ra.n0);
-    const float* ta = tile + (2 * l) * kFusedN;
-    const float* tb = ta + kFusedN;
-    auto ld = [&](int n) { return C2<float>{rp.hasa ? ta[n] : 0.0f, rp.hasb ? tb[n] : 0.0f}; };
-    auto st = [&](int k, float oa, float ob) {
-      if (rp.hasa) out[(unsigned)rp.ra * kFusedN + k] = oa;  // n < 2^31
-      if (rp.hasb) out[(unsigned)rp.rb * kFusedN + k] = ob;
-    };
-    rows_fwd_line<float, kFusedN>(ld, st, dct, scr + l * Sh::L, scr + l * Sh::L2, p, tw, ct);
-    __syncthreads();
-  }
+  // rows of slices 2 l and 2 l + 1 (tile rows 2 l, 2 l + 1)
+  const RowPair rp = row_pair(l * ra.n0 + i0, ra.nrows, ra.n0);
+  const float* ta = tile + (2 * l) * kFusedStride;
+  const float* tb = ta + kFusedStride;
+  C2<float> v[16];
+  rows_fwd_load<float, kFusedN>(
+      [&](int n) { return C2<float>{rp.hasa ? ta[n] : 0.0f, rp.hasb ? tb[n] : 0.0f}; }, dct, p,
+      v);
+  __syncthreads();  // the tile is read: its LDS takes the exchange areas
+  float* __restrict__ out = ra.data;
+  rows_fwd_xform<float, kFusedN>(
+      v,
+      [&](int k, float oa, float ob) {
+        if (rp.hasa) out[(unsigned)rp.ra * kFusedN + k] = oa;  // n < 2^31
+        if (rp.hasb) out[(unsigned)rp.rb * kFusedN + k] = ob;
+      },
+      dct, scr + l * Sh::L, scr + l * Sh::L2, p, tw_table<float>(ra.ax), ct_table<float>(ra.ax));
 }
 
 template <int MODE, int NTP, int CB, typename TX, typename TY, int WPB>
@@ -1127,33 +1180,46 @@ bool fused_fwd_ok(const Plan& P) {
          P.tune.fft_reg && P.ntp > 0 && !P.tune.tgemm_pers;
 }
 
-template <int MODE>
+template <int MODE, bool UPD>
 void fused_dispatch(const Plan& P, const GemmArgs<double, float>& ga, const RowsArgs<float>& ra,
-                    int gwaves, hipStream_t s) {
+                    const UpdArgs& ua, int gwaves, hipStream_t s) {
   const dim3 g(P.g.n0), b(kFusedThreads);
+#define MFG_FUSED(NTPV)                                                                  \
+  case NTPV:                                                                             \
+    hipLaunchKernelGGL((k_tgemm_rows_fwd<MODE, NTPV, UPD>), g, b, 0, s, ga, ra, ua, gwaves); \
+    break;
   switch (P.ntp) {
-    case 16: hipLaunchKernelGGL((k_tgemm_rows_fwd<MODE, 16>), g, b, 0, s, ga, ra, gwaves); break;
-    case 32: hipLaunchKernelGGL((k_tgemm_rows_fwd<MODE, 32>), g, b, 0, s, ga, ra, gwaves); break;
-    case 48: hipLaunchKernelGGL((k_tgemm_rows_fwd<MODE, 48>), g, b, 0, s, ga, ra, gwaves); break;
-    case 64: hipLaunchKernelGGL((k_tgemm_rows_fwd<MODE, 64>), g, b, 0, s, ga, ra, gwaves); break;
-    case 80: hipLaunchKernelGGL((k_tgemm_rows_fwd<MODE, 80>), g, b, 0, s, ga, ra, gwaves); break;
-    case 96: hipLaunchKernelGGL((k_tgemm_rows_fwd<MODE, 96>), g, b, 0, s, ga, ra, gwaves); break;
-    case 112: hipLaunchKernelGGL((k_tgemm_rows_fwd<MODE, 112>), g, b, 0, s, ga, ra, gwaves); break;
-    default: hipLaunchKernelGGL((k_tgemm_rows_fwd<MODE, 128>), g, b, 0, s, ga, ra, gwaves);
+    MFG_FUSED(16)
+    MFG_FUSED(32)
+    MFG_FUSED(48)
+    MFG_FUSED(64)
+    MFG_FUSED(80)
+    MFG_FUSED(96)
+    MFG_FUSED(112)
+    default: MFG_FUSED(128)
   }
+#undef MFG_FUSED
 }
 
 void launch_tgemm_rows_fwd(const Plan& P, int mode, const double* r, float* tmp,
-                           const RowsArgs<float>& ra, hipStream_t s) {
+                           const RowsArgs<float>& ra, const UpdArgs* ua, hipStream_t s) {
   // operands scaled in the separate forward GEMM's groups: lp_waves x lp_cb
-  // tiles of 16 nodes, i.e. that many 32-node waves of this kernel
-  const int gwaves = (P.tune.lp_waves == 8 ? 8 : 4) * (P.tune.lp_cb == 1 ? 1 : 2) / 2;
-  const GemmArgs<double, float> ga{lp_table(P, mode), r,       tmp,   P.g.nt,     P.g.M, 0,
-                                   DOT_NONE,          nullptr, nullptr, P.red, P.pcg_done,
-                                   P.rr_gate};
-  if (mode == GM_F32) fused_dispatch<GM_F32>(P, ga, ra, gwaves, s);
-  else if (mode == GM_F16) fused_dispatch<GM_F16>(P, ga, ra, gwaves, s);
-  else fused_dispatch<GM_BF16>(P, ga, ra, gwaves, s);
+  // tiles of 16 nodes, i.e. that many waves of this kernel
+  const int gwaves = (P.tune.lp_waves == 8 ? 8 : 4) * (P.tune.lp_cb == 1 ? 1 : 2);
+  // with the update the stopping test is left to a later kernel (nrr = 0)
+  const GemmArgs<double, float> ga{lp_table(P, mode), r,       tmp,     P.g.nt,     P.g.M,
+                                   0,                 DOT_NONE, nullptr, nullptr,    P.red,
+                                   P.pcg_done,        ua ? 0 : P.rr_gate};
+  const UpdArgs u = ua ? *ua : UpdArgs{};
+  if (ua) {
+    if (mode == GM_F32) fused_dispatch<GM_F32, true>(P, ga, ra, u, gwaves, s);
+    else if (mode == GM_F16) fused_dispatch<GM_F16, true>(P, ga, ra, u, gwaves, s);
+    else fused_dispatch<GM_BF16, true>(P, ga, ra, u, gwaves, s);
+  } else {
+    if (mode == GM_F32) fused_dispatch<GM_F32, false>(P, ga, ra, u, gwaves, s);
+    else if (mode == GM_F16) fused_dispatch<GM_F16, false>(P, ga, ra, u, gwaves, s);
+    else fused_dispatch<GM_BF16, false>(P, ga, ra, u, gwaves, s);
+  }
 }
 
 // ---- batched low-precision time GEMM (one N_t padding class per launch) ----

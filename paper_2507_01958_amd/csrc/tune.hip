@@ -147,6 +147,7 @@ void keep_untuned(const Tune& from, Tune& to) {
   to.lp_stream = from.lp_stream;
   to.rhs_tc = from.rhs_tc;
   to.fuse_fwd = from.fuse_fwd;
+  to.fuse_upd = from.fuse_upd;
 }
 
 // allow_pers = false keeps the time GEMM in the form the batched launches use.

@@ -7,6 +7,7 @@
 // kernels (batch.hip) with the block's place inside its instance.
 #include "batch_args.h"
 #include "device_util.h"
+#include "pcg_update.h"
 #include "plan.h"
 
 namespace mfg {
@@ -44,26 +45,11 @@ __device__ void pcg_init_body(const InitArgs& a, int bid, int nb) {
   reduce_store<1>(acc, a.rb, T_BB, bid);
 }
 
-// alpha = r.z / p.q from the partials of both sites (breakdown, p.q not
-// positive or not finite: alpha = 0 and S_BAD, which ends the solve at the next
-// r.r check); x += alpha p; r -= alpha q; partial r.r. Block 0 records p.q,
-// alpha and rho = r.z for the next direction. Skipped once the solve is done.
+// x += alpha p; r -= alpha q (alpha: pcg_alpha); partial r.r. Skipped once
+// the solve is done.
 __device__ void update_body(const UpdArgs& a, int bid, int nb) {
   if (a.done && *a.done != 0.0) return;
-  double pq[1], rz[1];
-  fold_partials<1>(a.rb, T_PQ, a.npq, pq);
-  fold_partials<1>(a.rb, T_RZ, a.nrz, rz);
-  // r.z = 0 means r = 0 (a warm start at the solution): a zero step, not a
-  // breakdown; the next r.r test ends the solve
-  const int bad = !finite_d(pq[0]) ? 2 : (!(pq[0] > 0.0) && rz[0] != 0.0 ? 1 : 0);
-  const double alpha = (bad || rz[0] == 0.0) ? 0.0 : rz[0] / pq[0];
-  if (bid == 0 && threadIdx.x == 0) {
-    double* S = a.rb.scal;
-    S[S_PQ] = pq[0];
-    S[S_ALPHA] = alpha;
-    S[S_RHO] = rz[0];
-    if (bad) S[S_BAD] = (double)bad;
-  }
+  const double alpha = pcg_alpha(a, bid);
   double acc[1] = {0.0};
   // explicit fused multiply-adds, so the operations do not depend on the
   // compiler's contraction choices in this kernel; the first update of a solve

@@ -73,6 +73,12 @@ def classify(seq):
             else:
                 d = "inv" if (is_rows(prev) or is_cols(prev)) else "fwd"
             out.append(f"tgemm_{mode}_{d}")
+        elif s.startswith("k_tgemm_rows_fwd"):
+            # k_tgemm_rows_fwd<MODE, NTP, UPD>: the fused forward pass (with
+            # the conjugate gradient update when UPD)
+            args = _targs(s)
+            pre = "update_" if args[2:3] == ["true"] else ""
+            out.append(f"{pre}tgemm_rows_{MODES.get(args[0], 'f32')}_fwd")
         elif s.startswith(("k_rows_batch", "k_rows_reg_batch", "k_cols_batch", "k_cols_reg_batch",
                            "k_AAt_batch", "k_tgemm_lp_batch")):
             out.append(s[2:].split("<")[0])

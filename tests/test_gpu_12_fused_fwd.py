@@ -65,3 +65,29 @@ def test_fused_forward_scale_groups(monkeypatch, shape):
     z1, u1, _ = _run(monkeypatch, shape + ",fuse_fwd=1", inst, "mixed_fp32", r, b)
     assert np.array_equal(z0, z1), np.abs(z0 - z1).max()
     assert np.array_equal(u0, u1), np.abs(u0 - u1).max()
+
+
+def _cp(monkeypatch, tune, inst, precision, warm, iters=4):
+    from paper_2507_01958_amd import mfg
+    monkeypatch.setenv("MFG_TUNE", tune)
+    with plan_of(inst, precision) as P:
+        mfg.mfg_set_warm_start(P, warm)
+        st = mfg.CPState(P)
+        mfg.mfg_cp_init(P, st)
+        stats = mfg.mfg_cp_solve(P, st, iters, 1e-8, 200)
+        return host(st.xi), host(st.y), stats["pcg_iters"]
+
+
+@pytest.mark.parametrize("precision,warm", [("mixed_fp32", False), ("mixed_fp16", True),
+                                            ("mixed_bf16", False)])
+def test_fused_update_cp_bitwise(monkeypatch, precision, warm):
+    """The conjugate gradient update inside the fused forward pass (fuse_upd=1)
+    against its own kernel (fuse_upd=0) over whole CP iterations (standard and
+    flexible PCG, cold and warm starts): the same bits, the same PCG counts."""
+    inst = wl.small_instance(75, 2, 8, 256, 40, "neumann", 0.05)
+    say(f"fused update cp {precision} warm={warm}")
+    a = _cp(monkeypatch, "fuse_upd=0", inst, precision, warm)
+    b = _cp(monkeypatch, "fuse_upd=1", inst, precision, warm)
+    assert list(a[2]) == list(b[2])
+    assert np.array_equal(a[0], b[0]), np.abs(a[0] - b[0]).max()
+    assert np.array_equal(a[1], b[1]), np.abs(a[1] - b[1]).max()
