@@ -864,7 +864,7 @@ void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
 // output is not used).
 void launch_update_precond(const Plan& P, double* x, double* r, const double* p,
                            const double* q, double* z, bool first, hipStream_t s) {
-  if (!(P.tune.fuse_upd && P.pcg_done && fused_fwd_ok(P))) {
+  if (!fused_upd_ok(P)) {
     launch_update(P, x, r, p, q, first, s);
     launch_precond(P, r, z, true, q, s);
     return;

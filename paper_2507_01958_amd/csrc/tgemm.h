@@ -29,6 +29,8 @@ void tgemm(const Plan& P, int mode, const TX* X, TY* Y, int dotmode, const doubl
 // bits of the separate kernels (the same operand scaling groups, row pairs and
 // transform arithmetic). Whether the plan can take it:
 bool fused_fwd_ok(const Plan& P);
+// Whether a PCG iteration can also run its update in the fused forward pass.
+bool fused_upd_ok(const Plan& P);
 // ua: also apply the conjugate gradient update first (r is then ua->r, and the
 // kernel leaves the r.r stopping test to a later launch); nullptr: none.
 void launch_tgemm_rows_fwd(const Plan& P, int mode, const double* r, float* tmp,

@@ -410,43 +410,75 @@ __global__ __launch_bounds__(WPB * 64) void k_tgemm_lp(GemmArgs<TX, TY> a) {
   tgemm_lp_body<MODE, NTP, CB, TX, TY, WPB>(a, blockIdx.x);
 }
 
+// Raw buffer access (a range-checked vector memory descriptor): a load beyond
+// `bytes` returns 0 and a store beyond it is dropped, so code at the ragged end
+// of an array needs no branch (branches around loads and stores leave the
+// compiler unsure how many are outstanding, and it then waits for all).
+typedef unsigned int v2u32 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, unsigned bytes) {
+  // third descriptor word of a raw (untyped, stride 0) buffer on gfx9
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t rs, unsigned off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u32, v), rs, (int)off, 0, 0);
+}
+
 // The conjugate gradient update of the wave's tiles (x += alpha p, r -= alpha q,
 // the same multiply-adds as the update kernel), adding r.r to rr; the new r
 // values are the GEMM operands (as lp_load reads them). Returns their largest
-// magnitude.
-template <int MODE, int NTP, int CB>
+// magnitude. The elements go in groups of one k-step (PER values per tile);
+// the loads of group g + 1 are issued before group g is computed and stored,
+// so a wave keeps two groups of loads in flight. Elements with t >= N_t lie
+// beyond the descriptors' range: they read 0 (a zero operand, as lp_load's)
+// and their stores are dropped. Requires NTP M 8 < 2^31 bytes (the caller
+// checks). FIRST: x = 0 before the update (written, not read).
+template <int MODE, int NTP, int CB, bool FIRST>
 __device__ __forceinline__ float upd_load(const UpdArgs& a, double alpha, int nt, int M, int col0,
                                           int kq, float (&xs)[CB][LpShape<MODE, NTP>::NKS]
                                                              [LpShape<MODE, NTP>::PER],
                                           double& rr) {
   using L = LpShape<MODE, NTP>;
-  double* __restrict__ x = a.x;
-  double* __restrict__ r = a.r;
-  const double* __restrict__ p = a.p;
-  const double* __restrict__ q = a.q;
-  const bool first = a.first;
+  constexpr int G = CB * L::PER;  // elements per group
+  const unsigned bytes = (unsigned)nt * (unsigned)M * 8u;
+  const __amdgpu_buffer_rsrc_t xr = buf_rsrc(a.x, bytes), rr_ = buf_rsrc(a.r, bytes);
+  const __amdgpu_buffer_rsrc_t pr = buf_rsrc(a.p, bytes), qr = buf_rsrc(a.q, bytes);
+  auto off = [&](int ks, int e) {
+    const int cb = e / L::PER, j = e % L::PER;
+    const int t = L::KSTEP * ks + L::PER * kq + j, col = col0 + cb * 16;
+    return ((unsigned)t * (unsigned)M + (unsigned)col) * 8u;
+  };
+  double pb[2][G], qb[2][G], rb[2][G], xb[2][G];
+  auto load = [&](int ks, int buf) {
+#pragma unroll
+    for (int e = 0; e < G; ++e) {
+      const unsigned o = off(ks, e);
+      pb[buf][e] = buf_ld(pr, o);
+      qb[buf][e] = buf_ld(qr, o);
+      rb[buf][e] = buf_ld(rr_, o);
+      if (!FIRST) xb[buf][e] = buf_ld(xr, o);
+    }
+  };
   float amax = 0.0f;
+  load(0, 0);
 #pragma unroll
-  for (int cb = 0; cb < CB; ++cb) {
-    const int col = col0 + cb * 16;
+  for (int ks = 0; ks < L::NKS; ++ks) {
+    const int cur = ks & 1;
+    if (ks + 1 < L::NKS) load(ks + 1, cur ^ 1);
 #pragma unroll
-    for (int ks = 0; ks < L::NKS; ++ks)
-#pragma unroll
-      for (int j = 0; j < L::PER; ++j) {
-        const int t = L::KSTEP * ks + L::PER * kq + j;
-        float v = 0.0f;
-        if (t < nt && col < M) {
-          const size_t i = (size_t)t * M + col;
-          const double pv = p[i], qv = q[i], rv = r[i];
-          x[i] = first ? alpha * pv : __builtin_fma(alpha, pv, x[i]);
-          const double ri = __builtin_fma(-alpha, qv, rv);
-          r[i] = ri;
-          rr += ri * ri;
-          v = (float)ri;
-        }
-        xs[cb][ks][j] = v;
-        amax = fmaxf(amax, fabsf(v));
-      }
+    for (int e = 0; e < G; ++e) {
+      const unsigned o = off(ks, e);
+      buf_st(xr, o, FIRST ? alpha * pb[cur][e] : __builtin_fma(alpha, pb[cur][e], xb[cur][e]));
+      const double ri = __builtin_fma(-alpha, qb[cur][e], rb[cur][e]);
+      buf_st(rr_, o, ri);
+      rr += ri * ri;
+      const float v = (float)ri;
+      xs[e / L::PER][ks][e % L::PER] = v;
+      amax = fmaxf(amax, fabsf(v));
+    }
   }
   return amax;
 }
@@ -497,7 +529,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_tgemm_rows_fwd(GemmArgs<doubl
   if constexpr (UPD) {
     const double alpha = pcg_alpha(ua, bid);
     double rr[1] = {0.0};
-    amax = upd_load<MODE, NTP, CB>(ua, alpha, nt, M, col0, kq, xs, rr[0]);
+    amax = ua.first ? upd_load<MODE, NTP, CB, true>(ua, alpha, nt, M, col0, kq, xs, rr[0])
+                    : upd_load<MODE, NTP, CB, false>(ua, alpha, nt, M, col0, kq, xs, rr[0]);
     lp_stage_v<MODE, NTP>(static_cast<const VT*>(ga.V), Vs, kFusedThreads);
     reduce_store<1>(rr, ua.rb, T_RR, bid);
   } else {
@@ -1178,6 +1211,12 @@ template void tgemm<float, double>(const Plan&, int, const float*, double*, int,
 bool fused_fwd_ok(const Plan& P) {
   return P.tune.fuse_fwd && P.precision != MFG_FP64 && P.g.has0 && P.g.n1 == kFusedN &&
          P.tune.fft_reg && P.ntp > 0 && !P.tune.tgemm_pers;
+}
+
+bool fused_upd_ok(const Plan& P) {
+  // the update addresses its vectors through 32-bit byte offsets
+  return P.tune.fuse_upd && P.pcg_done && fused_fwd_ok(P) &&
+         (long long)P.ntp * P.g.M * 8 < (1LL << 31);
 }
 
 template <int MODE, bool UPD>
