@@ -92,7 +92,7 @@ def algorithmic(kernel, inst, variant, its=1.0, steps=1):
         return "hbm", upd * 8 * n + 4 * n, None
     if kernel.startswith("tgemm_") and kernel.endswith("_fwd"):
         return "hbm", (8 + 4) * n, None          # read r (f64), write f32
-    if kernel.startswith("tgemm_") and kernel.endswith("_inv"):
+    if kernel.startswith(("tgemm_", "rows_tgemm_")) and kernel.endswith("_inv"):
         return "hbm", (4 + 8 + 8 + (8 if flex else 0)) * n, None  # + r (and q) for the dots
     if kernel in table:
         return "hbm", table[kernel], None

@@ -176,6 +176,7 @@ static void read_tune_env(Tune& t) {
       else if (k == "rhs_tc" && v >= 0 && v <= 64) t.rhs_tc = v;
       else if (k == "fuse_fwd" && (v == 0 || v == 1)) t.fuse_fwd = v;
       else if (k == "fuse_upd" && (v == 0 || v == 1)) t.fuse_upd = v;
+      else if (k == "fuse_inv" && (v == 0 || v == 1)) t.fuse_inv = v;
     }
     pos = end + 1;
   }

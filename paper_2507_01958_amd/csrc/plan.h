@@ -42,6 +42,9 @@ struct Tune {
   // inside PCG, the update (x += alpha p, r -= alpha q) runs in the fused
   // forward pass too; 0: its own kernel
   int fuse_upd = 1;
+  // inverse pass fused (row transforms + inverse time GEMM) where it applies
+  // (as fuse_fwd, and one 16-node tile per wave in the inverse GEMM)
+  int fuse_inv = 1;
 };
 
 // Optional per-kernel timing with HIP events recorded on the plan's stream

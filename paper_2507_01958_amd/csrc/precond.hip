@@ -378,10 +378,8 @@ __device__ void rows_fwd_reg(const RowsArgs<T>& a, int bid, C2<T>* lds) {
                       tw_table<T>(a.ax), ct_table<T>(a.ax));
 }
 
-// Inverse real transform along the contiguous axis (times N): spectra in,
-// lines out in natural order. The complex input of the inverse FFT is formed
-// from the pair (k, N - k) read directly: DHT: Re F = (H[k] + H[N-k])/2,
-// Im F = (H[N-k] - H[k])/2; DCT-II: V[k] = exp(i pi k/(2N)) (C[k] - i C[N-k]).
+// Inverse real transform along the contiguous axis (rows_inv_line), lines out
+// in natural order.
 template <typename T, int N>
 __device__ void rows_inv_reg(const RowsArgs<T>& a, int bid, C2<T>* lds) {
   using Sh = fftr::Shape<T, N>;
@@ -391,32 +389,14 @@ __device__ void rows_inv_reg(const RowsArgs<T>& a, int bid, C2<T>* lds) {
   const bool hasa = rp.hasa, hasb = rp.hasb;
   const bool dct = a.ax.kind == 1;
   T* __restrict__ data = a.data;
-  const T* __restrict__ tw = tw_table<T>(a.ax);
-  const T* __restrict__ ct = ct_table<T>(a.ax);
   C2<T> v[16];
-#pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int k = p + Sh::N2 * m;
-    const int kr = k ? N - k : 0;
-    const T ca = hasa ? data[(unsigned)ra * N + k] : (T)0;  // n < 2^31
-    const T cb = hasb ? data[(unsigned)rb * N + k] : (T)0;
-    T ra_ = hasa ? data[(unsigned)ra * N + kr] : (T)0;
-    T rb_ = hasb ? data[(unsigned)rb * N + kr] : (T)0;
-    if (!dct) {
-      const T fa_re = (T)0.5 * (ca + ra_), fa_im = (T)0.5 * (ra_ - ca);
-      const T fb_re = (T)0.5 * (cb + rb_), fb_im = (T)0.5 * (rb_ - cb);
-      v[m] = C2<T>{fa_re - fb_im, fa_im + fb_re};
-    } else {
-      if (k == 0) {
-        ra_ = (T)0;
-        rb_ = (T)0;
-      }
-      const T c = ct[2 * k], sn = ct[2 * k + 1];
-      v[m].x = fftr::ffma(c, ca, sn * ra_) - fftr::ffma(sn, cb, -(c * rb_));
-      v[m].y = fftr::ffma(sn, ca, -(c * ra_)) + fftr::ffma(c, cb, sn * rb_);
-    }
-  }
-  fftr::fft4<T, N, +1>(v, lds + l * Sh::L, p, tw);
+  // n < 2^31: 32-bit offsets
+  rows_inv_line<T, N>(
+      [&](int k) {
+        return C2<T>{hasa ? data[(unsigned)ra * N + k] : (T)0,
+                     hasb ? data[(unsigned)rb * N + k] : (T)0};
+      },
+      dct, lds + l * Sh::L, p, tw_table<T>(a.ax), ct_table<T>(a.ax), v);
 #pragma unroll
   for (int m = 0; m < 16; ++m) {
     const int n = p + Sh::N2 * m;
@@ -773,9 +753,11 @@ ColsArgs<T> cols_args(const Plan& P, const SpatialShape& sh, T* data, const doub
   return ColsArgs<T>{data, P.g, P.ax0, sh.cw, solve_ctx(P), done, sh.creg};
 }
 
-// skip_fwd: the forward row transforms were done by the fused forward pass.
+// skip_fwd / skip_inv: the forward / inverse row transforms are done by the
+// fused forward / inverse pass.
 template <typename T>
-void spatial_solves(const Plan& P, T* data, hipStream_t s, bool skip_fwd = false) {
+void spatial_solves(const Plan& P, T* data, hipStream_t s, bool skip_fwd = false,
+                    bool skip_inv = false) {
   const Geom& g = P.g;
   const SpatialShape sh = spatial_shape<T>(P);
   if (!g.has0) {
@@ -794,6 +776,7 @@ void spatial_solves(const Plan& P, T* data, hipStream_t s, bool skip_fwd = false
     launch_cols_cls<T>(sh.creg, dim3(sh.cblocks), dim3(sh.cthreads), sh.cshm, s,
                        cols_args<T>(P, sh, data, P.pcg_done));
   }
+  if (skip_inv) return;
   ProfScope ps(P, sizeof(T) == 8 ? "rows_inv_f64" : "rows_inv_f32", s);
   launch_rows_cls<T>(sh.rreg, dim3(sh.rblocks), dim3(sh.rthreads), sh.rshm, s,
                      rows_args<T>(P, sh, data, 1, P.pcg_done));
@@ -816,6 +799,33 @@ const char* const kFusedNames[4] = {"", "tgemm_rows_f32_fwd", "tgemm_rows_f16_fw
                                     "tgemm_rows_bf16_fwd"};
 const char* const kUpdFusedNames[4] = {"", "update_tgemm_rows_f32_fwd",
                                        "update_tgemm_rows_f16_fwd", "update_tgemm_rows_bf16_fwd"};
+const char* const kInvFusedNames[4] = {"", "rows_tgemm_f32_inv", "rows_tgemm_f16_inv",
+                                       "rows_tgemm_bf16_inv"};
+
+// Spatial solves after the forward pass (its row transforms done when
+// fwd_fused) and the inverse pass (z, with the dot partials of dotmode).
+void mixed_tail(const Plan& P, int mode, float* tmp, double* z, int dotmode, const double* r,
+                const double* q, bool fwd_fused, hipStream_t s) {
+  const int gate = P.rr_gate;  // stopping test of the inverse pass (0: none)
+  P.rr_gate = 0;
+  const bool inv_fused = fused_inv_ok(P);
+  spatial_solves<float>(P, tmp, s, fwd_fused, inv_fused);
+  P.rr_gate = gate;
+  if (inv_fused) {
+    int parts;
+    {
+      ProfScope ps(P, kInvFusedNames[mode], s);
+      parts = launch_rows_tgemm_inv(P, mode,
+                                    rows_args<float>(P, spatial_shape<float>(P), tmp, 1,
+                                                     P.pcg_done),
+                                    z, dotmode, r, q, s);
+    }
+    if (dotmode != DOT_NONE) P.rz_blocks = parts;
+  } else {
+    tgemm<float, double>(P, mode, tmp, z, dotmode, r, q, s, kInvNames[mode]);
+  }
+  P.rr_gate = 0;
+}
 
 }  // namespace
 
@@ -839,21 +849,17 @@ void launch_precond(const Plan& P, const double* r, double* z, bool fused_dots,
   // plan's matrix-core precision
   const int mode = mixed_mode(P);
   float* tmp = reinterpret_cast<float*>(P.tmp);
-  if (fused_fwd_ok(P)) {
-    {
-      ProfScope ps(P, kFusedNames[mode], s);
-      launch_tgemm_rows_fwd(P, mode, r, tmp,
-                            rows_args<float>(P, spatial_shape<float>(P), tmp, 0, P.pcg_done),
-                            nullptr, s);
-    }
-    P.rr_gate = 0;
-    spatial_solves<float>(P, tmp, s, true);
+  const bool fwd_fused = fused_fwd_ok(P);
+  if (fwd_fused) {
+    ProfScope ps(P, kFusedNames[mode], s);
+    launch_tgemm_rows_fwd(P, mode, r, tmp,
+                          rows_args<float>(P, spatial_shape<float>(P), tmp, 0, P.pcg_done),
+                          nullptr, s);
   } else {
     tgemm<double, float>(P, mode, r, tmp, DOT_NONE, nullptr, nullptr, s, kFwdNames[mode]);
-    P.rr_gate = 0;
-    spatial_solves<float>(P, tmp, s);
   }
-  tgemm<float, double>(P, mode, tmp, z, dotmode, r, q, s, kInvNames[mode]);
+  P.rr_gate = 0;
+  mixed_tail(P, mode, tmp, z, dotmode, r, q, fwd_fused, s);
 }
 
 // One PCG iteration's update and preconditioning: x += alpha p, r -= alpha q
@@ -879,12 +885,8 @@ void launch_update_precond(const Plan& P, double* x, double* r, const double* p,
                           s);
   }
   P.rr_blocks = P.g.n0;  // one r.r partial per block (axis-0 row)
-  P.rr_gate = 0;
-  spatial_solves<float>(P, tmp, s, true);
   P.rr_gate = P.rr_blocks;
-  tgemm<float, double>(P, mode, tmp, z, pcg_flexible(P) ? DOT_FLEX : DOT_STD, r, q, s,
-                       kInvNames[mode]);
-  P.rr_gate = 0;
+  mixed_tail(P, mode, tmp, z, pcg_flexible(P) ? DOT_FLEX : DOT_STD, r, q, true, s);
 }
 
 // ---- batched spatial solves (float32 data in the mixed modes, float64 in FP64) ----

@@ -110,4 +110,42 @@ __device__ __forceinline__ void rows_fwd_line(LD ld, ST st, bool dct, C2<T>* lds
   rows_fwd_xform<T, N>(v, st, dct, lds, zb, p, tw, ct);
 }
 
+// Inverse real transform of one line along the contiguous axis (times N):
+// spectra in, the two rows' values out in v (register m holds position
+// n = p + Shape::N2 m of the complex line; with DCT-II it goes to element
+// dct_perm(n) of the rows). The complex input of the inverse FFT is formed
+// from the pair (k, N - k): DHT: Re F = (H[k] + H[N-k])/2,
+// Im F = (H[N-k] - H[k])/2; DCT-II: V[k] = exp(i pi k/(2N)) (C[k] - i C[N-k]).
+// ld(k) returns the two rows' spectra at k (row a real part, row b imaginary
+// part). lds: the line's exchange area of fft4. Called by every thread of the
+// block.
+template <typename T, int N, class LD>
+__device__ __forceinline__ void rows_inv_line(LD ld, bool dct, C2<T>* lds, int p,
+                                              const T* __restrict__ tw,
+                                              const T* __restrict__ ct, C2<T> (&v)[16]) {
+  using Sh = fftr::Shape<T, N>;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int k = p + Sh::N2 * m;
+    const int kr = k ? N - k : 0;
+    const C2<T> cz = ld(k), rz = ld(kr);
+    const T ca = cz.x, cb = cz.y;
+    T ra_ = rz.x, rb_ = rz.y;
+    if (!dct) {
+      const T fa_re = (T)0.5 * (ca + ra_), fa_im = (T)0.5 * (ra_ - ca);
+      const T fb_re = (T)0.5 * (cb + rb_), fb_im = (T)0.5 * (rb_ - cb);
+      v[m] = C2<T>{fa_re - fb_im, fa_im + fb_re};
+    } else {
+      if (k == 0) {
+        ra_ = (T)0;
+        rb_ = (T)0;
+      }
+      const T c = ct[2 * k], sn = ct[2 * k + 1];
+      v[m].x = fftr::ffma(c, ca, sn * ra_) - fftr::ffma(sn, cb, -(c * rb_));
+      v[m].y = fftr::ffma(sn, ca, -(c * ra_)) + fftr::ffma(c, cb, sn * rb_);
+    }
+  }
+  fftr::fft4<T, N, +1>(v, lds, p, tw);
+}
+
 }  // namespace mfg

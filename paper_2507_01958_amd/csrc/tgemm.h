@@ -31,6 +31,14 @@ void tgemm(const Plan& P, int mode, const TX* X, TY* Y, int dotmode, const doubl
 bool fused_fwd_ok(const Plan& P);
 // Whether a PCG iteration can also run its update in the fused forward pass.
 bool fused_upd_ok(const Plan& P);
+
+// The inverse pass fused (row transforms along axis 1 of length 256, then the
+// inverse time GEMM with its dot products, N_t <= 128, one 16-node tile per
+// wave): reads the intermediate ra.data, writes z and the r.z (z.q) partials
+// exactly as the separate kernels. Returns the number of partials.
+bool fused_inv_ok(const Plan& P);
+int launch_rows_tgemm_inv(const Plan& P, int mode, const RowsArgs<float>& ra, double* z,
+                          int dotmode, const double* r, const double* q, hipStream_t s);
 // ua: also apply the conjugate gradient update first (r is then ua->r, and the
 // kernel leaves the r.r stopping test to a later launch); nullptr: none.
 void launch_tgemm_rows_fwd(const Plan& P, int mode, const double* r, float* tmp,

@@ -582,6 +582,146 @@ __global__ __launch_bounds__(kFusedThreads) void k_tgemm_rows_fwd(GemmArgs<doubl
       dct, scr + l * Sh::L, scr + l * Sh::L2, p, tw_table<float>(ra.ax), ct_table<float>(ra.ax));
 }
 
+// Fused inverse pass (row transforms along axis 1, N = 256, then the inverse
+// time GEMM with its r.z (and z.q) partials): the block owns axis-0 row bid.
+// Its 64 lines (slices 2 tp, 2 tp + 1) load their spectra from the float32
+// intermediate and take the inverse transform, exchanging through LDS; the
+// rows then go to an LDS tile in the same space (rows of kInvStride floats:
+// the tile's column reads by the four row groups of a wave fall in distinct
+// banks), each wave (one tile of 16 nodes) takes its operands from it, V
+// replaces the tile, and the products
+// and the epilogue follow the separate GEMM with one 16-node tile per wave:
+// operands scaled per group of gwaves waves, each group's partials formed in
+// the same order and stored at the index of the separate kernel's block
+// (gpr groups per row), so both give the same bits.
+constexpr int kInvStride = kFusedN + 4;
+
+template <int MODE, int NTP>
+__global__ __launch_bounds__(kFusedThreads) void k_rows_tgemm_inv(GemmArgs<float, double> ga,
+                                                                  RowsArgs<float> ra, int gwaves,
+                                                                  int gpr) {
+  const int bid = blockIdx.x;
+  if (gemm_skip(ga, bid)) return;
+  using L = LpShape<MODE, NTP>;
+  using VT = typename L::VT;
+  using Sh = fftr::Shape<float, kFusedN>;
+  constexpr int WAVES = kFusedThreads / 64;
+  static_assert(WAVES * 16 == kFusedN, "a block covers one row of 256 nodes");
+  constexpr int LINES = kFusedThreads / Sh::N2;
+  static_assert(2 * LINES >= 128, "one pass transforms every time slice");
+  constexpr int TILE_BYTES = 2 * LINES * kInvStride * 4;
+  constexpr int VS_BYTES = L::VROWS * NTP * (int)sizeof(VT);
+  constexpr int SCR_BYTES = LINES * (Sh::L > Sh::L2 ? Sh::L : Sh::L2) * (int)sizeof(C2<float>);
+  constexpr int A1 = TILE_BYTES > VS_BYTES ? TILE_BYTES : VS_BYTES;
+  constexpr int A_BYTES = A1 > SCR_BYTES ? A1 : SCR_BYTES;
+  __shared__ __align__(16) unsigned char smem[A_BYTES];
+  __shared__ float smax[WAVES];
+  __shared__ double dsum[2][WAVES];
+  C2<float>* scr = reinterpret_cast<C2<float>*>(smem);  // exchange areas,
+  float* tile = reinterpret_cast<float*>(smem);         // then the rows,
+  VT* Vs = reinterpret_cast<VT*>(smem);                 // then V
+  const int nt = ga.nt, M = ga.M;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, kq = lane >> 4;
+  const int i0 = bid;
+  // inverse row transforms of slices 2 l, 2 l + 1
+  const bool dct = ra.ax.kind == 1;
+  const int l = threadIdx.x / Sh::N2, p = threadIdx.x % Sh::N2;
+  const RowPair rp = row_pair(l * ra.n0 + i0, ra.nrows, ra.n0);
+  {
+    const float* __restrict__ in = ra.data;
+    C2<float> v[16];
+    rows_inv_line<float, kFusedN>(
+        [&](int k) {
+          return C2<float>{rp.hasa ? in[(unsigned)rp.ra * kFusedN + k] : 0.0f,
+                           rp.hasb ? in[(unsigned)rp.rb * kFusedN + k] : 0.0f};
+        },
+        dct, scr + l * Sh::L, p, tw_table<float>(ra.ax), ct_table<float>(ra.ax), v);
+    __syncthreads();  // the exchanges are over: their LDS takes the rows
+    float* ta = tile + (2 * l) * kInvStride;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int n = p + Sh::N2 * m;
+      const int dst = dct ? dct_perm(n, kFusedN) : n;
+      ta[dst] = v[m].x;
+      ta[kInvStride + dst] = v[m].y;
+    }
+  }
+  __syncthreads();
+  // the wave's operands (t = KSTEP ks + PER kq + j; zero beyond N_t)
+  float xs[1][L::NKS][L::PER];
+  float amax = 0.0f;
+#pragma unroll
+  for (int ks = 0; ks < L::NKS; ++ks)
+#pragma unroll
+    for (int j = 0; j < L::PER; ++j) {
+      const int t = L::KSTEP * ks + L::PER * kq + j;
+      const float v = t < nt ? tile[t * kInvStride + wave * 16 + (lane & 15)] : 0.0f;
+      xs[0][ks][j] = v;
+      amax = fmaxf(amax, fabsf(v));
+    }
+  __syncthreads();  // the tile is read: V takes its LDS
+  lp_stage_v<MODE, NTP>(static_cast<const VT*>(ga.V), Vs, kFusedThreads);
+  if (L::SCALED) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
+    if (lane == 0) smax[wave] = amax;
+  }
+  __syncthreads();
+  float bm = 0.0f;
+  if (L::SCALED) {
+    const int g0 = (wave / gwaves) * gwaves;
+    bm = smax[g0];
+    for (int w = 1; w < gwaves; ++w) bm = fmaxf(bm, smax[g0 + w]);
+  }
+  float scale, unscale;
+  lp_scales<MODE, NTP>(bm, scale, unscale);
+  v4f acc[1][L::NKB];
+  lp_mma<MODE, NTP, 1>(Vs, xs, scale, lane, acc);
+  // epilogue: z and the dot partials
+  const int dotmode = ga.dotmode;
+  const double* __restrict__ rvec = ga.rvec;
+  const double* __restrict__ qvec = ga.qvec;
+  double* __restrict__ Y = ga.Y;
+  const int col = i0 * kFusedN + wave * 16 + (lane & 15);
+  double dots[2] = {0.0, 0.0};
+#pragma unroll
+  for (int kb = 0; kb < L::NKB; ++kb)
+#pragma unroll
+    for (int jr = 0; jr < 4; ++jr) {
+      const int k = kb * 16 + 4 * kq + jr;
+      if (k < nt) {
+        const size_t o = (size_t)k * M + col;
+        const double v = (double)(acc[0][kb][jr] * unscale);
+        Y[o] = v;
+        if (dotmode != DOT_NONE) {
+          dots[0] += rvec[o] * v;
+          if (dotmode == DOT_FLEX) dots[1] += qvec[o] * v;
+        }
+      }
+    }
+  if (dotmode != DOT_NONE) {
+    // as reduce_store over the separate kernel's block of gwaves waves: the
+    // wave sums, then the group's waves added in order from zero
+#pragma unroll
+    for (int k = 0; k < 2; ++k) dots[k] = wave_sum(dots[k]);
+    if (lane == 0) {
+      dsum[0][wave] = dots[0];
+      dsum[1][wave] = dots[1];
+    }
+    __syncthreads();
+    if (threadIdx.x < gpr) {
+      const int g = threadIdx.x;
+      double* part = ga.rb.partials + (size_t)T_RZ * kSlotsPerSite * ga.rb.max_blocks;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        double sum = 0.0;
+        for (int w = 0; w < gwaves; ++w) sum += dsum[k][g * gwaves + w];
+        part[(size_t)k * ga.rb.max_blocks + i0 * gpr + g] = sum;
+      }
+    }
+  }
+}
+
 template <int MODE, int NTP, int CB, typename TX, typename TY, int WPB>
 __global__ __launch_bounds__(WPB * 64) void k_tgemm_lp_batch(const GemmArgs<TX, TY>* A,
                                                              const int* off, int ninst) {
@@ -1259,6 +1399,47 @@ void launch_tgemm_rows_fwd(const Plan& P, int mode, const double* r, float* tmp,
     else if (mode == GM_F16) fused_dispatch<GM_F16, false>(P, ga, ra, u, gwaves, s);
     else fused_dispatch<GM_BF16, false>(P, ga, ra, u, gwaves, s);
   }
+}
+
+bool fused_inv_ok(const Plan& P) {
+  return P.tune.fuse_inv && P.precision != MFG_FP64 && P.g.has0 && P.g.n1 == kFusedN &&
+         P.tune.fft_reg && P.ntp > 0 && !P.tune.tgemm_pers && P.tune.lp_cb_i == 1;
+}
+
+template <int MODE>
+void fused_inv_dispatch(const Plan& P, const GemmArgs<float, double>& ga,
+                        const RowsArgs<float>& ra, int gwaves, int gpr, hipStream_t s) {
+  const dim3 g(P.g.n0), b(kFusedThreads);
+#define MFG_FUSED_INV(NTPV)                                                                \
+  case NTPV:                                                                               \
+    hipLaunchKernelGGL((k_rows_tgemm_inv<MODE, NTPV>), g, b, 0, s, ga, ra, gwaves, gpr);  \
+    break;
+  switch (P.ntp) {
+    MFG_FUSED_INV(16)
+    MFG_FUSED_INV(32)
+    MFG_FUSED_INV(48)
+    MFG_FUSED_INV(64)
+    MFG_FUSED_INV(80)
+    MFG_FUSED_INV(96)
+    MFG_FUSED_INV(112)
+    default: MFG_FUSED_INV(128)
+  }
+#undef MFG_FUSED_INV
+}
+
+int launch_rows_tgemm_inv(const Plan& P, int mode, const RowsArgs<float>& ra, double* z,
+                          int dotmode, const double* r, const double* q, hipStream_t s) {
+  // the separate inverse GEMM's blocks: lp_waves_i tiles of 16 nodes (one per
+  // wave here), gpr of them per row of 256 nodes
+  const int gwaves = P.tune.lp_waves_i == 8 ? 8 : 4;
+  const int gpr = kFusedN / (16 * gwaves);
+  const GemmArgs<float, double> ga{lp_table(P, mode), ra.data, z,       P.g.nt,     P.g.M,
+                                   0,                 dotmode, r,       q,          P.red,
+                                   P.pcg_done,        P.rr_gate};
+  if (mode == GM_F32) fused_inv_dispatch<GM_F32>(P, ga, ra, gwaves, gpr, s);
+  else if (mode == GM_F16) fused_inv_dispatch<GM_F16>(P, ga, ra, gwaves, gpr, s);
+  else fused_inv_dispatch<GM_BF16>(P, ga, ra, gwaves, gpr, s);
+  return P.g.n0 * gpr;
 }
 
 // ---- batched low-precision time GEMM (one N_t padding class per launch) ----

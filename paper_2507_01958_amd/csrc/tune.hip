@@ -148,6 +148,7 @@ void keep_untuned(const Tune& from, Tune& to) {
   to.rhs_tc = from.rhs_tc;
   to.fuse_fwd = from.fuse_fwd;
   to.fuse_upd = from.fuse_upd;
+  to.fuse_inv = from.fuse_inv;
 }
 
 // allow_pers = false keeps the time GEMM in the form the batched launches use.

@@ -79,6 +79,9 @@ def classify(seq):
             args = _targs(s)
             pre = "update_" if args[2:3] == ["true"] else ""
             out.append(f"{pre}tgemm_rows_{MODES.get(args[0], 'f32')}_fwd")
+        elif s.startswith("k_rows_tgemm_inv"):
+            # k_rows_tgemm_inv<MODE, NTP>: the fused inverse pass
+            out.append(f"rows_tgemm_{MODES.get(_targs(s)[0], 'f32')}_inv")
         elif s.startswith(("k_rows_batch", "k_rows_reg_batch", "k_cols_batch", "k_cols_reg_batch",
                            "k_AAt_batch", "k_tgemm_lp_batch")):
             out.append(s[2:].split("<")[0])

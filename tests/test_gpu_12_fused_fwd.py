@@ -1,4 +1,4 @@
-"""The fused forward preconditioner pass against the separate kernels.
+"""The fused preconditioner passes against the separate kernels.
 
 With the mixed precisions, axis 1 of 256 nodes and N_t <= 128, the time GEMM
 of the residual and the forward row transforms of Algorithm 2 run as one
@@ -9,7 +9,9 @@ pairs the same rows and runs the same transform arithmetic, so both give the
 same bits: checked on P^{-1} r and on whole PCG solves (where the forward pass
 also takes the r.r stopping test) for every mixed precision, both boundary
 conditions, several N_t (ragged time padding) and operand-scaling group
-widths.
+widths. The same holds for the update inside the forward pass (fuse_upd) and
+for the fused inverse pass (fuse_inv: row transforms, inverse time GEMM and
+its dot partials).
 """
 import numpy as np
 import pytest
@@ -88,6 +90,40 @@ def test_fused_update_cp_bitwise(monkeypatch, precision, warm):
     say(f"fused update cp {precision} warm={warm}")
     a = _cp(monkeypatch, "fuse_upd=0", inst, precision, warm)
     b = _cp(monkeypatch, "fuse_upd=1", inst, precision, warm)
+    assert list(a[2]) == list(b[2])
+    assert np.array_equal(a[0], b[0]), np.abs(a[0] - b[0]).max()
+    assert np.array_equal(a[1], b[1]), np.abs(a[1] - b[1]).max()
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("bc", ["periodic", "neumann"])
+@pytest.mark.parametrize("nx,nt,waves", [(6, 5, 8), (8, 70, 4), (4, 128, 8)])
+def test_fused_inverse_bitwise(monkeypatch, precision, bc, nx, nt, waves):
+    """The fused inverse pass (row transforms + inverse time GEMM with the dot
+    partials) against the separate kernels with one 16-node tile per wave:
+    the same z, the same partials (hence the same PCG iterates)."""
+    inst = wl.small_instance(76, 2, nx, 256, nt, bc, 0.1)
+    n = nt * nx * 256
+    rng = np.random.default_rng(77 + nt)
+    r = rng.standard_normal(n) * np.exp(rng.uniform(-3, 3, n))
+    b = rng.standard_normal(n)
+    say(f"fused inv {precision} {bc} {nx}x256x{nt} waves={waves}")
+    shape = f"lp_cb_i=1,lp_waves_i={waves}"
+    z0, u0, s0 = _run(monkeypatch, shape + ",fuse_inv=0", inst, precision, r, b)
+    z1, u1, s1 = _run(monkeypatch, shape + ",fuse_inv=1", inst, precision, r, b)
+    assert np.array_equal(z0, z1), np.abs(z0 - z1).max()
+    assert np.array_equal(u0, u1), np.abs(u0 - u1).max()
+    assert s0 == s1
+
+
+@pytest.mark.parametrize("precision,warm", [("mixed_fp32", True), ("mixed_fp16", False)])
+def test_fused_passes_cp_bitwise(monkeypatch, precision, warm):
+    """Every fused pass on (forward with the update, inverse) against every
+    one off, over whole CP iterations."""
+    inst = wl.small_instance(78, 2, 8, 256, 40, "periodic", 0.05)
+    say(f"fused passes cp {precision} warm={warm}")
+    a = _cp(monkeypatch, "fuse_fwd=0,fuse_upd=0,fuse_inv=0", inst, precision, warm)
+    b = _cp(monkeypatch, "fuse_fwd=1,fuse_upd=1,fuse_inv=1", inst, precision, warm)
     assert list(a[2]) == list(b[2])
     assert np.array_equal(a[0], b[0]), np.abs(a[0] - b[0]).max()
     assert np.array_equal(a[1], b[1]), np.abs(a[1] - b[1]).max()
