@@ -445,30 +445,45 @@ struct SliceSymbol {
 // k). Neumann: DCT-II via Makhoul's reordering; both C[k] and C[N-k] are
 // formed from the pair (Z[k], Z[N-k]) so the inverse input needs no second
 // exchange.
+// One column tile of the register path: two columns (ja, ja + 1) of slice t
+// per line, 2 LPB adjacent columns per tile.
+struct ColTile {
+  int t, ja;
+  bool hasa, hasb, pair_ld;
+};
+
 template <typename T, int N>
-__device__ void cols_reg(const ColsArgs<T>& a, int bid, int nb, C2<T>* lds) {
+__device__ __forceinline__ ColTile col_tile(const ColsArgs<T>& a, int blk) {
   using Sh = fftr::Shape<T, N, true>;
   const Geom& g = a.g;
-  const SolveCtx& sc = a.sc;
-  const int l = Sh::line(threadIdx.x), p = Sh::pos(threadIdx.x);
+  const int l = Sh::line(threadIdx.x);
   const int cw = 2 * Sh::LPB;
   const int ncb = (g.n1 + cw - 1) / cw;
-  const int blk = xcd_remap(bid, nb);
-  const int t = blk / ncb;
-  const int ja = (blk - t * ncb) * cw + 2 * l, jb = ja + 1;
-  const bool hasa = ja < g.n1, hasb = jb < g.n1;
-  const bool pair_ld = hasb && ((g.n1 & 1) == 0);  // 2-element aligned vector access
+  ColTile c;
+  c.t = blk / ncb;
+  c.ja = (blk - c.t * ncb) * cw + 2 * l;
+  c.hasa = c.ja < g.n1;
+  c.hasb = c.ja + 1 < g.n1;
+  c.pair_ld = c.hasb && ((g.n1 & 1) == 0);  // 2-element aligned vector access
+  return c;
+}
+
+// The tile's inputs.
+template <typename T, int N>
+__device__ __forceinline__ void cols_load(const ColsArgs<T>& a, const ColTile& c,
+                                          C2<T> (&v)[16]) {
+  using Sh = fftr::Shape<T, N, true>;
+  const int p = Sh::pos(threadIdx.x);
   const bool dct = a.ax.kind == 1;
-  T* __restrict__ slice = a.data + (size_t)t * g.M;
-  const T* __restrict__ tw = tw_table<T>(a.ax);
-  C2<T> v[16];
+  const unsigned n1s = (unsigned)a.g.n1;
+  const T* __restrict__ slice = a.data + (size_t)c.t * a.g.M;
   // 32-bit offsets within the slice (M < 2^31); the column-pair test is
   // uniform, so each form is one straight run of loads
-  if (pair_ld) {
+  if (c.pair_ld) {
 #pragma unroll
     for (int n1 = 0; n1 < 16; ++n1) {
       const int n = p + Sh::N2 * n1;
-      const unsigned o = (unsigned)(dct ? dct_perm(n, N) : n) * (unsigned)g.n1 + (unsigned)ja;
+      const unsigned o = (unsigned)(dct ? dct_perm(n, N) : n) * n1s + (unsigned)c.ja;
       const V2<T> w = *reinterpret_cast<const V2<T>*>(slice + o);
       v[n1] = C2<T>{w.x, w.y};
     }
@@ -476,11 +491,52 @@ __device__ void cols_reg(const ColsArgs<T>& a, int bid, int nb, C2<T>* lds) {
 #pragma unroll
     for (int n1 = 0; n1 < 16; ++n1) {
       const int n = p + Sh::N2 * n1;
-      const unsigned o = (unsigned)(dct ? dct_perm(n, N) : n) * (unsigned)g.n1 + (unsigned)ja;
-      v[n1].x = hasa ? slice[o] : (T)0;
-      v[n1].y = hasb ? slice[o + 1] : (T)0;
+      const unsigned o = (unsigned)(dct ? dct_perm(n, N) : n) * n1s + (unsigned)c.ja;
+      v[n1].x = c.hasa ? slice[o] : (T)0;
+      v[n1].y = c.hasb ? slice[o + 1] : (T)0;
     }
   }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void cols_store(const ColsArgs<T>& a, const ColTile& c,
+                                           const C2<T> (&v)[16]) {
+  using Sh = fftr::Shape<T, N, true>;
+  const int p = Sh::pos(threadIdx.x);
+  const bool dct = a.ax.kind == 1;
+  const unsigned n1s = (unsigned)a.g.n1;
+  T* __restrict__ slice = a.data + (size_t)c.t * a.g.M;
+  if (c.pair_ld) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int n = p + Sh::N2 * m;
+      const unsigned o = (unsigned)(dct ? dct_perm(n, N) : n) * n1s + (unsigned)c.ja;
+      *reinterpret_cast<V2<T>*>(slice + o) = V2<T>{v[m].x, v[m].y};
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int n = p + Sh::N2 * m;
+      const unsigned o = (unsigned)(dct ? dct_perm(n, N) : n) * n1s + (unsigned)c.ja;
+      if (c.hasa) slice[o] = v[m].x;
+      if (c.hasb) slice[o + 1] = v[m].y;
+    }
+  }
+}
+
+// Forward transform, division by S, inverse transform of the tile's lines in
+// registers (exchanges through lds; called by every thread of the block; the
+// caller synchronises before lds is used again).
+template <typename T, int N>
+__device__ __forceinline__ void cols_xform(const ColsArgs<T>& a, const ColTile& c,
+                                           C2<T> (&v)[16], C2<T>* lds) {
+  using Sh = fftr::Shape<T, N, true>;
+  const SolveCtx& sc = a.sc;
+  const int l = Sh::line(threadIdx.x), p = Sh::pos(threadIdx.x);
+  const bool dct = a.ax.kind == 1;
+  const T* __restrict__ tw = tw_table<T>(a.ax);
+  const int t = c.t, ja = c.ja, jb = ja + 1;
+  const bool hasa = c.hasa, hasb = c.hasb;
   fftr::fft4<T, N, -1, true>(v, lds + l * Sh::L, p, tw);
   __syncthreads();
   C2<T>* zb = lds + l * Sh::L2;
@@ -523,22 +579,15 @@ __device__ void cols_reg(const ColsArgs<T>& a, int bid, int nb, C2<T>* lds) {
   }
   __syncthreads();
   fftr::fft4<T, N, +1, true>(v, lds + l * Sh::L, p, tw);
-  if (pair_ld) {
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int n = p + Sh::N2 * m;
-      const unsigned o = (unsigned)(dct ? dct_perm(n, N) : n) * (unsigned)g.n1 + (unsigned)ja;
-      *reinterpret_cast<V2<T>*>(slice + o) = V2<T>{v[m].x, v[m].y};
-    }
-  } else {
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int n = p + Sh::N2 * m;
-      const unsigned o = (unsigned)(dct ? dct_perm(n, N) : n) * (unsigned)g.n1 + (unsigned)ja;
-      if (hasa) slice[o] = v[m].x;
-      if (hasb) slice[o + 1] = v[m].y;
-    }
-  }
+}
+
+template <typename T, int N>
+__device__ void cols_reg(const ColsArgs<T>& a, int bid, int nb, C2<T>* lds) {
+  const ColTile c = col_tile<T, N>(a, xcd_remap(bid, nb));
+  C2<T> v[16];
+  cols_load<T, N>(a, c, v);
+  cols_xform<T, N>(a, c, v, lds);
+  cols_store<T, N>(a, c, v);
 }
 
 // The float64 LDS-path bodies are compiled once, as functions of their own,
@@ -623,6 +672,7 @@ template <typename T, int N>
 __global__ __launch_bounds__(256) void k_cols_reg(ColsArgs<T> a) {
   cols_reg_entry<T, N>(a, blockIdx.x, gridDim.x);
 }
+
 
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_cols_reg_batch(const ColsArgs<T>* A, const int* off,

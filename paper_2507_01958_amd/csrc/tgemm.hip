@@ -486,13 +486,14 @@ __device__ __forceinline__ float upd_load(const UpdArgs& a, double alpha, int nt
 // Fused forward pass (time GEMM + row transforms along axis 1, N = 256): the
 // block owns axis-0 row bid, all 256 nodes (16 waves x one tile of 16) and all
 // time slices. The operands are scaled per group of gwaves waves, the columns
-// the separate GEMM's blocks cover. The output goes to LDS (rows padded to
-// 272 floats: the four row groups of an accumulator store fall in distinct
-// banks); each of the 64 lines (slices 2 tp, 2 tp + 1) loads its two rows,
-// and after a barrier the same LDS serves the row transforms' exchanges.
+// the separate GEMM's blocks cover. The output goes to LDS (rows of
+// kFusedStride floats: 4 rows apart, the four row groups of a wave's
+// accumulator stores, lie 16 banks apart); each of the 64 lines (slices 2 tp,
+// 2 tp + 1) loads its two rows, and after a barrier the same LDS serves the
+// row transforms' exchanges.
 constexpr int kFusedThreads = 1024;
 constexpr int kFusedN = 256;
-constexpr int kFusedStride = kFusedN + 16;
+constexpr int kFusedStride = kFusedN + 4;
 
 // UPD: the block first applies the conjugate gradient update to its columns
 // (ua; x, r and the r.r partials are written as by the update kernel) and
@@ -587,14 +588,14 @@ __global__ __launch_bounds__(kFusedThreads) void k_tgemm_rows_fwd(GemmArgs<doubl
 // Its 64 lines (slices 2 tp, 2 tp + 1) load their spectra from the float32
 // intermediate and take the inverse transform, exchanging through LDS; the
 // rows then go to an LDS tile in the same space (rows of kInvStride floats:
-// the tile's column reads by the four row groups of a wave fall in distinct
-// banks), each wave (one tile of 16 nodes) takes its operands from it, V
+// the tile's column reads by the four row groups of a wave lie 16 banks
+// apart), each wave (one tile of 16 nodes) takes its operands from it, V
 // replaces the tile, and the products
 // and the epilogue follow the separate GEMM with one 16-node tile per wave:
 // operands scaled per group of gwaves waves, each group's partials formed in
 // the same order and stored at the index of the separate kernel's block
 // (gpr groups per row), so both give the same bits.
-constexpr int kInvStride = kFusedN + 4;
+constexpr int kInvStride = kFusedStride;
 
 template <int MODE, int NTP>
 __global__ __launch_bounds__(kFusedThreads) void k_rows_tgemm_inv(GemmArgs<float, double> ga,

@@ -127,3 +127,4 @@ def test_fused_passes_cp_bitwise(monkeypatch, precision, warm):
     assert list(a[2]) == list(b[2])
     assert np.array_equal(a[0], b[0]), np.abs(a[0] - b[0]).max()
     assert np.array_equal(a[1], b[1]), np.abs(a[1] - b[1]).max()
+
