@@ -58,7 +58,10 @@ def classify(seq):
         prev = shorts[i - 1] if i else ""
         nxt = shorts[i + 1] if i + 1 < len(shorts) else ""
         if s.startswith("k_AAt_tile"):
-            out.append("aat_fused" if s.endswith("true>") else "aat")
+            # k_AAt_tile<HAS0, FUSE, BIG>: with the fused PCG direction when FUSE
+            out.append("aat_fused" if _targs(s)[1:2] == ["true"] else "aat")
+        elif s.startswith("k_rhs_tile") or s.startswith("k_rhs_batch"):
+            out.append("rhs" if s.startswith("k_rhs_tile") else "rhs_batch")
         elif s.startswith("k_rhs"):
             # k_rhs<HASBAR, ...>: the right-hand side with HASBAR, else C y
             out.append("rhs" if _targs(s)[:1] == ["true"] else "apply_C")
