@@ -81,10 +81,16 @@ def test_mixed_precond(case, l):
 
 
 @pytest.mark.parametrize("precision,tol", [("mixed_fp32", 2e-5), ("mixed_fp16", 1e-2)])
-@pytest.mark.parametrize("case", CASES[2:5], ids=_ids)
+@pytest.mark.parametrize("case", CASES[2:], ids=_ids)
 def test_mixed_precond_low_precision(case, precision, tol):
     inst = _inst(case)
     g = grid_of(inst)
+    if precision == "mixed_fp32":
+        # float32 spatial solves: each transform leaves an absolute error of
+        # order u |r| on every mode, and the modes with the smallest symbol,
+        # which dominate P^{-1} r, carry about 1/sqrt(M) of it, so the relative
+        # error scales as u sqrt(M) (u = 2^-24)
+        tol = max(tol, 8 * 2.0 ** -24 * np.sqrt(g.M))
     say(f"mixed precond {precision} {_ids(case)}")
     r = np.random.default_rng(6).standard_normal(g.n)
     ref = pc.apply_Pinv_fast(g, r)

@@ -128,3 +128,21 @@ def test_fused_passes_cp_bitwise(monkeypatch, precision, warm):
     assert np.array_equal(a[0], b[0]), np.abs(a[0] - b[0]).max()
     assert np.array_equal(a[1], b[1]), np.abs(a[1] - b[1]).max()
 
+
+
+@pytest.mark.parametrize("bc_x,bc_y", [("periodic", "neumann"), ("neumann", "periodic")])
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_fp16"])
+def test_fused_passes_per_axis_boundaries(monkeypatch, bc_x, bc_y, precision):
+    """A boundary type per axis (the transform along axis 1 is the one of
+    bc_y): every fused pass on against every one off, P^{-1} r and PCG."""
+    inst = wl.mixed_instance(81, 8, 256, 21, bc_x, bc_y, 0.05)
+    n = 21 * 8 * 256
+    rng = np.random.default_rng(82)
+    r = rng.standard_normal(n) * np.exp(rng.uniform(-3, 3, n))
+    b = rng.standard_normal(n)
+    say(f"fused per-axis {precision} {bc_x}/{bc_y}")
+    z0, u0, s0 = _run(monkeypatch, "fuse_fwd=0,fuse_upd=0,fuse_inv=0", inst, precision, r, b)
+    z1, u1, s1 = _run(monkeypatch, "fuse_fwd=1,fuse_upd=1,fuse_inv=1", inst, precision, r, b)
+    assert np.array_equal(z0, z1), np.abs(z0 - z1).max()
+    assert np.array_equal(u0, u1), np.abs(u0 - u1).max()
+    assert s0 == s1
