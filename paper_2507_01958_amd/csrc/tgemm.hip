@@ -435,8 +435,9 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t rs, unsigned off, 
 // so a wave keeps two groups of loads in flight. Elements with t >= N_t lie
 // beyond the descriptors' range: they read 0 (a zero operand, as lp_load's)
 // and their stores are dropped. Requires NTP M 8 < 2^31 bytes (the caller
-// checks). FIRST: x = 0 before the update (written, not read).
-template <int MODE, int NTP, int CB, bool FIRST>
+// checks). FIRST: x = 0 before the update (written, not read). XUPD = false:
+// only r (x += alpha p is left to XStream).
+template <int MODE, int NTP, int CB, bool FIRST, bool XUPD = true>
 __device__ __forceinline__ float upd_load(const UpdArgs& a, double alpha, int nt, int M, int col0,
                                           int kq, float (&xs)[CB][LpShape<MODE, NTP>::NKS]
                                                              [LpShape<MODE, NTP>::PER],
@@ -456,10 +457,10 @@ __device__ __forceinline__ float upd_load(const UpdArgs& a, double alpha, int nt
 #pragma unroll
     for (int e = 0; e < G; ++e) {
       const unsigned o = off(ks, e);
-      pb[buf][e] = buf_ld(pr, o);
+      if (XUPD) pb[buf][e] = buf_ld(pr, o);
       qb[buf][e] = buf_ld(qr, o);
       rb[buf][e] = buf_ld(rr_, o);
-      if (!FIRST) xb[buf][e] = buf_ld(xr, o);
+      if (XUPD && !FIRST) xb[buf][e] = buf_ld(xr, o);
     }
   };
   float amax = 0.0f;
@@ -471,7 +472,8 @@ __device__ __forceinline__ float upd_load(const UpdArgs& a, double alpha, int nt
 #pragma unroll
     for (int e = 0; e < G; ++e) {
       const unsigned o = off(ks, e);
-      buf_st(xr, o, FIRST ? alpha * pb[cur][e] : __builtin_fma(alpha, pb[cur][e], xb[cur][e]));
+      if (XUPD)
+        buf_st(xr, o, FIRST ? alpha * pb[cur][e] : __builtin_fma(alpha, pb[cur][e], xb[cur][e]));
       const double ri = __builtin_fma(-alpha, qb[cur][e], rb[cur][e]);
       buf_st(rr_, o, ri);
       rr += ri * ri;
@@ -482,6 +484,57 @@ __device__ __forceinline__ float upd_load(const UpdArgs& a, double alpha, int nt
   }
   return amax;
 }
+
+// x += alpha p of the fused kernel's column (one 16-node tile, CB = 1) by
+// ranges of k-steps whose loads are issued before one of the kernel's
+// LDS-only phases (products, tile, row loads, transforms) and whose stores
+// follow it, so most of this third of the update's traffic overlaps the
+// computation. The ranges (bound(c), c = 0..5) give each phase what its free
+// registers hold (1/8 of the k-steps during the products and the transforms,
+// 2/8 during the tile phases); the last quarter follows the transforms. The
+// same multiply-add as the update kernel; t >= N_t lies beyond the
+// descriptors' range.
+template <int MODE, int NTP, bool FIRST>
+struct XStream {
+  using L = LpShape<MODE, NTP>;
+  static constexpr int bound(int c) {
+    return c == 0 ? 0 : c == 1 ? L::NKS / 8 : c == 2 ? 3 * L::NKS / 8
+                      : c == 3 ? 5 * L::NKS / 8 : c == 4 ? 6 * L::NKS / 8 : L::NKS;
+  }
+  __amdgpu_buffer_rsrc_t xr, pr;
+  double alpha;
+  int M, col0, kq;
+  double xb[L::NKS][L::PER], pb[L::NKS][L::PER];
+  __device__ __forceinline__ unsigned off(int ks, int j) const {
+    const int t = L::KSTEP * ks + L::PER * kq + j;
+    return ((unsigned)t * (unsigned)M + (unsigned)col0) * 8u;
+  }
+  // the compiler's scheduler keeps each range's loads at their place (hoisted
+  // into the products, they would hold registers there)
+  template <int C>
+  __device__ __forceinline__ void load() {
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int ks = bound(C); ks < bound(C + 1); ++ks)
+#pragma unroll
+      for (int j = 0; j < L::PER; ++j) {
+        const unsigned o = off(ks, j);
+        pb[ks][j] = buf_ld(pr, o);
+        if (!FIRST) xb[ks][j] = buf_ld(xr, o);
+      }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  template <int C>
+  __device__ __forceinline__ void store() {
+#pragma unroll
+    for (int ks = bound(C); ks < bound(C + 1); ++ks)
+#pragma unroll
+      for (int j = 0; j < L::PER; ++j) {
+        const double pv = pb[ks][j];
+        buf_st(xr, off(ks, j), FIRST ? alpha * pv : __builtin_fma(alpha, pv, xb[ks][j]));
+      }
+  }
+};
 
 // Fused forward pass (time GEMM + row transforms along axis 1, N = 256): the
 // block owns axis-0 row bid, all 256 nodes (16 waves x one tile of 16) and all
@@ -498,26 +551,37 @@ constexpr int kFusedStride = kFusedN + 4;
 // UPD: the block first applies the conjugate gradient update to its columns
 // (ua; x, r and the r.r partials are written as by the update kernel) and
 // takes the new r as the GEMM operand.
-template <int MODE, int NTP, bool UPD>
-__global__ __launch_bounds__(kFusedThreads) void k_tgemm_rows_fwd(GemmArgs<double, float> ga,
-                                                                  RowsArgs<float> ra, UpdArgs ua,
-                                                                  int gwaves) {
+template <int MODE, int NTP>
+struct FusedFwdLds {
+  using L = LpShape<MODE, NTP>;
+  using Sh = fftr::Shape<float, kFusedN>;
+  static constexpr int LINES = kFusedThreads / Sh::N2;  // 64 lines: up to 128 time slices
+  static constexpr int TILE_BYTES = NTP * kFusedStride * 4;
+  static constexpr int VS_BYTES = L::VROWS * NTP * (int)sizeof(typename L::VT);
+  static constexpr int SCR_BYTES =
+      LINES * (Sh::L > Sh::L2 ? Sh::L : Sh::L2) * (int)sizeof(C2<float>);
+  static constexpr int A1 = TILE_BYTES > VS_BYTES ? TILE_BYTES : VS_BYTES;
+  static constexpr int BYTES = A1 > SCR_BYTES ? A1 : SCR_BYTES;
+};
+
+// XM: 0 no update; 1 the update with x = 0 before it (x written, not read);
+// 2 the update. smem: FusedFwdLds bytes; smax: one float per wave; twc: the
+// row transform's twiddles (2 N floats) and DCT post-twiddles (2 N floats),
+// staged from global memory so the transform phase issues no global loads
+// (which would also wait for the x chunk's loads in flight).
+template <int MODE, int NTP, int XM>
+__device__ __forceinline__ void tgemm_rows_fwd_body(const GemmArgs<double, float>& ga,
+                                                    const RowsArgs<float>& ra, const UpdArgs& ua,
+                                                    int gwaves, unsigned char* smem, float* smax,
+                                                    float* twc) {
   const int bid = blockIdx.x;
-  if (gemm_skip(ga, bid)) return;
   using L = LpShape<MODE, NTP>;
   using VT = typename L::VT;
   using Sh = fftr::Shape<float, kFusedN>;
   constexpr int CB = 1, WAVES = kFusedThreads / 64;
   static_assert(WAVES * CB * 16 == kFusedN, "a block covers one row of 256 nodes");
-  constexpr int LINES = kFusedThreads / Sh::N2;  // 64 lines: up to 128 time slices
-  static_assert(2 * LINES >= 128, "one pass transforms every time slice");
-  constexpr int TILE_BYTES = NTP * kFusedStride * 4;
-  constexpr int VS_BYTES = L::VROWS * NTP * (int)sizeof(VT);
-  constexpr int SCR_BYTES = LINES * (Sh::L > Sh::L2 ? Sh::L : Sh::L2) * (int)sizeof(C2<float>);
-  constexpr int A1 = TILE_BYTES > VS_BYTES ? TILE_BYTES : VS_BYTES;
-  constexpr int A_BYTES = A1 > SCR_BYTES ? A1 : SCR_BYTES;
-  __shared__ __align__(16) unsigned char smem[A_BYTES];
-  __shared__ float smax[WAVES];
+  static_assert(2 * FusedFwdLds<MODE, NTP>::LINES >= 128, "one pass transforms every slice");
+  static_assert(kFusedThreads == 4 * kFusedN, "one thread per staged table entry");
   VT* Vs = reinterpret_cast<VT*>(smem);              // V during the products,
   float* tile = reinterpret_cast<float*>(smem);      // then the output tile,
   C2<float>* scr = reinterpret_cast<C2<float>*>(smem);  // then the exchange areas
@@ -525,15 +589,27 @@ __global__ __launch_bounds__(kFusedThreads) void k_tgemm_rows_fwd(GemmArgs<doubl
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, kq = lane >> 4;
   const int i0 = bid;
   const int col0 = i0 * kFusedN + wave * 16 + (lane & 15);
+  const bool dct = ra.ax.kind == 1;
   float xs[CB][L::NKS][L::PER];
   float amax;
-  if constexpr (UPD) {
+  // x += alpha p streamed through the compute phases (XS), or with r in the
+  // first phase (the float32 split: its products and conversions leave no
+  // registers for the streamed ranges)
+  constexpr bool XS = XM != 0 && MODE != GM_F32;
+  XStream<MODE, NTP, XM == 1> xst;
+  if constexpr (XM != 0) {
     const double alpha = pcg_alpha(ua, bid);
     double rr[1] = {0.0};
-    amax = ua.first ? upd_load<MODE, NTP, CB, true>(ua, alpha, nt, M, col0, kq, xs, rr[0])
-                    : upd_load<MODE, NTP, CB, false>(ua, alpha, nt, M, col0, kq, xs, rr[0]);
+    amax = upd_load<MODE, NTP, CB, XM == 1, !XS>(ua, alpha, nt, M, col0, kq, xs, rr[0]);
     lp_stage_v<MODE, NTP>(static_cast<const VT*>(ga.V), Vs, kFusedThreads);
     reduce_store<1>(rr, ua.rb, T_RR, bid);
+    const unsigned bytes = (unsigned)nt * (unsigned)M * 8u;
+    xst.xr = buf_rsrc(ua.x, bytes);
+    xst.pr = buf_rsrc(ua.p, bytes);
+    xst.alpha = alpha;
+    xst.M = M;
+    xst.col0 = col0;
+    xst.kq = kq;
   } else {
     amax = lp_load<MODE, NTP, CB>(ga.X, nt, M, col0, kq, xs);
     lp_stage_v<MODE, NTP>(static_cast<const VT*>(ga.V), Vs, kFusedThreads);
@@ -544,6 +620,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_tgemm_rows_fwd(GemmArgs<doubl
     if (lane == 0) smax[wave] = amax;
   }
   __syncthreads();
+  // table entry of this thread (written to LDS before the transforms; loaded
+  // here, after the update's registers are free)
+  float tcv = 0.0f;
+  if (threadIdx.x < 2 * kFusedN) tcv = tw_table<float>(ra.ax)[threadIdx.x];
+  else if (dct) tcv = ct_table<float>(ra.ax)[threadIdx.x - 2 * kFusedN];
+  if constexpr (XS) xst.template load<0>();
   float bm = 0.0f;
   if (L::SCALED) {
     const int g0 = (wave / gwaves) * gwaves;
@@ -554,6 +636,10 @@ __global__ __launch_bounds__(kFusedThreads) void k_tgemm_rows_fwd(GemmArgs<doubl
   lp_scales<MODE, NTP>(bm, scale, unscale);
   v4f acc[CB][L::NKB];
   lp_mma<MODE, NTP, CB>(Vs, xs, scale, lane, acc);
+  if constexpr (XS) {
+    xst.template store<0>();
+    xst.template load<1>();
+  }
   __syncthreads();  // V is no longer read: its LDS takes the output tile
 #pragma unroll
   for (int kb = 0; kb < L::NKB; ++kb)
@@ -561,8 +647,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_tgemm_rows_fwd(GemmArgs<doubl
     for (int jr = 0; jr < 4; ++jr)
       tile[(kb * 16 + 4 * kq + jr) * kFusedStride + wave * 16 + (lane & 15)] =
           acc[0][kb][jr] * unscale;
+  twc[threadIdx.x] = tcv;
   __syncthreads();
-  const bool dct = ra.ax.kind == 1;
+  if constexpr (XS) {
+    xst.template store<1>();
+    xst.template load<2>();
+  }
   const int l = threadIdx.x / Sh::N2, p = threadIdx.x % Sh::N2;
   // rows of slices 2 l and 2 l + 1 (tile rows 2 l, 2 l + 1)
   const RowPair rp = row_pair(l * ra.n0 + i0, ra.nrows, ra.n0);
@@ -573,6 +663,10 @@ __global__ __launch_bounds__(kFusedThreads) void k_tgemm_rows_fwd(GemmArgs<doubl
       [&](int n) { return C2<float>{rp.hasa ? ta[n] : 0.0f, rp.hasb ? tb[n] : 0.0f}; }, dct, p,
       v);
   __syncthreads();  // the tile is read: its LDS takes the exchange areas
+  if constexpr (XS) {
+    xst.template store<2>();
+    xst.template load<3>();
+  }
   float* __restrict__ out = ra.data;
   rows_fwd_xform<float, kFusedN>(
       v,
@@ -580,7 +674,28 @@ __global__ __launch_bounds__(kFusedThreads) void k_tgemm_rows_fwd(GemmArgs<doubl
         if (rp.hasa) out[(unsigned)rp.ra * kFusedN + k] = oa;  // n < 2^31
         if (rp.hasb) out[(unsigned)rp.rb * kFusedN + k] = ob;
       },
-      dct, scr + l * Sh::L, scr + l * Sh::L2, p, tw_table<float>(ra.ax), ct_table<float>(ra.ax));
+      dct, scr + l * Sh::L, scr + l * Sh::L2, p, twc, twc + 2 * kFusedN);
+  if constexpr (XS) {
+    xst.template store<3>();
+    xst.template load<4>();
+    xst.template store<4>();
+  }
+}
+
+template <int MODE, int NTP, bool UPD>
+__global__ __launch_bounds__(kFusedThreads) void k_tgemm_rows_fwd(GemmArgs<double, float> ga,
+                                                                  RowsArgs<float> ra, UpdArgs ua,
+                                                                  int gwaves) {
+  if (gemm_skip(ga, blockIdx.x)) return;
+  __shared__ __align__(16) unsigned char smem[FusedFwdLds<MODE, NTP>::BYTES];
+  __shared__ float smax[kFusedThreads / 64];
+  __shared__ float twc[4 * kFusedN];
+  if constexpr (UPD) {
+    if (ua.first) tgemm_rows_fwd_body<MODE, NTP, 1>(ga, ra, ua, gwaves, smem, smax, twc);
+    else tgemm_rows_fwd_body<MODE, NTP, 2>(ga, ra, ua, gwaves, smem, smax, twc);
+  } else {
+    tgemm_rows_fwd_body<MODE, NTP, 0>(ga, ra, ua, gwaves, smem, smax, twc);
+  }
 }
 
 // Fused inverse pass (row transforms along axis 1, N = 256, then the inverse
