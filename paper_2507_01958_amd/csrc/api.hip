@@ -177,6 +177,7 @@ static void read_tune_env(Tune& t) {
       else if (k == "fuse_fwd" && (v == 0 || v == 1)) t.fuse_fwd = v;
       else if (k == "fuse_upd" && (v == 0 || v == 1)) t.fuse_upd = v;
       else if (k == "fuse_inv" && (v == 0 || v == 1)) t.fuse_inv = v;
+      else if (k == "batch_queue" && (v == 0 || v == 1)) t.batch_queue = v;
     }
     pos = end + 1;
   }

@@ -95,6 +95,10 @@ struct Batch {
   hipGraphExec_t exec = nullptr;
   int graph_k = 0;
   std::vector<void*> dev;
+  // persistent A phase over a tile queue (Tune::batch_queue): the counter and
+  // the resident grid
+  int* queue = nullptr;
+  int qgrid = 0;
 };
 
 }  // namespace mfg
@@ -433,7 +437,7 @@ void precond_phase(Batch& B, bool init, hipStream_t s) {
 // PCG iteration k >= 1 for every instance not yet converged.
 void pcg_iteration(Batch& B, int k, hipStream_t s) {
   const auto& aat = (k == 1) ? B.aat_first : ((k & 1) ? B.aat_odd : B.aat_even);
-  launch_aat_batch(true, aat.args, aat.off, B.count, aat.total, s);
+  launch_aat_batch(true, aat.args, aat.off, B.count, aat.total, s, B.queue, B.qgrid);
   const auto& upd = (k == 1) ? B.upd_first : ((k & 1) ? B.upd_odd : B.upd_even);
   launch_update_batch(upd.args, upd.off, B.count, upd.total, s);
   precond_phase(B, false, s);
@@ -513,6 +517,12 @@ int batch_create(Batch& B, const mfg_problem_t* pbs, const double* const* V,
       hipSuccess)
     return fail(MFG_ERR_OOM, "pinned allocation failed");
   B.host_scal = static_cast<double*>(p);
+  if (plan_of(B, 0).tune.batch_queue) {
+    if ((rc = dmalloc(B, &p, sizeof(int)))) return rc;
+    B.queue = static_cast<int*>(p);
+    B.qgrid = aat_queue_grid(true);
+    if (B.qgrid <= 0) B.queue = nullptr;  // occupancy unknown: one block per tile
+  }
   return build_pcg_phases(B);
 }
 

@@ -210,8 +210,11 @@ void launch_update_batch(const UpdArgs* A, const int* off, int ninst, int total,
 void launch_finish_batch(const FinishArgs* F, int ninst, hipStream_t s);
 void launch_cp_advance_batch(double* scal, int stride, int ninst, const double* sched, int maxit,
                              hipStream_t s);
+// queue != nullptr: the persistent form over a tile queue (queue: one device
+// int; qgrid: resident blocks, aat_queue_grid; 0 = not available).
 void launch_aat_batch(bool has0, const AatArgs* A, const int* off, int ninst, int total,
-                      hipStream_t s);
+                      hipStream_t s, int* queue = nullptr, int qgrid = 0);
+int aat_queue_grid(bool has0);
 void launch_rhs_batch(const RhsArgs* A, const int* off, int ninst, int total, hipStream_t s);
 void launch_backproj_batch(const BackprojArgs* A, const int* off, int ninst, int total,
                            hipStream_t s);

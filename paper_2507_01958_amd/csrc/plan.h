@@ -45,6 +45,9 @@ struct Tune {
   // inverse pass fused (row transforms + inverse time GEMM) where it applies
   // (as fuse_fwd, and one 16-node tile per wave in the inverse GEMM)
   int fuse_inv = 1;
+  // batched solves: the A phase as a persistent grid over a tile queue
+  // (0: one block per instance tile)
+  int batch_queue = 0;
 };
 
 // Optional per-kernel timing with HIP events recorded on the plan's stream

@@ -861,6 +861,31 @@ __global__ __launch_bounds__((Tile<HAS0, HAS0 ? kBatchBig : 0>::NT)) void k_AAt_
   aat_body<HAS0, true, HAS0 ? kBatchBig : 0>(A[i], blockIdx.x - off[i], off[i + 1] - off[i]);
 }
 
+// Persistent form of the batched A phase over a tile queue: a resident grid
+// whose blocks take virtual block ids (instance tiles in the batch's order) from
+// a device counter until every one is taken; each runs the batched kernel's
+// body with that id, so the results are the same bits. The counter starts at 0
+// (k_queue_reset, a kernel so the step can be recorded in a graph); every block
+// leaves once the counter passes `total`.
+__global__ void k_queue_reset(int* q) {
+  if (threadIdx.x == 0) *q = 0;
+}
+
+template <bool HAS0>
+__global__ __launch_bounds__((Tile<HAS0, HAS0 ? kBatchBig : 0>::NT)) void k_AAt_batch_queue(
+    const AatArgs* A, const int* off, int ninst, int total, int* queue) {
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+    __syncthreads();  // also: the previous tile's LDS reads are over
+    const int vb = next;
+    __syncthreads();  // `next` is read before thread 0 takes the next id
+    if (vb >= total) return;
+    const int i = batch_instance(off, ninst, vb);
+    aat_body<HAS0, true, HAS0 ? kBatchBig : 0>(A[i], vb - off[i], off[i + 1] - off[i]);
+  }
+}
+
 // One thread per node up to `cap` blocks (grid-stride beyond that).
 int grid_for(long long n, int cap = kStreamGrid) {
   long long b = (n + kThreads - 1) / kThreads;
@@ -1084,8 +1109,33 @@ AatArgs aat_args(const Plan& P, const double* z, const double* pold, double* pne
                  pcg_flexible(P) ? 1 : 0};
 }
 
+int aat_queue_grid(bool has0) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const hipError_t e =
+      has0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_AAt_batch_queue<true>,
+                                                          Tile<true, kBatchBig>::NT, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_AAt_batch_queue<false>,
+                                                          Tile<false, 0>::NT, 0);
+  if (e != hipSuccess || per < 1) return 0;
+  return cus * per;
+}
+
 void launch_aat_batch(bool has0, const AatArgs* A, const int* off, int ninst, int total,
-                      hipStream_t s) {
+                      hipStream_t s, int* queue, int qgrid) {
+  if (queue && qgrid > 0) {
+    const int grid = qgrid < total ? qgrid : total;
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
+    if (has0)
+      hipLaunchKernelGGL(k_AAt_batch_queue<true>, dim3(grid), dim3(Tile<true, kBatchBig>::NT), 0,
+                         s, A, off, ninst, total, queue);
+    else
+      hipLaunchKernelGGL(k_AAt_batch_queue<false>, dim3(grid), dim3(Tile<false, 0>::NT), 0, s,
+                         A, off, ninst, total, queue);
+    return;
+  }
   if (has0)
     hipLaunchKernelGGL(k_AAt_batch<true>, dim3(total), dim3(Tile<true, kBatchBig>::NT), 0, s, A,
                        off, ninst);

@@ -149,6 +149,7 @@ void keep_untuned(const Tune& from, Tune& to) {
   to.fuse_fwd = from.fuse_fwd;
   to.fuse_upd = from.fuse_upd;
   to.fuse_inv = from.fuse_inv;
+  to.batch_queue = from.batch_queue;
 }
 
 // allow_pers = false keeps the time GEMM in the form the batched launches use.

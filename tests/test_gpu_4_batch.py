@@ -236,3 +236,21 @@ def test_mixed_batch_long_horizons(precision):
         assert b[5] == ref[5], (inst.name, b[5], ref[5])
         for name, x, y in zip(["xi", "y", "ybar"], b[:3], ref[:3]):
             assert np.array_equal(x, y), (inst.name, name)
+
+
+@pytest.mark.parametrize("precision,use_graph", [("mixed_fp32", True), ("fp64", False)])
+def test_batch_tile_queue_bitwise_equals_single(monkeypatch, precision, use_graph):
+    """The batched A phase as a persistent grid over a tile queue (MFG_TUNE
+    batch_queue=1: resident blocks take instance tiles from a device counter)
+    gives the bits of single plans."""
+    monkeypatch.setenv("MFG_TUNE", "batch_queue=1")
+    insts = _instances()
+    chunks = [1, 4, 3]
+    rtol, maxit = 1e-10, 300
+    say(f"batch tile queue {precision} graph={use_graph} x{len(insts)}")
+    got = _batched(insts, precision, chunks, rtol, maxit, use_graph)
+    for inst, b in zip(insts, got):
+        ref = _single(inst, precision, chunks, rtol, maxit)
+        assert b[5] == ref[5], (inst.name, b[5], ref[5])
+        for name, x, y in zip(["xi", "y", "ybar"], b[:3], ref[:3]):
+            assert np.array_equal(x, y), (inst.name, name, np.abs(x - y).max())
