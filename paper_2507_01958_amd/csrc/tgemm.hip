@@ -548,9 +548,8 @@ constexpr int kFusedThreads = 1024;
 constexpr int kFusedN = 256;
 constexpr int kFusedStride = kFusedN + 4;
 
-// UPD: the block first applies the conjugate gradient update to its columns
-// (ua; x, r and the r.r partials are written as by the update kernel) and
-// takes the new r as the GEMM operand.
+// LDS of the fused forward pass: V during the products, then the output tile,
+// then the row transforms' exchange areas, in one space of BYTES.
 template <int MODE, int NTP>
 struct FusedFwdLds {
   using L = LpShape<MODE, NTP>;
@@ -682,6 +681,9 @@ __device__ __forceinline__ void tgemm_rows_fwd_body(const GemmArgs<double, float
   }
 }
 
+// UPD: the block first applies the conjugate gradient update to its columns
+// (ua; x, r and the r.r partials are written as by the update kernel) and
+// takes the new r as the GEMM operand.
 template <int MODE, int NTP, bool UPD>
 __global__ __launch_bounds__(kFusedThreads) void k_tgemm_rows_fwd(GemmArgs<double, float> ga,
                                                                   RowsArgs<float> ra, UpdArgs ua,
